@@ -1,0 +1,106 @@
+"""Leaf-set construction for sparse-voxel octrees (structure only).
+
+An octree is stored as its leaves only: each leaf has a level ``l`` and an
+integer cell ``ijk`` in [0, 2^l)^3.  Corners are identified by their exact
+integer position on the finest grid, so neighbouring leaves share corner
+entries (one raw density per grid corner, as in the paper's initialisation
+section where densities are assigned "for each grid corner").
+"""
+import numpy as np
+
+
+def leaves_from_grid(level, ijk):
+    """Return (level u8[N], ijk i32[3,N]) for cells given as an [N,3] array."""
+    ijk = np.asarray(ijk, dtype=np.int64).reshape(-1, 3)
+    lv = np.full(ijk.shape[0], level, dtype=np.uint8)
+    return lv, np.ascontiguousarray(ijk.T.astype(np.int32))
+
+
+def full_grid(level):
+    n = 1 << level
+    g = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n),
+                             indexing="ij"), -1).reshape(-1, 3)
+    return leaves_from_grid(level, g)
+
+
+def children(level, ijk):
+    """Children of a set of cells: level+1, 8 per cell (m = mx+2my+4mz)."""
+    ijk = np.asarray(ijk, dtype=np.int64).reshape(3, -1)
+    out = []
+    for m in range(8):
+        off = np.array([m & 1, (m >> 1) & 1, (m >> 2) & 1])[:, None]
+        out.append(2 * ijk + off)
+    ch = np.concatenate(out, axis=1)
+    return np.full(ch.shape[1], level + 1, np.uint8), ch.astype(np.int32)
+
+
+def random_subdivide(level, ijk, n_sub, max_level, rng):
+    """Apply ``n_sub`` subdivisions, each of a leaf drawn uniformly among
+    the leaves whose level is below ``max_level``.  Order of the returned
+    leaves: the surviving originals, then children in creation order."""
+    lv = list(np.asarray(level, dtype=np.int64))
+    cells = [tuple(c) for c in np.asarray(ijk).T.tolist()]
+    for _ in range(n_sub):
+        cand = [i for i, l in enumerate(lv) if l < max_level]
+        if not cand:
+            break
+        k = cand[int(rng.integers(len(cand)))]
+        l, c = lv.pop(k), cells.pop(k)
+        for m in range(8):
+            lv.append(l + 1)
+            cells.append((2 * c[0] + (m & 1), 2 * c[1] + ((m >> 1) & 1),
+                          2 * c[2] + ((m >> 2) & 1)))
+    return (np.array(lv, np.uint8),
+            np.ascontiguousarray(np.array(cells, np.int64).T.astype(np.int32)))
+
+
+def corner_positions(level, ijk, max_level):
+    """Integer finest-grid positions of the 8 corners: int64[8,3,N]."""
+    lv = np.asarray(level, np.int64)
+    ijk = np.asarray(ijk, np.int64)
+    sh = (max_level - lv)[None, :]
+    out = np.empty((8, 3, lv.shape[0]), np.int64)
+    for m in range(8):
+        off = np.array([m & 1, (m >> 1) & 1, (m >> 2) & 1])[:, None]
+        out[m] = (ijk + off) << sh
+    return out
+
+
+def dedup_corners(level, ijk, max_level):
+    """Shared-corner table: corner_idx i32[8,N] and the unique integer
+    positions int64[Nc,3] (finest grid) in first-appearance-sorted order."""
+    pos = corner_positions(level, ijk, max_level)  # [8,3,N]
+    n = pos.shape[2]
+    flat = pos.transpose(0, 2, 1).reshape(-1, 3)  # [8N,3], m-major
+    side = (1 << max_level) + 1
+    key = (flat[:, 0] * side + flat[:, 1]) * side + flat[:, 2]
+    uniq, inv = np.unique(key, return_inverse=True)
+    cidx = inv.reshape(8, n).astype(np.int32)
+    upos = np.stack([uniq // (side * side), (uniq // side) % side,
+                     uniq % side], -1)
+    return np.ascontiguousarray(cidx), upos
+
+
+def make_octree(root_min, root_size, max_level, level, ijk, corner_idx,
+                corner_density, sh, box_min=None, box_max=None):
+    level = np.ascontiguousarray(level, dtype=np.uint8)
+    ijk = np.ascontiguousarray(ijk, dtype=np.int32)
+    sh = np.ascontiguousarray(sh, dtype=np.float32)
+    s = sh.shape[0]
+    deg = int(round(np.sqrt(s))) - 1
+    assert (deg + 1) ** 2 == s and sh.shape[1] == 3
+    o = dict(root_min=np.asarray(root_min, np.float64).copy(),
+             root_size=float(root_size), max_level=int(max_level),
+             level=level, ijk=ijk,
+             corner_idx=np.ascontiguousarray(corner_idx, dtype=np.int32),
+             corner_density=np.ascontiguousarray(corner_density,
+                                                 dtype=np.float32),
+             sh_degree=deg, sh=sh)
+    if box_min is not None:
+        o["box_min"] = np.asarray(box_min, np.float64).copy()
+        o["box_max"] = np.asarray(box_max, np.float64).copy()
+    return o
+
+
+def n_voxels(o):
+    return int(o["level"].shape[0])
