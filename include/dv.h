@@ -1,0 +1,285 @@
+/*
+ * dv.h - C ABI of the compositional multi-octree sparse-voxel renderer.
+ *
+ * The renderer follows DrivingVoxels (arXiv 2606.23031): a static
+ * world-frame octree O_bg plus one local-frame octree O_i per rigid actor
+ * (Sec. 3.1-3.2) are rendered in a single pass (Sec. 3, overview).  Each
+ * camera ray is split by the actors' box intervals into background and
+ * asset segments (Sec. 3.4, App. A, Alg. 1), every segment is integrated
+ * with trilinear raw density, exp-linear activation and alpha compositing,
+ * and the result is composited over a constant sky colour (Eq. 2).
+ *
+ * Conventions used by every call:
+ *  - "device" pointers are HIP device memory of the context's GPU; "host"
+ *    pointers are ordinary CPU memory.  No call takes ownership of a caller
+ *    pointer; caller arrays must stay alive as long as the object that
+ *    references them (scene, forward state, request).
+ *  - Every call returns dv_status; no C++ exception crosses this boundary.
+ *    On failure dv_last_error() returns a message for the calling thread.
+ *  - Work is enqueued on the caller's HIP stream (passed as void*; NULL is
+ *    the default stream).  Results are valid when that stream completes.
+ *  - Arrays are structure-of-arrays: ijk is [3][N], corner_idx is [8][N],
+ *    sh is [S][3][N] with S = (degree+1)^2; images are planar [C][h][w].
+ */
+#ifndef DV_H
+#define DV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dv_status;
+#define DV_OK 0
+#define DV_PENDING 1            /* serving: request not finished yet      */
+#define DV_ERR_INVALID (-1)     /* malformed argument                     */
+#define DV_ERR_OOM (-2)         /* device or host allocation failed       */
+#define DV_ERR_DEVICE (-3)      /* HIP error; the context is poisoned     */
+#define DV_ERR_OVERLAP (-4)     /* two leaves of one octree overlap       */
+#define DV_ERR_RANGE (-5)       /* level / index / corner out of range    */
+#define DV_ERR_LIMIT (-6)       /* a size exceeds a documented limit      */
+#define DV_ERR_TICKET (-7)      /* unknown serving ticket                 */
+#define DV_ERR_SHUTDOWN (-8)    /* server is shutting down                */
+
+/* Output selection (dv_render_opts.out_mask). */
+#define DV_OUT_RGB 1u
+#define DV_OUT_DEPTH 2u
+#define DV_OUT_NORMAL 4u
+#define DV_OUT_T 8u
+
+/* Documented limits. */
+#define DV_MAX_LEVEL 16         /* octree depth                           */
+#define DV_MAX_SH_DEGREE 3
+#define DV_MAX_OCTREES 4096     /* background + actors                    */
+#define DV_MAX_TILE_ACTORS 255  /* actor boxes binned to one 16x16 tile   */
+#define DV_MAX_K 16             /* midpoint samples per piece             */
+
+typedef struct dv_ctx dv_ctx;
+typedef struct dv_scene dv_scene;
+typedef struct dv_fwd_state dv_fwd_state;
+typedef struct dv_server dv_server;
+
+/* One octree (Sec. 3.1 static background, Sec. 3.2 actor asset).
+ * Only leaves are stored: leaf v at level[v] with integer cell ijk[:,v]
+ * in [0, 2^level)^3 occupies root_min + ijk*h .. root_min + (ijk+1)*h,
+ * h = root_size / 2^level, in the octree's own frame.  Corner m of a leaf
+ * (m = mx + 2*my + 4*mz) holds raw density corner_density[corner_idx[m][v]]
+ * (shared between leaves when indices coincide).  SH coefficients give the
+ * view-dependent colour.  Leaves must not overlap.  For actors, the box
+ * [box_min, box_max] (local frame) bounds the asset interval along rays;
+ * with has_box = 0 the root cube is used (Sec. 3.3 'Assets'). */
+typedef struct {
+  double root_min[3];
+  double root_size;             /* cube side, > 0                         */
+  int32_t n_voxels;             /* N >= 0                                  */
+  int32_t max_level;            /* all levels <= max_level <= 16           */
+  int32_t n_corners;            /* Nc                                      */
+  int32_t sh_degree;            /* 0..3                                    */
+  const uint8_t* level;         /* device [N]                              */
+  const int32_t* ijk;           /* device [3][N]                           */
+  const int32_t* corner_idx;    /* device [8][N], values in [0, Nc)        */
+  const float* corner_density;  /* device [Nc]; may change between calls   */
+  const float* sh;              /* device [S][3][N]; may change            */
+  int32_t has_box;
+  double box_min[3];
+  double box_max[3];
+} dv_octree_desc;
+
+/* Track of actor i (Sec. 3.2: rigid T_t^i from tracking).  Reading used
+ * for the synthetic tracks: yaw about world +z and translation, each
+ * linear in t between keyframes; the actor is active iff
+ * t[0] <= t <= t[n_keys-1].  x_world = R(yaw) x_local + trans.
+ * Host arrays; copied by dv_build_scene. */
+typedef struct {
+  int32_t n_keys;               /* >= 1, t strictly increasing             */
+  const double* t;              /* host [n_keys]                           */
+  const double* yaw;            /* host [n_keys] radians                   */
+  const double* trans;          /* host [n_keys][3]                        */
+} dv_track_desc;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  Rays pass
+ * through pixel centres; tau is the Euclidean distance.  Only the window
+ * [x0, x0+w) x [y0, y0+h) of the W x H image is rendered; outputs are
+ * window-sized.  c2w is the row-major 3x4 camera-to-world matrix. */
+typedef struct {
+  double fx, fy, cx, cy;
+  int32_t W, H;
+  int32_t x0, y0, w, h;
+  double c2w[12];
+  double t;                     /* timestamp used to pose the actors       */
+} dv_view;
+
+typedef struct {
+  int32_t K;                    /* midpoint samples per piece, 1..16       */
+  float eps_stop;               /* stop a ray once T < eps_stop (Alg. 1)   */
+  float tau_near;               /* rays start at tau_near >= 0             */
+  float bg[3];                  /* constant sky colour C_sky (Eq. 2)       */
+  float explin_c;               /* knee of the exp-linear activation, > 0  */
+  uint32_t out_mask;            /* DV_OUT_* bits                           */
+} dv_render_opts;
+
+/* Per-view device output planes (window-sized, float).  Entries not in
+ * out_mask may be NULL. */
+typedef struct {
+  float* rgb;                   /* [3][h][w]  C_voxels + T * bg            */
+  float* depth;                 /* [h][w]     sum w_i (a_i + b_i) / 2      */
+  float* normal;                /* [3][h][w]  sum w_i R n_i (world frame)  */
+  float* T;                     /* [h][w]     final transmittance          */
+} dv_outputs;
+
+/* Per-view upstream gradients (device, same layout as dv_outputs); a
+ * NULL plane counts as zero. */
+typedef struct {
+  const float* rgb;
+  const float* depth;
+  const float* normal;
+  const float* T;
+} dv_out_grads;
+
+/* Gradient accumulators of one octree (device; results are ADDED). */
+typedef struct {
+  float* corner;                /* [Nc] or NULL                            */
+  float* sh;                    /* [S][3][N] or NULL                       */
+} dv_octree_grads;
+
+typedef struct {
+  const dv_octree_grads* octrees; /* host array [n_octrees]                */
+  float* pose;                  /* device [n_views][n_actors][12] or NULL:
+                                   dL/dR row-major (9) then dL/dp (3)      */
+} dv_param_grads;
+
+typedef struct {
+  int32_t n_views;
+  int64_t n_visible;            /* (view, leaf) records after culling      */
+  int64_t n_pairs;              /* (leaf, tile) pairs                      */
+  int64_t n_actor_pairs;        /* (actor box, tile) pairs                 */
+  int64_t n_tiles;              /* 16x16 tiles over all windows            */
+  int32_t key_bits;             /* bits of the record sort key             */
+  int32_t tile_bits;            /* bits of the pair sort key               */
+} dv_state_info;
+
+/* ---------------------------------------------------------------- context */
+/* Create a context on HIP device `hip_device` (memory pool, streams of the
+ * caller are used for work).  *out is set on success. */
+dv_status dv_ctx_create(int32_t hip_device, dv_ctx** out);
+void dv_ctx_destroy(dv_ctx* ctx);
+/* Message of the last failing call on this thread ("" if none). */
+const char* dv_last_error(void);
+/* Library version string. */
+const char* dv_version(void);
+
+/* ---------------------------------------------------------------- scene */
+/* Validate and index a scene: octrees[0] is the background O_bg,
+ * octrees[1..] are actors with tracks[i-1] (Sec. 3.1-3.2; App. A inputs).
+ * Copies leaf structure to the host for validation (no overlapping or
+ * duplicate leaves, levels <= max_level <= 16, cells inside the root,
+ * corner indices in range, SH degree 0..3) and builds packed device
+ * geometry tables.  corner_density and sh stay caller-owned and are read
+ * at every render.  Errors: DV_ERR_INVALID, DV_ERR_RANGE, DV_ERR_OVERLAP,
+ * DV_ERR_LIMIT, DV_ERR_OOM, DV_ERR_DEVICE. */
+dv_status dv_build_scene(dv_ctx* ctx, const dv_octree_desc* octrees,
+                         int32_t n_octrees, const dv_track_desc* tracks,
+                         dv_scene** out);
+void dv_scene_destroy(dv_scene* scene);
+
+/* Host-only validation of one octree's leaf structure (the checks of
+ * dv_build_scene).  All pointers are host arrays.  Writes a message into
+ * msg (capacity msg_len) on failure. */
+dv_status dv_validate_octree_host(const uint8_t* level, const int32_t* ijk,
+                                  const int32_t* corner_idx, int32_t n,
+                                  int32_t max_level, int32_t n_corners,
+                                  int32_t sh_degree, char* msg,
+                                  int32_t msg_len);
+
+/* Actor pose at time t from a track (host, FP64): R row-major 3x3 and p.
+ * Returns 1 if the actor is active at t, else 0. */
+int32_t dv_track_pose(const dv_track_desc* track, double t, double R[9],
+                      double p[3]);
+
+/* ---------------------------------------------------------------- render */
+/* Render n_views views of the scene in one pass (Sec. 3.4; Alg. 1):
+ * per-view leaf preprocessing (culling, tile rectangle, depth rank, SH
+ * colour), tile binning, device radix sort, per-tile directories, and
+ * the per-pixel compositing walk over the background and actor octrees.
+ * pose_override: NULL (poses from tracks at view.t) or a host array
+ * [n_views][n_actors][12] (R row-major, then p; all actors active).
+ * keep: NULL, or receives a forward state that dv_render_backward needs;
+ * release it with dv_fwd_state_release.  Synchronises the stream twice
+ * (to size the record and pair arrays).  Errors: DV_ERR_INVALID,
+ * DV_ERR_LIMIT, DV_ERR_OOM, DV_ERR_DEVICE. */
+dv_status dv_render(dv_ctx* ctx, const dv_scene* scene, const dv_view* views,
+                    int32_t n_views, const double* pose_override,
+                    const dv_render_opts* opts, const dv_outputs* outs,
+                    dv_fwd_state** keep, void* stream);
+
+/* Reverse pass of dv_render (Sec. 3.4: gradients flow through each
+ * segment; pose gradients go beyond the paper, which keeps tracks fixed).
+ * Re-walks every pixel's pieces in forward order with identical FP32
+ * arithmetic, accumulating gradients of corner densities, SH coefficients
+ * and actor poses (R, p) into `acc` with wave-reduced atomics.  g: host
+ * array [n_views] of device gradient planes.  Corner/SH/pose values must
+ * be those used by the forward call. */
+dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
+                             const dv_fwd_state* state,
+                             const dv_out_grads* g, const dv_param_grads* acc,
+                             void* stream);
+
+void dv_fwd_state_release(dv_fwd_state* state);
+dv_status dv_fwd_state_info(const dv_fwd_state* state, dv_state_info* info);
+/* Copy the sorted tile lists of one view to the host (synchronises):
+ * tile_start [n_tiles_of_view + 1] and, for each entry, its octree and
+ * leaf index; capacity = length of entry arrays.  Actor lists likewise
+ * into actor_start [n_tiles_of_view + 1] / actor_oct (may be NULL). */
+dv_status dv_fwd_state_export_lists(const dv_fwd_state* state, int32_t view,
+                                    int64_t* tile_start, int32_t* entry_oct,
+                                    int32_t* entry_leaf, int64_t capacity,
+                                    int64_t* actor_start, int32_t* actor_oct,
+                                    int64_t actor_capacity);
+
+/* ---------------------------------------------------------------- serving */
+typedef struct {
+  int32_t max_inflight;         /* requests admitted at once (slots)       */
+  int64_t mem_budget;           /* device bytes for in-flight requests     */
+  int32_t batched;              /* 1: continuous batching, 0: one launch
+                                   per request in FIFO order               */
+  int32_t max_batch;            /* requests per batched launch             */
+  dv_render_opts opts;
+} dv_serve_opts;
+
+typedef struct {
+  dv_view view;                 /* camera, resolution/window, timestamp    */
+  dv_outputs out;               /* caller-owned device planes; must stay
+                                   valid until poll returns DV_OK          */
+} dv_request;
+
+typedef struct {
+  dv_status status;             /* DV_OK, DV_PENDING or an error           */
+  double t_submit;              /* seconds, monotonic clock                */
+  double t_admit;
+  double t_done;
+} dv_result;
+
+/* Start a serving loop on `scene` (kept resident; the scene must outlive
+ * the server).  A scheduler thread admits queued requests while slots and
+ * memory allow, renders them in batched launches that overlap on the
+ * device, and marks them done.  Errors: DV_ERR_INVALID, DV_ERR_OOM. */
+dv_status dv_serve_create(dv_ctx* ctx, const dv_scene* scene,
+                          const dv_serve_opts* opts, dv_server** out);
+/* Queue a request (thread-safe); *ticket identifies it.  A malformed
+ * request still gets a ticket whose poll reports DV_ERR_INVALID. */
+dv_status dv_serve_submit(dv_server* srv, const dv_request* req,
+                          uint64_t* ticket);
+/* Status of a ticket, waiting up to wait_us microseconds (0: no wait,
+ * <0: wait until finished).  Returns the request's status (DV_OK,
+ * DV_PENDING or its error) and fills *res.  A finished ticket is
+ * forgotten after its final status has been returned once. */
+dv_status dv_serve_poll(dv_server* srv, uint64_t ticket, int32_t wait_us,
+                        dv_result* res);
+/* Drain, stop and free the server. */
+dv_status dv_serve_destroy(dv_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DV_H */

@@ -1,0 +1,194 @@
+// Context, error reporting, device memory pool and small fill kernels.
+#include <cstdarg>
+#include <cstring>
+
+#include "dv_internal.h"
+
+namespace dv {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+const char* get_error() { return g_err.c_str(); }
+
+Pool::~Pool() {
+  hipSetDevice(device_);
+  for (auto& kv : free_) {
+    hipEventDestroy(kv.second.ev);
+    hipFree(kv.second.p);
+  }
+  for (auto& kv : live_) hipFree(kv.first);
+  for (auto e : spare_events_) hipEventDestroy(e);
+}
+
+static size_t round_size(size_t b) {
+  if (b < 256) return 256;
+  if (b < (1u << 20)) {
+    size_t r = 256;
+    while (r < b) r <<= 1;
+    return r;
+  }
+  const size_t g = 2u << 20;
+  return (b + g - 1) / g * g;
+}
+
+void* Pool::alloc(size_t bytes, hipStream_t s) {
+  size_t want = round_size(bytes);
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = free_.lower_bound(want);
+    while (it != free_.end() && it->first <= 2 * want) {
+      Block& b = it->second;
+      if (b.stream == s || hipEventQuery(b.ev) == hipSuccess) {
+        void* p = b.p;
+        live_[p] = b.size;
+        in_use_ += b.size;
+        spare_events_.push_back(b.ev);
+        free_.erase(it);
+        return p;
+      }
+      ++it;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    trim();
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  std::lock_guard<std::mutex> lk(mu_);
+  live_[p] = want;
+  in_use_ += want;
+  return p;
+}
+
+void Pool::release(void* p, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = live_.find(p);
+  if (it == live_.end()) return;
+  Block b;
+  b.p = p;
+  b.size = it->second;
+  b.stream = s;
+  if (!spare_events_.empty()) {
+    b.ev = spare_events_.back();
+    spare_events_.pop_back();
+  } else {
+    hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+  }
+  hipEventRecord(b.ev, s);
+  in_use_ -= b.size;
+  live_.erase(it);
+  free_.emplace(b.size, b);
+}
+
+void Pool::trim() {
+  std::lock_guard<std::mutex> lk(mu_);
+  for (auto it = free_.begin(); it != free_.end();) {
+    if (hipEventQuery(it->second.ev) == hipSuccess) {
+      hipFree(it->second.p);
+      spare_events_.push_back(it->second.ev);
+      it = free_.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+dv_status alloc(dv_ctx* ctx, DBuf& b, size_t bytes, hipStream_t s) {
+  b.reset();
+  void* p = ctx->pool->alloc(bytes, s);
+  if (!p) {
+    set_error("device allocation of %zu bytes failed", bytes);
+    return DV_ERR_OOM;
+  }
+  b.pool = ctx->pool.get();
+  b.p = p;
+  b.bytes = bytes;
+  b.stream = s;
+  return DV_OK;
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+dv_status fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return DV_OK;
+  unsigned g = grid_for(n, TPB);
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(TPB), 0, s, p, v, n);
+  DV_TRY_HIP(hipGetLastError());
+  return DV_OK;
+}
+
+dv_status fill_f32(float* p, float v, int64_t n, hipStream_t s) {
+  uint32_t bits;
+  std::memcpy(&bits, &v, 4);
+  return fill_u32(reinterpret_cast<uint32_t*>(p), bits, n, s);
+}
+
+}  // namespace dv
+
+using namespace dv;
+
+extern "C" {
+
+const char* dv_last_error(void) { return get_error(); }
+
+const char* dv_version(void) { return "dvox 0.1 (gfx950)"; }
+
+dv_status dv_ctx_create(int32_t hip_device, dv_ctx** out) {
+  if (!out) {
+    set_error("dv_ctx_create: out is NULL");
+    return DV_ERR_INVALID;
+  }
+  *out = nullptr;
+  int n = 0;
+  DV_TRY_HIP(hipGetDeviceCount(&n));
+  if (hip_device < 0 || hip_device >= n) {
+    set_error("dv_ctx_create: device %d out of range (%d devices)",
+              hip_device, n);
+    return DV_ERR_INVALID;
+  }
+  DV_TRY_HIP(hipSetDevice(hip_device));
+  auto* c = new (std::nothrow) dv_ctx();
+  if (!c) return DV_ERR_OOM;
+  c->device = hip_device;
+  c->pool.reset(new Pool(hip_device));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess)
+    c->n_cu = prop.multiProcessorCount;
+  if (hipHostMalloc((void**)&c->pinned, 64 * sizeof(uint64_t),
+                    hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    set_error("dv_ctx_create: pinned allocation failed");
+    return DV_ERR_OOM;
+  }
+  *out = c;
+  return DV_OK;
+}
+
+void dv_ctx_destroy(dv_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  reap_states(ctx, true);
+  ctx->pool.reset();
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+}  // extern "C"

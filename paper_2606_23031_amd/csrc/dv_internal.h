@@ -1,0 +1,227 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dv.h"
+
+namespace dv {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+const char* get_error();
+
+#define DV_TRY_HIP(expr)                                                    \
+  do {                                                                      \
+    hipError_t _e = (expr);                                                 \
+    if (_e != hipSuccess) {                                                 \
+      ::dv::set_error("HIP error %s at %s:%d: %s", hipGetErrorName(_e),     \
+                      __FILE__, __LINE__, #expr);                           \
+      return DV_ERR_DEVICE;                                                 \
+    }                                                                       \
+  } while (0)
+
+#define DV_TRY(expr)                                                        \
+  do {                                                                      \
+    dv_status _s = (expr);                                                  \
+    if (_s != DV_OK) return _s;                                             \
+  } while (0)
+
+// ------------------------------------------------------------------ memory
+// Stream-aware caching pool: a freed block is reusable at once on the stream
+// that freed it (stream order) and on any other stream after the event
+// recorded at free time has completed.
+class Pool {
+ public:
+  explicit Pool(int device) : device_(device) {}
+  ~Pool();
+  void* alloc(size_t bytes, hipStream_t s);
+  void release(void* p, hipStream_t s);
+  void trim();
+  size_t bytes_in_use() const { return in_use_; }
+
+ private:
+  struct Block {
+    void* p;
+    size_t size;
+    hipStream_t stream;
+    hipEvent_t ev;
+  };
+  std::mutex mu_;
+  std::multimap<size_t, Block> free_;
+  std::map<void*, size_t> live_;
+  std::vector<hipEvent_t> spare_events_;
+  size_t in_use_ = 0;
+  int device_;
+};
+
+// Owning device buffer returned to the pool on destruction.
+struct DBuf {
+  Pool* pool = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept { *this = std::move(o); }
+  DBuf& operator=(DBuf&& o) noexcept {
+    reset();
+    pool = o.pool; p = o.p; bytes = o.bytes; stream = o.stream;
+    o.p = nullptr; o.bytes = 0;
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void reset() {
+    if (p && pool) pool->release(p, stream);
+    p = nullptr; bytes = 0;
+  }
+  template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+}  // namespace dv
+
+struct dv_fwd_state;
+
+struct dv_ctx {
+  int device = 0;
+  // forward states whose stream work may still be in flight; deleted once
+  // their event has completed
+  std::mutex gy_mu;
+  std::vector<std::pair<hipEvent_t, dv_fwd_state*>> graveyard;
+  std::unique_ptr<dv::Pool> pool;
+  // pinned host words for device->host counters
+  uint64_t* pinned = nullptr;
+  std::mutex pinned_mu;
+  std::atomic<bool> poisoned{false};
+  int n_cu = 0;
+};
+
+namespace dv {
+
+dv_status alloc(dv_ctx* ctx, DBuf& b, size_t bytes, hipStream_t s);
+// Defer deletion of a forward state until its stream has passed this point.
+void retire_state(dv_ctx* ctx, dv_fwd_state* st);
+// Delete retired states whose work has completed (all of them if wait).
+void reap_states(dv_ctx* ctx, bool wait);
+template <class T>
+dv_status alloc_n(dv_ctx* ctx, DBuf& b, size_t n, hipStream_t s) {
+  return alloc(ctx, b, (n ? n : 1) * sizeof(T), s);
+}
+
+// ------------------------------------------------------------------ layout
+constexpr int TILE = 16;
+constexpr int TPB = 256;          // threads per block (4 wave64)
+constexpr float Z_EPS = 1e-3f;    // binning near-plane (R18 contract)
+constexpr int QBITS = 24;         // camera quantisation for ranks
+
+// Packed leaf geometry: i | j << 19 | k << 38 | level << 57.
+__host__ __device__ inline uint64_t pack_geo(uint32_t l, uint32_t i,
+                                             uint32_t j, uint32_t k) {
+  return (uint64_t)i | ((uint64_t)j << 19) | ((uint64_t)k << 38) |
+         ((uint64_t)l << 57);
+}
+__host__ __device__ inline void unpack_geo(uint64_t g, int& l, int& i, int& j,
+                                           int& k) {
+  i = (int)(g & 0x7FFFF);
+  j = (int)((g >> 19) & 0x7FFFF);
+  k = (int)((g >> 38) & 0x7FFFF);
+  l = (int)(g >> 57);
+}
+
+// Device view of one octree (built once per scene).
+struct OctDev {
+  const uint64_t* geo;
+  const int32_t* corner_idx;
+  const float* dens;
+  const float* sh;
+  int32_t n_vox;
+  int32_t n_corners;
+  int32_t sh_degree;
+  int32_t max_level;
+  double root_min[3];
+  double root_size;
+};
+
+// Per view constants.
+struct ViewConst {
+  double fx, fy, cx, cy;
+  float inv_fx, inv_fy, fcx, fcy;
+  float Rc[9];              // camera -> world rotation (row-major)
+  int32_t x0, y0, w, h;
+  int32_t ntx, nty;
+  uint32_t tile_base;       // first global tile of this view
+  int32_t pad;
+};
+
+// Per (view, octree) constants.
+struct VOConst {
+  double A[9];              // octree frame -> camera frame (binning)
+  double b[3];
+  double rootrel[3];        // root_min - P (camera in octree frame)
+  int64_t Q[3];             // quantised camera for ranks
+  float Rt[9];              // world -> octree rotation (d_k = Rt d)
+  float R[9];               // octree -> world rotation (normals)
+  float boxlo[3];           // box - P (actors)
+  float boxhi[3];
+  float omp[3];             // camera - p in world (pose gradients)
+  int32_t active;
+  int32_t octree;
+  int32_t view;
+  int32_t pad;
+};
+
+}  // namespace dv
+
+struct dv_scene {
+  dv_ctx* ctx = nullptr;
+  int32_t n_oct = 0;
+  std::vector<dv_octree_desc> desc;
+  std::vector<std::vector<double>> trk_t, trk_yaw, trk_trans;
+  std::vector<dv::DBuf> geo;       // per octree packed geometry
+  dv::DBuf oct_dev;                // OctDev[n_oct]
+  std::vector<dv::OctDev> oct_host;
+  int32_t max_level_all = 0;
+  int32_t max_sh_degree = 0;
+  int64_t total_vox = 0;
+};
+
+namespace dv {
+
+// Scan: exclusive prefix sum of n uint32 counts into out (uint32), with
+// the uint64 total written to *total_dev.  Temp buffers from ctx pool.
+dv_status exclusive_scan_u32(dv_ctx* ctx, const uint32_t* in, uint32_t* out,
+                             uint64_t* total_dev, int64_t n, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs by the low `bits` bits of the
+// key.  Result lands in (keys, vals) (ping-ponging through the alt arrays).
+dv_status radix_sort_u64(dv_ctx* ctx, uint64_t* keys, uint32_t* vals,
+                         uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                         int bits, hipStream_t s, bool* in_alt);
+dv_status radix_sort_u32(dv_ctx* ctx, uint32_t* keys, uint32_t* vals,
+                         uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                         int bits, hipStream_t s, bool* in_alt);
+
+dv_status fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+dv_status fill_f32(float* p, float v, int64_t n, hipStream_t s);
+
+inline int ceil_log2(uint64_t x) {
+  int b = 0;
+  while ((1ull << b) < x && b < 63) ++b;
+  return b;
+}
+
+inline unsigned grid_for(int64_t n, int per_block) {
+  return (unsigned)((n + per_block - 1) / per_block);
+}
+
+}  // namespace dv

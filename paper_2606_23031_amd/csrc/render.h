@@ -1,0 +1,177 @@
+// Forward-state layout and device helpers shared by the forward and
+// backward translation units.
+#pragma once
+
+#include "dv_internal.h"
+
+namespace dv {
+
+constexpr float F_INF = __builtin_huge_valf();
+constexpr double Z_EPS_D = 1e-3;
+constexpr float LOG2E = 1.4426950408889634f;
+constexpr uint32_t SRC_NONE = 0x3FFu;
+
+// Arguments of the compositing kernels (forward and backward).
+struct CompArgs {
+  const ViewConst* views;
+  const VOConst* vo;
+  int32_t n_views;
+  int32_t n_oct;
+  const uint32_t* tile_start;
+  const uint32_t* tile_end;
+  const uint32_t* tile_bgend;
+  const uint32_t* pair_val;
+  const float4* rec_geo;   // vmin - camera (octree frame), h
+  const float4* rec_g8a;   // corner densities 0..3
+  const float4* rec_g8b;   // corner densities 4..7
+  const float4* rec_cn;    // colour rgb, 1/h
+  const float4* rec_nrm;   // world normal xyz, 0
+  const uint32_t* act_beg; // per global tile, n_tiles + 1
+  const uint32_t* act_oct; // actor octree index per (tile, slot)
+  const uint2* act_sub;    // pair sub-range per (tile, slot)
+  float2* seg_se;          // per-pixel box intervals / segments
+  uint32_t* seg_meta;
+  float4* seg_p0;          // partial C.rgb, D
+  float4* seg_p1;          // partial N.xyz, T
+  float4* seg_bw;          // backward: T_pre, S_after, dL/dstart, dL/dend
+  uint32_t* pix_nseg;
+  float4* fin0;            // final C.rgb, D
+  float4* fin1;            // final N.xyz, T
+  const dv_outputs* outs;  // per view
+  const dv_out_grads* gin; // per view (backward)
+  float4* gr_col;          // backward per-record: dL/dc (rgb), 0
+  float4* gr_nrm;          // dL/dn_world, 0
+  float4* gr_g8a;          // dL/dg corners 0..3
+  float4* gr_g8b;          // corners 4..7
+  float* pose_grad;        // [n_views][n_actors][12] or null
+  int32_t n_actors;
+  int32_t K;
+  float eps;
+  float tau_near;
+  float c;
+  float inv_c;
+  float bg[3];
+  uint32_t mask;
+};
+
+__device__ inline int view_of_tile(const ViewConst* views, int n_views,
+                                   uint32_t gt) {
+  int lo = 0, hi = n_views - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (views[mid].tile_base <= gt) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline float3 mat3_mul(const float* M, float3 v) {
+  return make_float3(
+      fmaf(M[2], v.z, fmaf(M[1], v.y, M[0] * v.x)),
+      fmaf(M[5], v.z, fmaf(M[4], v.y, M[3] * v.x)),
+      fmaf(M[8], v.z, fmaf(M[7], v.y, M[6] * v.x)));
+}
+
+__device__ inline float fast_exp(float x) {
+  return __builtin_amdgcn_exp2f(x * LOG2E);
+}
+
+// exp-linear activation (knee c): x above c, else c * exp(x/c - 1).
+__device__ inline float explin(float x, float c, float inv_c) {
+  return x > c ? x : c * fast_exp(fmaf(x, inv_c, -1.0f));
+}
+__device__ inline float explin_grad(float x, float c, float inv_c) {
+  return x > c ? 1.0f : fast_exp(fmaf(x, inv_c, -1.0f));
+}
+
+__device__ inline float lerpf(float a, float b, float t) {
+  return fmaf(t, b - a, a);
+}
+
+__device__ inline float trilerp(float4 ga, float4 gb, float ux, float uy,
+                                float uz) {
+  float x0 = lerpf(ga.x, ga.y, ux), x1 = lerpf(ga.z, ga.w, ux);
+  float x2 = lerpf(gb.x, gb.y, ux), x3 = lerpf(gb.z, gb.w, ux);
+  float y0 = lerpf(x0, x1, uy), y1 = lerpf(x2, x3, uy);
+  return lerpf(y0, y1, uz);
+}
+
+__device__ inline float clamp01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
+
+// Slab test against an axis-aligned box [lo, lo + h] given relative to the
+// ray origin, with precomputed reciprocal direction.
+__device__ inline void slab(float3 lo, float h, float3 inv, float& t0,
+                            float& t1) {
+  float ax = lo.x * inv.x, bx = (lo.x + h) * inv.x;
+  float ay = lo.y * inv.y, by = (lo.y + h) * inv.y;
+  float az = lo.z * inv.z, bz = (lo.z + h) * inv.z;
+  t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fminf(az, bz));
+  t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
+}
+
+// Same, also reporting the axes that define entry and exit.
+__device__ inline void slab_axes(float3 lo, float3 hi, float3 inv, float& t0,
+                                 float& t1, int& a0, int& a1) {
+  float ax = lo.x * inv.x, bx = hi.x * inv.x;
+  float ay = lo.y * inv.y, by = hi.y * inv.y;
+  float az = lo.z * inv.z, bz = hi.z * inv.z;
+  float nx = fminf(ax, bx), ny = fminf(ay, by), nz = fminf(az, bz);
+  float fx = fmaxf(ax, bx), fy = fmaxf(ay, by), fz = fmaxf(az, bz);
+  t0 = nx; a0 = 0;
+  if (ny > t0) { t0 = ny; a0 = 1; }
+  if (nz > t0) { t0 = nz; a0 = 2; }
+  t1 = fx; a1 = 0;
+  if (fy < t1) { t1 = fy; a1 = 1; }
+  if (fz < t1) { t1 = fz; a1 = 2; }
+}
+
+__device__ inline float3 safe_inv(float3 d) {
+  return make_float3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+}
+
+// Optical depth of the piece [a, b] of one leaf: K-point midpoint rule of
+// explin(trilinear raw density).  Shared verbatim by forward and backward
+// so both take identical rounding.
+__device__ inline float piece_tau(float4 geo, float4 ga, float4 gb,
+                                  float inv_h, float3 d, float a, float b,
+                                  int K, float invK, float c, float inv_c) {
+  const float step = (b - a) * invK;
+  float sum = 0.0f;
+  for (int q = 0; q < K; ++q) {
+    const float tq = fmaf((float)q + 0.5f, step, a);
+    const float ux = clamp01(fmaf(tq, d.x, -geo.x) * inv_h);
+    const float uy = clamp01(fmaf(tq, d.y, -geo.y) * inv_h);
+    const float uz = clamp01(fmaf(tq, d.z, -geo.z) * inv_h);
+    sum += explin(trilerp(ga, gb, ux, uy, uz), c, inv_c);
+  }
+  return sum * step;
+}
+
+// Per-pixel segment scratch: slot s of tile gt, pixel tid.
+__device__ inline size_t seg_index(uint32_t slot, int tid) {
+  return (size_t)slot * TPB + tid;
+}
+
+}  // namespace dv
+
+struct dv_fwd_state {
+  dv_ctx* ctx = nullptr;
+  const dv_scene* scene = nullptr;
+  hipStream_t stream = nullptr;
+  int32_t n_views = 0, n_oct = 0, n_actors = 0;
+  dv_render_opts opts{};
+  std::vector<dv::ViewConst> views_h;
+  std::vector<dv::VOConst> vo_h;
+  std::vector<dv_view> views_in;
+  int64_t n_vis = 0, n_pairs = 0, n_apairs = 0, n_tiles = 0;
+  int key_bits = 0, tile_bits = 0, rank_bits = 0;
+  std::vector<uint32_t> act_beg_h, act_oct_h, act_tile_h;
+  std::vector<int64_t> seg_start_h;
+  std::vector<dv_out_grads> grads_h;
+  dv::DBuf views_d, vo_d, outs_d;
+  dv::DBuf rec_geo, rec_g8a, rec_g8b, rec_cn, rec_nrm, rec_vox, rec_seg;
+  dv::DBuf pair_val;
+  dv::DBuf tile_start, tile_end, tile_bgend;
+  dv::DBuf act_beg, act_oct, act_sub;
+  dv::DBuf seg_se, seg_meta, seg_p0, seg_p1, seg_bw, pix_nseg;
+  dv::DBuf fin0, fin1;
+};

@@ -1,0 +1,1224 @@
+// Forward render: per-view leaf preprocessing, record sort, tile binning,
+// pair sort, tile directories and the compositing walk (Sec. 3.4, App. A,
+// Alg. 1, Eq. 2).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "render.h"
+
+namespace dv {
+
+// ------------------------------------------------------------------ SH
+// Real spherical harmonics up to degree 3 (Sec. 3.1 view-dependent
+// colour), orthonormal, with Y_{1,-1}, Y_{1,0}, Y_{1,1} proportional to
+// y, z, x.  Coefficients are SoA [S][3][N].
+__device__ inline void sh_basis(int deg, float x, float y, float z,
+                                float* Y) {
+  Y[0] = 0.28209479177387814f;
+  if (deg < 1) return;
+  Y[1] = 0.4886025119029199f * y;
+  Y[2] = 0.4886025119029199f * z;
+  Y[3] = 0.4886025119029199f * x;
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = 1.0925484305920792f * (x * y);
+  Y[5] = 1.0925484305920792f * (y * z);
+  Y[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
+  Y[7] = 1.0925484305920792f * (x * z);
+  Y[8] = 0.5462742152960396f * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = 0.5900435899266435f * y * (3.0f * xx - yy);
+  Y[10] = 2.890611442640554f * (x * y * z);
+  Y[11] = 0.4570457994644658f * y * (5.0f * zz - 1.0f);
+  Y[12] = 0.3731763325901154f * z * (5.0f * zz - 3.0f);
+  Y[13] = 0.4570457994644658f * x * (5.0f * zz - 1.0f);
+  Y[14] = 1.445305721320277f * z * (xx - yy);
+  Y[15] = 0.5900435899266435f * x * (xx - 3.0f * yy);
+}
+
+// ------------------------------------------------------------------ binning
+// Tile rectangle of a box (contract: FP64, fixed operation order, no
+// contraction).  status 0 culled, 1 rectangle, 2 whole window.
+struct Rect { int status, xl, xh, yl, yh; };
+
+__host__ __device__ inline Rect bin_box(const double A[9], const double b[3],
+                                        const double lo[3], const double hi[3],
+                                        double fx, double fy, double cx,
+                                        double cy, int x0, int y0, int w,
+                                        int h) {
+  double umin = 0, umax = 0, vmin = 0, vmax = 0;
+  bool allneg = true, anynear = false;
+  for (int m = 0; m < 8; ++m) {
+    const double x = (m & 1) ? hi[0] : lo[0];
+    const double y = (m & 2) ? hi[1] : lo[1];
+    const double z = (m & 4) ? hi[2] : lo[2];
+    const double X = ((A[0] * x + A[1] * y) + A[2] * z) + b[0];
+    const double Y = ((A[3] * x + A[4] * y) + A[5] * z) + b[1];
+    const double Z = ((A[6] * x + A[7] * y) + A[8] * z) + b[2];
+    allneg = allneg && (Z <= 0.0);
+    anynear = anynear || (Z < Z_EPS_D);
+    const double u = cx + fx * (X / Z);
+    const double v = cy + fy * (Y / Z);
+    if (m == 0) { umin = umax = u; vmin = vmax = v; }
+    else {
+      umin = fmin(umin, u); umax = fmax(umax, u);
+      vmin = fmin(vmin, v); vmax = fmax(vmax, v);
+    }
+  }
+  Rect r;
+  if (allneg) { r.status = 0; r.xl = 1; r.xh = 0; r.yl = 1; r.yh = 0; return r; }
+  if (anynear) { r.status = 2; r.xl = 0; r.xh = w - 1; r.yl = 0; r.yh = h - 1; return r; }
+  r.status = 1;
+  double lo_x = ceil(fmin(fmax(umin - 0.5625, x0 - 1.0), x0 + (double)w));
+  double hi_x = floor(fmin(fmax(umax - 0.4375, x0 - 1.0), x0 + (double)w));
+  double lo_y = ceil(fmin(fmax(vmin - 0.5625, y0 - 1.0), y0 + (double)h));
+  double hi_y = floor(fmin(fmax(vmax - 0.4375, y0 - 1.0), y0 + (double)h));
+  r.xl = (int)fmax(lo_x, (double)x0) - x0;
+  r.xh = (int)fmin(hi_x, (double)(x0 + w - 1)) - x0;
+  r.yl = (int)fmax(lo_y, (double)y0) - y0;
+  r.yh = (int)fmin(hi_y, (double)(y0 + h - 1)) - y0;
+  return r;
+}
+
+struct PreArgs {
+  const ViewConst* views;
+  const VOConst* vo;
+  const OctDev* oct;
+  const int64_t* seg_start;
+  int32_t n_seg;
+  int32_t n_oct;
+  int64_t n_items;
+  int32_t rank_bits;
+  uint32_t* block_count;
+  const uint32_t* block_off;
+  uint64_t* keys;
+  uint32_t* vals;
+  float4* s_geo;
+  float4* s_g8a;
+  float4* s_g8b;
+  float4* s_cn;
+  float4* s_nrm;
+  uint32_t* s_vox;
+  uint64_t* s_rect;
+};
+
+template <int PASS>
+__global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
+  __shared__ uint32_t wtot[TPB / 64];
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  bool vis = false;
+  int s = 0, vox = 0;
+  Rect r{0, 1, 0, 1, 0};
+  int l = 0, ii = 0, jj = 0, kk = 0;
+  if (t < p.n_items) {
+    int lo = 0, hi = p.n_seg - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (p.seg_start[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    s = lo;
+    vox = (int)(t - p.seg_start[s]);
+    const int v = s / p.n_oct, k = s % p.n_oct;
+    const ViewConst& V = p.views[v];
+    const VOConst& C = p.vo[s];
+    const OctDev& O = p.oct[k];
+    unpack_geo(O.geo[vox], l, ii, jj, kk);
+    const double h = ldexp(O.root_size, -l);
+    double blo[3], bhi[3];
+    const int ijk[3] = {ii, jj, kk};
+    for (int a = 0; a < 3; ++a) {
+      blo[a] = O.root_min[a] + (double)ijk[a] * h;
+      bhi[a] = O.root_min[a] + (double)(ijk[a] + 1) * h;
+    }
+    r = bin_box(C.A, C.b, blo, bhi, V.fx, V.fy, V.cx, V.cy, V.x0, V.y0, V.w,
+                V.h);
+    vis = r.status != 0 && r.xl <= r.xh && r.yl <= r.yh;
+  }
+  const uint64_t m = __ballot(vis);
+  const uint32_t wcount = (uint32_t)__popcll(m);
+  if (lane == 0) wtot[w] = wcount;
+  __syncthreads();
+  if (PASS == 0) {
+    if (threadIdx.x == 0) {
+      uint32_t tot = 0;
+      for (int i = 0; i < TPB / 64; ++i) tot += wtot[i];
+      p.block_count[blockIdx.x] = tot;
+    }
+    return;
+  }
+  uint32_t woff = 0;
+  for (int i = 0; i < w; ++i) woff += wtot[i];
+  if (!vis) return;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t slot = p.block_off[blockIdx.x] + woff + (uint32_t)__popcll(m & lt);
+  const int v = s / p.n_oct, k = s % p.n_oct;
+  const VOConst& C = p.vo[s];
+  const OctDev& O = p.oct[k];
+  // depth rank: BSP painter's order from the quantised camera position
+  const int L = O.max_level;
+  const int ijk[3] = {ii, jj, kk};
+  uint64_t rank = 0;
+  for (int d = 0; d < l; ++d) {
+    uint32_t digit = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int64_t parent = ijk[a] >> (l - d);
+      const int64_t plane = (2 * parent + 1) << (QBITS - d - 1);
+      const uint32_t flip = C.Q[a] >= plane ? 1u : 0u;
+      const uint32_t bit = (ijk[a] >> (l - d - 1)) & 1;
+      digit |= (bit ^ flip) << a;
+    }
+    rank |= (uint64_t)digit << (3 * (L - 1 - d));
+  }
+  p.keys[slot] = ((uint64_t)s << p.rank_bits) | rank;
+  p.vals[slot] = slot;
+  p.s_vox[slot] = (uint32_t)vox;
+  p.s_rect[slot] = (uint64_t)(uint32_t)(r.xl >> 4) |
+                   ((uint64_t)(uint32_t)(r.yl >> 4) << 16) |
+                   ((uint64_t)(uint32_t)(r.xh >> 4) << 32) |
+                   ((uint64_t)(uint32_t)(r.yh >> 4) << 48);
+  // leaf record in the octree frame relative to the camera
+  const double h = ldexp(O.root_size, -l);
+  double rel[3];
+  for (int a = 0; a < 3; ++a) rel[a] = C.rootrel[a] + (double)ijk[a] * h;
+  p.s_geo[slot] = make_float4((float)rel[0], (float)rel[1], (float)rel[2],
+                              (float)h);
+  const int N = O.n_vox;
+  float g[8];
+  for (int c8 = 0; c8 < 8; ++c8)
+    g[c8] = O.dens[O.corner_idx[(int64_t)c8 * N + vox]];
+  p.s_g8a[slot] = make_float4(g[0], g[1], g[2], g[3]);
+  p.s_g8b[slot] = make_float4(g[4], g[5], g[6], g[7]);
+  // colour from SH at the direction camera -> leaf centre
+  double cx = rel[0] + 0.5 * h, cy = rel[1] + 0.5 * h, cz = rel[2] + 0.5 * h;
+  double rn = sqrt(cx * cx + cy * cy + cz * cz);
+  double inv_r = rn > 0 ? 1.0 / rn : 0.0;
+  float Y[16];
+  sh_basis(O.sh_degree, (float)(cx * inv_r), (float)(cy * inv_r),
+           (float)(cz * inv_r), Y);
+  const int S = (O.sh_degree + 1) * (O.sh_degree + 1);
+  float col[3];
+  for (int ch = 0; ch < 3; ++ch) {
+    float acc = 0.0f;
+    for (int q = 0; q < S; ++q)
+      acc = fmaf(Y[q], O.sh[((int64_t)q * 3 + ch) * N + vox], acc);
+    col[ch] = fmaxf(acc + 0.5f, 0.0f);
+  }
+  p.s_cn[slot] = make_float4(col[0], col[1], col[2], (float)(1.0 / h));
+  // normal: -grad of the trilinear field at the centre, rotated to world
+  float gx = 0.25f * ((g[1] - g[0]) + (g[3] - g[2]) + (g[5] - g[4]) + (g[7] - g[6]));
+  float gy = 0.25f * ((g[2] - g[0]) + (g[3] - g[1]) + (g[6] - g[4]) + (g[7] - g[5]));
+  float gz = 0.25f * ((g[4] - g[0]) + (g[5] - g[1]) + (g[6] - g[2]) + (g[7] - g[3]));
+  float gn = sqrtf(gx * gx + gy * gy + gz * gz);
+  float3 nl = gn > 0.0f ? make_float3(-gx / gn, -gy / gn, -gz / gn)
+                        : make_float3(0.0f, 0.0f, 0.0f);
+  float3 nw = mat3_mul(C.R, nl);
+  p.s_nrm[slot] = make_float4(nw.x, nw.y, nw.z, 0.0f);
+  (void)v;
+}
+
+__global__ void k_gather(int64_t n, const uint64_t* __restrict__ keys,
+                         const uint32_t* __restrict__ vals, int rank_bits,
+                         const float4* s_geo, const float4* s_g8a,
+                         const float4* s_g8b, const float4* s_cn,
+                         const float4* s_nrm, const uint32_t* s_vox,
+                         const uint64_t* s_rect, float4* r_geo, float4* r_g8a,
+                         float4* r_g8b, float4* r_cn, float4* r_nrm,
+                         uint32_t* r_vox, uint32_t* r_seg, uint32_t* r_count,
+                         uint64_t* r_rect) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t sl = vals[i];
+  r_geo[i] = s_geo[sl];
+  r_g8a[i] = s_g8a[sl];
+  r_g8b[i] = s_g8b[sl];
+  r_cn[i] = s_cn[sl];
+  r_nrm[i] = s_nrm[sl];
+  r_vox[i] = s_vox[sl];
+  r_seg[i] = (uint32_t)(keys[i] >> rank_bits);
+  const uint64_t rc = s_rect[sl];
+  const uint32_t tx0 = rc & 0xFFFF, ty0 = (rc >> 16) & 0xFFFF;
+  const uint32_t tx1 = (rc >> 32) & 0xFFFF, ty1 = (rc >> 48) & 0xFFFF;
+  r_count[i] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+  r_rect[i] = rc;
+}
+
+__global__ void k_emit(int64_t n_pairs, int64_t n_rec,
+                       const uint32_t* __restrict__ off,
+                       const uint64_t* __restrict__ rect,
+                       const uint32_t* __restrict__ seg, int n_oct,
+                       const ViewConst* __restrict__ views,
+                       uint32_t* __restrict__ pkey,
+                       uint32_t* __restrict__ pval) {
+  const int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (p >= n_pairs) return;
+  int64_t lo = 0, hi = n_rec - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if ((int64_t)off[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  const uint64_t rc = rect[lo];
+  const uint32_t tx0 = rc & 0xFFFF, ty0 = (rc >> 16) & 0xFFFF;
+  const uint32_t tx1 = (rc >> 32) & 0xFFFF;
+  const uint32_t wdt = tx1 - tx0 + 1;
+  const uint32_t i = (uint32_t)(p - off[lo]);
+  const ViewConst& V = views[seg[lo] / n_oct];
+  pkey[p] = V.tile_base + (ty0 + i / wdt) * V.ntx + (tx0 + i % wdt);
+  pval[p] = (uint32_t)lo;
+}
+
+__global__ void k_tile_bounds(int64_t n, const uint32_t* __restrict__ key,
+                              uint32_t* start, uint32_t* end) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = key[i];
+  if (i == 0 || key[i - 1] != k) start[k] = (uint32_t)i;
+  if (i == n - 1 || key[i + 1] != k) end[k] = (uint32_t)(i + 1);
+}
+
+__device__ inline uint32_t first_oct_at_least(const uint32_t* pval,
+                                              const uint32_t* rseg, int n_oct,
+                                              uint32_t lo, uint32_t hi,
+                                              uint32_t k) {
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (rseg[pval[mid]] % n_oct >= k) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+__global__ void k_tile_dir(int64_t n_tiles, const uint32_t* start,
+                           const uint32_t* end, const uint32_t* pval,
+                           const uint32_t* rseg, int n_oct, uint32_t* bgend) {
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= n_tiles) return;
+  bgend[t] = first_oct_at_least(pval, rseg, n_oct, start[t], end[t], 1);
+}
+
+__global__ void k_actor_ranges(int64_t n, const uint32_t* act_tile,
+                               const uint32_t* act_oct,
+                               const uint32_t* bgend, const uint32_t* end,
+                               const uint32_t* pval, const uint32_t* rseg,
+                               int n_oct, uint2* sub) {
+  const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (e >= n) return;
+  const uint32_t t = act_tile[e], k = act_oct[e];
+  const uint32_t a = first_oct_at_least(pval, rseg, n_oct, bgend[t], end[t], k);
+  const uint32_t b = first_oct_at_least(pval, rseg, n_oct, a, end[t], k + 1);
+  sub[e] = make_uint2(a, b);
+}
+
+// ------------------------------------------------------------------ composite
+struct Batch {
+  float4 geo[TPB];
+  float4 ga[TPB];
+  float4 gb[TPB];
+  float4 cn[TPB];
+  float4 nrm[TPB];
+};
+
+__device__ inline void load_batch(Batch& B, const CompArgs& a, uint32_t base,
+                                  uint32_t n) {
+  const int tid = threadIdx.x;
+  if ((uint32_t)tid < n) {
+    const uint32_t r = a.pair_val[base + tid];
+    B.geo[tid] = a.rec_geo[r];
+    B.ga[tid] = a.rec_g8a[r];
+    B.gb[tid] = a.rec_g8b[r];
+    B.cn[tid] = a.rec_cn[r];
+    B.nrm[tid] = a.rec_nrm[r];
+  }
+}
+
+__device__ inline uint32_t src_code(int slot, int axis) {
+  return ((uint32_t)slot << 2) | (uint32_t)axis;
+}
+
+// Build the pixel's ownership segments from the actor boxes of its tile.
+// Reading for overlapping boxes: a point belongs to the lowest-index actor
+// whose box contains it; the background owns the rest.
+__device__ inline int build_segments(const CompArgs& a, uint32_t sbase,
+                                     int n_at, uint32_t a_beg, int v,
+                                     float3 d, int tid) {
+  // box intervals -> slots [sbase, sbase + n_at)
+  for (int j = 0; j < n_at; ++j) {
+    const VOConst& C = a.vo[v * a.n_oct + a.act_oct[a_beg + j]];
+    float3 dj = mat3_mul(C.Rt, d);
+    float3 inv = safe_inv(dj);
+    float t0, t1;
+    int a0, a1;
+    slab_axes(make_float3(C.boxlo[0], C.boxlo[1], C.boxlo[2]),
+              make_float3(C.boxhi[0], C.boxhi[1], C.boxhi[2]), inv, t0, t1,
+              a0, a1);
+    uint32_t s0 = src_code(j, a0);
+    if (t0 < a.tau_near) { t0 = a.tau_near; s0 = SRC_NONE; }
+    uint32_t meta = s0 | (src_code(j, a1) << 10) | ((t1 > t0) ? (1u << 20) : 0u);
+    a.seg_se[seg_index(sbase + j, tid)] = make_float2(t0, t1);
+    a.seg_meta[seg_index(sbase + j, tid)] = meta;
+  }
+  // sweep over breakpoints in increasing order
+  int nseg = 0;
+  float cur = -F_INF;
+  uint32_t cur_src = SRC_NONE;
+  const uint32_t seg0 = sbase + n_at;
+  for (int guard = 0; guard < 2 * n_at + 1; ++guard) {
+    float nb = F_INF;
+    uint32_t nb_src = SRC_NONE;
+    for (int j = 0; j < n_at; ++j) {
+      const uint32_t mj = a.seg_meta[seg_index(sbase + j, tid)];
+      if (!(mj & (1u << 20))) continue;
+      const float2 ab = a.seg_se[seg_index(sbase + j, tid)];
+      if (ab.x > cur && ab.x < nb) { nb = ab.x; nb_src = mj & 0x3FF; }
+      if (ab.y > cur && ab.y < nb) { nb = ab.y; nb_src = (mj >> 10) & 0x3FF; }
+    }
+    if (nb == F_INF) break;
+    int owner = -1;
+    for (int j = 0; j < n_at && cur > -F_INF; ++j) {
+      const uint32_t mj = a.seg_meta[seg_index(sbase + j, tid)];
+      if (!(mj & (1u << 20))) continue;
+      const float2 ab = a.seg_se[seg_index(sbase + j, tid)];
+      if (ab.x <= cur && cur < ab.y) { owner = j; break; }
+    }
+    if (owner >= 0) {
+      const size_t li = seg_index(seg0 + nseg - 1, tid);
+      bool extend = false;
+      if (nseg > 0) {
+        const uint32_t ml = a.seg_meta[li];
+        extend = (int)(ml & 0xFF) == owner && a.seg_se[li].y == cur;
+      }
+      if (extend) {
+        a.seg_se[li].y = nb;
+        a.seg_meta[li] = (a.seg_meta[li] & ~(0x3FFu << 18)) | (nb_src << 18);
+      } else {
+        const size_t qi = seg_index(seg0 + nseg, tid);
+        a.seg_se[qi] = make_float2(cur, nb);
+        a.seg_meta[qi] = (uint32_t)owner | (cur_src << 8) | (nb_src << 18);
+        a.seg_p0[qi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        a.seg_p1[qi] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+        ++nseg;
+      }
+    }
+    cur = nb;
+    cur_src = nb_src;
+  }
+  return nseg;
+}
+
+__device__ inline int next_seg_of(const CompArgs& a, uint32_t seg0, int nseg,
+                                  int from, int j, int tid) {
+  for (int q = from; q < nseg; ++q)
+    if ((int)(a.seg_meta[seg_index(seg0 + q, tid)] & 0xFF) == j) return q;
+  return nseg;
+}
+
+template <bool NORMALS>
+__global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
+  __shared__ Batch B;
+  const uint32_t gt = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int v = view_of_tile(a.views, a.n_views, gt);
+  const ViewConst& V = a.views[v];
+  const uint32_t lt = gt - V.tile_base;
+  const int px = (int)(lt % V.ntx) * TILE + (tid & 15);
+  const int py = (int)(lt / V.ntx) * TILE + (tid >> 4);
+  const bool valid = px < V.w && py < V.h;
+  float3 d;
+  {
+    const float dx = ((float)(V.x0 + px) + 0.5f - V.fcx) * V.inv_fx;
+    const float dy = ((float)(V.y0 + py) + 0.5f - V.fcy) * V.inv_fy;
+    d = mat3_mul(V.Rc, make_float3(dx, dy, 1.0f));
+    const float inv = 1.0f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+    d = make_float3(d.x * inv, d.y * inv, d.z * inv);
+  }
+  const int K = a.K;
+  const float invK = 1.0f / (float)K;
+  const size_t pix = (size_t)gt * TPB + tid;
+
+  // ---------------------------------------------------- actor segments
+  const uint32_t a_beg = a.act_beg[gt];
+  const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
+  const uint32_t sbase = 3 * a_beg;
+  const uint32_t seg0 = sbase + n_at;
+  int nseg = 0;
+  if (n_at > 0 && valid) nseg = build_segments(a, sbase, n_at, a_beg, v, d, tid);
+  if (n_at > 0) a.pix_nseg[pix] = (uint32_t)nseg;
+
+  // ---------------------------------------------------- phase 1: actors
+  for (int j = 0; j < n_at; ++j) {
+    int q = next_seg_of(a, seg0, nseg, 0, j, tid);
+    bool has = q < nseg;
+    if (!__syncthreads_or(has)) continue;
+    const VOConst& C = a.vo[v * a.n_oct + a.act_oct[a_beg + j]];
+    const float3 dj = mat3_mul(C.Rt, d);
+    const float3 inv = safe_inv(dj);
+    float qs = 0, qe = 0;
+    float4 p0 = make_float4(0, 0, 0, 0), p1 = make_float4(0, 0, 0, 1);
+    bool qdone = false;
+    if (has) {
+      const float2 se = a.seg_se[seg_index(seg0 + q, tid)];
+      qs = se.x; qe = se.y;
+    }
+    const uint2 sub = a.act_sub[a_beg + j];
+    for (uint32_t base = sub.x; base < sub.y; base += TPB) {
+      const uint32_t nb = min((uint32_t)TPB, sub.y - base);
+      load_batch(B, a, base, nb);
+      __syncthreads();
+      for (uint32_t r = 0; r < nb && has; ++r) {
+        const float4 geo = B.geo[r];
+        float t0, t1;
+        slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+        if (!(t1 > t0) || t1 <= qs) continue;
+        while (true) {
+          if (qe <= t0) {
+            // segment q finished: store and move to the next one of j
+            a.seg_p0[seg_index(seg0 + q, tid)] = p0;
+            a.seg_p1[seg_index(seg0 + q, tid)] = p1;
+            q = next_seg_of(a, seg0, nseg, q + 1, j, tid);
+            if (q >= nseg) { has = false; break; }
+            const float2 se = a.seg_se[seg_index(seg0 + q, tid)];
+            qs = se.x; qe = se.y;
+            p0 = make_float4(0, 0, 0, 0); p1 = make_float4(0, 0, 0, 1);
+            qdone = false;
+            continue;
+          }
+          const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
+          if (pb > pa && !qdone) {
+            const float4 cn = B.cn[r];
+            const float tau = piece_tau(geo, B.ga[r], B.gb[r], cn.w, dj, pa,
+                                        pb, K, invK, a.c, a.inv_c);
+            const float e = fast_exp(-tau);
+            const float wgt = p1.w * (1.0f - e);
+            p0.x = fmaf(wgt, cn.x, p0.x);
+            p0.y = fmaf(wgt, cn.y, p0.y);
+            p0.z = fmaf(wgt, cn.z, p0.z);
+            p0.w = fmaf(wgt, 0.5f * (pa + pb), p0.w);
+            if (NORMALS) {
+              const float4 nr = B.nrm[r];
+              p1.x = fmaf(wgt, nr.x, p1.x);
+              p1.y = fmaf(wgt, nr.y, p1.y);
+              p1.z = fmaf(wgt, nr.z, p1.z);
+            }
+            p1.w *= e;
+            if (p1.w < a.eps) qdone = true;
+          }
+          if (t1 > qe) {  // chord continues into a later segment of j
+            qe = t0;      // forces the store-and-advance branch above
+            continue;
+          }
+          break;
+        }
+      }
+      if (!__syncthreads_or(has)) break;
+    }
+    if (has) {
+      a.seg_p0[seg_index(seg0 + q, tid)] = p0;
+      a.seg_p1[seg_index(seg0 + q, tid)] = p1;
+    }
+  }
+
+  // ---------------------------------------------------- phase 2: background
+  float3 C3 = make_float3(0, 0, 0), N3 = make_float3(0, 0, 0);
+  float D = 0.0f, T = 1.0f;
+  bool done = !valid;
+  int qn = 0;
+  float ns = nseg > 0 ? a.seg_se[seg_index(seg0, tid)].x : F_INF;
+  float excl = -F_INF;
+  const float3 inv = safe_inv(d);
+  auto splice = [&](int qq) {
+    const size_t qi = seg_index(seg0 + qq, tid);
+    const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
+    C3.x = fmaf(T, q0.x, C3.x); C3.y = fmaf(T, q0.y, C3.y);
+    C3.z = fmaf(T, q0.z, C3.z); D = fmaf(T, q0.w, D);
+    if (NORMALS) {
+      N3.x = fmaf(T, q1.x, N3.x); N3.y = fmaf(T, q1.y, N3.y);
+      N3.z = fmaf(T, q1.z, N3.z);
+    }
+    T *= q1.w;
+    excl = a.seg_se[qi].y;
+  };
+  const uint32_t beg = a.tile_start[gt], bgend = a.tile_bgend[gt];
+  for (uint32_t base = beg; base < bgend; base += TPB) {
+    const uint32_t nb = min((uint32_t)TPB, bgend - base);
+    load_batch(B, a, base, nb);
+    __syncthreads();
+    for (uint32_t r = 0; r < nb && !done; ++r) {
+      const float4 geo = B.geo[r];
+      float t0, t1;
+      slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+      t0 = fmaxf(t0, a.tau_near);
+      if (!(t1 > t0)) continue;
+      float pa = fmaxf(t0, excl);
+      while (pa < t1 && !done) {
+        if (pa >= ns) {
+          splice(qn);
+          pa = fmaxf(pa, excl);
+          ++qn;
+          ns = qn < nseg ? a.seg_se[seg_index(seg0 + qn, tid)].x : F_INF;
+          if (T < a.eps) done = true;
+          continue;
+        }
+        const float pb = fminf(t1, ns);
+        const float4 cn = B.cn[r];
+        const float tau = piece_tau(geo, B.ga[r], B.gb[r], cn.w, d, pa, pb, K,
+                                    invK, a.c, a.inv_c);
+        const float e = fast_exp(-tau);
+        const float wgt = T * (1.0f - e);
+        C3.x = fmaf(wgt, cn.x, C3.x);
+        C3.y = fmaf(wgt, cn.y, C3.y);
+        C3.z = fmaf(wgt, cn.z, C3.z);
+        D = fmaf(wgt, 0.5f * (pa + pb), D);
+        if (NORMALS) {
+          const float4 nr = B.nrm[r];
+          N3.x = fmaf(wgt, nr.x, N3.x);
+          N3.y = fmaf(wgt, nr.y, N3.y);
+          N3.z = fmaf(wgt, nr.z, N3.z);
+        }
+        T *= e;
+        if (T < a.eps) done = true;
+        pa = pb;
+      }
+    }
+    if (__syncthreads_and(done)) break;
+  }
+  while (!done && qn < nseg) {
+    splice(qn);
+    ++qn;
+    if (T < a.eps) done = true;
+  }
+  if (!valid) return;
+  a.fin0[pix] = make_float4(C3.x, C3.y, C3.z, D);
+  a.fin1[pix] = make_float4(N3.x, N3.y, N3.z, T);
+  const dv_outputs& O = a.outs[v];
+  const size_t hw = (size_t)V.w * V.h, o = (size_t)py * V.w + px;
+  if ((a.mask & DV_OUT_RGB) && O.rgb) {
+    O.rgb[o] = fmaf(T, a.bg[0], C3.x);
+    O.rgb[hw + o] = fmaf(T, a.bg[1], C3.y);
+    O.rgb[2 * hw + o] = fmaf(T, a.bg[2], C3.z);
+  }
+  if ((a.mask & DV_OUT_DEPTH) && O.depth) O.depth[o] = D;
+  if ((a.mask & DV_OUT_NORMAL) && O.normal) {
+    O.normal[o] = N3.x;
+    O.normal[hw + o] = N3.y;
+    O.normal[2 * hw + o] = N3.z;
+  }
+  if ((a.mask & DV_OUT_T) && O.T) O.T[o] = T;
+}
+
+// ------------------------------------------------------------------ host
+static void mat_t_mul(const double Rc[9], const double Rk[9], double A[9]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      A[i * 3 + j] = (Rc[0 * 3 + i] * Rk[0 * 3 + j] + Rc[1 * 3 + i] * Rk[1 * 3 + j]) +
+                     Rc[2 * 3 + i] * Rk[2 * 3 + j];
+}
+
+static dv_status check_view(const dv_view& v) {
+  if (!(v.fx > 0) || !(v.fy > 0) || !std::isfinite(v.cx) ||
+      !std::isfinite(v.cy) || v.W <= 0 || v.H <= 0 || v.w <= 0 || v.h <= 0 ||
+      v.x0 < 0 || v.y0 < 0 || v.x0 + v.w > v.W || v.y0 + v.h > v.H ||
+      !std::isfinite(v.t)) {
+    set_error("invalid view (intrinsics, size or window)");
+    return DV_ERR_INVALID;
+  }
+  if (v.w > 16 * 65535 || v.h > 16 * 65535) {
+    set_error("view window too large");
+    return DV_ERR_LIMIT;
+  }
+  for (int i = 0; i < 12; ++i)
+    if (!std::isfinite(v.c2w[i])) {
+      set_error("view c2w not finite");
+      return DV_ERR_INVALID;
+    }
+  return DV_OK;
+}
+
+}  // namespace dv
+
+using namespace dv;
+
+namespace dv {
+
+// Host setup shared by dv_render and the serving loop: poses, per-view and
+// per-(view, octree) constants, the preprocess segment table and the
+// actor-tile lists.
+dv_status setup_state(dv_fwd_state* st, const dv_scene* sc,
+                      const dv_view* views, int32_t n_views,
+                      const double* pose_override) {
+  std::vector<int64_t>& seg_start = st->seg_start_h;
+  std::vector<uint32_t>& act_tile = st->act_tile_h;
+  const int n_oct = sc->n_oct;
+  st->n_views = n_views;
+  st->n_oct = n_oct;
+  st->n_actors = n_oct - 1;
+  st->views_h.resize(n_views);
+  st->vo_h.resize((size_t)n_views * n_oct);
+  st->views_in.assign(views, views + n_views);
+  uint32_t tile_base = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const dv_view& in = views[v];
+    DV_TRY(check_view(in));
+    ViewConst& V = st->views_h[v];
+    std::memset(&V, 0, sizeof(V));
+    V.fx = in.fx; V.fy = in.fy; V.cx = in.cx; V.cy = in.cy;
+    V.inv_fx = (float)(1.0 / in.fx);
+    V.inv_fy = (float)(1.0 / in.fy);
+    V.fcx = (float)in.cx;
+    V.fcy = (float)in.cy;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) V.Rc[r * 3 + c] = (float)in.c2w[r * 4 + c];
+    V.x0 = in.x0; V.y0 = in.y0; V.w = in.w; V.h = in.h;
+    V.ntx = (in.w + TILE - 1) / TILE;
+    V.nty = (in.h + TILE - 1) / TILE;
+    V.tile_base = tile_base;
+    const uint64_t nt = (uint64_t)V.ntx * V.nty;
+    if ((uint64_t)tile_base + nt >= (1ull << 31)) {
+      set_error("too many tiles");
+      return DV_ERR_LIMIT;
+    }
+    tile_base += (uint32_t)nt;
+  }
+  st->n_tiles = tile_base;
+  // poses and per-(view, octree) constants
+  seg_start.assign((size_t)n_views * n_oct + 1, 0);
+  std::vector<std::vector<uint32_t>> tile_lists;  // built below
+  std::vector<std::pair<uint32_t, uint32_t>> apairs;  // (tile, octree)
+  int64_t items = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const dv_view& in = views[v];
+    double Rc[9], o[3];
+    for (int r = 0; r < 3; ++r) {
+      for (int c = 0; c < 3; ++c) Rc[r * 3 + c] = in.c2w[r * 4 + c];
+      o[r] = in.c2w[r * 4 + 3];
+    }
+    for (int k = 0; k < n_oct; ++k) {
+      double R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, p[3] = {0, 0, 0};
+      int active = 1;
+      if (k > 0) {
+        if (pose_override) {
+          const double* po = pose_override + ((size_t)v * (n_oct - 1) + (k - 1)) * 12;
+          for (int i = 0; i < 9; ++i) R[i] = po[i];
+          for (int i = 0; i < 3; ++i) p[i] = po[9 + i];
+          for (int i = 0; i < 12; ++i)
+            if (!std::isfinite(po[i])) {
+              set_error("pose_override not finite (view %d actor %d)", v, k);
+              return DV_ERR_INVALID;
+            }
+        } else {
+          dv_track_desc tr;
+          tr.n_keys = (int32_t)sc->trk_t[k].size();
+          tr.t = sc->trk_t[k].data();
+          tr.yaw = sc->trk_yaw[k].data();
+          tr.trans = sc->trk_trans[k].data();
+          active = dv_track_pose(&tr, in.t, R, p);
+        }
+      }
+      VOConst& C = st->vo_h[(size_t)v * n_oct + k];
+      std::memset(&C, 0, sizeof(C));
+      C.active = active;
+      C.octree = k;
+      C.view = v;
+      mat_t_mul(Rc, R, C.A);
+      const double q[3] = {p[0] - o[0], p[1] - o[1], p[2] - o[2]};
+      for (int i = 0; i < 3; ++i)
+        C.b[i] = (Rc[0 * 3 + i] * q[0] + Rc[1 * 3 + i] * q[1]) + Rc[2 * 3 + i] * q[2];
+      const double om[3] = {o[0] - p[0], o[1] - p[1], o[2] - p[2]};
+      double P[3];
+      for (int j = 0; j < 3; ++j)
+        P[j] = (R[0 * 3 + j] * om[0] + R[1 * 3 + j] * om[1]) + R[2 * 3 + j] * om[2];
+      const dv_octree_desc& od = sc->desc[k];
+      for (int a = 0; a < 3; ++a) {
+        double qq = (P[a] - od.root_min[a]) / od.root_size;
+        qq = std::min(std::max(qq, -1.0), 2.0);
+        C.Q[a] = (int64_t)std::floor(std::ldexp(qq, QBITS));
+        C.rootrel[a] = od.root_min[a] - P[a];
+        C.omp[a] = (float)om[a];
+      }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          C.Rt[i * 3 + j] = (float)R[j * 3 + i];
+          C.R[i * 3 + j] = (float)R[i * 3 + j];
+        }
+      double blo[3], bhi[3];
+      for (int a = 0; a < 3; ++a) {
+        blo[a] = (k > 0 && od.has_box) ? od.box_min[a] : od.root_min[a];
+        bhi[a] = (k > 0 && od.has_box) ? od.box_max[a] : od.root_min[a] + od.root_size;
+        C.boxlo[a] = (float)(blo[a] - P[a]);
+        C.boxhi[a] = (float)(bhi[a] - P[a]);
+      }
+      const size_t sidx = (size_t)v * n_oct + k;
+      const int64_t cnt = active ? sc->desc[k].n_voxels : 0;
+      seg_start[sidx + 1] = seg_start[sidx] + cnt;
+      items += cnt;
+      if (k > 0 && active) {
+        const ViewConst& V = st->views_h[v];
+        Rect r = bin_box(C.A, C.b, blo, bhi, V.fx, V.fy, V.cx, V.cy, V.x0,
+                         V.y0, V.w, V.h);
+        if (r.status != 0 && r.xl <= r.xh && r.yl <= r.yh) {
+          for (int ty = r.yl >> 4; ty <= (r.yh >> 4); ++ty)
+            for (int tx = r.xl >> 4; tx <= (r.xh >> 4); ++tx)
+              apairs.emplace_back(V.tile_base + ty * V.ntx + tx, k);
+        }
+      }
+    }
+  }
+  (void)items;
+  // actor-tile CSR (stable by tile, actors ascending within a tile)
+  st->act_beg_h.assign(st->n_tiles + 1, 0);
+  for (auto& pr : apairs) st->act_beg_h[pr.first + 1]++;
+  for (int64_t t = 0; t < st->n_tiles; ++t) {
+    if (st->act_beg_h[t + 1] > DV_MAX_TILE_ACTORS) {
+      set_error("tile %lld has %u actor boxes (limit %d)", (long long)t,
+                st->act_beg_h[t + 1], DV_MAX_TILE_ACTORS);
+      return DV_ERR_LIMIT;
+    }
+    st->act_beg_h[t + 1] += st->act_beg_h[t];
+  }
+  st->n_apairs = (int64_t)apairs.size();
+  st->act_oct_h.assign(apairs.size(), 0);
+  act_tile.assign(apairs.size(), 0);
+  {
+    std::vector<uint32_t> fillp(st->act_beg_h.begin(), st->act_beg_h.end() - 1);
+    std::stable_sort(apairs.begin(), apairs.end(),
+                     [](const std::pair<uint32_t, uint32_t>& x,
+                        const std::pair<uint32_t, uint32_t>& y) {
+                       return x.first < y.first ||
+                              (x.first == y.first && x.second < y.second);
+                     });
+    for (size_t e = 0; e < apairs.size(); ++e) {
+      st->act_oct_h[e] = apairs[e].second;
+      act_tile[e] = apairs[e].first;
+    }
+  }
+  return DV_OK;
+}
+
+// Enqueue the whole forward pass on stream s.  Two host synchronisations
+// read the record and pair counts.
+dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
+                      const dv_outputs* outs, hipStream_t s) {
+  const std::vector<int64_t>& seg_start = st->seg_start_h;
+  const std::vector<uint32_t>& act_tile = st->act_tile_h;
+  const int n_views = st->n_views, n_oct = st->n_oct;
+  const dv_render_opts& op = st->opts;
+  const int64_t n_items = seg_start.back();
+  const int n_seg = n_views * n_oct;
+  // constants
+  DV_TRY(alloc_n<ViewConst>(ctx, st->views_d, n_views, s));
+  DV_TRY(alloc_n<VOConst>(ctx, st->vo_d, (size_t)n_seg, s));
+  DV_TRY(alloc_n<dv_outputs>(ctx, st->outs_d, n_views, s));
+  DBuf segs_d;
+  DV_TRY(alloc_n<int64_t>(ctx, segs_d, seg_start.size(), s));
+  DV_TRY_HIP(hipMemcpyAsync(st->views_d.p, st->views_h.data(),
+                            sizeof(ViewConst) * n_views, hipMemcpyHostToDevice, s));
+  DV_TRY_HIP(hipMemcpyAsync(st->vo_d.p, st->vo_h.data(),
+                            sizeof(VOConst) * n_seg, hipMemcpyHostToDevice, s));
+  DV_TRY_HIP(hipMemcpyAsync(st->outs_d.p, outs, sizeof(dv_outputs) * n_views,
+                            hipMemcpyHostToDevice, s));
+  DV_TRY_HIP(hipMemcpyAsync(segs_d.p, seg_start.data(),
+                            sizeof(int64_t) * seg_start.size(),
+                            hipMemcpyHostToDevice, s));
+  // key layout
+  int seg_bits = ceil_log2((uint64_t)n_seg);
+  st->rank_bits = 3 * sc->max_level_all;
+  st->key_bits = st->rank_bits + seg_bits;
+  if (st->key_bits > 64) {
+    set_error("record key needs %d bits", st->key_bits);
+    return DV_ERR_LIMIT;
+  }
+  st->tile_bits = ceil_log2((uint64_t)std::max<int64_t>(st->n_tiles, 2));
+  // pass 0: visibility counts per block
+  const unsigned nblk = grid_for(std::max<int64_t>(n_items, 1), TPB);
+  DBuf bcount, boff, total;
+  DV_TRY(alloc_n<uint32_t>(ctx, bcount, nblk, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, boff, nblk, s));
+  DV_TRY(alloc_n<uint64_t>(ctx, total, 2, s));
+  PreArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  pa.views = st->views_d.as<ViewConst>();
+  pa.vo = st->vo_d.as<VOConst>();
+  pa.oct = sc->oct_dev.as<OctDev>();
+  pa.seg_start = segs_d.as<int64_t>();
+  pa.n_seg = n_seg;
+  pa.n_oct = n_oct;
+  pa.n_items = n_items;
+  pa.rank_bits = st->rank_bits;
+  pa.block_count = bcount.as<uint32_t>();
+  pa.block_off = boff.as<uint32_t>();
+  if (n_items > 0)
+    hipLaunchKernelGGL(k_preprocess<0>, dim3(nblk), dim3(TPB), 0, s, pa);
+  else
+    DV_TRY(fill_u32(bcount.as<uint32_t>(), 0, nblk, s));
+  DV_TRY_HIP(hipGetLastError());
+  DV_TRY(exclusive_scan_u32(ctx, bcount.as<uint32_t>(), boff.as<uint32_t>(),
+                            total.as<uint64_t>(), nblk, s));
+  uint64_t n_vis = 0;
+  {
+    std::lock_guard<std::mutex> lk(ctx->pinned_mu);
+    DV_TRY_HIP(hipMemcpyAsync(ctx->pinned, total.p, 8, hipMemcpyDeviceToHost, s));
+    DV_TRY_HIP(hipStreamSynchronize(s));
+    n_vis = ctx->pinned[0];
+  }
+  st->n_vis = (int64_t)n_vis;
+  if (n_vis >= 0xFFFFFFFFull) {
+    set_error("%llu visible records exceed the 32-bit range",
+              (unsigned long long)n_vis);
+    return DV_ERR_LIMIT;
+  }
+  const int64_t nv = (int64_t)n_vis;
+  // pass 1: records in slot order
+  DBuf keys, vals, keys2, vals2, s_geo, s_g8a, s_g8b, s_cn, s_nrm, s_vox, s_rect;
+  DV_TRY(alloc_n<uint64_t>(ctx, keys, nv, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, vals, nv, s));
+  DV_TRY(alloc_n<uint64_t>(ctx, keys2, nv, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, vals2, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, s_geo, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, s_g8a, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, s_g8b, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, s_cn, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, s_nrm, nv, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, s_vox, nv, s));
+  DV_TRY(alloc_n<uint64_t>(ctx, s_rect, nv, s));
+  pa.keys = keys.as<uint64_t>();
+  pa.vals = vals.as<uint32_t>();
+  pa.s_geo = s_geo.as<float4>();
+  pa.s_g8a = s_g8a.as<float4>();
+  pa.s_g8b = s_g8b.as<float4>();
+  pa.s_cn = s_cn.as<float4>();
+  pa.s_nrm = s_nrm.as<float4>();
+  pa.s_vox = s_vox.as<uint32_t>();
+  pa.s_rect = s_rect.as<uint64_t>();
+  if (n_items > 0 && nv > 0)
+    hipLaunchKernelGGL(k_preprocess<1>, dim3(nblk), dim3(TPB), 0, s, pa);
+  DV_TRY_HIP(hipGetLastError());
+  // sort records by (view, octree, rank)
+  bool alt = false;
+  DV_TRY(radix_sort_u64(ctx, keys.as<uint64_t>(), vals.as<uint32_t>(),
+                        keys2.as<uint64_t>(), vals2.as<uint32_t>(), nv,
+                        st->key_bits, s, &alt));
+  uint64_t* ks = alt ? keys2.as<uint64_t>() : keys.as<uint64_t>();
+  uint32_t* vs = alt ? vals2.as<uint32_t>() : vals.as<uint32_t>();
+  // records in sorted order
+  DBuf r_count, r_off, r_rect;
+  DV_TRY(alloc_n<float4>(ctx, st->rec_geo, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, st->rec_g8a, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, st->rec_g8b, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, st->rec_cn, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, st->rec_nrm, nv, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->rec_vox, nv, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->rec_seg, nv, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, r_count, nv, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, r_off, nv, s));
+  DV_TRY(alloc_n<uint64_t>(ctx, r_rect, nv, s));
+  if (nv > 0)
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(nv, TPB)), dim3(TPB), 0, s, nv,
+                       ks, vs, st->rank_bits, s_geo.as<float4>(),
+                       s_g8a.as<float4>(), s_g8b.as<float4>(), s_cn.as<float4>(),
+                       s_nrm.as<float4>(), s_vox.as<uint32_t>(),
+                       s_rect.as<uint64_t>(), st->rec_geo.as<float4>(),
+                       st->rec_g8a.as<float4>(), st->rec_g8b.as<float4>(),
+                       st->rec_cn.as<float4>(), st->rec_nrm.as<float4>(),
+                       st->rec_vox.as<uint32_t>(), st->rec_seg.as<uint32_t>(),
+                       r_count.as<uint32_t>(), r_rect.as<uint64_t>());
+  DV_TRY_HIP(hipGetLastError());
+  DV_TRY(exclusive_scan_u32(ctx, r_count.as<uint32_t>(), r_off.as<uint32_t>(),
+                            total.as<uint64_t>(), nv, s));
+  uint64_t n_pairs = 0;
+  {
+    std::lock_guard<std::mutex> lk(ctx->pinned_mu);
+    DV_TRY_HIP(hipMemcpyAsync(ctx->pinned, total.p, 8, hipMemcpyDeviceToHost, s));
+    DV_TRY_HIP(hipStreamSynchronize(s));
+    n_pairs = ctx->pinned[0];
+  }
+  if (n_pairs >= 0xFFFFFFFFull) {
+    set_error("%llu (leaf, tile) pairs exceed the 32-bit range",
+              (unsigned long long)n_pairs);
+    return DV_ERR_LIMIT;
+  }
+  st->n_pairs = (int64_t)n_pairs;
+  const int64_t np = (int64_t)n_pairs;
+  // free slot-order buffers early
+  s_geo.reset(); s_g8a.reset(); s_g8b.reset(); s_cn.reset(); s_nrm.reset();
+  s_vox.reset(); s_rect.reset();
+  DBuf pkey, pkey2, pval2;
+  DV_TRY(alloc_n<uint32_t>(ctx, pkey, np, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->pair_val, np, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, pkey2, np, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, pval2, np, s));
+  if (np > 0)
+    hipLaunchKernelGGL(k_emit, dim3(grid_for(np, TPB)), dim3(TPB), 0, s, np, nv,
+                       r_off.as<uint32_t>(), r_rect.as<uint64_t>(),
+                       st->rec_seg.as<uint32_t>(), n_oct,
+                       st->views_d.as<ViewConst>(), pkey.as<uint32_t>(),
+                       st->pair_val.as<uint32_t>());
+  DV_TRY_HIP(hipGetLastError());
+  DV_TRY(radix_sort_u32(ctx, pkey.as<uint32_t>(), st->pair_val.as<uint32_t>(),
+                        pkey2.as<uint32_t>(), pval2.as<uint32_t>(), np,
+                        st->tile_bits, s, &alt));
+  if (alt) {
+    std::swap(pkey, pkey2);
+    std::swap(st->pair_val, pval2);
+  }
+  pkey2.reset();
+  pval2.reset();
+  // tile directory
+  const int64_t nt = st->n_tiles;
+  DV_TRY(alloc_n<uint32_t>(ctx, st->tile_start, nt, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->tile_end, nt, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->tile_bgend, nt, s));
+  DV_TRY(fill_u32(st->tile_start.as<uint32_t>(), 0, nt, s));
+  DV_TRY(fill_u32(st->tile_end.as<uint32_t>(), 0, nt, s));
+  if (np > 0)
+    hipLaunchKernelGGL(k_tile_bounds, dim3(grid_for(np, TPB)), dim3(TPB), 0, s,
+                       np, pkey.as<uint32_t>(), st->tile_start.as<uint32_t>(),
+                       st->tile_end.as<uint32_t>());
+  hipLaunchKernelGGL(k_tile_dir, dim3(grid_for(nt, TPB)), dim3(TPB), 0, s, nt,
+                     st->tile_start.as<uint32_t>(), st->tile_end.as<uint32_t>(),
+                     st->pair_val.as<uint32_t>(), st->rec_seg.as<uint32_t>(),
+                     n_oct, st->tile_bgend.as<uint32_t>());
+  DV_TRY_HIP(hipGetLastError());
+  // actor lists
+  const int64_t na = st->n_apairs;
+  DBuf atile;
+  DV_TRY(alloc_n<uint32_t>(ctx, st->act_beg, nt + 1, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->act_oct, na, s));
+  DV_TRY(alloc_n<uint2>(ctx, st->act_sub, na, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, atile, na, s));
+  DV_TRY_HIP(hipMemcpyAsync(st->act_beg.p, st->act_beg_h.data(),
+                            4 * (size_t)(nt + 1), hipMemcpyHostToDevice, s));
+  if (na > 0) {
+    DV_TRY_HIP(hipMemcpyAsync(st->act_oct.p, st->act_oct_h.data(), 4 * (size_t)na,
+                              hipMemcpyHostToDevice, s));
+    DV_TRY_HIP(hipMemcpyAsync(atile.p, act_tile.data(), 4 * (size_t)na,
+                              hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_actor_ranges, dim3(grid_for(na, TPB)), dim3(TPB), 0, s,
+                       na, atile.as<uint32_t>(), st->act_oct.as<uint32_t>(),
+                       st->tile_bgend.as<uint32_t>(), st->tile_end.as<uint32_t>(),
+                       st->pair_val.as<uint32_t>(), st->rec_seg.as<uint32_t>(),
+                       n_oct, st->act_sub.as<uint2>());
+    DV_TRY_HIP(hipGetLastError());
+  }
+  // per-pixel scratch
+  const size_t nslots = (size_t)3 * na * TPB;
+  DV_TRY(alloc_n<float2>(ctx, st->seg_se, nslots, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->seg_meta, nslots, s));
+  DV_TRY(alloc_n<float4>(ctx, st->seg_p0, nslots, s));
+  DV_TRY(alloc_n<float4>(ctx, st->seg_p1, nslots, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->pix_nseg, (size_t)nt * TPB, s));
+  DV_TRY(alloc_n<float4>(ctx, st->fin0, (size_t)nt * TPB, s));
+  DV_TRY(alloc_n<float4>(ctx, st->fin1, (size_t)nt * TPB, s));
+  CompArgs ca;
+  std::memset(&ca, 0, sizeof(ca));
+  ca.views = st->views_d.as<ViewConst>();
+  ca.vo = st->vo_d.as<VOConst>();
+  ca.n_views = n_views;
+  ca.n_oct = n_oct;
+  ca.tile_start = st->tile_start.as<uint32_t>();
+  ca.tile_end = st->tile_end.as<uint32_t>();
+  ca.tile_bgend = st->tile_bgend.as<uint32_t>();
+  ca.pair_val = st->pair_val.as<uint32_t>();
+  ca.rec_geo = st->rec_geo.as<float4>();
+  ca.rec_g8a = st->rec_g8a.as<float4>();
+  ca.rec_g8b = st->rec_g8b.as<float4>();
+  ca.rec_cn = st->rec_cn.as<float4>();
+  ca.rec_nrm = st->rec_nrm.as<float4>();
+  ca.act_beg = st->act_beg.as<uint32_t>();
+  ca.act_oct = st->act_oct.as<uint32_t>();
+  ca.act_sub = st->act_sub.as<uint2>();
+  ca.seg_se = st->seg_se.as<float2>();
+  ca.seg_meta = st->seg_meta.as<uint32_t>();
+  ca.seg_p0 = st->seg_p0.as<float4>();
+  ca.seg_p1 = st->seg_p1.as<float4>();
+  ca.pix_nseg = st->pix_nseg.as<uint32_t>();
+  ca.fin0 = st->fin0.as<float4>();
+  ca.fin1 = st->fin1.as<float4>();
+  ca.outs = st->outs_d.as<dv_outputs>();
+  ca.n_actors = n_oct - 1;
+  ca.K = op.K;
+  ca.eps = op.eps_stop;
+  ca.tau_near = op.tau_near;
+  ca.c = op.explin_c;
+  ca.inv_c = 1.0f / op.explin_c;
+  for (int i = 0; i < 3; ++i) ca.bg[i] = op.bg[i];
+  ca.mask = op.out_mask;
+  if (nt > 0) {
+    if (op.out_mask & DV_OUT_NORMAL)
+      hipLaunchKernelGGL(k_composite_fwd<true>, dim3((unsigned)nt), dim3(TPB), 0,
+                         s, ca);
+    else
+      hipLaunchKernelGGL(k_composite_fwd<false>, dim3((unsigned)nt), dim3(TPB),
+                         0, s, ca);
+  }
+  DV_TRY_HIP(hipGetLastError());
+  return DV_OK;
+}
+
+void retire_state(dv_ctx* ctx, dv_fwd_state* st) {
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ev, st->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    if (ev) hipEventDestroy(ev);
+    hipStreamSynchronize(st->stream);
+    delete st;
+    return;
+  }
+  std::lock_guard<std::mutex> lk(ctx->gy_mu);
+  ctx->graveyard.emplace_back(ev, st);
+}
+
+void reap_states(dv_ctx* ctx, bool wait) {
+  std::vector<std::pair<hipEvent_t, dv_fwd_state*>> done;
+  {
+    std::lock_guard<std::mutex> lk(ctx->gy_mu);
+    auto& g = ctx->graveyard;
+    for (size_t i = 0; i < g.size();) {
+      if (wait) hipEventSynchronize(g[i].first);
+      if (hipEventQuery(g[i].first) == hipSuccess) {
+        done.push_back(g[i]);
+        g[i] = g.back();
+        g.pop_back();
+      } else {
+        ++i;
+      }
+    }
+  }
+  for (auto& pr : done) {
+    hipEventDestroy(pr.first);
+    delete pr.second;
+  }
+}
+
+dv_status check_opts(const dv_render_opts* op) {
+  if (!op || op->K < 1 || op->K > DV_MAX_K || !(op->eps_stop >= 0.0f) ||
+      !(op->tau_near >= 0.0f) || !(op->explin_c > 0.0f) ||
+      !std::isfinite(op->tau_near)) {
+    set_error("invalid render options");
+    return DV_ERR_INVALID;
+  }
+  return DV_OK;
+}
+
+}  // namespace dv
+
+extern "C" {
+
+dv_status dv_render(dv_ctx* ctx, const dv_scene* scene, const dv_view* views,
+                    int32_t n_views, const double* pose_override,
+                    const dv_render_opts* opts, const dv_outputs* outs,
+                    dv_fwd_state** keep, void* stream) {
+  if (keep) *keep = nullptr;
+  if (!ctx || !scene || !views || n_views < 1 || !outs) {
+    set_error("dv_render: invalid arguments");
+    return DV_ERR_INVALID;
+  }
+  if (ctx->poisoned) {
+    set_error("dv_render: context poisoned by an earlier device error");
+    return DV_ERR_DEVICE;
+  }
+  DV_TRY(check_opts(opts));
+  DV_TRY_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  std::unique_ptr<dv_fwd_state> st(new dv_fwd_state());
+  st->ctx = ctx;
+  st->scene = scene;
+  st->stream = s;
+  st->opts = *opts;
+  reap_states(ctx, false);
+  DV_TRY(setup_state(st.get(), scene, views, n_views, pose_override));
+  dv_status rs = run_forward(ctx, scene, st.get(), outs, s);
+  if (rs == DV_ERR_DEVICE) ctx->poisoned = true;
+  if (rs != DV_OK) {
+    if (rs == DV_ERR_DEVICE) return rs;
+    retire_state(ctx, st.release());
+    return rs;
+  }
+  if (keep) *keep = st.release();
+  else retire_state(ctx, st.release());
+  return DV_OK;
+}
+
+void dv_fwd_state_release(dv_fwd_state* state) {
+  if (!state) return;
+  retire_state(state->ctx, state);
+}
+
+dv_status dv_fwd_state_info(const dv_fwd_state* st, dv_state_info* info) {
+  if (!st || !info) return DV_ERR_INVALID;
+  info->n_views = st->n_views;
+  info->n_visible = st->n_vis;
+  info->n_pairs = st->n_pairs;
+  info->n_actor_pairs = st->n_apairs;
+  info->n_tiles = st->n_tiles;
+  info->key_bits = st->key_bits;
+  info->tile_bits = st->tile_bits;
+  return DV_OK;
+}
+
+dv_status dv_fwd_state_export_lists(const dv_fwd_state* st, int32_t view,
+                                    int64_t* tile_start, int32_t* entry_oct,
+                                    int32_t* entry_leaf, int64_t capacity,
+                                    int64_t* actor_start, int32_t* actor_oct,
+                                    int64_t actor_capacity) {
+  if (!st || view < 0 || view >= st->n_views || !tile_start) {
+    set_error("dv_fwd_state_export_lists: invalid arguments");
+    return DV_ERR_INVALID;
+  }
+  DV_TRY_HIP(hipSetDevice(st->ctx->device));
+  DV_TRY_HIP(hipStreamSynchronize(st->stream));
+  const ViewConst& V = st->views_h[view];
+  const int64_t nt = (int64_t)V.ntx * V.nty;
+  std::vector<uint32_t> ts(nt), te(nt);
+  if (nt > 0) {
+    DV_TRY_HIP(hipMemcpy(ts.data(), st->tile_start.as<uint32_t>() + V.tile_base,
+                         4 * nt, hipMemcpyDeviceToHost));
+    DV_TRY_HIP(hipMemcpy(te.data(), st->tile_end.as<uint32_t>() + V.tile_base,
+                         4 * nt, hipMemcpyDeviceToHost));
+  }
+  std::vector<uint32_t> pv(st->n_pairs), seg(st->n_vis), vox(st->n_vis);
+  if (st->n_pairs > 0)
+    DV_TRY_HIP(hipMemcpy(pv.data(), st->pair_val.p, 4 * st->n_pairs,
+                         hipMemcpyDeviceToHost));
+  if (st->n_vis > 0) {
+    DV_TRY_HIP(hipMemcpy(seg.data(), st->rec_seg.p, 4 * st->n_vis,
+                         hipMemcpyDeviceToHost));
+    DV_TRY_HIP(hipMemcpy(vox.data(), st->rec_vox.p, 4 * st->n_vis,
+                         hipMemcpyDeviceToHost));
+  }
+  int64_t pos = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    tile_start[t] = pos;
+    const uint32_t b = te[t] > ts[t] ? ts[t] : 0, e = te[t] > ts[t] ? te[t] : 0;
+    for (uint32_t i = b; i < e; ++i) {
+      if (pos >= capacity) {
+        set_error("export capacity %lld too small", (long long)capacity);
+        return DV_ERR_LIMIT;
+      }
+      const uint32_t r = pv[i];
+      if (entry_oct) entry_oct[pos] = (int32_t)(seg[r] % st->n_oct);
+      if (entry_leaf) entry_leaf[pos] = (int32_t)vox[r];
+      ++pos;
+    }
+  }
+  tile_start[nt] = pos;
+  if (actor_start) {
+    int64_t ap = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+      actor_start[t] = ap;
+      const uint32_t b = st->act_beg_h[V.tile_base + t];
+      const uint32_t e = st->act_beg_h[V.tile_base + t + 1];
+      for (uint32_t i = b; i < e; ++i) {
+        if (ap >= actor_capacity) {
+          set_error("actor export capacity too small");
+          return DV_ERR_LIMIT;
+        }
+        if (actor_oct) actor_oct[ap] = (int32_t)st->act_oct_h[i];
+        ++ap;
+      }
+    }
+    actor_start[nt] = ap;
+  }
+  return DV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Stable LSD radix sort of (key, value) pairs, 8-bit digits.
+//
+// Each pass: per-block digit histograms (LDS atomics), a device scan of the
+// digit-major count matrix, and a stable scatter.  In the scatter every
+// wave64 ranks its 64 keys per round with ballots (one ballot per digit
+// bit gives the set of lanes holding the same digit), keeps running
+// per-wave digit counters in LDS, then offsets waves within the block.
+// Element order inside a block is (wave, round, lane), so equal digits keep
+// their input order and the sort is stable.
+#include "dv_internal.h"
+
+namespace dv {
+
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = TPB * RS_ITEMS;     // 4096 keys per block
+constexpr int RS_WAVE_SPAN = 64 * RS_ITEMS;  // 1024 keys per wave
+constexpr int RS_BINS = 256;
+
+template <class K>
+__global__ void __launch_bounds__(TPB)
+k_rs_hist(const K* __restrict__ keys, int64_t n, int sh,
+          uint32_t* __restrict__ counts, int64_t nb) {
+  __shared__ uint32_t hist[RS_BINS];
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    int64_t idx = base + (int64_t)i * TPB + threadIdx.x;
+    if (idx < n) {
+      uint32_t d = (uint32_t)(keys[idx] >> sh) & 0xFF;
+      atomicAdd(&hist[d], 1u);
+    }
+  }
+  __syncthreads();
+  counts[(int64_t)threadIdx.x * nb + blockIdx.x] = hist[threadIdx.x];
+}
+
+template <class K>
+__global__ void __launch_bounds__(TPB)
+k_rs_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+             K* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n,
+             int sh, const uint32_t* __restrict__ offs, int64_t nb) {
+  __shared__ uint32_t wcnt[TPB / 64][RS_BINS];
+  __shared__ uint32_t wbase[TPB / 64][RS_BINS];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < TPB / 64; ++i) wcnt[i][threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * RS_WAVE_SPAN;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  K key[RS_ITEMS];
+  uint32_t val[RS_ITEMS], pos[RS_ITEMS], dig[RS_ITEMS];
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; ++j) {
+    const int64_t idx = base + j * 64 + lane;
+    const bool valid = idx < n;
+    K k = valid ? kin[idx] : (K)0;
+    uint32_t v = valid ? vin[idx] : 0u;
+    uint32_t d = (uint32_t)(k >> sh) & 0xFF;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1;
+      uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t r = (uint32_t)__popcll(peers & lt);
+    const uint32_t c0 = wcnt[w][d];
+    __builtin_amdgcn_wave_barrier();
+    if (valid && r == 0) wcnt[w][d] = c0 + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    key[j] = k;
+    val[j] = v;
+    dig[j] = valid ? d : 0xFFFFFFFFu;
+    pos[j] = c0 + r;
+  }
+  __syncthreads();
+  {
+    const int d = threadIdx.x;
+    uint32_t off = offs[(int64_t)d * nb + blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < TPB / 64; ++i) {
+      wbase[i][d] = off;
+      off += wcnt[i][d];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; ++j) {
+    if (dig[j] != 0xFFFFFFFFu) {
+      const uint32_t dst = wbase[w][dig[j]] + pos[j];
+      kout[dst] = key[j];
+      vout[dst] = val[j];
+    }
+  }
+}
+
+template <class K>
+static dv_status radix_sort(dv_ctx* ctx, K* keys, uint32_t* vals, K* kalt,
+                            uint32_t* valt, int64_t n, int bits,
+                            hipStream_t s, bool* in_alt) {
+  *in_alt = false;
+  if (n <= 1 || bits <= 0) return DV_OK;
+  if (n >= (int64_t)0xFFFFFFFFll) {
+    set_error("radix sort: %lld elements exceed the 32-bit index range",
+              (long long)n);
+    return DV_ERR_LIMIT;
+  }
+  const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+  DBuf cnt, off;
+  DV_TRY(alloc_n<uint32_t>(ctx, cnt, nb * RS_BINS, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, off, nb * RS_BINS, s));
+  K* ka = keys;
+  uint32_t* va = vals;
+  K* kb = kalt;
+  uint32_t* vb = valt;
+  for (int sh = 0; sh < bits; sh += 8) {
+    hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nb), dim3(TPB), 0, s, ka,
+                       n, sh, cnt.as<uint32_t>(), nb);
+    DV_TRY(exclusive_scan_u32(ctx, cnt.as<uint32_t>(), off.as<uint32_t>(),
+                              nullptr, nb * RS_BINS, s));
+    hipLaunchKernelGGL(k_rs_scatter<K>, dim3((unsigned)nb), dim3(TPB), 0, s,
+                       ka, va, kb, vb, n, sh, off.as<uint32_t>(), nb);
+    DV_TRY_HIP(hipGetLastError());
+    std::swap(ka, kb);
+    std::swap(va, vb);
+    *in_alt = !*in_alt;
+  }
+  return DV_OK;
+}
+
+dv_status radix_sort_u64(dv_ctx* ctx, uint64_t* keys, uint32_t* vals,
+                         uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                         int bits, hipStream_t s, bool* in_alt) {
+  return radix_sort<uint64_t>(ctx, keys, vals, keys_alt, vals_alt, n, bits, s,
+                              in_alt);
+}
+
+dv_status radix_sort_u32(dv_ctx* ctx, uint32_t* keys, uint32_t* vals,
+                         uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                         int bits, hipStream_t s, bool* in_alt) {
+  return radix_sort<uint32_t>(ctx, keys, vals, keys_alt, vals_alt, n, bits, s,
+                              in_alt);
+}
+
+}  // namespace dv

@@ -1,0 +1,420 @@
+"""ctypes binding of the C ABI in include/dv.h (argument marshalling only).
+
+Functions keep the C names (``dv_build_scene``, ``dv_render``,
+``dv_render_backward``, ``dv_serve_submit``, ``dv_serve_poll`` ...); they
+take torch tensors / numpy arrays / dicts, build the C structs and call the
+library.  Every step of rendering runs in the HIP library: if ``libdvox.so``
+is missing this module raises at import time.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdvox.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with "
+        "`python -m paper_2606_23031_amd.build` (hipcc, gfx950)")
+_lib = C.CDLL(LIB_PATH)
+
+DV_OK = 0
+DV_PENDING = 1
+STATUS_NAMES = {0: "DV_OK", 1: "DV_PENDING", -1: "DV_ERR_INVALID",
+                -2: "DV_ERR_OOM", -3: "DV_ERR_DEVICE", -4: "DV_ERR_OVERLAP",
+                -5: "DV_ERR_RANGE", -6: "DV_ERR_LIMIT", -7: "DV_ERR_TICKET",
+                -8: "DV_ERR_SHUTDOWN"}
+DV_OUT_RGB, DV_OUT_DEPTH, DV_OUT_NORMAL, DV_OUT_T = 1, 2, 4, 8
+
+
+class DVError(RuntimeError):
+    def __init__(self, status, where):
+        msg = _lib.dv_last_error().decode()
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(st, where):
+    if st != DV_OK:
+        raise DVError(st, where)
+    return st
+
+
+# ------------------------------------------------------------------ structs
+class dv_octree_desc(C.Structure):
+    _fields_ = [("root_min", C.c_double * 3), ("root_size", C.c_double),
+                ("n_voxels", C.c_int32), ("max_level", C.c_int32),
+                ("n_corners", C.c_int32), ("sh_degree", C.c_int32),
+                ("level", C.c_void_p), ("ijk", C.c_void_p),
+                ("corner_idx", C.c_void_p), ("corner_density", C.c_void_p),
+                ("sh", C.c_void_p), ("has_box", C.c_int32),
+                ("box_min", C.c_double * 3), ("box_max", C.c_double * 3)]
+
+
+class dv_track_desc(C.Structure):
+    _fields_ = [("n_keys", C.c_int32), ("t", C.c_void_p), ("yaw", C.c_void_p),
+                ("trans", C.c_void_p)]
+
+
+class dv_view(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double),
+                ("cy", C.c_double), ("W", C.c_int32), ("H", C.c_int32),
+                ("x0", C.c_int32), ("y0", C.c_int32), ("w", C.c_int32),
+                ("h", C.c_int32), ("c2w", C.c_double * 12), ("t", C.c_double)]
+
+
+class dv_render_opts(C.Structure):
+    _fields_ = [("K", C.c_int32), ("eps_stop", C.c_float),
+                ("tau_near", C.c_float), ("bg", C.c_float * 3),
+                ("explin_c", C.c_float), ("out_mask", C.c_uint32)]
+
+
+class dv_outputs(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p),
+                ("normal", C.c_void_p), ("T", C.c_void_p)]
+
+
+class dv_out_grads(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p),
+                ("normal", C.c_void_p), ("T", C.c_void_p)]
+
+
+class dv_octree_grads(C.Structure):
+    _fields_ = [("corner", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class dv_param_grads(C.Structure):
+    _fields_ = [("octrees", C.POINTER(dv_octree_grads)),
+                ("pose", C.c_void_p)]
+
+
+class dv_state_info(C.Structure):
+    _fields_ = [("n_views", C.c_int32), ("n_visible", C.c_int64),
+                ("n_pairs", C.c_int64), ("n_actor_pairs", C.c_int64),
+                ("n_tiles", C.c_int64), ("key_bits", C.c_int32),
+                ("tile_bits", C.c_int32)]
+
+
+class dv_serve_opts(C.Structure):
+    _fields_ = [("max_inflight", C.c_int32), ("mem_budget", C.c_int64),
+                ("batched", C.c_int32), ("max_batch", C.c_int32),
+                ("opts", dv_render_opts)]
+
+
+class dv_request(C.Structure):
+    _fields_ = [("view", dv_view), ("out", dv_outputs)]
+
+
+class dv_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+_P = C.c_void_p
+_sig = {
+    "dv_ctx_create": (C.c_int32, [C.c_int32, C.POINTER(_P)]),
+    "dv_ctx_destroy": (None, [_P]),
+    "dv_last_error": (C.c_char_p, []),
+    "dv_version": (C.c_char_p, []),
+    "dv_build_scene": (C.c_int32, [_P, C.POINTER(dv_octree_desc), C.c_int32,
+                                   C.POINTER(dv_track_desc), C.POINTER(_P)]),
+    "dv_scene_destroy": (None, [_P]),
+    "dv_validate_octree_host": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32,
+                                            C.c_int32, C.c_int32, C.c_char_p,
+                                            C.c_int32]),
+    "dv_track_pose": (C.c_int32, [C.POINTER(dv_track_desc), C.c_double,
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "dv_render": (C.c_int32, [_P, _P, C.POINTER(dv_view), C.c_int32, _P,
+                              C.POINTER(dv_render_opts),
+                              C.POINTER(dv_outputs), C.POINTER(_P), _P]),
+    "dv_render_backward": (C.c_int32, [_P, _P, _P, C.POINTER(dv_out_grads),
+                                       C.POINTER(dv_param_grads), _P]),
+    "dv_fwd_state_release": (None, [_P]),
+    "dv_fwd_state_info": (C.c_int32, [_P, C.POINTER(dv_state_info)]),
+    "dv_fwd_state_export_lists": (C.c_int32, [_P, C.c_int32, _P, _P, _P,
+                                              C.c_int64, _P, _P, C.c_int64]),
+    "dv_serve_create": (C.c_int32, [_P, _P, C.POINTER(dv_serve_opts),
+                                    C.POINTER(_P)]),
+    "dv_serve_submit": (C.c_int32, [_P, C.POINTER(dv_request),
+                                    C.POINTER(C.c_uint64)]),
+    "dv_serve_poll": (C.c_int32, [_P, C.c_uint64, C.c_int32,
+                                  C.POINTER(dv_result)]),
+    "dv_serve_destroy": (C.c_int32, [_P]),
+}
+
+EXPORTED = []
+for _name, (_res, _args) in _sig.items():
+    if hasattr(_lib, _name):
+        _f = getattr(_lib, _name)
+        _f.restype = _res
+        _f.argtypes = _args
+        EXPORTED.append(_name)
+
+
+def lib():
+    return _lib
+
+
+def version():
+    return _lib.dv_version().decode()
+
+
+# ------------------------------------------------------------------ helpers
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def make_view(v):
+    """dict (as produced by ``synth``) -> dv_view."""
+    cv = dv_view()
+    cv.fx, cv.fy, cv.cx, cv.cy = v["fx"], v["fy"], v["cx"], v["cy"]
+    cv.W, cv.H = v["W"], v["H"]
+    cv.x0, cv.y0, cv.w, cv.h = v["x0"], v["y0"], v["w"], v["h"]
+    cv.c2w[:] = [float(x) for x in np.asarray(v["c2w"], np.float64).reshape(12)]
+    cv.t = v["t"]
+    return cv
+
+
+def make_opts(o, mask=DV_OUT_RGB | DV_OUT_DEPTH | DV_OUT_T):
+    co = dv_render_opts()
+    co.K = int(o.get("K", 1))
+    co.eps_stop = float(o.get("eps_stop", 1e-4))
+    co.tau_near = float(o.get("tau_near", 0.0))
+    co.bg[:] = [float(x) for x in o.get("bg", (0.0, 0.0, 0.0))]
+    co.explin_c = float(o.get("explin_c", 1.1))
+    co.out_mask = int(o.get("out_mask", mask))
+    return co
+
+
+# ------------------------------------------------------------------ context
+def dv_ctx_create(device=0):
+    h = C.c_void_p()
+    _check(_lib.dv_ctx_create(device, C.byref(h)), "dv_ctx_create")
+    return h
+
+
+def dv_ctx_destroy(ctx):
+    _lib.dv_ctx_destroy(ctx)
+
+
+def dv_validate_octree_host(level, ijk, corner_idx, max_level, n_corners,
+                            sh_degree):
+    """Host-only structural validation; returns (status, message)."""
+    level = np.ascontiguousarray(level, np.uint8)
+    ijk = np.ascontiguousarray(ijk, np.int32)
+    corner_idx = np.ascontiguousarray(corner_idx, np.int32)
+    n = level.shape[0]
+    buf = C.create_string_buffer(512)
+    st = _lib.dv_validate_octree_host(
+        level.ctypes.data_as(C.c_void_p), ijk.ctypes.data_as(C.c_void_p),
+        corner_idx.ctypes.data_as(C.c_void_p), n, max_level, n_corners,
+        sh_degree, buf, 512)
+    return st, buf.value.decode()
+
+
+def dv_track_pose(track, t):
+    """(active, R [3,3], p [3]) from a track dict, FP64 on the host."""
+    tt = np.ascontiguousarray(track["t"], np.float64)
+    yy = np.ascontiguousarray(track["yaw"], np.float64)
+    pp = np.ascontiguousarray(track["trans"], np.float64)
+    d = dv_track_desc(len(tt), tt.ctypes.data, yy.ctypes.data, pp.ctypes.data)
+    R = (C.c_double * 9)()
+    p = (C.c_double * 3)()
+    act = _lib.dv_track_pose(C.byref(d), t, R, p)
+    return bool(act), np.array(R[:]).reshape(3, 3), np.array(p[:])
+
+
+class Scene:
+    """Device-resident scene: torch tensors for every octree array (caller
+    owned, referenced by the library) plus the built dv_scene handle."""
+
+    def __init__(self, ctx, scene, device="cuda"):
+        import torch
+        self.ctx = ctx
+        self.tensors = []
+        self.octs = []
+        descs = (dv_octree_desc * len(scene["octrees"]))()
+        for k, o in enumerate(scene["octrees"]):
+            t = dict(
+                level=torch.from_numpy(np.ascontiguousarray(o["level"], np.uint8)).to(device),
+                ijk=torch.from_numpy(np.ascontiguousarray(o["ijk"], np.int32)).to(device),
+                corner_idx=torch.from_numpy(np.ascontiguousarray(o["corner_idx"], np.int32)).to(device),
+                corner_density=torch.from_numpy(np.ascontiguousarray(o["corner_density"], np.float32)).to(device),
+                sh=torch.from_numpy(np.ascontiguousarray(o["sh"], np.float32)).to(device))
+            self.octs.append(t)
+            d = descs[k]
+            d.root_min[:] = [float(x) for x in o["root_min"]]
+            d.root_size = float(o["root_size"])
+            d.n_voxels = int(o["level"].shape[0])
+            d.max_level = int(o["max_level"])
+            d.n_corners = int(o["corner_density"].shape[0])
+            d.sh_degree = int(o["sh_degree"])
+            d.level = t["level"].data_ptr()
+            d.ijk = t["ijk"].data_ptr()
+            d.corner_idx = t["corner_idx"].data_ptr()
+            d.corner_density = t["corner_density"].data_ptr()
+            d.sh = t["sh"].data_ptr()
+            if "box_min" in o:
+                d.has_box = 1
+                d.box_min[:] = [float(x) for x in o["box_min"]]
+                d.box_max[:] = [float(x) for x in o["box_max"]]
+        n_act = len(scene["octrees"]) - 1
+        self.n_octrees = len(scene["octrees"])
+        self.n_actors = n_act
+        self._track_arrays = []
+        tracks = (dv_track_desc * max(1, n_act))()
+        for i in range(n_act):
+            tr = scene["tracks"][i + 1]
+            tt = np.ascontiguousarray(tr["t"], np.float64)
+            yy = np.ascontiguousarray(tr["yaw"], np.float64)
+            pp = np.ascontiguousarray(tr["trans"], np.float64)
+            self._track_arrays += [tt, yy, pp]
+            tracks[i] = dv_track_desc(len(tt), tt.ctypes.data, yy.ctypes.data,
+                                      pp.ctypes.data)
+        torch.cuda.synchronize()
+        self.handle = dv_build_scene(ctx, descs, tracks if n_act else None)
+
+    def close(self):
+        if self.handle is not None:
+            dv_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dv_build_scene(ctx, descs, tracks):
+    h = C.c_void_p()
+    _check(_lib.dv_build_scene(ctx, descs, len(descs), tracks, C.byref(h)),
+           "dv_build_scene")
+    return h
+
+
+def dv_scene_destroy(h):
+    _lib.dv_scene_destroy(h)
+
+
+def alloc_outputs(views, mask=DV_OUT_RGB | DV_OUT_DEPTH | DV_OUT_T,
+                  device="cuda"):
+    import torch
+    outs = []
+    for v in views:
+        h, w = v["h"], v["w"]
+        outs.append(dict(
+            rgb=torch.zeros(3, h, w, device=device) if mask & DV_OUT_RGB else None,
+            depth=torch.zeros(h, w, device=device) if mask & DV_OUT_DEPTH else None,
+            normal=torch.zeros(3, h, w, device=device) if mask & DV_OUT_NORMAL else None,
+            T=torch.zeros(h, w, device=device) if mask & DV_OUT_T else None))
+    return outs
+
+
+def dv_render(ctx, scene, views, opts, outs, pose_override=None, keep=False,
+              stream=None):
+    """Render ``views`` (list of view dicts) into ``outs`` (list of dicts of
+    torch tensors).  Returns a forward-state handle if keep, else None."""
+    nv = len(views)
+    cviews = (dv_view * nv)(*[make_view(v) for v in views])
+    couts = (dv_outputs * nv)()
+    for i, o in enumerate(outs):
+        couts[i] = dv_outputs(_ptr(o.get("rgb")), _ptr(o.get("depth")),
+                              _ptr(o.get("normal")), _ptr(o.get("T")))
+    po = None
+    if pose_override is not None:
+        pov = np.ascontiguousarray(pose_override, np.float64)
+        po = pov.ctypes.data_as(C.c_void_p)
+    st = C.c_void_p()
+    rc = _lib.dv_render(ctx, scene.handle, cviews, nv, po, C.byref(opts),
+                        couts, C.byref(st) if keep else None,
+                        _stream_handle(stream))
+    _check(rc, "dv_render")
+    return st if keep else None
+
+
+def dv_render_backward(ctx, scene, state, grads, acc_octrees, pose_grad=None,
+                       stream=None):
+    """grads: list per view of dicts (rgb/depth/normal/T upstream gradient
+    tensors or None); acc_octrees: list per octree of dicts with 'corner'
+    and 'sh' accumulator tensors (or None)."""
+    nv = len(grads)
+    cg = (dv_out_grads * nv)()
+    for i, g in enumerate(grads):
+        cg[i] = dv_out_grads(_ptr(g.get("rgb")), _ptr(g.get("depth")),
+                             _ptr(g.get("normal")), _ptr(g.get("T")))
+    no = len(acc_octrees)
+    co = (dv_octree_grads * no)()
+    for k, a in enumerate(acc_octrees):
+        a = a or {}
+        co[k] = dv_octree_grads(_ptr(a.get("corner")), _ptr(a.get("sh")))
+    pg = dv_param_grads(co, _ptr(pose_grad))
+    _check(_lib.dv_render_backward(ctx, scene.handle, state, cg, C.byref(pg),
+                                   _stream_handle(stream)),
+           "dv_render_backward")
+
+
+def dv_fwd_state_release(state):
+    _lib.dv_fwd_state_release(state)
+
+
+def dv_fwd_state_info(state):
+    info = dv_state_info()
+    _check(_lib.dv_fwd_state_info(state, C.byref(info)), "dv_fwd_state_info")
+    return {f: getattr(info, f) for f, _ in dv_state_info._fields_}
+
+
+def dv_fwd_state_export_lists(state, view, n_tiles, capacity, actor_capacity=0):
+    ts = np.zeros(n_tiles + 1, np.int64)
+    eo = np.zeros(max(capacity, 1), np.int32)
+    el = np.zeros(max(capacity, 1), np.int32)
+    ast = np.zeros(n_tiles + 1, np.int64)
+    ao = np.zeros(max(actor_capacity, 1), np.int32)
+    _check(_lib.dv_fwd_state_export_lists(
+        state, view, ts.ctypes.data, eo.ctypes.data, el.ctypes.data, capacity,
+        ast.ctypes.data, ao.ctypes.data, actor_capacity),
+        "dv_fwd_state_export_lists")
+    return ts, eo[:ts[-1]], el[:ts[-1]], ast, ao[:ast[-1]]
+
+
+# ------------------------------------------------------------------ serving
+def dv_serve_create(ctx, scene, opts, max_inflight=8, mem_budget=8 << 30,
+                    batched=True, max_batch=8):
+    so = dv_serve_opts(max_inflight, mem_budget, 1 if batched else 0,
+                       max_batch, opts)
+    h = C.c_void_p()
+    _check(_lib.dv_serve_create(ctx, scene.handle, C.byref(so), C.byref(h)),
+           "dv_serve_create")
+    return h
+
+
+def dv_serve_submit(srv, view, out):
+    req = dv_request(make_view(view),
+                     dv_outputs(_ptr(out.get("rgb")), _ptr(out.get("depth")),
+                                _ptr(out.get("normal")), _ptr(out.get("T"))))
+    t = C.c_uint64()
+    _check(_lib.dv_serve_submit(srv, C.byref(req), C.byref(t)),
+           "dv_serve_submit")
+    return t.value
+
+
+def dv_serve_poll(srv, ticket, wait_us=0):
+    """Returns (status, t_submit, t_admit, t_done)."""
+    r = dv_result()
+    st = _lib.dv_serve_poll(srv, ticket, wait_us, C.byref(r))
+    return st, r.t_submit, r.t_admit, r.t_done
+
+
+def dv_serve_destroy(srv):
+    _check(_lib.dv_serve_destroy(srv), "dv_serve_destroy")
