@@ -1,0 +1,779 @@
+// Reverse pass (Sec. 3.4: gradients flow through each voxel segment).
+//
+// With v_i = G_C.c_i + G_D (a_i+b_i)/2 + G_N.n_i and
+// L = G_C.C + G_D D + G_N.N + (G_C.bg + G_T) T_final, the derivative with
+// respect to the optical depth of piece i is
+//     dL/dtau_i = T_{i+1} v_i - (L - sum_{j<=i} w_j v_j),
+// so the backward re-walks every pixel in forward order with identical
+// FP32 arithmetic (same piece evaluation, same stop decisions) instead of
+// storing per-sample state.  Asset segments were composited in the forward
+// as partial states spliced into the background walk; the re-walk records
+// for every spliced segment its entry transmittance T_pre and the suffix
+// S_after = L - (prefix through the segment), after which each asset's
+// pieces can be differentiated on their own:
+//     dL/dtau_i = T_pre T_loc,i+1 v_i - (T_pre (V_q - P_loc,i) + S_after).
+// Pose gradients (beyond the paper, which keeps tracks fixed) follow the
+// ray in each actor frame: samples, leaf faces, box faces bounding
+// segments, SH direction and the rotation of normals.
+#include <cmath>
+#include <cstring>
+
+#include "render.h"
+
+namespace dv {
+
+constexpr int NACC = 14;  // per-record: dcol(3), dnrm(3), dg(8)
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+struct PieceDer {
+  float dtda, dtdb;       // d tau / d(a), d(b)
+  float dg[8];            // d tau / d corner value
+  float3 dx;              // sum_q d tau / d x_q
+  float3 dxt;             // sum_q tau_q d tau / d x_q
+};
+
+// Derivatives of piece_tau (same sample positions; clamps are inactive
+// inside the piece).
+template <bool GEO>
+__device__ inline void piece_der(float4 geo, float4 ga, float4 gb,
+                                 float inv_h, float3 d, float a, float b,
+                                 int K, float invK, float c, float inv_c,
+                                 PieceDer& o) {
+  const float step = (b - a) * invK;
+  float ssum = 0.0f, pa = 0.0f, pb = 0.0f;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) o.dg[m] = 0.0f;
+  o.dx = make_float3(0, 0, 0);
+  o.dxt = make_float3(0, 0, 0);
+  for (int q = 0; q < K; ++q) {
+    const float f = ((float)q + 0.5f) * invK;
+    const float tq = fmaf((float)q + 0.5f, step, a);
+    const float ux = clamp01(fmaf(tq, d.x, -geo.x) * inv_h);
+    const float uy = clamp01(fmaf(tq, d.y, -geo.y) * inv_h);
+    const float uz = clamp01(fmaf(tq, d.z, -geo.z) * inv_h);
+    const float g = trilerp(ga, gb, ux, uy, uz);
+    const float coef = step * explin_grad(g, c, inv_c);
+    ssum += explin(g, c, inv_c);
+    const float vx = 1.0f - ux, vy = 1.0f - uy, vz = 1.0f - uz;
+    o.dg[0] = fmaf(coef, vx * vy * vz, o.dg[0]);
+    o.dg[1] = fmaf(coef, ux * vy * vz, o.dg[1]);
+    o.dg[2] = fmaf(coef, vx * uy * vz, o.dg[2]);
+    o.dg[3] = fmaf(coef, ux * uy * vz, o.dg[3]);
+    o.dg[4] = fmaf(coef, vx * vy * uz, o.dg[4]);
+    o.dg[5] = fmaf(coef, ux * vy * uz, o.dg[5]);
+    o.dg[6] = fmaf(coef, vx * uy * uz, o.dg[6]);
+    o.dg[7] = fmaf(coef, ux * uy * uz, o.dg[7]);
+    if (GEO) {
+      const float gx = vy * vz * (ga.y - ga.x) + uy * vz * (ga.w - ga.z) +
+                       vy * uz * (gb.y - gb.x) + uy * uz * (gb.w - gb.z);
+      const float gy = vx * vz * (ga.z - ga.x) + ux * vz * (ga.w - ga.y) +
+                       vx * uz * (gb.z - gb.x) + ux * uz * (gb.w - gb.y);
+      const float gz = vx * vy * (gb.x - ga.x) + ux * vy * (gb.y - ga.y) +
+                       vx * uy * (gb.z - ga.z) + ux * uy * (gb.w - ga.w);
+      const float s = coef * inv_h;
+      const float3 dtdx = make_float3(s * gx, s * gy, s * gz);
+      const float proj = dtdx.x * d.x + dtdx.y * d.y + dtdx.z * d.z;
+      pa = fmaf(proj, 1.0f - f, pa);
+      pb = fmaf(proj, f, pb);
+      o.dx.x += dtdx.x; o.dx.y += dtdx.y; o.dx.z += dtdx.z;
+      o.dxt.x = fmaf(tq, dtdx.x, o.dxt.x);
+      o.dxt.y = fmaf(tq, dtdx.y, o.dxt.y);
+      o.dxt.z = fmaf(tq, dtdx.z, o.dxt.z);
+    }
+  }
+  o.dtda = -ssum * invK + pa;
+  o.dtdb = ssum * invK + pb;
+}
+
+__device__ inline void add_axis(float3& v, int ax, float x) {
+  if (ax == 0) v.x += x; else if (ax == 1) v.y += x; else v.z += x;
+}
+__device__ inline float get_axis(float3 v, int ax) {
+  return ax == 0 ? v.x : (ax == 1 ? v.y : v.z);
+}
+
+struct BwdBatch {
+  float4 geo[TPB];
+  float4 ga[TPB];
+  float4 gb[TPB];
+  float4 cn[TPB];
+  float4 nrm[TPB];
+  uint32_t rid[TPB];
+  float acc[NACC][TPB];
+};
+
+__device__ inline void load_bwd_batch(BwdBatch& B, const CompArgs& a,
+                                      uint32_t base, uint32_t n) {
+  const int tid = threadIdx.x;
+  if ((uint32_t)tid < n) {
+    const uint32_t r = a.pair_val[base + tid];
+    B.rid[tid] = r;
+    B.geo[tid] = a.rec_geo[r];
+    B.ga[tid] = a.rec_g8a[r];
+    B.gb[tid] = a.rec_g8b[r];
+    B.cn[tid] = a.rec_cn[r];
+    B.nrm[tid] = a.rec_nrm[r];
+  }
+}
+
+// Reduce one lane-contribution set into the batch slot r (wave reduce +
+// LDS atomics).  Must be called wave-uniformly.
+template <bool NORMALS>
+__device__ inline void accum_record(BwdBatch& B, uint32_t r, bool hit,
+                                    float3 dcol, float3 dnrm,
+                                    const float* dg) {
+  if (__ballot(hit) == 0) return;
+  const int lane = threadIdx.x & 63;
+  float v[NACC];
+  v[0] = dcol.x; v[1] = dcol.y; v[2] = dcol.z;
+  v[3] = dnrm.x; v[4] = dnrm.y; v[5] = dnrm.z;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) v[6 + m] = dg[m];
+#pragma unroll
+  for (int c = 0; c < NACC; ++c) {
+    if (!NORMALS && c >= 3 && c < 6) continue;
+    const float s = wave_sum(hit ? v[c] : 0.0f);
+    if (lane == 0 && s != 0.0f) atomicAdd(&B.acc[c][r], s);
+  }
+}
+
+__device__ inline void flush_batch(BwdBatch& B, const CompArgs& a,
+                                   uint32_t n) {
+  __syncthreads();
+  const int tid = threadIdx.x;
+  if ((uint32_t)tid < n) {
+    const uint32_t r = B.rid[tid];
+    float* gc = reinterpret_cast<float*>(a.gr_col + r);
+    float* gn = reinterpret_cast<float*>(a.gr_nrm + r);
+    float* g0 = reinterpret_cast<float*>(a.gr_g8a + r);
+    float* g1 = reinterpret_cast<float*>(a.gr_g8b + r);
+#pragma unroll
+    for (int c = 0; c < NACC; ++c) {
+      const float x = B.acc[c][tid];
+      if (x != 0.0f) {
+        float* dst = c < 3 ? gc + c : (c < 6 ? gn + (c - 3)
+                                             : (c < 10 ? g0 + (c - 6) : g1 + (c - 10)));
+        atomicAdd(dst, x);
+        B.acc[c][tid] = 0.0f;
+      }
+    }
+  }
+}
+
+// Block-reduce 12 floats per thread and add them to dst (one atomic each).
+__device__ inline void block_add12(float* red, const float* v, float* dst) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const float s = wave_sum(v[c]);
+    if (lane == 0) red[w * 12 + c] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 12) {
+    float s = 0.0f;
+    for (int i = 0; i < TPB / 64; ++i) s += red[i * 12 + threadIdx.x];
+    if (s != 0.0f) atomicAdd(dst + threadIdx.x, s);
+  }
+}
+
+// (o_k, d_k) gradients of one pixel -> (R, p) gradient row-major 9 + 3.
+__device__ inline void pose12(const VOConst& C, float3 d, float3 go, float3 gd,
+                              float* out) {
+  const float om[3] = {C.omp[0], C.omp[1], C.omp[2]};
+  const float dd[3] = {d.x, d.y, d.z};
+  const float g_o[3] = {go.x, go.y, go.z}, g_d[3] = {gd.x, gd.y, gd.z};
+  for (int b = 0; b < 3; ++b)
+    for (int a = 0; a < 3; ++a) out[b * 3 + a] = om[b] * g_o[a] + dd[b] * g_d[a];
+  for (int b = 0; b < 3; ++b)
+    out[9 + b] = -(C.R[b * 3 + 0] * g_o[0] + C.R[b * 3 + 1] * g_o[1] +
+                   C.R[b * 3 + 2] * g_o[2]);
+}
+
+template <bool NORMALS>
+__global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
+  __shared__ BwdBatch B;
+  __shared__ float red[(TPB / 64) * 12];
+  const uint32_t gt = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int c = 0; c < NACC; ++c) B.acc[c][tid] = 0.0f;
+  const int v = view_of_tile(a.views, a.n_views, gt);
+  const ViewConst& V = a.views[v];
+  const uint32_t lt = gt - V.tile_base;
+  const int px = (int)(lt % V.ntx) * TILE + (tid & 15);
+  const int py = (int)(lt / V.ntx) * TILE + (tid >> 4);
+  const bool valid = px < V.w && py < V.h;
+  float3 d;
+  {
+    const float dx = ((float)(V.x0 + px) + 0.5f - V.fcx) * V.inv_fx;
+    const float dy = ((float)(V.y0 + py) + 0.5f - V.fcy) * V.inv_fy;
+    d = mat3_mul(V.Rc, make_float3(dx, dy, 1.0f));
+    const float inv = 1.0f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+    d = make_float3(d.x * inv, d.y * inv, d.z * inv);
+  }
+  const int K = a.K;
+  const float invK = 1.0f / (float)K;
+  const size_t pix = (size_t)gt * TPB + tid;
+  // upstream gradients and the scalar L
+  float3 GC = make_float3(0, 0, 0), GN = make_float3(0, 0, 0);
+  float GD = 0.0f, GT = 0.0f, L = 0.0f;
+  if (valid) {
+    const dv_out_grads& G = a.gin[v];
+    const size_t hw = (size_t)V.w * V.h, o = (size_t)py * V.w + px;
+    if (G.rgb) GC = make_float3(G.rgb[o], G.rgb[hw + o], G.rgb[2 * hw + o]);
+    if (G.depth) GD = G.depth[o];
+    if (NORMALS && G.normal)
+      GN = make_float3(G.normal[o], G.normal[hw + o], G.normal[2 * hw + o]);
+    if (G.T) GT = G.T[o];
+    const float4 f0 = a.fin0[pix], f1 = a.fin1[pix];
+    L = GC.x * f0.x + GC.y * f0.y + GC.z * f0.z + GD * f0.w +
+        GN.x * f1.x + GN.y * f1.y + GN.z * f1.z +
+        (GC.x * a.bg[0] + GC.y * a.bg[1] + GC.z * a.bg[2] + GT) * f1.w;
+  }
+  const uint32_t a_beg = a.act_beg[gt];
+  const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
+  const uint32_t seg0 = 3 * a_beg + n_at;
+  const int nseg = (n_at > 0 && valid) ? (int)a.pix_nseg[pix] : 0;
+  for (int q = 0; q < nseg; ++q)
+    a.seg_bw[seg_index(seg0 + q, tid)] = make_float4(-1.0f, 0.0f, 0.0f, 0.0f);
+
+  // ---------------------------------------------------- B1: background
+  {
+    float T = 1.0f, P = 0.0f;
+    bool done = !valid;
+    int qn = 0;
+    float ns = nseg > 0 ? a.seg_se[seg_index(seg0, tid)].x : F_INF;
+    float excl = -F_INF;
+    const float3 inv = safe_inv(d);
+    const uint32_t beg = a.tile_start[gt], bgend = a.tile_bgend[gt];
+    for (uint32_t base = beg; base < bgend; base += TPB) {
+      const uint32_t nb = min((uint32_t)TPB, bgend - base);
+      load_bwd_batch(B, a, base, nb);
+      __syncthreads();
+      for (uint32_t r = 0; r < nb; ++r) {
+        const float4 geo = B.geo[r];
+        float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
+        float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        bool hit = false;
+        if (!done) {
+          float t0, t1;
+          slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+          t0 = fmaxf(t0, a.tau_near);
+          if (t1 > t0) {
+            float pa = fmaxf(t0, excl);
+            bool a_seg = excl > t0;
+            while (pa < t1 && !done) {
+              if (pa >= ns) {
+                const size_t qi = seg_index(seg0 + qn, tid);
+                const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
+                const float Vq = GC.x * q0.x + GC.y * q0.y + GC.z * q0.z +
+                                 GD * q0.w + GN.x * q1.x + GN.y * q1.y +
+                                 GN.z * q1.z;
+                const float Tpre = T;
+                P = fmaf(T, Vq, P);
+                T *= q1.w;
+                // keep .z: the piece just before may have added dL/dstart
+                float4 bw = a.seg_bw[qi];
+                bw.x = Tpre;
+                bw.y = L - P;
+                a.seg_bw[qi] = bw;
+                const float ex = a.seg_se[qi].y;
+                if (ex > pa) { pa = ex; a_seg = true; }
+                excl = ex;
+                ++qn;
+                ns = qn < nseg ? a.seg_se[seg_index(seg0 + qn, tid)].x : F_INF;
+                if (T < a.eps) done = true;
+                continue;
+              }
+              const bool b_seg = ns < t1;
+              const float pb = fminf(t1, ns);
+              const float4 cn = B.cn[r];
+              const float tau = piece_tau(geo, B.ga[r], B.gb[r], cn.w, d, pa,
+                                          pb, K, invK, a.c, a.inv_c);
+              const float e = fast_exp(-tau);
+              const float wgt = T * (1.0f - e);
+              const float4 nr = B.nrm[r];
+              const float mid = 0.5f * (pa + pb);
+              float vi = GC.x * cn.x + GC.y * cn.y + GC.z * cn.z + GD * mid;
+              if (NORMALS) vi += GN.x * nr.x + GN.y * nr.y + GN.z * nr.z;
+              const float Tn = T * e;
+              P = fmaf(wgt, vi, P);
+              const float dtau = Tn * vi - (L - P);
+              PieceDer pd;
+              if (a_seg || b_seg)
+                piece_der<true>(geo, B.ga[r], B.gb[r], cn.w, d, pa, pb, K, invK,
+                                a.c, a.inv_c, pd);
+              else
+                piece_der<false>(geo, B.ga[r], B.gb[r], cn.w, d, pa, pb, K,
+                                 invK, a.c, a.inv_c, pd);
+              hit = true;
+              dcol.x += wgt * GC.x; dcol.y += wgt * GC.y; dcol.z += wgt * GC.z;
+              if (NORMALS) {
+                dnrm.x += wgt * GN.x; dnrm.y += wgt * GN.y; dnrm.z += wgt * GN.z;
+              }
+#pragma unroll
+              for (int m = 0; m < 8; ++m) dg[m] = fmaf(dtau, pd.dg[m], dg[m]);
+              if (a_seg && qn > 0)
+                a.seg_bw[seg_index(seg0 + qn - 1, tid)].w +=
+                    dtau * pd.dtda + 0.5f * wgt * GD;
+              if (b_seg)
+                a.seg_bw[seg_index(seg0 + qn, tid)].z +=
+                    dtau * pd.dtdb + 0.5f * wgt * GD;
+              T = Tn;
+              if (T < a.eps) done = true;
+              pa = pb;
+              a_seg = false;
+            }
+          }
+        }
+        accum_record<NORMALS>(B, r, hit, dcol, dnrm, dg);
+      }
+      flush_batch(B, a, nb);
+      if (__syncthreads_and(done)) break;
+    }
+    while (!done && qn < nseg) {
+      const size_t qi = seg_index(seg0 + qn, tid);
+      const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
+      const float Vq = GC.x * q0.x + GC.y * q0.y + GC.z * q0.z + GD * q0.w +
+                       GN.x * q1.x + GN.y * q1.y + GN.z * q1.z;
+      const float Tpre = T;
+      P = fmaf(T, Vq, P);
+      T *= q1.w;
+      float4 bw = a.seg_bw[qi];
+      bw.x = Tpre;
+      bw.y = L - P;
+      a.seg_bw[qi] = bw;
+      ++qn;
+      if (T < a.eps) done = true;
+    }
+  }
+
+  // ---------------------------------------------------- B2: actors
+  for (int j = 0; j < n_at; ++j) {
+    // first spliced segment of slot j
+    int q = nseg;
+    for (int i = 0; i < nseg; ++i) {
+      const size_t qi = seg_index(seg0 + i, tid);
+      if ((int)(a.seg_meta[qi] & 0xFF) == j && a.seg_bw[qi].x >= 0.0f) { q = i; break; }
+    }
+    bool has = q < nseg;
+    if (!__syncthreads_or(has)) continue;
+    const uint32_t koct = a.act_oct[a_beg + j];
+    const VOConst& C = a.vo[v * a.n_oct + koct];
+    const float3 dj = mat3_mul(C.Rt, d);
+    const float3 inv = safe_inv(dj);
+    float qs = 0, qe = 0, Tpre = 0, Saft = 0, Vq = 0, Tl = 1.0f, Pl = 0.0f;
+    bool qdone = false;
+    float3 go = make_float3(0, 0, 0), gd = make_float3(0, 0, 0);
+    auto load_q = [&](int qq) {
+      const size_t qi = seg_index(seg0 + qq, tid);
+      const float2 se = a.seg_se[qi];
+      const float4 bw = a.seg_bw[qi];
+      const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
+      qs = se.x; qe = se.y; Tpre = bw.x; Saft = bw.y;
+      Vq = GC.x * q0.x + GC.y * q0.y + GC.z * q0.z + GD * q0.w + GN.x * q1.x +
+           GN.y * q1.y + GN.z * q1.z;
+      Tl = 1.0f; Pl = 0.0f; qdone = false;
+    };
+    auto next_q = [&](int from) {
+      for (int i = from; i < nseg; ++i) {
+        const size_t qi = seg_index(seg0 + i, tid);
+        if ((int)(a.seg_meta[qi] & 0xFF) == j && a.seg_bw[qi].x >= 0.0f) return i;
+      }
+      return nseg;
+    };
+    if (has) load_q(q);
+    const uint2 sub = a.act_sub[a_beg + j];
+    for (uint32_t base = sub.x; base < sub.y; base += TPB) {
+      const uint32_t nb = min((uint32_t)TPB, sub.y - base);
+      load_bwd_batch(B, a, base, nb);
+      __syncthreads();
+      for (uint32_t r = 0; r < nb; ++r) {
+        float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
+        float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        bool hit = false;
+        if (has) {
+          const float4 geo = B.geo[r];
+          float t0, t1;
+          int ax0, ax1;
+          slab_axes(make_float3(geo.x, geo.y, geo.z),
+                    make_float3(geo.x + geo.w, geo.y + geo.w, geo.z + geo.w),
+                    inv, t0, t1, ax0, ax1);
+          if (t1 > t0 && t1 > qs) {
+            while (true) {
+              if (qe <= t0) {
+                q = next_q(q + 1);
+                if (q >= nseg) { has = false; break; }
+                load_q(q);
+                continue;
+              }
+              const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
+              if (pb > pa && !qdone) {
+                const float4 cn = B.cn[r];
+                const float tau = piece_tau(geo, B.ga[r], B.gb[r], cn.w, dj, pa,
+                                            pb, K, invK, a.c, a.inv_c);
+                const float e = fast_exp(-tau);
+                const float wl = Tl * (1.0f - e);
+                const float4 nr = B.nrm[r];
+                const float mid = 0.5f * (pa + pb);
+                float vi = GC.x * cn.x + GC.y * cn.y + GC.z * cn.z + GD * mid;
+                if (NORMALS) vi += GN.x * nr.x + GN.y * nr.y + GN.z * nr.z;
+                const float Tln = Tl * e;
+                Pl = fmaf(wl, vi, Pl);
+                const float dtau = Tpre * Tln * vi - (Tpre * (Vq - Pl) + Saft);
+                const float wt = Tpre * wl;
+                PieceDer pd;
+                piece_der<true>(geo, B.ga[r], B.gb[r], cn.w, dj, pa, pb, K,
+                                invK, a.c, a.inv_c, pd);
+                hit = true;
+                dcol.x += wt * GC.x; dcol.y += wt * GC.y; dcol.z += wt * GC.z;
+                if (NORMALS) {
+                  dnrm.x += wt * GN.x; dnrm.y += wt * GN.y; dnrm.z += wt * GN.z;
+                }
+#pragma unroll
+                for (int m = 0; m < 8; ++m) dg[m] = fmaf(dtau, pd.dg[m], dg[m]);
+                if (a.pose_grad) {
+                  go.x = fmaf(dtau, pd.dx.x, go.x);
+                  go.y = fmaf(dtau, pd.dx.y, go.y);
+                  go.z = fmaf(dtau, pd.dx.z, go.z);
+                  gd.x = fmaf(dtau, pd.dxt.x, gd.x);
+                  gd.y = fmaf(dtau, pd.dxt.y, gd.y);
+                  gd.z = fmaf(dtau, pd.dxt.z, gd.z);
+                  const float ga_ = dtau * pd.dtda + 0.5f * wt * GD;
+                  const float gb_ = dtau * pd.dtdb + 0.5f * wt * GD;
+                  if (qs > t0) {
+                    a.seg_bw[seg_index(seg0 + q, tid)].z += ga_;
+                  } else {
+                    const float di = get_axis(dj, ax0);
+                    add_axis(go, ax0, -ga_ / di);
+                    add_axis(gd, ax0, -ga_ * pa / di);
+                  }
+                  if (qe < t1) {
+                    a.seg_bw[seg_index(seg0 + q, tid)].w += gb_;
+                  } else {
+                    const float di = get_axis(dj, ax1);
+                    add_axis(go, ax1, -gb_ / di);
+                    add_axis(gd, ax1, -gb_ * pb / di);
+                  }
+                }
+                Tl = Tln;
+                if (Tl < a.eps) qdone = true;
+              }
+              if (t1 > qe) { qe = t0; continue; }
+              break;
+            }
+          }
+        }
+        accum_record<NORMALS>(B, r, hit, dcol, dnrm, dg);
+      }
+      flush_batch(B, a, nb);
+      if (!__syncthreads_or(has)) break;
+    }
+    if (a.pose_grad) {
+      float p12[12];
+      pose12(C, d, go, gd, p12);
+      block_add12(red, p12,
+                  a.pose_grad + ((size_t)v * a.n_actors + (koct - 1)) * 12);
+    }
+  }
+
+  // ---------------------------------------------------- B3: box faces
+  if (a.pose_grad) {
+    for (int j = 0; j < n_at; ++j) {
+      const uint32_t koct = a.act_oct[a_beg + j];
+      const VOConst& C = a.vo[v * a.n_oct + koct];
+      const float3 dj = mat3_mul(C.Rt, d);
+      float3 go = make_float3(0, 0, 0), gd = make_float3(0, 0, 0);
+      bool any = false;
+      for (int q = 0; q < nseg; ++q) {
+        const size_t qi = seg_index(seg0 + q, tid);
+        const float4 bw = a.seg_bw[qi];
+        if (bw.x < 0.0f) continue;
+        const uint32_t meta = a.seg_meta[qi];
+        const float2 se = a.seg_se[qi];
+        const uint32_t ss = (meta >> 8) & 0x3FF, se_ = (meta >> 18) & 0x3FF;
+        if (ss != SRC_NONE && (int)(ss >> 2) == j && bw.z != 0.0f) {
+          const int ax = ss & 3;
+          const float di = get_axis(dj, ax);
+          add_axis(go, ax, -bw.z / di);
+          add_axis(gd, ax, -bw.z * se.x / di);
+          any = true;
+        }
+        if (se_ != SRC_NONE && (int)(se_ >> 2) == j && bw.w != 0.0f) {
+          const int ax = se_ & 3;
+          const float di = get_axis(dj, ax);
+          add_axis(go, ax, -bw.w / di);
+          add_axis(gd, ax, -bw.w * se.y / di);
+          any = true;
+        }
+      }
+      if (!__syncthreads_or(any)) continue;
+      float p12[12];
+      pose12(C, d, go, gd, p12);
+      block_add12(red, p12,
+                  a.pose_grad + ((size_t)v * a.n_actors + (koct - 1)) * 12);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ records
+template <bool POSE>
+__global__ void __launch_bounds__(TPB)
+k_record_bwd(int64_t n, const uint32_t* rseg, const uint32_t* rvox,
+             const float4* rgeo, const float4* rcn, const float4* rg8a,
+             const float4* rg8b, const float4* gcol, const float4* gnrm,
+             const float4* gg8a, const float4* gg8b, const OctDev* oct,
+             const OctGrad* og, const VOConst* vo, int n_oct, int n_actors,
+             float* pose_grad, bool normals) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  float p12[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) p12[c] = 0.0f;
+  uint32_t seg = 0xFFFFFFFFu;
+  if (i < n) {
+    seg = rseg[i];
+    const int k = (int)(seg % n_oct);
+    const OctDev& O = oct[k];
+    const OctGrad& G = og[k];
+    const VOConst& C = vo[seg];
+    const uint32_t vox = rvox[i];
+    const int N = O.n_vox;
+    const float4 dc = gcol[i];
+    const float4 cn = rcn[i];
+    const float4 geo = rgeo[i];
+    // direction camera -> leaf centre (octree frame)
+    const float cx = geo.x + 0.5f * geo.w, cy = geo.y + 0.5f * geo.w,
+                cz = geo.z + 0.5f * geo.w;
+    const float rn = sqrtf(cx * cx + cy * cy + cz * cz);
+    const float ir = rn > 0.0f ? 1.0f / rn : 0.0f;
+    const float wx = cx * ir, wy = cy * ir, wz = cz * ir;
+    const float mc[3] = {cn.x > 0.0f ? dc.x : 0.0f, cn.y > 0.0f ? dc.y : 0.0f,
+                         cn.z > 0.0f ? dc.z : 0.0f};
+    const int S = (O.sh_degree + 1) * (O.sh_degree + 1);
+    if (G.sh && (mc[0] != 0.0f || mc[1] != 0.0f || mc[2] != 0.0f)) {
+      float Y[16];
+      sh_basis(O.sh_degree, wx, wy, wz, Y);
+      for (int q = 0; q < S; ++q)
+        for (int ch = 0; ch < 3; ++ch)
+          if (mc[ch] != 0.0f)
+            atomicAdd(G.sh + ((int64_t)q * 3 + ch) * N + vox, Y[q] * mc[ch]);
+    }
+    if (POSE && k > 0 && (mc[0] != 0.0f || mc[1] != 0.0f || mc[2] != 0.0f)) {
+      float gx[16], gy[16], gz[16];
+      sh_basis_grad(O.sh_degree, wx, wy, wz, gx, gy, gz);
+      float dw[3] = {0, 0, 0};
+      for (int q = 0; q < S; ++q) {
+        float s = 0.0f;
+        for (int ch = 0; ch < 3; ++ch)
+          s = fmaf(mc[ch], O.sh[((int64_t)q * 3 + ch) * N + vox], s);
+        dw[0] = fmaf(s, gx[q], dw[0]);
+        dw[1] = fmaf(s, gy[q], dw[1]);
+        dw[2] = fmaf(s, gz[q], dw[2]);
+      }
+      // w = (c - P) / |c - P|:  dL/dP = -(I - w w^T) dw / |c - P|
+      const float pr = dw[0] * wx + dw[1] * wy + dw[2] * wz;
+      const float dP[3] = {-(dw[0] - pr * wx) * ir, -(dw[1] - pr * wy) * ir,
+                           -(dw[2] - pr * wz) * ir};
+      for (int b = 0; b < 3; ++b)
+        for (int a2 = 0; a2 < 3; ++a2) p12[b * 3 + a2] += C.omp[b] * dP[a2];
+      for (int b = 0; b < 3; ++b)
+        p12[9 + b] -= C.R[b * 3 + 0] * dP[0] + C.R[b * 3 + 1] * dP[1] +
+                      C.R[b * 3 + 2] * dP[2];
+    }
+    // corners: density samples plus the normal's dependence
+    const float4 a8 = gg8a[i], b8 = gg8b[i];
+    float dg[8] = {a8.x, a8.y, a8.z, a8.w, b8.x, b8.y, b8.z, b8.w};
+    if (normals) {
+      const float4 gn = gnrm[i];
+      if (gn.x != 0.0f || gn.y != 0.0f || gn.z != 0.0f) {
+        const float4 ga = rg8a[i], gb = rg8b[i];
+        const float g[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+        float vx = 0.25f * ((g[1] - g[0]) + (g[3] - g[2]) + (g[5] - g[4]) + (g[7] - g[6]));
+        float vy = 0.25f * ((g[2] - g[0]) + (g[3] - g[1]) + (g[6] - g[4]) + (g[7] - g[5]));
+        float vz = 0.25f * ((g[4] - g[0]) + (g[5] - g[1]) + (g[6] - g[2]) + (g[7] - g[3]));
+        const float nv = sqrtf(vx * vx + vy * vy + vz * vz);
+        if (nv > 0.0f) {
+          const float nl[3] = {-vx / nv, -vy / nv, -vz / nv};
+          // dL/dn_loc = R^T dL/dn_world
+          float dn[3];
+          for (int a2 = 0; a2 < 3; ++a2)
+            dn[a2] = C.R[0 * 3 + a2] * gn.x + C.R[1 * 3 + a2] * gn.y +
+                     C.R[2 * 3 + a2] * gn.z;
+          const float pr = dn[0] * nl[0] + dn[1] * nl[1] + dn[2] * nl[2];
+          const float dv[3] = {-(dn[0] - pr * nl[0]) / nv,
+                               -(dn[1] - pr * nl[1]) / nv,
+                               -(dn[2] - pr * nl[2]) / nv};
+          for (int m = 0; m < 8; ++m) {
+            const float sx = (m & 1) ? 0.25f : -0.25f;
+            const float sy = (m & 2) ? 0.25f : -0.25f;
+            const float sz = (m & 4) ? 0.25f : -0.25f;
+            dg[m] += sx * dv[0] + sy * dv[1] + sz * dv[2];
+          }
+          if (POSE && k > 0) {
+            const float gw[3] = {gn.x, gn.y, gn.z};
+            for (int a2 = 0; a2 < 3; ++a2)
+              for (int b = 0; b < 3; ++b) p12[a2 * 3 + b] += gw[a2] * nl[b];
+          }
+        }
+      }
+    }
+    if (G.corner) {
+      for (int m = 0; m < 8; ++m)
+        if (dg[m] != 0.0f)
+          atomicAdd(G.corner + O.corner_idx[(int64_t)m * N + vox], dg[m]);
+    }
+  }
+  if (!POSE) return;
+  // pose: wave-reduce when the whole wave shares one (view, actor)
+  const int lane = threadIdx.x & 63;
+  const uint32_t s0 = __shfl(seg, 0, 64);
+  const bool same = __ballot(seg != s0) == 0;
+  if (same) {
+    if (s0 == 0xFFFFFFFFu || (int)(s0 % n_oct) == 0) return;
+    float tot[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) tot[c] = wave_sum(p12[c]);
+    if (lane == 0) {
+      const int v = s0 / n_oct, k = s0 % n_oct;
+      float* dst = pose_grad + ((size_t)v * n_actors + (k - 1)) * 12;
+      for (int c = 0; c < 12; ++c)
+        if (tot[c] != 0.0f) atomicAdd(dst + c, tot[c]);
+    }
+  } else if (seg != 0xFFFFFFFFu && (int)(seg % n_oct) > 0) {
+    const int v = seg / n_oct, k = seg % n_oct;
+    float* dst = pose_grad + ((size_t)v * n_actors + (k - 1)) * 12;
+    for (int c = 0; c < 12; ++c)
+      if (p12[c] != 0.0f) atomicAdd(dst + c, p12[c]);
+  }
+}
+
+}  // namespace dv
+
+using namespace dv;
+
+extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
+                                        const dv_fwd_state* cst,
+                                        const dv_out_grads* g,
+                                        const dv_param_grads* acc,
+                                        void* stream) {
+  if (!ctx || !scene || !cst || !g || !acc || cst->scene != scene) {
+    set_error("dv_render_backward: invalid arguments");
+    return DV_ERR_INVALID;
+  }
+  if (ctx->poisoned) {
+    set_error("dv_render_backward: context poisoned");
+    return DV_ERR_DEVICE;
+  }
+  dv_fwd_state* st = const_cast<dv_fwd_state*>(cst);
+  DV_TRY_HIP(hipSetDevice(ctx->device));
+  reap_states(ctx, false);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nv = st->n_vis, nt = st->n_tiles;
+  const int n_oct = st->n_oct;
+  const bool normals = (st->opts.out_mask & DV_OUT_NORMAL) != 0;
+  // per-view upstream gradients and per-octree accumulators
+  st->grads_keep.emplace_back(g, g + st->n_views);
+  st->og_keep.emplace_back(n_oct);
+  std::vector<OctGrad>& og = st->og_keep.back();
+  for (int k = 0; k < n_oct; ++k) {
+    og[k].corner = acc->octrees ? acc->octrees[k].corner : nullptr;
+    og[k].sh = acc->octrees ? acc->octrees[k].sh : nullptr;
+  }
+  DBuf gin, ogd, gcol, gnrm, gg8a, gg8b, segbw;
+  DV_TRY(alloc_n<dv_out_grads>(ctx, gin, st->n_views, s));
+  DV_TRY(alloc_n<OctGrad>(ctx, ogd, n_oct, s));
+  DV_TRY_HIP(hipMemcpyAsync(gin.p, st->grads_keep.back().data(),
+                            sizeof(dv_out_grads) * st->n_views,
+                            hipMemcpyHostToDevice, s));
+  DV_TRY_HIP(hipMemcpyAsync(ogd.p, og.data(), sizeof(OctGrad) * n_oct,
+                            hipMemcpyHostToDevice, s));
+  DV_TRY(alloc_n<float4>(ctx, gcol, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, gnrm, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, gg8a, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, gg8b, nv, s));
+  DV_TRY(fill_f32(gcol.as<float>(), 0.0f, 4 * nv, s));
+  DV_TRY(fill_f32(gnrm.as<float>(), 0.0f, 4 * nv, s));
+  DV_TRY(fill_f32(gg8a.as<float>(), 0.0f, 4 * nv, s));
+  DV_TRY(fill_f32(gg8b.as<float>(), 0.0f, 4 * nv, s));
+  const size_t nslots = (size_t)3 * st->n_apairs * TPB;
+  DV_TRY(alloc_n<float4>(ctx, segbw, nslots, s));
+  CompArgs ca;
+  std::memset(&ca, 0, sizeof(ca));
+  ca.views = st->views_d.as<ViewConst>();
+  ca.vo = st->vo_d.as<VOConst>();
+  ca.n_views = st->n_views;
+  ca.n_oct = n_oct;
+  ca.tile_start = st->tile_start.as<uint32_t>();
+  ca.tile_end = st->tile_end.as<uint32_t>();
+  ca.tile_bgend = st->tile_bgend.as<uint32_t>();
+  ca.pair_val = st->pair_val.as<uint32_t>();
+  ca.rec_geo = st->rec_geo.as<float4>();
+  ca.rec_g8a = st->rec_g8a.as<float4>();
+  ca.rec_g8b = st->rec_g8b.as<float4>();
+  ca.rec_cn = st->rec_cn.as<float4>();
+  ca.rec_nrm = st->rec_nrm.as<float4>();
+  ca.act_beg = st->act_beg.as<uint32_t>();
+  ca.act_oct = st->act_oct.as<uint32_t>();
+  ca.act_sub = st->act_sub.as<uint2>();
+  ca.seg_se = st->seg_se.as<float2>();
+  ca.seg_meta = st->seg_meta.as<uint32_t>();
+  ca.seg_p0 = st->seg_p0.as<float4>();
+  ca.seg_p1 = st->seg_p1.as<float4>();
+  ca.seg_bw = segbw.as<float4>();
+  ca.pix_nseg = st->pix_nseg.as<uint32_t>();
+  ca.fin0 = st->fin0.as<float4>();
+  ca.fin1 = st->fin1.as<float4>();
+  ca.gin = gin.as<dv_out_grads>();
+  ca.gr_col = gcol.as<float4>();
+  ca.gr_nrm = gnrm.as<float4>();
+  ca.gr_g8a = gg8a.as<float4>();
+  ca.gr_g8b = gg8b.as<float4>();
+  ca.pose_grad = st->n_actors > 0 ? acc->pose : nullptr;
+  ca.n_actors = st->n_actors;
+  const dv_render_opts& op = st->opts;
+  ca.K = op.K;
+  ca.eps = op.eps_stop;
+  ca.tau_near = op.tau_near;
+  ca.c = op.explin_c;
+  ca.inv_c = 1.0f / op.explin_c;
+  for (int i = 0; i < 3; ++i) ca.bg[i] = op.bg[i];
+  ca.mask = op.out_mask;
+  if (nt > 0) {
+    if (normals)
+      hipLaunchKernelGGL(k_composite_bwd<true>, dim3((unsigned)nt), dim3(TPB),
+                         0, s, ca);
+    else
+      hipLaunchKernelGGL(k_composite_bwd<false>, dim3((unsigned)nt), dim3(TPB),
+                         0, s, ca);
+    DV_TRY_HIP(hipGetLastError());
+  }
+  if (nv > 0) {
+    if (ca.pose_grad)
+      hipLaunchKernelGGL(k_record_bwd<true>, dim3(grid_for(nv, TPB)), dim3(TPB),
+                         0, s, nv, st->rec_seg.as<uint32_t>(),
+                         st->rec_vox.as<uint32_t>(), st->rec_geo.as<float4>(),
+                         st->rec_cn.as<float4>(), st->rec_g8a.as<float4>(),
+                         st->rec_g8b.as<float4>(), gcol.as<float4>(),
+                         gnrm.as<float4>(), gg8a.as<float4>(), gg8b.as<float4>(),
+                         scene->oct_dev.as<OctDev>(), ogd.as<OctGrad>(),
+                         st->vo_d.as<VOConst>(), n_oct, st->n_actors,
+                         ca.pose_grad, normals);
+    else
+      hipLaunchKernelGGL(k_record_bwd<false>, dim3(grid_for(nv, TPB)), dim3(TPB),
+                         0, s, nv, st->rec_seg.as<uint32_t>(),
+                         st->rec_vox.as<uint32_t>(), st->rec_geo.as<float4>(),
+                         st->rec_cn.as<float4>(), st->rec_g8a.as<float4>(),
+                         st->rec_g8b.as<float4>(), gcol.as<float4>(),
+                         gnrm.as<float4>(), gg8a.as<float4>(), gg8b.as<float4>(),
+                         scene->oct_dev.as<OctDev>(), ogd.as<OctGrad>(),
+                         st->vo_d.as<VOConst>(), n_oct, st->n_actors,
+                         (float*)nullptr, normals);
+    DV_TRY_HIP(hipGetLastError());
+  }
+  return DV_OK;
+}

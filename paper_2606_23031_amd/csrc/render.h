@@ -146,6 +146,71 @@ __device__ inline float piece_tau(float4 geo, float4 ga, float4 gb,
   return sum * step;
 }
 
+// Real spherical harmonics up to degree 3 (Sec. 3.1 view-dependent
+// colour), orthonormal, with Y_{1,-1}, Y_{1,0}, Y_{1,1} proportional to
+// y, z, x.  Coefficients are SoA [S][3][N].
+__device__ inline void sh_basis(int deg, float x, float y, float z,
+                                float* Y) {
+  Y[0] = 0.28209479177387814f;
+  if (deg < 1) return;
+  Y[1] = 0.4886025119029199f * y;
+  Y[2] = 0.4886025119029199f * z;
+  Y[3] = 0.4886025119029199f * x;
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = 1.0925484305920792f * (x * y);
+  Y[5] = 1.0925484305920792f * (y * z);
+  Y[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
+  Y[7] = 1.0925484305920792f * (x * z);
+  Y[8] = 0.5462742152960396f * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = 0.5900435899266435f * y * (3.0f * xx - yy);
+  Y[10] = 2.890611442640554f * (x * y * z);
+  Y[11] = 0.4570457994644658f * y * (5.0f * zz - 1.0f);
+  Y[12] = 0.3731763325901154f * z * (5.0f * zz - 3.0f);
+  Y[13] = 0.4570457994644658f * x * (5.0f * zz - 1.0f);
+  Y[14] = 1.445305721320277f * z * (xx - yy);
+  Y[15] = 0.5900435899266435f * x * (xx - 3.0f * yy);
+}
+
+// d Y_q / d(x, y, z) of the polynomials above (unit-sphere restriction is
+// applied by the caller).
+__device__ inline void sh_basis_grad(int deg, float x, float y, float z,
+                                     float* gx, float* gy, float* gz) {
+  gx[0] = gy[0] = gz[0] = 0.0f;
+  if (deg < 1) return;
+  const float c1 = 0.4886025119029199f;
+  gx[1] = 0.0f; gy[1] = c1;  gz[1] = 0.0f;
+  gx[2] = 0.0f; gy[2] = 0.0f; gz[2] = c1;
+  gx[3] = c1;  gy[3] = 0.0f; gz[3] = 0.0f;
+  if (deg < 2) return;
+  const float a = 1.0925484305920792f, b = 0.31539156525252005f,
+              c = 0.5462742152960396f;
+  gx[4] = a * y; gy[4] = a * x; gz[4] = 0.0f;
+  gx[5] = 0.0f;  gy[5] = a * z; gz[5] = a * y;
+  gx[6] = 0.0f;  gy[6] = 0.0f;  gz[6] = 6.0f * b * z;
+  gx[7] = a * z; gy[7] = 0.0f;  gz[7] = a * x;
+  gx[8] = 2.0f * c * x; gy[8] = -2.0f * c * y; gz[8] = 0.0f;
+  if (deg < 3) return;
+  const float e = 0.5900435899266435f, f = 2.890611442640554f,
+              g = 0.4570457994644658f, h = 0.3731763325901154f,
+              i = 1.445305721320277f;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  gx[9] = 6.0f * e * x * y; gy[9] = e * (3.0f * xx - 3.0f * yy); gz[9] = 0.0f;
+  gx[10] = f * y * z; gy[10] = f * x * z; gz[10] = f * x * y;
+  gx[11] = 0.0f; gy[11] = g * (5.0f * zz - 1.0f); gz[11] = 10.0f * g * y * z;
+  gx[12] = 0.0f; gy[12] = 0.0f; gz[12] = h * (15.0f * zz - 3.0f);
+  gx[13] = g * (5.0f * zz - 1.0f); gy[13] = 0.0f; gz[13] = 10.0f * g * x * z;
+  gx[14] = 2.0f * i * x * z; gy[14] = -2.0f * i * y * z; gz[14] = i * (xx - yy);
+  gx[15] = e * (3.0f * xx - 3.0f * yy); gy[15] = -6.0f * e * x * y; gz[15] = 0.0f;
+}
+
+// Gradient accumulators of one octree (device pointers).
+struct OctGrad {
+  float* corner;
+  float* sh;
+};
+
 // Per-pixel segment scratch: slot s of tile gt, pixel tid.
 __device__ inline size_t seg_index(uint32_t slot, int tid) {
   return (size_t)slot * TPB + tid;
@@ -166,7 +231,10 @@ struct dv_fwd_state {
   int key_bits = 0, tile_bits = 0, rank_bits = 0;
   std::vector<uint32_t> act_beg_h, act_oct_h, act_tile_h;
   std::vector<int64_t> seg_start_h;
-  std::vector<dv_out_grads> grads_h;
+  // host copies uploaded asynchronously by backward calls; kept until the
+  // state is retired (after its stream has passed them)
+  std::vector<std::vector<dv_out_grads>> grads_keep;
+  std::vector<std::vector<dv::OctGrad>> og_keep;
   dv::DBuf views_d, vo_d, outs_d;
   dv::DBuf rec_geo, rec_g8a, rec_g8b, rec_cn, rec_nrm, rec_vox, rec_seg;
   dv::DBuf pair_val;

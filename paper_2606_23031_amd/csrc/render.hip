@@ -9,34 +9,6 @@
 
 namespace dv {
 
-// ------------------------------------------------------------------ SH
-// Real spherical harmonics up to degree 3 (Sec. 3.1 view-dependent
-// colour), orthonormal, with Y_{1,-1}, Y_{1,0}, Y_{1,1} proportional to
-// y, z, x.  Coefficients are SoA [S][3][N].
-__device__ inline void sh_basis(int deg, float x, float y, float z,
-                                float* Y) {
-  Y[0] = 0.28209479177387814f;
-  if (deg < 1) return;
-  Y[1] = 0.4886025119029199f * y;
-  Y[2] = 0.4886025119029199f * z;
-  Y[3] = 0.4886025119029199f * x;
-  if (deg < 2) return;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  Y[4] = 1.0925484305920792f * (x * y);
-  Y[5] = 1.0925484305920792f * (y * z);
-  Y[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
-  Y[7] = 1.0925484305920792f * (x * z);
-  Y[8] = 0.5462742152960396f * (xx - yy);
-  if (deg < 3) return;
-  Y[9] = 0.5900435899266435f * y * (3.0f * xx - yy);
-  Y[10] = 2.890611442640554f * (x * y * z);
-  Y[11] = 0.4570457994644658f * y * (5.0f * zz - 1.0f);
-  Y[12] = 0.3731763325901154f * z * (5.0f * zz - 3.0f);
-  Y[13] = 0.4570457994644658f * x * (5.0f * zz - 1.0f);
-  Y[14] = 1.445305721320277f * z * (xx - yy);
-  Y[15] = 0.5900435899266435f * x * (xx - 3.0f * yy);
-}
-
 // ------------------------------------------------------------------ binning
 // Tile rectangle of a box (contract: FP64, fixed operation order, no
 // contraction).  status 0 culled, 1 rectangle, 2 whole window.

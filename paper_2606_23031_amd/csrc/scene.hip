@@ -9,15 +9,15 @@
 
 namespace dv {
 
-// Interleave the low 16 bits of x, y, z (x lowest) into a 48-bit code.
-static uint64_t spread3(uint64_t v) {
-  v &= 0xFFFF;
-  v = (v | (v << 32)) & 0x0000FFFF0000FFFFull;
-  v = (v | (v << 16)) & 0x00FF0000FF0000FFull;
-  v = (v | (v << 8)) & 0xF00F00F00F00F00Full;
-  v = (v | (v << 4)) & 0x30C30C30C30C30C3ull;
-  v = (v | (v << 2)) & 0x9249249249249249ull;
-  return v;
+// Interleave the low 21 bits of x, y, z (x lowest) into a 63-bit code.
+static uint64_t spread3(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | x << 32) & 0x1f00000000ffffull;
+  x = (x | x << 16) & 0x1f0000ff0000ffull;
+  x = (x | x << 8) & 0x100f00f00f00f00full;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+  x = (x | x << 2) & 0x1249249249249249ull;
+  return x;
 }
 
 static dv_status validate(const uint8_t* level, const int32_t* ijk,

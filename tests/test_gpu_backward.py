@@ -1,0 +1,99 @@
+"""GPU backward parity against the oracle's FP64 adjoint (itself pinned to
+central differences), through the C ABI.
+
+Bar (gradient reading): per gradient tensor, elementwise
+|g - g_ref| <= 1e-3 * max(|g_ref|, 1e-2 * max|g_ref|).  eps_stop = 0 so
+both sides differentiate the same pieces.
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint as AD
+from oracle import render as RD
+from scenes import actor_scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from gpu_helpers import gpu_ctx
+    return gpu_ctx()
+
+
+def _close(name, g, ref, rel=1e-3, floor=1e-2):
+    g = np.asarray(g, np.float64)
+    ref = np.asarray(ref, np.float64)
+    scale = np.abs(ref).max()
+    if scale == 0.0:
+        assert np.abs(g).max() == 0.0, name
+        return
+    bound = rel * np.maximum(np.abs(ref), floor * scale)
+    err = np.abs(g - ref)
+    worst = float((err / bound).max())
+    print(f"  {name}: max|ref| {scale:.3e} worst err/bound {worst:.3f}")
+    assert np.all(err <= bound), (name, worst)
+
+
+def _run(ctx, cfg, mask_normals=True, seed=0, pose=True):
+    import torch
+    from paper_2606_23031_amd import dv
+    scene, view, opts = cfg["scene"], cfg["views"][0], cfg["opts"]
+    mask = dv.DV_OUT_RGB | dv.DV_OUT_DEPTH | dv.DV_OUT_T
+    if mask_normals:
+        mask |= dv.DV_OUT_NORMAL
+    sc = dv.Scene(ctx, scene)
+    outs = dv.alloc_outputs([view], mask)
+    st = dv.dv_render(ctx, sc, [view], dv.make_opts(opts, mask), outs, keep=True)
+    rng = np.random.default_rng(seed)
+    h, w = view["h"], view["w"]
+    G = dict(rgb=rng.normal(size=(3, h, w)), depth=rng.normal(size=(h, w)) * 0.3,
+             normal=rng.normal(size=(3, h, w)) if mask_normals else np.zeros((3, h, w)),
+             T=rng.normal(size=(h, w)))
+    gt = {k: torch.tensor(v, dtype=torch.float32, device="cuda") for k, v in G.items()}
+    if not mask_normals:
+        gt["normal"] = None
+    acc = [dict(corner=torch.zeros(len(o["corner_density"]), device="cuda"),
+                sh=torch.zeros(o["sh"].shape, device="cuda"))
+           for o in scene["octrees"]]
+    na = len(scene["octrees"]) - 1
+    pg = torch.zeros(1, max(na, 1), 12, device="cuda") if pose else None
+    dv.dv_render_backward(ctx, sc, st, [gt], acc, pg)
+    torch.cuda.synchronize()
+    dv.dv_fwd_state_release(st)
+    # oracle
+    pix = RD.window_pixels(view)
+    gy, gx = pix[:, 1] - view["y0"], pix[:, 0] - view["x0"]
+    grads = np.zeros((len(pix), 8))
+    g32 = {k: v.astype(np.float32).astype(np.float64) for k, v in G.items()}
+    grads[:, 0:3] = g32["rgb"][:, gy, gx].T
+    grads[:, 3] = g32["depth"][gy, gx]
+    grads[:, 4:7] = g32["normal"][:, gy, gx].T
+    grads[:, 7] = g32["T"][gy, gx]
+    _, ref = AD.render_and_grad(scene, view, opts, grads, pix)
+    return acc, pg, ref, sc
+
+
+@pytest.mark.parametrize("seed,K,overlap,normals", [
+    (0, 1, False, True), (1, 2, False, True), (2, 1, True, True),
+    (3, 1, False, False)])
+def test_backward_matches_oracle_adjoint(ctx, seed, K, overlap, normals):
+    cfg = actor_scene(seed=seed, n_actors=3 if overlap else 2, deg=2,
+                      overlap=overlap, K=K)
+    acc, pg, ref, _ = _run(ctx, cfg, mask_normals=normals, seed=seed)
+    for k in range(len(acc)):
+        _close(f"corner[{k}]", acc[k]["corner"].cpu().numpy(), ref["corner"][k])
+        _close(f"sh[{k}]", acc[k]["sh"].cpu().numpy(), ref["sh"][k])
+    p = pg.cpu().numpy()[0]
+    for i in range(len(acc) - 1):
+        _close(f"dR[{i}]", p[i, :9].reshape(3, 3), ref["dR"][i + 1])
+        _close(f"dp[{i}]", p[i, 9:], ref["dp"][i + 1])
+
+
+def test_backward_without_pose_buffer(ctx):
+    cfg = actor_scene(seed=4, n_actors=2, deg=1)
+    acc, _, ref, _ = _run(ctx, cfg, seed=4, pose=False)
+    for k in range(len(acc)):
+        _close(f"corner[{k}]", acc[k]["corner"].cpu().numpy(), ref["corner"][k])
