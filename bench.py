@@ -1,0 +1,267 @@
+"""Benchmark: one training step of the compositional renderer on one MI355X.
+
+A step is the whole hot path over one batch: forward render of the
+driving workload (1M-leaf static octree + 8 car octrees of ~20k leaves,
+one 1920x1080 camera; preprocessing, binning, sorts, directories and the
+multi-octree compositing walk), an L1 loss against a random target, and the
+hand-written backward to corner densities, SH coefficients and actor poses.
+Inputs are synthetic and resident in HBM before timing starts.
+
+Prints one JSON line (metric, value, roofline of the dominant kernel,
+CPU-oracle baseline).  ``--gpus`` above 1 is not supported: this build
+runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
+PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (published)
+
+# Algorithmic FLOPs (FMA = 2) of the compositing walks, K = 1:
+#   per (pixel, list entry) slab test           21
+#   per piece, forward (optical depth 49,
+#     compositing 22)                            71
+#   per piece, backward (re-evaluation 71,
+#     derivatives w.r.t. corners/geometry 90)   161
+FLOP_TEST = 21
+FLOP_PIECE_FWD = 71
+FLOP_PIECE_BWD = 161
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--v-close", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-steps", type=int, default=3)
+    return ap.parse_args()
+
+
+class Step:
+    """Forward + L1 loss gradient + backward for one batch of views."""
+
+    def __init__(self, ctx, dv, scene_dict, views, opts):
+        import torch
+        self.torch, self.dv, self.ctx = torch, dv, ctx
+        self.views = views
+        self.mask = dv.DV_OUT_RGB | dv.DV_OUT_DEPTH | dv.DV_OUT_T
+        self.copts = dv.make_opts(opts, self.mask)
+        self.sc = dv.Scene(ctx, scene_dict)
+        self.outs = dv.alloc_outputs(views, self.mask)
+        g = torch.Generator(device="cpu").manual_seed(1234)
+        self.targets = [torch.rand(3, v["h"], v["w"], generator=g).cuda()
+                        for v in views]
+        self.grads = [dict(rgb=torch.zeros(3, v["h"], v["w"], device="cuda"))
+                      for v in views]
+        self.acc = [dict(corner=torch.zeros(len(o["corner_density"]), device="cuda"),
+                         sh=torch.zeros(o["sh"].shape, device="cuda"))
+                    for o in scene_dict["octrees"]]
+        na = len(scene_dict["octrees"]) - 1
+        self.pose = torch.zeros(len(views), max(na, 1), 12, device="cuda")
+        self.npix = sum(v["w"] * v["h"] for v in views)
+        self.last_info = None
+
+    def __call__(self, info=False):
+        torch, dv = self.torch, self.dv
+        st = dv.dv_render(self.ctx, self.sc, self.views, self.copts, self.outs,
+                          keep=True)
+        # L1 loss: d/d rgb of mean |rgb - target|
+        for o, t, g in zip(self.outs, self.targets, self.grads):
+            torch.sign(o["rgb"] - t, out=g["rgb"])
+            g["rgb"].mul_(1.0 / self.npix / 3.0)
+        for a in self.acc:
+            a["corner"].zero_()
+            a["sh"].zero_()
+        self.pose.zero_()
+        dv.dv_render_backward(self.ctx, self.sc, st, self.grads, self.acc,
+                              self.pose)
+        if info:
+            self.last_info = dv.dv_fwd_state_info(st)
+        dv.dv_fwd_state_release(st)
+
+
+def cpu_baseline(cfg, budget_s):
+    """Time the FP64 oracle (forward + adjoint) on a strided pixel sample."""
+    import multiprocessing as mp
+    from oracle import adjoint as AD
+    from oracle import render as RD
+    scene, view, opts = cfg["scene"], cfg["views"][0], cfg["opts"]
+    procs = RD.default_procs()
+    t0 = time.time()
+    ctx = RD.ViewContext(scene, view, opts)
+    t_ctx = time.time() - t0
+    rng = np.random.default_rng(0)
+    # estimate the cost of one ray, then size the sample to the budget
+    probe = RD.window_pixels(view)[::97][:4]
+    t0 = time.time()
+    _work(ctx, probe, rng.normal(size=(len(probe), 8)))
+    per_ray = (time.time() - t0) / len(probe)
+    n = int(max(procs, min(4096, budget_s * procs / max(per_ray, 1e-6))))
+    stride = max(1, int(np.sqrt(view["w"] * view["h"] / n)))
+    pix = RD.window_pixels(dict(view, w=view["w"] // stride * stride,
+                                h=view["h"] // stride * stride))
+    pix = pix[(pix[:, 0] % stride == 0) & (pix[:, 1] % stride == 0)][:n]
+    grads = rng.normal(size=(len(pix), 8))
+    global _CTX
+    _CTX = ctx
+    chunks = np.array_split(np.arange(len(pix)), procs * 2)
+    t0 = time.time()
+    with mp.get_context("fork").Pool(procs) as pool:
+        pool.map(_pool_work, [(pix[c], grads[c]) for c in chunks])
+    dt = time.time() - t0
+    return dict(value=len(pix) / dt / 1e6, unit="Mpix/s", cores=procs,
+                kind="oracle",
+                sample=f"{len(pix)} rays (every {stride}th row/column of the "
+                       f"1920x1080 view), FP64 forward+adjoint, "
+                       f"{dt:.1f}s wall; per-view setup {t_ctx:.1f}s excluded")
+
+
+_CTX = None
+
+
+def _work(ctx, pix, grads):
+    from oracle import adjoint as AD
+    from oracle import geometry as G
+    acc = AD.new_accumulators(ctx)
+    for (px, py), g in zip(pix, grads):
+        o, d = G.camera_ray(ctx.view, px, py)
+        AD.ray_adjoint(ctx, o, d, g[0:3], g[3], g[4:7], g[7], acc)
+    return 0
+
+
+def _pool_work(arg):
+    return _work(_CTX, arg[0], arg[1])
+
+
+def roofline(stage, ms, calls, info, counters, scene_stats):
+    """Roofline entry for the dominant stage (per launch)."""
+    per = ms / max(calls, 1) / 1e3   # seconds per launch
+    if stage in ("composite_fwd", "composite_bwd"):
+        if stage == "composite_fwd":
+            flops = FLOP_TEST * counters["entries_fwd"] + FLOP_PIECE_FWD * counters["pieces_fwd"]
+        else:
+            flops = FLOP_TEST * counters["entries_bwd"] + FLOP_PIECE_BWD * counters["pieces_bwd"]
+        ach = flops / per / 1e12
+        return dict(bound="alu", achieved=ach, peak=PEAK_FP32_TFLOPS,
+                    unit="TFLOP/s", frac=ach / PEAK_FP32_TFLOPS, traffic=None,
+                    kernel=stage, flops_per_launch=flops)
+    nv, npairs = info["n_visible"], info["n_pairs"]
+    if stage == "sort_pairs":
+        passes = (info["tile_bits"] + 7) // 8
+        byts = npairs * 16 * passes
+    elif stage == "sort_records":
+        passes = (info["key_bits"] + 7) // 8
+        byts = nv * 24 * passes
+    elif stage == "preprocess":
+        byts = scene_stats["items"] * 8 * 2 + nv * (64 + 12 * scene_stats["S"] + 112)
+    elif stage == "emit_pairs":
+        byts = npairs * 8 + nv * 12
+    else:
+        byts = nv * 16
+    ach = byts / per / 1e9
+    return dict(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=ach / PEAK_HBM_GBS, traffic=None, kernel=stage,
+                bytes_per_launch=byts)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this renderer "
+              "runs on one GPU (see the sharding design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2606_23031_amd import dv
+    from synth import make_config
+    t0 = time.time()
+    cfg = make_config(args.config, v_close=args.v_close)
+    views = cfg["views"]
+    log(f"[bench] generated {cfg['name']} in {time.time() - t0:.1f}s: "
+        f"{cfg['info']['n_total']} leaves, {len(views)} view(s)")
+    ctx = dv.dv_ctx_create(0)
+    step = Step(ctx, dv, cfg["scene"], views, cfg["opts"])
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        step(info=(i == 0))
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done; info {step.last_info}")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt / args.steps * 1e3
+    value = step.npix / (dt / args.steps) / 1e6
+    log(f"[bench] timed {args.steps} steps: {ms:.3f} ms/step, {value:.1f} Mpix/s")
+    # per-stage device times (HIP events on the stream of each kernel)
+    dv.dv_ctx_set_profiling(ctx, dv.PROFILE_EVENTS)
+    dv.dv_ctx_stage_times(ctx, reset=True)
+    for _ in range(args.profile_steps):
+        step()
+    torch.cuda.synchronize()
+    stages = dv.dv_ctx_stage_times(ctx, reset=True)
+    counters = stages.pop("_counters")
+    # work counters in a separate, untimed step
+    dv.dv_ctx_set_profiling(ctx, dv.PROFILE_COUNTERS)
+    step()
+    torch.cuda.synchronize()
+    counters = dv.dv_ctx_stage_times(ctx, reset=True)["_counters"]
+    dv.dv_ctx_set_profiling(ctx, 0)
+    stage_avg = {k: (v[0] / max(v[1], 1)) for k, v in stages.items() if v[1] > 0}
+    dom = max((k for k in stage_avg if k not in ("host_sync", "other")),
+              key=lambda k: stages[k][0])
+    S = max((o["sh_degree"] + 1) ** 2 for o in cfg["scene"]["octrees"])
+    items = sum(len(o["level"]) for o in cfg["scene"]["octrees"]) * len(views)
+    rl = roofline(dom, stages[dom][0], stages[dom][1], step.last_info, counters,
+                  dict(items=items, S=S))
+    out = {
+        "metric": "fwd+bwd Mpix/s per train step",
+        "value": round(value, 3),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "pixels_per_step": step.npix,
+                   "leaves": int(cfg["info"]["n_total"]),
+                   "actors": len(cfg["scene"]["octrees"]) - 1,
+                   "v_close": args.v_close, "K": cfg["opts"]["K"],
+                   "eps_stop": cfg["opts"]["eps_stop"],
+                   "n_visible": step.last_info["n_visible"],
+                   "n_pairs": step.last_info["n_pairs"],
+                   "work": counters},
+        "roofline": rl,
+        "stages_ms_per_step": {k: round(v[0] / args.profile_steps, 4)
+                               for k, v in stages.items() if v[1] > 0},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

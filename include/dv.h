@@ -169,6 +169,29 @@ const char* dv_last_error(void);
 /* Library version string. */
 const char* dv_version(void);
 
+/* Per-stage device timing (HIP events on the caller's stream) and work
+ * counters of the compositing kernels.  Enable with
+ * dv_ctx_set_profiling(ctx, flags): bit 0 records events around every
+ * stage, bit 1 counts the (pixel, list entry) tests and pieces composited
+ * by the walks (one wave-reduced atomic per wave; costs a few percent, so
+ * time without it).  dv_ctx_stage_times synchronises the recorded events,
+ * adds their durations and optionally resets. */
+#define DV_PROFILE_EVENTS 1
+#define DV_PROFILE_COUNTERS 2
+#define DV_NUM_STAGES 12
+typedef struct {
+  double ms[DV_NUM_STAGES];     /* summed device time per stage            */
+  int64_t calls[DV_NUM_STAGES]; /* number of timed intervals               */
+  int64_t entries_fwd;          /* (pixel, entry) slab tests, forward      */
+  int64_t pieces_fwd;           /* pieces composited, forward              */
+  int64_t entries_bwd;          /* same, backward re-walk                  */
+  int64_t pieces_bwd;
+} dv_stage_times;
+dv_status dv_ctx_set_profiling(dv_ctx* ctx, int32_t flags);
+dv_status dv_ctx_stage_times(dv_ctx* ctx, dv_stage_times* out, int32_t reset);
+/* Name of stage i (0 <= i < DV_NUM_STAGES), e.g. "composite_fwd". */
+const char* dv_stage_name(int32_t i);
+
 /* ---------------------------------------------------------------- scene */
 /* Validate and index a scene: octrees[0] is the background O_bg,
  * octrees[1..] are actors with tracks[i-1] (Sec. 3.1-3.2; App. A inputs).

@@ -219,6 +219,7 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
   const int K = a.K;
   const float invK = 1.0f / (float)K;
   const size_t pix = (size_t)gt * TPB + tid;
+  uint32_t n_test = 0, n_piece = 0;
   // upstream gradients and the scalar L
   float3 GC = make_float3(0, 0, 0), GN = make_float3(0, 0, 0);
   float GD = 0.0f, GT = 0.0f, L = 0.0f;
@@ -263,6 +264,7 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
         if (!done) {
           float t0, t1;
           slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+          ++n_test;
           t0 = fmaxf(t0, a.tau_near);
           if (t1 > t0) {
             float pa = fmaxf(t0, excl);
@@ -295,6 +297,7 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
               const float4 cn = B.cn[r];
               const float tau = piece_tau(geo, B.ga[r], B.gb[r], cn.w, d, pa,
                                           pb, K, invK, a.c, a.inv_c);
+              ++n_piece;
               const float e = fast_exp(-tau);
               const float wgt = T * (1.0f - e);
               const float4 nr = B.nrm[r];
@@ -404,6 +407,7 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
           slab_axes(make_float3(geo.x, geo.y, geo.z),
                     make_float3(geo.x + geo.w, geo.y + geo.w, geo.z + geo.w),
                     inv, t0, t1, ax0, ax1);
+          ++n_test;
           if (t1 > t0 && t1 > qs) {
             while (true) {
               if (qe <= t0) {
@@ -417,6 +421,7 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
                 const float4 cn = B.cn[r];
                 const float tau = piece_tau(geo, B.ga[r], B.gb[r], cn.w, dj, pa,
                                             pb, K, invK, a.c, a.inv_c);
+                ++n_piece;
                 const float e = fast_exp(-tau);
                 const float wl = Tl * (1.0f - e);
                 const float4 nr = B.nrm[r];
@@ -481,6 +486,8 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
                   a.pose_grad + ((size_t)v * a.n_actors + (koct - 1)) * 12);
     }
   }
+
+  count_work(a.counters, 2, n_test, n_piece);
 
   // ---------------------------------------------------- B3: box faces
   if (a.pose_grad) {
@@ -696,6 +703,7 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   DV_TRY(alloc_n<float4>(ctx, gnrm, nv, s));
   DV_TRY(alloc_n<float4>(ctx, gg8a, nv, s));
   DV_TRY(alloc_n<float4>(ctx, gg8b, nv, s));
+  StageTimer tm_clear(ctx, ST_BWD_CLEAR, s);
   DV_TRY(fill_f32(gcol.as<float>(), 0.0f, 4 * nv, s));
   DV_TRY(fill_f32(gnrm.as<float>(), 0.0f, 4 * nv, s));
   DV_TRY(fill_f32(gg8a.as<float>(), 0.0f, 4 * nv, s));
@@ -743,6 +751,9 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   ca.inv_c = 1.0f / op.explin_c;
   for (int i = 0; i < 3; ++i) ca.bg[i] = op.bg[i];
   ca.mask = op.out_mask;
+  ca.counters = (ctx->prof_flags.load() & DV_PROFILE_COUNTERS) ? ctx->counters : nullptr;
+  tm_clear.stop();
+  StageTimer tm_comp(ctx, ST_COMPOSITE_BWD, s);
   if (nt > 0) {
     if (normals)
       hipLaunchKernelGGL(k_composite_bwd<true>, dim3((unsigned)nt), dim3(TPB),
@@ -752,6 +763,8 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
                          0, s, ca);
     DV_TRY_HIP(hipGetLastError());
   }
+  tm_comp.stop();
+  StageTimer tm_rec(ctx, ST_RECORD_BWD, s);
   if (nv > 0) {
     if (ca.pose_grad)
       hipLaunchKernelGGL(k_record_bwd<true>, dim3(grid_for(nv, TPB)), dim3(TPB),

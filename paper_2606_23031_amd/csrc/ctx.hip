@@ -140,6 +140,33 @@ dv_status fill_f32(float* p, float v, int64_t n, hipStream_t s) {
   return fill_u32(reinterpret_cast<uint32_t*>(p), bits, n, s);
 }
 
+StageTimer::StageTimer(dv_ctx* c, int st, hipStream_t strm)
+    : ctx(c), stage(st), s(strm) {
+  if (!(ctx->prof_flags.load() & DV_PROFILE_EVENTS)) return;
+  if (hipEventCreate(&a) != hipSuccess || hipEventRecord(a, s) != hipSuccess) {
+    (void)hipGetLastError();
+    a = nullptr;
+  }
+}
+
+void StageTimer::stop() {
+  if (!a) return;
+  hipEvent_t b = nullptr;
+  if (hipEventCreate(&b) != hipSuccess || hipEventRecord(b, s) != hipSuccess) {
+    (void)hipGetLastError();
+    a = nullptr;
+    return;
+  }
+  std::lock_guard<std::mutex> lk(ctx->prof_mu);
+  ctx->prof_pending.push_back({stage, a, b});
+  a = nullptr;
+}
+
+static const char* kStageNames[DV_NUM_STAGES] = {
+    "preprocess", "sort_records", "gather_scan", "emit_pairs", "sort_pairs",
+    "tile_directory", "composite_fwd", "bwd_clear", "composite_bwd",
+    "record_bwd", "host_sync", "other"};
+
 }  // namespace dv
 
 using namespace dv;
@@ -181,11 +208,74 @@ dv_status dv_ctx_create(int32_t hip_device, dv_ctx** out) {
   return DV_OK;
 }
 
+dv_status dv_ctx_set_profiling(dv_ctx* ctx, int32_t flags) {
+  if (!ctx) return DV_ERR_INVALID;
+  DV_TRY_HIP(hipSetDevice(ctx->device));
+  if ((flags & DV_PROFILE_COUNTERS) && !ctx->counters) {
+    DV_TRY_HIP(hipMalloc((void**)&ctx->counters, 4 * sizeof(unsigned long long)));
+    DV_TRY_HIP(hipMemset(ctx->counters, 0, 4 * sizeof(unsigned long long)));
+  }
+  ctx->prof_flags = flags;
+  return DV_OK;
+}
+
+dv_status dv_ctx_stage_times(dv_ctx* ctx, dv_stage_times* out, int32_t reset) {
+  if (!ctx || !out) return DV_ERR_INVALID;
+  DV_TRY_HIP(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> lk(ctx->prof_mu);
+  for (auto& iv : ctx->prof_pending) {
+    DV_TRY_HIP(hipEventSynchronize(iv.b));
+    float ms = 0.0f;
+    DV_TRY_HIP(hipEventElapsedTime(&ms, iv.a, iv.b));
+    ctx->prof_ms[iv.stage] += ms;
+    ctx->prof_calls[iv.stage] += 1;
+    hipEventDestroy(iv.a);
+    hipEventDestroy(iv.b);
+  }
+  ctx->prof_pending.clear();
+  std::memset(out, 0, sizeof(*out));
+  for (int i = 0; i < DV_NUM_STAGES; ++i) {
+    out->ms[i] = ctx->prof_ms[i];
+    out->calls[i] = ctx->prof_calls[i];
+  }
+  if (ctx->counters) {
+    unsigned long long c[4];
+    DV_TRY_HIP(hipDeviceSynchronize());
+    DV_TRY_HIP(hipMemcpy(c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost));
+    out->entries_fwd = (int64_t)c[0];
+    out->pieces_fwd = (int64_t)c[1];
+    out->entries_bwd = (int64_t)c[2];
+    out->pieces_bwd = (int64_t)c[3];
+    if (reset) DV_TRY_HIP(hipMemset(ctx->counters, 0, sizeof(c)));
+  }
+  if (reset) {
+    for (int i = 0; i < DV_NUM_STAGES; ++i) {
+      ctx->prof_ms[i] = 0.0;
+      ctx->prof_calls[i] = 0;
+    }
+  }
+  return DV_OK;
+}
+
+const char* dv_stage_name(int32_t i) {
+  if (i < 0 || i >= DV_NUM_STAGES) return "";
+  return kStageNames[i];
+}
+
 void dv_ctx_destroy(dv_ctx* ctx) {
   if (!ctx) return;
   hipSetDevice(ctx->device);
   hipDeviceSynchronize();
   reap_states(ctx, true);
+  {
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
+    for (auto& iv : ctx->prof_pending) {
+      hipEventDestroy(iv.a);
+      hipEventDestroy(iv.b);
+    }
+    ctx->prof_pending.clear();
+  }
+  if (ctx->counters) hipFree(ctx->counters);
   ctx->pool.reset();
   if (ctx->pinned) hipHostFree(ctx->pinned);
   delete ctx;

@@ -92,6 +92,14 @@ struct DBuf {
 
 struct dv_fwd_state;
 
+namespace dv {
+enum Stage {
+  ST_PREPROCESS = 0, ST_SORT_RECORDS, ST_GATHER, ST_EMIT, ST_SORT_PAIRS,
+  ST_TILE_DIR, ST_COMPOSITE_FWD, ST_BWD_CLEAR, ST_COMPOSITE_BWD,
+  ST_RECORD_BWD, ST_HOST_SYNC, ST_OTHER
+};
+}  // namespace dv
+
 struct dv_ctx {
   int device = 0;
   // forward states whose stream work may still be in flight; deleted once
@@ -104,6 +112,14 @@ struct dv_ctx {
   std::mutex pinned_mu;
   std::atomic<bool> poisoned{false};
   int n_cu = 0;
+  // profiling
+  std::atomic<int> prof_flags{0};
+  std::mutex prof_mu;
+  struct Interval { int stage; hipEvent_t a, b; };
+  std::vector<Interval> prof_pending;
+  double prof_ms[DV_NUM_STAGES] = {0};
+  int64_t prof_calls[DV_NUM_STAGES] = {0};
+  unsigned long long* counters = nullptr;  // device [4]
 };
 
 namespace dv {
@@ -113,6 +129,17 @@ dv_status alloc(dv_ctx* ctx, DBuf& b, size_t bytes, hipStream_t s);
 void retire_state(dv_ctx* ctx, dv_fwd_state* st);
 // Delete retired states whose work has completed (all of them if wait).
 void reap_states(dv_ctx* ctx, bool wait);
+// Records HIP events around a stage when profiling is on.
+struct StageTimer {
+  dv_ctx* ctx;
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  StageTimer(dv_ctx* c, int st, hipStream_t strm);
+  ~StageTimer() { stop(); }
+  void stop();
+};
+
 template <class T>
 dv_status alloc_n(dv_ctx* ctx, DBuf& b, size_t n, hipStream_t s) {
   return alloc(ctx, b, (n ? n : 1) * sizeof(T), s);

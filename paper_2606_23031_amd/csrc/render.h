@@ -52,7 +52,25 @@ struct CompArgs {
   float inv_c;
   float bg[3];
   uint32_t mask;
+  unsigned long long* counters;  // work counters or null
 };
+
+// Add per-thread work counts into counters[i], counters[i+1] (one atomic
+// per wave).  Called by every thread of the block.
+__device__ inline void count_work(unsigned long long* counters, int i,
+                                  uint32_t entries, uint32_t pieces) {
+  if (!counters) return;
+  unsigned long long e = entries, p = pieces;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    e += __shfl_xor(e, o, 64);
+    p += __shfl_xor(p, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(counters + i, e);
+    atomicAdd(counters + i + 1, p);
+  }
+}
 
 __device__ inline int view_of_tile(const ViewConst* views, int n_views,
                                    uint32_t gt) {

@@ -406,6 +406,7 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
   const int K = a.K;
   const float invK = 1.0f / (float)K;
   const size_t pix = (size_t)gt * TPB + tid;
+  uint32_t n_test = 0, n_piece = 0;
 
   // ---------------------------------------------------- actor segments
   const uint32_t a_beg = a.act_beg[gt];
@@ -440,6 +441,7 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
         const float4 geo = B.geo[r];
         float t0, t1;
         slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+        ++n_test;
         if (!(t1 > t0) || t1 <= qs) continue;
         while (true) {
           if (qe <= t0) {
@@ -459,6 +461,7 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
             const float4 cn = B.cn[r];
             const float tau = piece_tau(geo, B.ga[r], B.gb[r], cn.w, dj, pa,
                                         pb, K, invK, a.c, a.inv_c);
+            ++n_piece;
             const float e = fast_exp(-tau);
             const float wgt = p1.w * (1.0f - e);
             p0.x = fmaf(wgt, cn.x, p0.x);
@@ -518,6 +521,7 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
       const float4 geo = B.geo[r];
       float t0, t1;
       slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+      ++n_test;
       t0 = fmaxf(t0, a.tau_near);
       if (!(t1 > t0)) continue;
       float pa = fmaxf(t0, excl);
@@ -534,6 +538,7 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
         const float4 cn = B.cn[r];
         const float tau = piece_tau(geo, B.ga[r], B.gb[r], cn.w, d, pa, pb, K,
                                     invK, a.c, a.inv_c);
+        ++n_piece;
         const float e = fast_exp(-tau);
         const float wgt = T * (1.0f - e);
         C3.x = fmaf(wgt, cn.x, C3.x);
@@ -558,6 +563,7 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
     ++qn;
     if (T < a.eps) done = true;
   }
+  count_work(a.counters, 0, n_test, n_piece);
   if (!valid) return;
   a.fin0[pix] = make_float4(C3.x, C3.y, C3.z, D);
   a.fin1[pix] = make_float4(N3.x, N3.y, N3.z, T);
@@ -817,13 +823,16 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   pa.rank_bits = st->rank_bits;
   pa.block_count = bcount.as<uint32_t>();
   pa.block_off = boff.as<uint32_t>();
-  if (n_items > 0)
-    hipLaunchKernelGGL(k_preprocess<0>, dim3(nblk), dim3(TPB), 0, s, pa);
-  else
-    DV_TRY(fill_u32(bcount.as<uint32_t>(), 0, nblk, s));
-  DV_TRY_HIP(hipGetLastError());
-  DV_TRY(exclusive_scan_u32(ctx, bcount.as<uint32_t>(), boff.as<uint32_t>(),
-                            total.as<uint64_t>(), nblk, s));
+  {
+    StageTimer tm(ctx, ST_PREPROCESS, s);
+    if (n_items > 0)
+      hipLaunchKernelGGL(k_preprocess<0>, dim3(nblk), dim3(TPB), 0, s, pa);
+    else
+      DV_TRY(fill_u32(bcount.as<uint32_t>(), 0, nblk, s));
+    DV_TRY_HIP(hipGetLastError());
+    DV_TRY(exclusive_scan_u32(ctx, bcount.as<uint32_t>(), boff.as<uint32_t>(),
+                              total.as<uint64_t>(), nblk, s));
+  }
   uint64_t n_vis = 0;
   {
     std::lock_guard<std::mutex> lk(ctx->pinned_mu);
@@ -860,14 +869,20 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   pa.s_nrm = s_nrm.as<float4>();
   pa.s_vox = s_vox.as<uint32_t>();
   pa.s_rect = s_rect.as<uint64_t>();
-  if (n_items > 0 && nv > 0)
-    hipLaunchKernelGGL(k_preprocess<1>, dim3(nblk), dim3(TPB), 0, s, pa);
-  DV_TRY_HIP(hipGetLastError());
+  {
+    StageTimer tm(ctx, ST_PREPROCESS, s);
+    if (n_items > 0 && nv > 0)
+      hipLaunchKernelGGL(k_preprocess<1>, dim3(nblk), dim3(TPB), 0, s, pa);
+    DV_TRY_HIP(hipGetLastError());
+  }
   // sort records by (view, octree, rank)
   bool alt = false;
-  DV_TRY(radix_sort_u64(ctx, keys.as<uint64_t>(), vals.as<uint32_t>(),
-                        keys2.as<uint64_t>(), vals2.as<uint32_t>(), nv,
-                        st->key_bits, s, &alt));
+  {
+    StageTimer tm(ctx, ST_SORT_RECORDS, s);
+    DV_TRY(radix_sort_u64(ctx, keys.as<uint64_t>(), vals.as<uint32_t>(),
+                          keys2.as<uint64_t>(), vals2.as<uint32_t>(), nv,
+                          st->key_bits, s, &alt));
+  }
   uint64_t* ks = alt ? keys2.as<uint64_t>() : keys.as<uint64_t>();
   uint32_t* vs = alt ? vals2.as<uint32_t>() : vals.as<uint32_t>();
   // records in sorted order
@@ -882,6 +897,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   DV_TRY(alloc_n<uint32_t>(ctx, r_count, nv, s));
   DV_TRY(alloc_n<uint32_t>(ctx, r_off, nv, s));
   DV_TRY(alloc_n<uint64_t>(ctx, r_rect, nv, s));
+  StageTimer tm_gather(ctx, ST_GATHER, s);
   if (nv > 0)
     hipLaunchKernelGGL(k_gather, dim3(grid_for(nv, TPB)), dim3(TPB), 0, s, nv,
                        ks, vs, st->rank_bits, s_geo.as<float4>(),
@@ -895,6 +911,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   DV_TRY_HIP(hipGetLastError());
   DV_TRY(exclusive_scan_u32(ctx, r_count.as<uint32_t>(), r_off.as<uint32_t>(),
                             total.as<uint64_t>(), nv, s));
+  tm_gather.stop();
   uint64_t n_pairs = 0;
   {
     std::lock_guard<std::mutex> lk(ctx->pinned_mu);
@@ -917,6 +934,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   DV_TRY(alloc_n<uint32_t>(ctx, st->pair_val, np, s));
   DV_TRY(alloc_n<uint32_t>(ctx, pkey2, np, s));
   DV_TRY(alloc_n<uint32_t>(ctx, pval2, np, s));
+  StageTimer tm_emit(ctx, ST_EMIT, s);
   if (np > 0)
     hipLaunchKernelGGL(k_emit, dim3(grid_for(np, TPB)), dim3(TPB), 0, s, np, nv,
                        r_off.as<uint32_t>(), r_rect.as<uint64_t>(),
@@ -924,9 +942,13 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
                        st->views_d.as<ViewConst>(), pkey.as<uint32_t>(),
                        st->pair_val.as<uint32_t>());
   DV_TRY_HIP(hipGetLastError());
-  DV_TRY(radix_sort_u32(ctx, pkey.as<uint32_t>(), st->pair_val.as<uint32_t>(),
-                        pkey2.as<uint32_t>(), pval2.as<uint32_t>(), np,
-                        st->tile_bits, s, &alt));
+  tm_emit.stop();
+  {
+    StageTimer tm(ctx, ST_SORT_PAIRS, s);
+    DV_TRY(radix_sort_u32(ctx, pkey.as<uint32_t>(), st->pair_val.as<uint32_t>(),
+                          pkey2.as<uint32_t>(), pval2.as<uint32_t>(), np,
+                          st->tile_bits, s, &alt));
+  }
   if (alt) {
     std::swap(pkey, pkey2);
     std::swap(st->pair_val, pval2);
@@ -934,6 +956,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   pkey2.reset();
   pval2.reset();
   // tile directory
+  StageTimer tm_dir(ctx, ST_TILE_DIR, s);
   const int64_t nt = st->n_tiles;
   DV_TRY(alloc_n<uint32_t>(ctx, st->tile_start, nt, s));
   DV_TRY(alloc_n<uint32_t>(ctx, st->tile_end, nt, s));
@@ -970,6 +993,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
                        n_oct, st->act_sub.as<uint2>());
     DV_TRY_HIP(hipGetLastError());
   }
+  tm_dir.stop();
   // per-pixel scratch
   const size_t nslots = (size_t)3 * na * TPB;
   DV_TRY(alloc_n<float2>(ctx, st->seg_se, nslots, s));
@@ -1013,6 +1037,8 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   ca.inv_c = 1.0f / op.explin_c;
   for (int i = 0; i < 3; ++i) ca.bg[i] = op.bg[i];
   ca.mask = op.out_mask;
+  ca.counters = (ctx->prof_flags.load() & DV_PROFILE_COUNTERS) ? ctx->counters : nullptr;
+  StageTimer tm_comp(ctx, ST_COMPOSITE_FWD, s);
   if (nt > 0) {
     if (op.out_mask & DV_OUT_NORMAL)
       hipLaunchKernelGGL(k_composite_fwd<true>, dim3((unsigned)nt), dim3(TPB), 0,

@@ -97,6 +97,16 @@ class dv_state_info(C.Structure):
                 ("tile_bits", C.c_int32)]
 
 
+NUM_STAGES = 12
+
+
+class dv_stage_times(C.Structure):
+    _fields_ = [("ms", C.c_double * NUM_STAGES),
+                ("calls", C.c_int64 * NUM_STAGES),
+                ("entries_fwd", C.c_int64), ("pieces_fwd", C.c_int64),
+                ("entries_bwd", C.c_int64), ("pieces_bwd", C.c_int64)]
+
+
 class dv_serve_opts(C.Structure):
     _fields_ = [("max_inflight", C.c_int32), ("mem_budget", C.c_int64),
                 ("batched", C.c_int32), ("max_batch", C.c_int32),
@@ -135,6 +145,9 @@ _sig = {
     "dv_fwd_state_info": (C.c_int32, [_P, C.POINTER(dv_state_info)]),
     "dv_fwd_state_export_lists": (C.c_int32, [_P, C.c_int32, _P, _P, _P,
                                               C.c_int64, _P, _P, C.c_int64]),
+    "dv_ctx_set_profiling": (C.c_int32, [_P, C.c_int32]),
+    "dv_ctx_stage_times": (C.c_int32, [_P, C.POINTER(dv_stage_times), C.c_int32]),
+    "dv_stage_name": (C.c_char_p, [C.c_int32]),
     "dv_serve_create": (C.c_int32, [_P, _P, C.POINTER(dv_serve_opts),
                                     C.POINTER(_P)]),
     "dv_serve_submit": (C.c_int32, [_P, C.POINTER(dv_request),
@@ -206,6 +219,25 @@ def dv_ctx_create(device=0):
 
 def dv_ctx_destroy(ctx):
     _lib.dv_ctx_destroy(ctx)
+
+
+PROFILE_EVENTS, PROFILE_COUNTERS = 1, 2
+
+
+def dv_ctx_set_profiling(ctx, flags):
+    _check(_lib.dv_ctx_set_profiling(ctx, flags), "dv_ctx_set_profiling")
+
+
+def dv_ctx_stage_times(ctx, reset=True):
+    """dict: per-stage {name: (ms, calls)} plus work counters."""
+    t = dv_stage_times()
+    _check(_lib.dv_ctx_stage_times(ctx, C.byref(t), 1 if reset else 0),
+           "dv_ctx_stage_times")
+    out = {_lib.dv_stage_name(i).decode(): (t.ms[i], t.calls[i])
+           for i in range(NUM_STAGES)}
+    out["_counters"] = dict(entries_fwd=t.entries_fwd, pieces_fwd=t.pieces_fwd,
+                            entries_bwd=t.entries_bwd, pieces_bwd=t.pieces_bwd)
+    return out
 
 
 def dv_validate_octree_host(level, ijk, corner_idx, max_level, n_corners,
