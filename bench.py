@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     return ap.parse_args()
 
 
@@ -147,6 +149,89 @@ def _work(ctx, pix, grads):
 
 def _pool_work(arg):
     return _work(_CTX, arg[0], arg[1])
+
+
+def serve_views(n, seed):
+    """Requests of the serving workload: timestamp U[0,10] s, an ego camera
+    on the lane at that time with a random heading, resolution drawn from
+    {640x360, 960x540, 1920x1080}."""
+    from synth import make_view, look_at_c2w
+    rng = np.random.default_rng(seed)
+    sizes = [(640, 360), (960, 540), (1920, 1080)]
+    out = []
+    for _ in range(n):
+        W, H = sizes[rng.integers(3)]
+        t = float(rng.uniform(0.0, 10.0))
+        yaw = rng.uniform(0.0, 2 * np.pi)
+        eye = np.array([-40.0 + 10.0 * t, 0.0, 1.6])
+        out.append(make_view(W, H, 60.0, look_at_c2w(
+            eye, eye + (np.cos(yaw), np.sin(yaw), 0.0)), t=t))
+    return out
+
+
+def serve_run(dv, ctx, sc, opts, views, rate, batched, seed):
+    """Open-loop Poisson arrivals; returns frames/s, Mpix/s and latency
+    percentiles measured from each request's scheduled arrival."""
+    import threading
+    import torch
+    mask = dv.DV_OUT_RGB | dv.DV_OUT_DEPTH
+    srv = dv.dv_serve_create(ctx, sc, dv.make_opts(opts, mask),
+                             max_inflight=16, mem_budget=16 << 30,
+                             batched=batched, max_batch=8)
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, len(views)))
+    free = {}
+    lock = threading.Lock()
+    tickets = [None] * len(views)
+    bufs = [None] * len(views)
+
+    def get_buf(v):
+        key = (v["w"], v["h"])
+        with lock:
+            lst = free.setdefault(key, [])
+            if lst:
+                return lst.pop()
+        return dv.alloc_outputs([v], mask)[0]
+
+    # warm the buffer pool and the server (untimed)
+    warm = [get_buf(v) for v in views[:48]]
+    for b in warm:
+        free.setdefault((b["rgb"].shape[2], b["rgb"].shape[1]), []).append(b)
+    torch.cuda.synchronize()
+    t0 = time.monotonic() + 0.2
+
+    def submitter():
+        for i, v in enumerate(views):
+            dt = t0 + arrivals[i] - time.monotonic()
+            if dt > 0:
+                time.sleep(dt)
+            b = get_buf(v)
+            bufs[i] = b
+            tickets[i] = dv.dv_serve_submit(srv, v, b)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat, done_t = [], []
+    for i in range(len(views)):
+        while tickets[i] is None:
+            time.sleep(0.0002)
+        st, ts, ta, td = dv.dv_serve_poll(srv, tickets[i], -1)
+        assert st == 0, st
+        lat.append(td - (t0 + arrivals[i]))
+        done_t.append(td)
+        with lock:
+            b = bufs[i]
+            free.setdefault((b["rgb"].shape[2], b["rgb"].shape[1]), []).append(b)
+    th.join()
+    dv.dv_serve_destroy(srv)
+    span = max(done_t) - t0
+    pix = sum(v["w"] * v["h"] for v in views)
+    lat = np.array(lat) * 1e3
+    return dict(frames_per_s=round(len(views) / span, 2),
+                mpix_per_s=round(pix / span / 1e6, 2),
+                p50_ms=round(float(np.percentile(lat, 50)), 3),
+                p99_ms=round(float(np.percentile(lat, 99)), 3),
+                requests=len(views), offered_req_per_s=rate)
 
 
 def roofline(stage, ms, calls, info, counters, scene_stats):
@@ -255,6 +340,17 @@ def main():
         "stages_ms_per_step": {k: round(v[0] / args.profile_steps, 4)
                                for k, v in stages.items() if v[1] > 0},
     }
+    if args.serve_requests > 0 and args.config == 2:
+        sv = serve_views(args.serve_requests, seed=4)
+        log(f"[bench] serving {len(sv)} requests at {args.serve_rate}/s ...")
+        out["serving"] = dict(
+            workload="driving-1M+8x20k-serving, Poisson arrivals, mixed "
+                     "640x360/960x540/1920x1080, RGB+depth",
+            batched=serve_run(dv, ctx, step.sc, cfg["opts"], sv,
+                              args.serve_rate, True, seed=5),
+            per_request=serve_run(dv, ctx, step.sc, cfg["opts"], sv,
+                                  args.serve_rate, False, seed=5))
+        log(f"[bench] serving: {out['serving']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)

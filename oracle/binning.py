@@ -8,11 +8,20 @@ lists and orders can be compared exactly:
 Binning.  Per (view, octree), a = R_c^T R_k and b = R_c^T (p_k - o) take
 octree-frame points to the camera frame.  For a leaf, each corner
 x = root_min + (ijk + m) h goes to X = a x + b (every sum taken left to
-right, no fused multiply-add).  All Z <= 0: culled.  Any Z < 1e-3: the
-leaf covers the whole window.  Otherwise u = cx + fx (X/Z),
-v = cy + fy (Y/Z); pixel column px is covered iff px >= ceil(umin - 9/16)
-and px <= floor(umax - 7/16) (pixel centre within 1/16 px of the box of
-projected corners), both bounds clamped to the window before rounding;
+right, no fused multiply-add).  All Z <= 0: culled.  If every Z >= e
+(e = 1e-3) the corners are projected, u = cx + fx (X/Z),
+v = cy + fy (Y/Z).  Otherwise the box straddles the plane Z = e: if the
+axis-aligned (camera-frame) bound of its corners comes closer to the
+camera than r_near (twice e times the largest |(x, y, 1)| of a window
+pixel-centre direction) it covers the whole window; else the projected
+points are the corners with Z >= e plus, on each of the 12 edges whose
+ends lie on both sides of the plane, the crossing point
+X_i = X_m + t (X_m' - X_m), t = (e - Z_m) / (Z_m' - Z_m), projected as
+u = cx + fx (X_i / e).  (A ray that meets the box only where Z < e does so
+within r_near / 2 of the camera, so the rule stays conservative.)  Pixel
+column px is covered iff px >= ceil(umin - 9/16) and
+px <= floor(umax - 7/16) (pixel centre within 1/16 px of the box of
+projected points), both bounds clamped to the window before rounding;
 rows likewise.  Tiles are 16x16 over the window.
 
 Order.  The rank of a leaf is a BSP painter's order from the camera
@@ -57,6 +66,76 @@ def camera_in_octree(view, R, p):
                      for j in range(3)])
 
 
+def near_radius2(view):
+    """r_near^2 = (2 e)^2 max over window corner pixel centres of
+    (1 + x^2 + y^2), x = (px + 1/2 - cx) / fx, y likewise."""
+    m2 = 0.0
+    for px in (view["x0"], view["x0"] + view["w"] - 1):
+        for py in (view["y0"], view["y0"] + view["h"] - 1):
+            x = (px + 0.5 - view["cx"]) / view["fx"]
+            y = (py + 0.5 - view["cy"]) / view["fy"]
+            m2 = max(m2, (1.0 + x * x) + y * y)
+    return (2.0 * Z_EPS) * (2.0 * Z_EPS) * m2
+
+
+def _rects_from_corners(Xs, view):
+    """Xs [8,3,n] camera-frame corners -> (status, xl, xh, yl, yh)."""
+    Z = Xs[:, 2]
+    n = Z.shape[1]
+    culled = np.all(Z <= 0.0, axis=0)
+    near = (~culled) & np.any(Z < Z_EPS, axis=0)
+    lo = Xs.min(0)                                   # [3,n]
+    hi = Xs.max(0)
+    dd = np.maximum(np.maximum(lo, 0.0), -hi)
+    dist2 = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2]
+    full = near & (dist2 < near_radius2(view))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = view["cx"] + view["fx"] * (Xs[:, 0] / Z)
+        v = view["cy"] + view["fy"] * (Xs[:, 1] / Z)
+    ok = Z >= Z_EPS                                  # [8,n]
+    big = np.inf
+    umin = np.where(ok, u, big).min(0)
+    umax = np.where(ok, u, -big).max(0)
+    vmin = np.where(ok, v, big).min(0)
+    vmax = np.where(ok, v, -big).max(0)
+    for bit in (1, 2, 4):
+        for m in range(8):
+            if m & bit:
+                continue
+            m2 = m | bit
+            cross = (Z[m] < Z_EPS) != (Z[m2] < Z_EPS)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                t = (Z_EPS - Z[m]) / (Z[m2] - Z[m])
+                xi = Xs[m, 0] + t * (Xs[m2, 0] - Xs[m, 0])
+                yi = Xs[m, 1] + t * (Xs[m2, 1] - Xs[m, 1])
+                ui = view["cx"] + view["fx"] * (xi / Z_EPS)
+                vi = view["cy"] + view["fy"] * (yi / Z_EPS)
+            umin = np.where(cross, np.minimum(umin, ui), umin)
+            umax = np.where(cross, np.maximum(umax, ui), umax)
+            vmin = np.where(cross, np.minimum(vmin, vi), vmin)
+            vmax = np.where(cross, np.maximum(vmax, vi), vmax)
+    x0, y0, w, hh = view["x0"], view["y0"], view["w"], view["h"]
+
+    def bounds(lo_val, hi_val, org, size):
+        lo_ = np.ceil(np.clip(lo_val - 0.5625, org - 1.0, org + size))
+        hi_ = np.floor(np.clip(hi_val - 0.4375, org - 1.0, org + size))
+        lo_ = np.maximum(lo_, org) - org
+        hi_ = np.minimum(hi_, org + size - 1) - org
+        return lo_.astype(np.int64), hi_.astype(np.int64)
+
+    rect = ~(culled | full)
+    xl, xh = bounds(np.where(rect, umin, 0.0), np.where(rect, umax, 0.0), x0, w)
+    yl, yh = bounds(np.where(rect, vmin, 0.0), np.where(rect, vmax, 0.0), y0, hh)
+    xl = np.where(full, 0, xl)
+    xh = np.where(full, w - 1, xh)
+    yl = np.where(full, 0, yl)
+    yh = np.where(full, hh - 1, yh)
+    status = np.where(culled, 0, np.where(full, 2, 1))
+    xl = np.where(culled, 1, xl)
+    xh = np.where(culled, 0, xh)
+    return status, xl, xh, yl, yh
+
+
 def leaf_rects(o, view, R, p):
     """Per leaf: status (0 culled, 1 rect, 2 whole window) and the covered
     window-relative pixel bounds (x_lo, x_hi, y_lo, y_hi), inclusive;
@@ -72,36 +151,7 @@ def leaf_rects(o, view, R, p):
              for a in range(3)]
         for i in range(3):
             Xs[m, i] = ((A[i, 0] * x[0] + A[i, 1] * x[1]) + A[i, 2] * x[2]) + b[i]
-    Z = Xs[:, 2]
-    culled = np.all(Z <= 0.0, axis=0)
-    full = (~culled) & np.any(Z < Z_EPS, axis=0)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        u = view["cx"] + view["fx"] * (Xs[:, 0] / Z)
-        v = view["cy"] + view["fy"] * (Xs[:, 1] / Z)
-    x0, y0, w, hh = view["x0"], view["y0"], view["w"], view["h"]
-
-    def bounds(lo_val, hi_val, org, size):
-        lo = np.ceil(np.clip(lo_val - 0.5625, org - 1.0, org + size))
-        hi = np.floor(np.clip(hi_val - 0.4375, org - 1.0, org + size))
-        lo = np.maximum(lo, org) - org
-        hi = np.minimum(hi, org + size - 1) - org
-        return lo.astype(np.int64), hi.astype(np.int64)
-
-    rect = ~(culled | full)
-    umin = np.where(rect, u.min(0), 0.0)
-    umax = np.where(rect, u.max(0), 0.0)
-    vmin = np.where(rect, v.min(0), 0.0)
-    vmax = np.where(rect, v.max(0), 0.0)
-    xl, xh = bounds(umin, umax, x0, w)
-    yl, yh = bounds(vmin, vmax, y0, hh)
-    xl = np.where(full, 0, xl)
-    xh = np.where(full, w - 1, xh)
-    yl = np.where(full, 0, yl)
-    yh = np.where(full, hh - 1, yh)
-    status = np.where(culled, 0, np.where(full, 2, 1))
-    xl = np.where(culled, 1, xl)
-    xh = np.where(culled, 0, xh)
-    return status, xl, xh, yl, yh
+    return _rects_from_corners(Xs, view)
 
 
 def quantised_camera(o, view, R, p):
@@ -181,25 +231,10 @@ def box_rect(bmin, bmax, view, R, p):
     """The binning rule above applied to one box given by min/max corners
     (corner m takes max on axis a iff bit a of m is set)."""
     A, b = camera_transform(view, R, p)
-    Xs = np.empty((8, 3))
+    Xs = np.empty((8, 3, 1))
     for m in range(8):
         x = [bmax[a] if (m >> a) & 1 else bmin[a] for a in range(3)]
         for i in range(3):
-            Xs[m, i] = ((A[i, 0] * x[0] + A[i, 1] * x[1]) + A[i, 2] * x[2]) + b[i]
-    Z = Xs[:, 2]
-    x0, y0, w, hh = view["x0"], view["y0"], view["w"], view["h"]
-    if np.all(Z <= 0.0):
-        return 0, 1, 0, 1, 0
-    if np.any(Z < Z_EPS):
-        return 2, 0, w - 1, 0, hh - 1
-    u = view["cx"] + view["fx"] * (Xs[:, 0] / Z)
-    v = view["cy"] + view["fy"] * (Xs[:, 1] / Z)
-
-    def bounds(lo_val, hi_val, org, size):
-        lo = np.ceil(np.clip(lo_val - 0.5625, org - 1.0, org + size))
-        hi = np.floor(np.clip(hi_val - 0.4375, org - 1.0, org + size))
-        return int(max(lo, org) - org), int(min(hi, org + size - 1) - org)
-
-    xl, xh = bounds(u.min(), u.max(), x0, w)
-    yl, yh = bounds(v.min(), v.max(), y0, hh)
-    return 1, xl, xh, yl, yh
+            Xs[m, i, 0] = ((A[i, 0] * x[0] + A[i, 1] * x[1]) + A[i, 2] * x[2]) + b[i]
+    st, xl, xh, yl, yh = _rects_from_corners(Xs, view)
+    return int(st[0]), int(xl[0]), int(xh[0]), int(yl[0]), int(yh[0])

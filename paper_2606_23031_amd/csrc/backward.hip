@@ -30,66 +30,6 @@ __device__ inline float wave_sum(float v) {
   return v;
 }
 
-struct PieceDer {
-  float dtda, dtdb;       // d tau / d(a), d(b)
-  float dg[8];            // d tau / d corner value
-  float3 dx;              // sum_q d tau / d x_q
-  float3 dxt;             // sum_q tau_q d tau / d x_q
-};
-
-// Derivatives of piece_tau (same sample positions; clamps are inactive
-// inside the piece).
-template <bool GEO>
-__device__ inline void piece_der(float4 geo, float4 ga, float4 gb,
-                                 float inv_h, float3 d, float a, float b,
-                                 int K, float invK, float c, float inv_c,
-                                 PieceDer& o) {
-  const float step = (b - a) * invK;
-  float ssum = 0.0f, pa = 0.0f, pb = 0.0f;
-#pragma unroll
-  for (int m = 0; m < 8; ++m) o.dg[m] = 0.0f;
-  o.dx = make_float3(0, 0, 0);
-  o.dxt = make_float3(0, 0, 0);
-  for (int q = 0; q < K; ++q) {
-    const float f = ((float)q + 0.5f) * invK;
-    const float tq = fmaf((float)q + 0.5f, step, a);
-    const float ux = clamp01(fmaf(tq, d.x, -geo.x) * inv_h);
-    const float uy = clamp01(fmaf(tq, d.y, -geo.y) * inv_h);
-    const float uz = clamp01(fmaf(tq, d.z, -geo.z) * inv_h);
-    const float g = trilerp(ga, gb, ux, uy, uz);
-    const float coef = step * explin_grad(g, c, inv_c);
-    ssum += explin(g, c, inv_c);
-    const float vx = 1.0f - ux, vy = 1.0f - uy, vz = 1.0f - uz;
-    o.dg[0] = fmaf(coef, vx * vy * vz, o.dg[0]);
-    o.dg[1] = fmaf(coef, ux * vy * vz, o.dg[1]);
-    o.dg[2] = fmaf(coef, vx * uy * vz, o.dg[2]);
-    o.dg[3] = fmaf(coef, ux * uy * vz, o.dg[3]);
-    o.dg[4] = fmaf(coef, vx * vy * uz, o.dg[4]);
-    o.dg[5] = fmaf(coef, ux * vy * uz, o.dg[5]);
-    o.dg[6] = fmaf(coef, vx * uy * uz, o.dg[6]);
-    o.dg[7] = fmaf(coef, ux * uy * uz, o.dg[7]);
-    if (GEO) {
-      const float gx = vy * vz * (ga.y - ga.x) + uy * vz * (ga.w - ga.z) +
-                       vy * uz * (gb.y - gb.x) + uy * uz * (gb.w - gb.z);
-      const float gy = vx * vz * (ga.z - ga.x) + ux * vz * (ga.w - ga.y) +
-                       vx * uz * (gb.z - gb.x) + ux * uz * (gb.w - gb.y);
-      const float gz = vx * vy * (gb.x - ga.x) + ux * vy * (gb.y - ga.y) +
-                       vx * uy * (gb.z - ga.z) + ux * uy * (gb.w - ga.w);
-      const float s = coef * inv_h;
-      const float3 dtdx = make_float3(s * gx, s * gy, s * gz);
-      const float proj = dtdx.x * d.x + dtdx.y * d.y + dtdx.z * d.z;
-      pa = fmaf(proj, 1.0f - f, pa);
-      pb = fmaf(proj, f, pb);
-      o.dx.x += dtdx.x; o.dx.y += dtdx.y; o.dx.z += dtdx.z;
-      o.dxt.x = fmaf(tq, dtdx.x, o.dxt.x);
-      o.dxt.y = fmaf(tq, dtdx.y, o.dxt.y);
-      o.dxt.z = fmaf(tq, dtdx.z, o.dxt.z);
-    }
-  }
-  o.dtda = -ssum * invK + pa;
-  o.dtdb = ssum * invK + pb;
-}
-
 __device__ inline void add_axis(float3& v, int ax, float x) {
   if (ax == 0) v.x += x; else if (ax == 1) v.y += x; else v.z += x;
 }
@@ -103,6 +43,7 @@ struct BwdBatch {
   float4 gb[TPB];
   float4 cn[TPB];
   float4 nrm[TPB];
+  uint2 rect[TPB];
   uint32_t rid[TPB];
   float acc[NACC][TPB];
 };
@@ -118,28 +59,47 @@ __device__ inline void load_bwd_batch(BwdBatch& B, const CompArgs& a,
     B.gb[tid] = a.rec_g8b[r];
     B.cn[tid] = a.rec_cn[r];
     B.nrm[tid] = a.rec_nrm[r];
+    const uint64_t rc = a.rec_rect[r];
+    B.rect[tid] = make_uint2((uint32_t)rc, (uint32_t)(rc >> 32));
   }
 }
 
-// Reduce one lane-contribution set into the batch slot r (wave reduce +
-// LDS atomics).  Must be called wave-uniformly.
-template <bool NORMALS>
+// Reduce one lane-contribution set into the batch slot r.  The 14
+// channels (padded to 16) are summed over the wave with a transposing
+// butterfly: at each exchange a lane keeps half of its channels and adds the
+// partner's copy of them, so 17 shuffles leave lane l holding the full sum
+// of channel l >> 2; lanes with l % 4 == 0 then add their channel into LDS.
+// Must be called wave-uniformly.
 __device__ inline void accum_record(BwdBatch& B, uint32_t r, bool hit,
                                     float3 dcol, float3 dnrm,
                                     const float* dg) {
   if (__ballot(hit) == 0) return;
   const int lane = threadIdx.x & 63;
-  float v[NACC];
+  float v[16];
   v[0] = dcol.x; v[1] = dcol.y; v[2] = dcol.z;
   v[3] = dnrm.x; v[4] = dnrm.y; v[5] = dnrm.z;
 #pragma unroll
   for (int m = 0; m < 8; ++m) v[6 + m] = dg[m];
+  v[14] = 0.0f;
+  v[15] = 0.0f;
+  if (!hit) {
 #pragma unroll
-  for (int c = 0; c < NACC; ++c) {
-    if (!NORMALS && c >= 3 && c < 6) continue;
-    const float s = wave_sum(hit ? v[c] : 0.0f);
-    if (lane == 0 && s != 0.0f) atomicAdd(&B.acc[c][r], s);
+    for (int c = 0; c < 16; ++c) v[c] = 0.0f;
   }
+#pragma unroll
+  for (int m = 32, n = 8; n >= 1; m >>= 1, n >>= 1) {
+    const bool upper = (lane & m) != 0;
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      const float send = upper ? v[i] : v[i + n];
+      const float keep = upper ? v[i + n] : v[i];
+      v[i] = keep + __shfl_xor(send, m, 64);
+    }
+  }
+  v[0] += __shfl_xor(v[0], 2, 64);
+  v[0] += __shfl_xor(v[0], 1, 64);
+  const int ch = lane >> 2;
+  if ((lane & 3) == 0 && ch < NACC && v[0] != 0.0f) atomicAdd(&B.acc[ch][r], v[0]);
 }
 
 __device__ inline void flush_batch(BwdBatch& B, const CompArgs& a,
@@ -205,8 +165,10 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
   const int v = view_of_tile(a.views, a.n_views, gt);
   const ViewConst& V = a.views[v];
   const uint32_t lt = gt - V.tile_base;
-  const int px = (int)(lt % V.ntx) * TILE + (tid & 15);
-  const int py = (int)(lt / V.ntx) * TILE + (tid >> 4);
+  const int px = (int)(lt % V.ntx) * TILE + tile_px(tid);
+  const int py = (int)(lt / V.ntx) * TILE + tile_py(tid);
+  const int bx = (int)(lt % V.ntx) * TILE + (((tid >> 6) & 1) << 3);
+  const int by = (int)(lt / V.ntx) * TILE + (((tid >> 6) >> 1) << 3);
   const bool valid = px < V.w && py < V.h;
   float3 d;
   {
@@ -257,6 +219,7 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
       load_bwd_batch(B, a, base, nb);
       __syncthreads();
       for (uint32_t r = 0; r < nb; ++r) {
+        if (!rect_hits_block(B.rect[r], bx, by)) continue;
         const float4 geo = B.geo[r];
         float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
         float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -295,8 +258,13 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
               const bool b_seg = ns < t1;
               const float pb = fminf(t1, ns);
               const float4 cn = B.cn[r];
-              const float tau = piece_tau(geo, B.ga[r], B.gb[r], cn.w, d, pa,
-                                          pb, K, invK, a.c, a.inv_c);
+              PieceDer pd;
+              const float tau =
+                  (a_seg || b_seg)
+                      ? piece_eval<2>(geo, B.ga[r], B.gb[r], cn.w, d, pa, pb, K,
+                                      invK, a.c, a.inv_c, &pd)
+                      : piece_eval<1>(geo, B.ga[r], B.gb[r], cn.w, d, pa, pb, K,
+                                      invK, a.c, a.inv_c, &pd);
               ++n_piece;
               const float e = fast_exp(-tau);
               const float wgt = T * (1.0f - e);
@@ -307,13 +275,6 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
               const float Tn = T * e;
               P = fmaf(wgt, vi, P);
               const float dtau = Tn * vi - (L - P);
-              PieceDer pd;
-              if (a_seg || b_seg)
-                piece_der<true>(geo, B.ga[r], B.gb[r], cn.w, d, pa, pb, K, invK,
-                                a.c, a.inv_c, pd);
-              else
-                piece_der<false>(geo, B.ga[r], B.gb[r], cn.w, d, pa, pb, K,
-                                 invK, a.c, a.inv_c, pd);
               hit = true;
               dcol.x += wgt * GC.x; dcol.y += wgt * GC.y; dcol.z += wgt * GC.z;
               if (NORMALS) {
@@ -334,7 +295,7 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
             }
           }
         }
-        accum_record<NORMALS>(B, r, hit, dcol, dnrm, dg);
+        accum_record(B, r, hit, dcol, dnrm, dg);
       }
       flush_batch(B, a, nb);
       if (__syncthreads_and(done)) break;
@@ -397,6 +358,7 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
       load_bwd_batch(B, a, base, nb);
       __syncthreads();
       for (uint32_t r = 0; r < nb; ++r) {
+        if (!rect_hits_block(B.rect[r], bx, by)) continue;
         float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
         float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         bool hit = false;
@@ -419,8 +381,10 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
               const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
               if (pb > pa && !qdone) {
                 const float4 cn = B.cn[r];
-                const float tau = piece_tau(geo, B.ga[r], B.gb[r], cn.w, dj, pa,
-                                            pb, K, invK, a.c, a.inv_c);
+                PieceDer pd;
+                const float tau = piece_eval<2>(geo, B.ga[r], B.gb[r], cn.w, dj,
+                                                pa, pb, K, invK, a.c, a.inv_c,
+                                                &pd);
                 ++n_piece;
                 const float e = fast_exp(-tau);
                 const float wl = Tl * (1.0f - e);
@@ -432,9 +396,6 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
                 Pl = fmaf(wl, vi, Pl);
                 const float dtau = Tpre * Tln * vi - (Tpre * (Vq - Pl) + Saft);
                 const float wt = Tpre * wl;
-                PieceDer pd;
-                piece_der<true>(geo, B.ga[r], B.gb[r], cn.w, dj, pa, pb, K,
-                                invK, a.c, a.inv_c, pd);
                 hit = true;
                 dcol.x += wt * GC.x; dcol.y += wt * GC.y; dcol.z += wt * GC.z;
                 if (NORMALS) {
@@ -474,7 +435,7 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
             }
           }
         }
-        accum_record<NORMALS>(B, r, hit, dcol, dnrm, dg);
+        accum_record(B, r, hit, dcol, dnrm, dg);
       }
       flush_batch(B, a, nb);
       if (!__syncthreads_or(has)) break;
@@ -725,6 +686,7 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   ca.rec_g8b = st->rec_g8b.as<float4>();
   ca.rec_cn = st->rec_cn.as<float4>();
   ca.rec_nrm = st->rec_nrm.as<float4>();
+  ca.rec_rect = st->rec_rect.as<uint64_t>();
   ca.act_beg = st->act_beg.as<uint32_t>();
   ca.act_oct = st->act_oct.as<uint32_t>();
   ca.act_sub = st->act_sub.as<uint2>();

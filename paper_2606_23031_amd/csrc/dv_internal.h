@@ -182,6 +182,7 @@ struct OctDev {
 // Per view constants.
 struct ViewConst {
   double fx, fy, cx, cy;
+  double rnear2;            // binning: whole-window radius^2 near the camera
   float inv_fx, inv_fy, fcx, fcy;
   float Rc[9];              // camera -> world rotation (row-major)
   int32_t x0, y0, w, h;

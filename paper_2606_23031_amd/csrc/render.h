@@ -26,6 +26,7 @@ struct CompArgs {
   const float4* rec_g8b;   // corner densities 4..7
   const float4* rec_cn;    // colour rgb, 1/h
   const float4* rec_nrm;   // world normal xyz, 0
+  const uint64_t* rec_rect;  // covered pixels: xl | xh<<16 | yl<<32 | yh<<48
   const uint32_t* act_beg; // per global tile, n_tiles + 1
   const uint32_t* act_oct; // actor octree index per (tile, slot)
   const uint2* act_sub;    // pair sub-range per (tile, slot)
@@ -70,6 +71,24 @@ __device__ inline void count_work(unsigned long long* counters, int i,
     atomicAdd(counters + i, e);
     atomicAdd(counters + i + 1, p);
   }
+}
+
+// Pixel of thread tid inside a 16x16 tile: each wave64 covers an 8x8
+// quadrant, so a wave can skip list entries whose pixel rectangle misses
+// its quadrant.
+__device__ inline int tile_px(int tid) {
+  return (((tid >> 6) & 1) << 3) | (tid & 7);
+}
+__device__ inline int tile_py(int tid) {
+  return (((tid >> 6) >> 1) << 3) | ((tid >> 3) & 7);
+}
+
+// Does the entry's covered pixel rectangle meet the 8x8 block at (bx, by)?
+// Evaluated identically by every lane of a wave (wave-uniform branch).
+__device__ inline bool rect_hits_block(uint2 rc, int bx, int by) {
+  const int xl = (int)(rc.x & 0xFFFF), xh = (int)(rc.x >> 16);
+  const int yl = (int)(rc.y & 0xFFFF), yh = (int)(rc.y >> 16);
+  return xl <= bx + 7 && xh >= bx && yl <= by + 7 && yh >= by;
 }
 
 __device__ inline int view_of_tile(const ViewConst* views, int n_views,
@@ -146,22 +165,82 @@ __device__ inline float3 safe_inv(float3 d) {
   return make_float3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
 }
 
+// Derivatives of the optical depth of one piece.
+struct PieceDer {
+  float dtda, dtdb;       // d tau / d(a), d(b)
+  float dg[8];            // d tau / d corner value
+  float3 dx;              // sum_q d tau / d x_q
+  float3 dxt;             // sum_q tau_q d tau / d x_q
+};
+
 // Optical depth of the piece [a, b] of one leaf: K-point midpoint rule of
-// explin(trilinear raw density).  Shared verbatim by forward and backward
-// so both take identical rounding.
-__device__ inline float piece_tau(float4 geo, float4 ga, float4 gb,
-                                  float inv_h, float3 d, float a, float b,
-                                  int K, float invK, float c, float inv_c) {
+// explin(trilinear raw density).  MODE 0: optical depth only; 1: also
+// corner derivatives; 2: also geometry derivatives (samples, ends).  The
+// optical depth takes the same operations in every mode, so forward and
+// backward walks see bit-identical values.
+template <int MODE>
+__device__ inline float piece_eval(float4 geo, float4 ga, float4 gb,
+                                   float inv_h, float3 d, float a, float b,
+                                   int K, float invK, float c, float inv_c,
+                                   PieceDer* o) {
   const float step = (b - a) * invK;
-  float sum = 0.0f;
+  float sum = 0.0f, pa = 0.0f, pb = 0.0f;
+  if (MODE >= 1) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) o->dg[m] = 0.0f;
+    o->dx = make_float3(0, 0, 0);
+    o->dxt = make_float3(0, 0, 0);
+  }
   for (int q = 0; q < K; ++q) {
     const float tq = fmaf((float)q + 0.5f, step, a);
     const float ux = clamp01(fmaf(tq, d.x, -geo.x) * inv_h);
     const float uy = clamp01(fmaf(tq, d.y, -geo.y) * inv_h);
     const float uz = clamp01(fmaf(tq, d.z, -geo.z) * inv_h);
-    sum += explin(trilerp(ga, gb, ux, uy, uz), c, inv_c);
+    const float g = trilerp(ga, gb, ux, uy, uz);
+    sum += explin(g, c, inv_c);
+    if (MODE >= 1) {
+      const float coef = step * explin_grad(g, c, inv_c);
+      const float vx = 1.0f - ux, vy = 1.0f - uy, vz = 1.0f - uz;
+      o->dg[0] = fmaf(coef, vx * vy * vz, o->dg[0]);
+      o->dg[1] = fmaf(coef, ux * vy * vz, o->dg[1]);
+      o->dg[2] = fmaf(coef, vx * uy * vz, o->dg[2]);
+      o->dg[3] = fmaf(coef, ux * uy * vz, o->dg[3]);
+      o->dg[4] = fmaf(coef, vx * vy * uz, o->dg[4]);
+      o->dg[5] = fmaf(coef, ux * vy * uz, o->dg[5]);
+      o->dg[6] = fmaf(coef, vx * uy * uz, o->dg[6]);
+      o->dg[7] = fmaf(coef, ux * uy * uz, o->dg[7]);
+      if (MODE >= 2) {
+        const float f = ((float)q + 0.5f) * invK;
+        const float gx = vy * vz * (ga.y - ga.x) + uy * vz * (ga.w - ga.z) +
+                         vy * uz * (gb.y - gb.x) + uy * uz * (gb.w - gb.z);
+        const float gy = vx * vz * (ga.z - ga.x) + ux * vz * (ga.w - ga.y) +
+                         vx * uz * (gb.z - gb.x) + ux * uz * (gb.w - gb.y);
+        const float gz = vx * vy * (gb.x - ga.x) + ux * vy * (gb.y - ga.y) +
+                         vx * uy * (gb.z - ga.z) + ux * uy * (gb.w - ga.w);
+        const float s = coef * inv_h;
+        const float3 dtdx = make_float3(s * gx, s * gy, s * gz);
+        const float proj = dtdx.x * d.x + dtdx.y * d.y + dtdx.z * d.z;
+        pa = fmaf(proj, 1.0f - f, pa);
+        pb = fmaf(proj, f, pb);
+        o->dx.x += dtdx.x; o->dx.y += dtdx.y; o->dx.z += dtdx.z;
+        o->dxt.x = fmaf(tq, dtdx.x, o->dxt.x);
+        o->dxt.y = fmaf(tq, dtdx.y, o->dxt.y);
+        o->dxt.z = fmaf(tq, dtdx.z, o->dxt.z);
+      }
+    }
+  }
+  if (MODE >= 1) {
+    o->dtda = -sum * invK + pa;
+    o->dtdb = sum * invK + pb;
   }
   return sum * step;
+}
+
+__device__ inline float piece_tau(float4 geo, float4 ga, float4 gb,
+                                  float inv_h, float3 d, float a, float b,
+                                  int K, float invK, float c, float inv_c) {
+  return piece_eval<0>(geo, ga, gb, inv_h, d, a, b, K, invK, c, inv_c,
+                       nullptr);
 }
 
 // Real spherical harmonics up to degree 3 (Sec. 3.1 view-dependent
@@ -254,7 +333,8 @@ struct dv_fwd_state {
   std::vector<std::vector<dv_out_grads>> grads_keep;
   std::vector<std::vector<dv::OctGrad>> og_keep;
   dv::DBuf views_d, vo_d, outs_d;
-  dv::DBuf rec_geo, rec_g8a, rec_g8b, rec_cn, rec_nrm, rec_vox, rec_seg;
+  dv::DBuf rec_geo, rec_g8a, rec_g8b, rec_cn, rec_nrm, rec_vox, rec_seg,
+      rec_rect;
   dv::DBuf pair_val;
   dv::DBuf tile_start, tile_end, tile_bgend;
   dv::DBuf act_beg, act_oct, act_sub;

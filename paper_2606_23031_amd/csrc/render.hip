@@ -18,29 +18,66 @@ __host__ __device__ inline Rect bin_box(const double A[9], const double b[3],
                                         const double lo[3], const double hi[3],
                                         double fx, double fy, double cx,
                                         double cy, int x0, int y0, int w,
-                                        int h) {
-  double umin = 0, umax = 0, vmin = 0, vmax = 0;
+                                        int h, double rnear2) {
+  double X[8], Y[8], Z[8];
   bool allneg = true, anynear = false;
+  double bl[3], bh[3];
   for (int m = 0; m < 8; ++m) {
     const double x = (m & 1) ? hi[0] : lo[0];
     const double y = (m & 2) ? hi[1] : lo[1];
     const double z = (m & 4) ? hi[2] : lo[2];
-    const double X = ((A[0] * x + A[1] * y) + A[2] * z) + b[0];
-    const double Y = ((A[3] * x + A[4] * y) + A[5] * z) + b[1];
-    const double Z = ((A[6] * x + A[7] * y) + A[8] * z) + b[2];
-    allneg = allneg && (Z <= 0.0);
-    anynear = anynear || (Z < Z_EPS_D);
-    const double u = cx + fx * (X / Z);
-    const double v = cy + fy * (Y / Z);
-    if (m == 0) { umin = umax = u; vmin = vmax = v; }
-    else {
-      umin = fmin(umin, u); umax = fmax(umax, u);
-      vmin = fmin(vmin, v); vmax = fmax(vmax, v);
+    X[m] = ((A[0] * x + A[1] * y) + A[2] * z) + b[0];
+    Y[m] = ((A[3] * x + A[4] * y) + A[5] * z) + b[1];
+    Z[m] = ((A[6] * x + A[7] * y) + A[8] * z) + b[2];
+    allneg = allneg && (Z[m] <= 0.0);
+    anynear = anynear || (Z[m] < Z_EPS_D);
+    if (m == 0) {
+      bl[0] = bh[0] = X[0]; bl[1] = bh[1] = Y[0]; bl[2] = bh[2] = Z[0];
+    } else {
+      bl[0] = fmin(bl[0], X[m]); bh[0] = fmax(bh[0], X[m]);
+      bl[1] = fmin(bl[1], Y[m]); bh[1] = fmax(bh[1], Y[m]);
+      bl[2] = fmin(bl[2], Z[m]); bh[2] = fmax(bh[2], Z[m]);
     }
   }
   Rect r;
   if (allneg) { r.status = 0; r.xl = 1; r.xh = 0; r.yl = 1; r.yh = 0; return r; }
-  if (anynear) { r.status = 2; r.xl = 0; r.xh = w - 1; r.yl = 0; r.yh = h - 1; return r; }
+  if (anynear) {
+    double dd[3];
+    for (int a = 0; a < 3; ++a) dd[a] = fmax(fmax(bl[a], 0.0), -bh[a]);
+    const double dist2 = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2];
+    if (dist2 < rnear2) {
+      r.status = 2; r.xl = 0; r.xh = w - 1; r.yl = 0; r.yh = h - 1;
+      return r;
+    }
+  }
+  // projected points: corners in front of the plane Z = e, plus the
+  // crossings of the edges that straddle it
+  double umin = __builtin_huge_val(), umax = -__builtin_huge_val();
+  double vmin = __builtin_huge_val(), vmax = -__builtin_huge_val();
+  for (int m = 0; m < 8; ++m) {
+    if (Z[m] >= Z_EPS_D) {
+      const double u = cx + fx * (X[m] / Z[m]);
+      const double v = cy + fy * (Y[m] / Z[m]);
+      umin = fmin(umin, u); umax = fmax(umax, u);
+      vmin = fmin(vmin, v); vmax = fmax(vmax, v);
+    }
+  }
+  if (anynear) {
+    for (int bit = 1; bit < 8; bit <<= 1) {
+      for (int m = 0; m < 8; ++m) {
+        if (m & bit) continue;
+        const int m2 = m | bit;
+        if ((Z[m] < Z_EPS_D) == (Z[m2] < Z_EPS_D)) continue;
+        const double t = (Z_EPS_D - Z[m]) / (Z[m2] - Z[m]);
+        const double xi = X[m] + t * (X[m2] - X[m]);
+        const double yi = Y[m] + t * (Y[m2] - Y[m]);
+        const double u = cx + fx * (xi / Z_EPS_D);
+        const double v = cy + fy * (yi / Z_EPS_D);
+        umin = fmin(umin, u); umax = fmax(umax, u);
+        vmin = fmin(vmin, v); vmax = fmax(vmax, v);
+      }
+    }
+  }
   r.status = 1;
   double lo_x = ceil(fmin(fmax(umin - 0.5625, x0 - 1.0), x0 + (double)w));
   double hi_x = floor(fmin(fmax(umax - 0.4375, x0 - 1.0), x0 + (double)w));
@@ -105,7 +142,7 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
       bhi[a] = O.root_min[a] + (double)(ijk[a] + 1) * h;
     }
     r = bin_box(C.A, C.b, blo, bhi, V.fx, V.fy, V.cx, V.cy, V.x0, V.y0, V.w,
-                V.h);
+                V.h, V.rnear2);
     vis = r.status != 0 && r.xl <= r.xh && r.yl <= r.yh;
   }
   const uint64_t m = __ballot(vis);
@@ -146,10 +183,10 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
   p.keys[slot] = ((uint64_t)s << p.rank_bits) | rank;
   p.vals[slot] = slot;
   p.s_vox[slot] = (uint32_t)vox;
-  p.s_rect[slot] = (uint64_t)(uint32_t)(r.xl >> 4) |
-                   ((uint64_t)(uint32_t)(r.yl >> 4) << 16) |
-                   ((uint64_t)(uint32_t)(r.xh >> 4) << 32) |
-                   ((uint64_t)(uint32_t)(r.yh >> 4) << 48);
+  // window-relative covered pixel bounds (inclusive), 16 bits each
+  p.s_rect[slot] = (uint64_t)(uint32_t)r.xl | ((uint64_t)(uint32_t)r.xh << 16) |
+                   ((uint64_t)(uint32_t)r.yl << 32) |
+                   ((uint64_t)(uint32_t)r.yh << 48);
   // leaf record in the octree frame relative to the camera
   const double h = ldexp(O.root_size, -l);
   double rel[3];
@@ -210,8 +247,8 @@ __global__ void k_gather(int64_t n, const uint64_t* __restrict__ keys,
   r_vox[i] = s_vox[sl];
   r_seg[i] = (uint32_t)(keys[i] >> rank_bits);
   const uint64_t rc = s_rect[sl];
-  const uint32_t tx0 = rc & 0xFFFF, ty0 = (rc >> 16) & 0xFFFF;
-  const uint32_t tx1 = (rc >> 32) & 0xFFFF, ty1 = (rc >> 48) & 0xFFFF;
+  const uint32_t tx0 = (rc & 0xFFFF) >> 4, tx1 = ((rc >> 16) & 0xFFFF) >> 4;
+  const uint32_t ty0 = ((rc >> 32) & 0xFFFF) >> 4, ty1 = (rc >> 48) >> 4;
   r_count[i] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
   r_rect[i] = rc;
 }
@@ -231,8 +268,8 @@ __global__ void k_emit(int64_t n_pairs, int64_t n_rec,
     if ((int64_t)off[mid] <= p) lo = mid; else hi = mid - 1;
   }
   const uint64_t rc = rect[lo];
-  const uint32_t tx0 = rc & 0xFFFF, ty0 = (rc >> 16) & 0xFFFF;
-  const uint32_t tx1 = (rc >> 32) & 0xFFFF;
+  const uint32_t tx0 = (rc & 0xFFFF) >> 4, tx1 = ((rc >> 16) & 0xFFFF) >> 4;
+  const uint32_t ty0 = ((rc >> 32) & 0xFFFF) >> 4;
   const uint32_t wdt = tx1 - tx0 + 1;
   const uint32_t i = (uint32_t)(p - off[lo]);
   const ViewConst& V = views[seg[lo] / n_oct];
@@ -288,6 +325,7 @@ struct Batch {
   float4 gb[TPB];
   float4 cn[TPB];
   float4 nrm[TPB];
+  uint2 rect[TPB];
 };
 
 __device__ inline void load_batch(Batch& B, const CompArgs& a, uint32_t base,
@@ -300,6 +338,8 @@ __device__ inline void load_batch(Batch& B, const CompArgs& a, uint32_t base,
     B.gb[tid] = a.rec_g8b[r];
     B.cn[tid] = a.rec_cn[r];
     B.nrm[tid] = a.rec_nrm[r];
+    const uint64_t rc = a.rec_rect[r];
+    B.rect[tid] = make_uint2((uint32_t)rc, (uint32_t)(rc >> 32));
   }
 }
 
@@ -392,8 +432,10 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
   const int v = view_of_tile(a.views, a.n_views, gt);
   const ViewConst& V = a.views[v];
   const uint32_t lt = gt - V.tile_base;
-  const int px = (int)(lt % V.ntx) * TILE + (tid & 15);
-  const int py = (int)(lt / V.ntx) * TILE + (tid >> 4);
+  const int px = (int)(lt % V.ntx) * TILE + tile_px(tid);
+  const int py = (int)(lt / V.ntx) * TILE + tile_py(tid);
+  const int bx = (int)(lt % V.ntx) * TILE + (((tid >> 6) & 1) << 3);
+  const int by = (int)(lt / V.ntx) * TILE + (((tid >> 6) >> 1) << 3);
   const bool valid = px < V.w && py < V.h;
   float3 d;
   {
@@ -438,6 +480,7 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
       load_batch(B, a, base, nb);
       __syncthreads();
       for (uint32_t r = 0; r < nb && has; ++r) {
+        if (!rect_hits_block(B.rect[r], bx, by)) continue;
         const float4 geo = B.geo[r];
         float t0, t1;
         slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
@@ -518,6 +561,7 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
     load_batch(B, a, base, nb);
     __syncthreads();
     for (uint32_t r = 0; r < nb && !done; ++r) {
+      if (!rect_hits_block(B.rect[r], bx, by)) continue;
       const float4 geo = B.geo[r];
       float t0, t1;
       slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
@@ -646,6 +690,19 @@ dv_status setup_state(dv_fwd_state* st, const dv_scene* sc,
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) V.Rc[r * 3 + c] = (float)in.c2w[r * 4 + c];
     V.x0 = in.x0; V.y0 = in.y0; V.w = in.w; V.h = in.h;
+    {
+      // r_near^2 = (2e)^2 max over window corner pixel centres |(x, y, 1)|^2
+      double m2 = 0.0;
+      const int pxs[2] = {in.x0, in.x0 + in.w - 1};
+      const int pys[2] = {in.y0, in.y0 + in.h - 1};
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          const double x = (pxs[i] + 0.5 - in.cx) / in.fx;
+          const double y = (pys[j] + 0.5 - in.cy) / in.fy;
+          m2 = std::max(m2, (1.0 + x * x) + y * y);
+        }
+      V.rnear2 = (2.0 * Z_EPS_D) * (2.0 * Z_EPS_D) * m2;
+    }
     V.ntx = (in.w + TILE - 1) / TILE;
     V.nty = (in.h + TILE - 1) / TILE;
     V.tile_base = tile_base;
@@ -731,7 +788,7 @@ dv_status setup_state(dv_fwd_state* st, const dv_scene* sc,
       if (k > 0 && active) {
         const ViewConst& V = st->views_h[v];
         Rect r = bin_box(C.A, C.b, blo, bhi, V.fx, V.fy, V.cx, V.cy, V.x0,
-                         V.y0, V.w, V.h);
+                         V.y0, V.w, V.h, V.rnear2);
         if (r.status != 0 && r.xl <= r.xh && r.yl <= r.yh) {
           for (int ty = r.yl >> 4; ty <= (r.yh >> 4); ++ty)
             for (int tx = r.xl >> 4; tx <= (r.xh >> 4); ++tx)
@@ -769,6 +826,18 @@ dv_status setup_state(dv_fwd_state* st, const dv_scene* sc,
     }
   }
   return DV_OK;
+}
+
+// One pinned host word per calling thread for device->host counts, so
+// concurrent renders on different streams never wait for each other.
+static uint64_t* pinned_word() {
+  static thread_local uint64_t* w = nullptr;
+  if (!w && hipHostMalloc((void**)&w, 64, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("pinned host allocation failed");
+    w = nullptr;
+  }
+  return w;
 }
 
 // Enqueue the whole forward pass on stream s.  Two host synchronisations
@@ -835,10 +904,12 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   }
   uint64_t n_vis = 0;
   {
-    std::lock_guard<std::mutex> lk(ctx->pinned_mu);
-    DV_TRY_HIP(hipMemcpyAsync(ctx->pinned, total.p, 8, hipMemcpyDeviceToHost, s));
+    uint64_t* pin = pinned_word();
+    if (!pin) return DV_ERR_OOM;
+    StageTimer tm(ctx, ST_HOST_SYNC, s);
+    DV_TRY_HIP(hipMemcpyAsync(pin, total.p, 8, hipMemcpyDeviceToHost, s));
     DV_TRY_HIP(hipStreamSynchronize(s));
-    n_vis = ctx->pinned[0];
+    n_vis = *pin;
   }
   st->n_vis = (int64_t)n_vis;
   if (n_vis >= 0xFFFFFFFFull) {
@@ -886,7 +957,8 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   uint64_t* ks = alt ? keys2.as<uint64_t>() : keys.as<uint64_t>();
   uint32_t* vs = alt ? vals2.as<uint32_t>() : vals.as<uint32_t>();
   // records in sorted order
-  DBuf r_count, r_off, r_rect;
+  DBuf r_count, r_off;
+  DBuf& r_rect = st->rec_rect;
   DV_TRY(alloc_n<float4>(ctx, st->rec_geo, nv, s));
   DV_TRY(alloc_n<float4>(ctx, st->rec_g8a, nv, s));
   DV_TRY(alloc_n<float4>(ctx, st->rec_g8b, nv, s));
@@ -914,10 +986,11 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   tm_gather.stop();
   uint64_t n_pairs = 0;
   {
-    std::lock_guard<std::mutex> lk(ctx->pinned_mu);
-    DV_TRY_HIP(hipMemcpyAsync(ctx->pinned, total.p, 8, hipMemcpyDeviceToHost, s));
+    uint64_t* pin = pinned_word();
+    if (!pin) return DV_ERR_OOM;
+    DV_TRY_HIP(hipMemcpyAsync(pin, total.p, 8, hipMemcpyDeviceToHost, s));
     DV_TRY_HIP(hipStreamSynchronize(s));
-    n_pairs = ctx->pinned[0];
+    n_pairs = *pin;
   }
   if (n_pairs >= 0xFFFFFFFFull) {
     set_error("%llu (leaf, tile) pairs exceed the 32-bit range",
@@ -1018,6 +1091,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   ca.rec_g8b = st->rec_g8b.as<float4>();
   ca.rec_cn = st->rec_cn.as<float4>();
   ca.rec_nrm = st->rec_nrm.as<float4>();
+  ca.rec_rect = st->rec_rect.as<uint64_t>();
   ca.act_beg = st->act_beg.as<uint32_t>();
   ca.act_oct = st->act_oct.as<uint32_t>();
   ca.act_sub = st->act_sub.as<uint2>();

@@ -497,3 +497,31 @@ def test_eps_stop_bounded_change():
     a = RD.render_image(sc, v, dict(cfg["opts"], eps_stop=0.0))
     b = RD.render_image(sc, v, dict(cfg["opts"], eps_stop=0.2))
     assert np.abs(a["rgb"] - b["rgb"]).max() <= 0.2 * 1.0 + 1e-12
+
+
+def test_p13_binning_superset_near_plane_boxes():
+    # camera a fraction of a millimetre from leaf faces, wide field of view:
+    # many leaves straddle the plane Z = 1e-3 and get clipped rectangles
+    rng = np.random.default_rng(21)
+    o = random_octree(rng, (-1, -1, -1), 2.0, 3, 60, 5, 0)
+    for eye, tgt in (((0.0003, 0.2502, -0.0004), (1.0, 0.3, 0.1)),
+                     ((0.5, 0.5001, 0.4998), (-1.0, 0.2, 0.6))):
+        v = make_view(40, 32, 100.0, look_at_c2w(eye, tgt))
+        sc = dict(octrees=[o], tracks=[None])
+        poses = G.octree_poses(sc, v)
+        st, *_ = B.leaf_rects(o, v, poses[0][1], poses[0][2])
+        lists = B.expected_tile_lists(sc, v, poses)
+        sets = {t: set(l) for t, l in lists.items()}
+        ctx = RD.ViewContext(sc, v, OPTS)
+        ntx = (v["w"] + 15) // 16
+        ent = ctx.oct[0]
+        n_full = int((st == 2).sum())
+        for py in range(v["h"]):
+            for px in range(v["w"]):
+                o_, d_ = G.camera_ray(v, px, py)
+                t0, t1, _, _ = G.slab_many(o_, d_, ent["vmin"], ent["vmax"])
+                tile = (py >> 4) * ntx + (px >> 4)
+                for vv in np.nonzero(t1 > np.maximum(t0, 0.0))[0]:
+                    assert (0, int(vv)) in sets.get(tile, ()), (vv, tile)
+        # the near-plane rule keeps most straddling leaves off the full window
+        assert n_full < 30
