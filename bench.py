@@ -234,6 +234,29 @@ def serve_run(dv, ctx, sc, opts, views, rate, batched, seed):
                 requests=len(views), offered_req_per_s=rate)
 
 
+KERNEL_OF_STAGE = {"composite_fwd": "dv::k_composite_fwd", "composite_bwd": "dv::k_composite_bwd",
+                   "record_bwd": "dv::k_record_bwd", "preprocess": "dv::k_preprocess<1>",
+                   "emit_pairs": "dv::k_emit", "gather_scan": "dv::k_gather"}
+
+
+def stored_traffic(stage, workload):
+    """HBM bytes (read + write) per launch of the stage's kernel from the
+    committed rocprofv3 counter summary, or None when the kernels have
+    changed since those counters were taken."""
+    from paper_2606_23031_amd.srchash import csrc_hash
+    path = os.path.join(ROOT, "profiles", "traffic_driving-1M-8x20k-1080p.json")
+    if not os.path.exists(path) or stage not in KERNEL_OF_STAGE:
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("csrc_hash") != csrc_hash() or d.get("workload") != workload:
+        return None
+    for name, v in d["kernels"].items():
+        if name.startswith(KERNEL_OF_STAGE[stage]):
+            return round(v["fetch_bytes"] + v["write_bytes"])
+    return None
+
+
 def roofline(stage, ms, calls, info, counters, scene_stats):
     """Roofline entry for the dominant stage (per launch)."""
     per = ms / max(calls, 1) / 1e3   # seconds per launch
@@ -315,6 +338,7 @@ def main():
     items = sum(len(o["level"]) for o in cfg["scene"]["octrees"]) * len(views)
     rl = roofline(dom, stages[dom][0], stages[dom][1], step.last_info, counters,
                   dict(items=items, S=S))
+    rl["traffic"] = stored_traffic(dom, cfg["name"])
     out = {
         "metric": "fwd+bwd Mpix/s per train step",
         "value": round(value, 3),
