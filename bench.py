@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-saturate", type=int, default=400,
+                    help="requests of the back-to-back capacity run (0: skip)")
     return ap.parse_args()
 
 
@@ -179,7 +181,10 @@ def serve_run(dv, ctx, sc, opts, views, rate, batched, seed):
                              max_inflight=16, mem_budget=16 << 30,
                              batched=batched, max_batch=8)
     rng = np.random.default_rng(seed)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, len(views)))
+    if np.isinf(rate):
+        arrivals = np.zeros(len(views))        # all queued at once: capacity
+    else:
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, len(views)))
     free = {}
     lock = threading.Lock()
     tickets = [None] * len(views)
@@ -194,7 +199,7 @@ def serve_run(dv, ctx, sc, opts, views, rate, batched, seed):
         return dv.alloc_outputs([v], mask)[0]
 
     # warm the buffer pool and the server (untimed)
-    warm = [get_buf(v) for v in views[:48]]
+    warm = [get_buf(v) for v in (views if np.isinf(rate) else views[:48])]
     for b in warm:
         free.setdefault((b["rgb"].shape[2], b["rgb"].shape[1]), []).append(b)
     torch.cuda.synchronize()
@@ -231,7 +236,8 @@ def serve_run(dv, ctx, sc, opts, views, rate, batched, seed):
                 mpix_per_s=round(pix / span / 1e6, 2),
                 p50_ms=round(float(np.percentile(lat, 50)), 3),
                 p99_ms=round(float(np.percentile(lat, 99)), 3),
-                requests=len(views), offered_req_per_s=rate)
+                requests=len(views),
+                offered_req_per_s=None if np.isinf(rate) else rate)
 
 
 KERNEL_OF_STAGE = {"composite_fwd": "dv::k_composite_fwd", "composite_bwd": "dv::k_composite_bwd",
@@ -374,6 +380,14 @@ def main():
                               args.serve_rate, True, seed=5),
             per_request=serve_run(dv, ctx, step.sc, cfg["opts"], sv,
                                   args.serve_rate, False, seed=5))
+        if args.serve_saturate > 0:
+            sat = sv[:args.serve_saturate]
+            log(f"[bench] serving capacity: {len(sat)} requests queued at once ...")
+            out["serving"]["capacity"] = dict(
+                batched=serve_run(dv, ctx, step.sc, cfg["opts"], sat,
+                                  float("inf"), True, seed=6),
+                per_request=serve_run(dv, ctx, step.sc, cfg["opts"], sat,
+                                      float("inf"), False, seed=6))
         log(f"[bench] serving: {out['serving']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle baseline ...")

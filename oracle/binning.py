@@ -186,10 +186,13 @@ def leaf_ranks(o, view, R, p):
     return rank.astype(np.uint64)
 
 
-def expected_tile_lists(scene, view, poses):
+def expected_tile_lists(scene, view, poses, tiles=None):
     """Reference tile lists: dict (tile id) -> list of (octree, leaf) in
-    (octree, rank) order.  ``poses`` as from geometry.octree_poses."""
+    (octree, rank) order.  ``poses`` as from geometry.octree_poses.  With
+    ``tiles`` (iterable of tile ids) only those lists are built."""
     ntx = (view["w"] + 15) // 16
+    if tiles is not None:
+        return _tile_lists_subset(scene, view, poses, sorted(set(tiles)), ntx)
     lists = {}
     for k, o in enumerate(scene["octrees"]):
         active, R, p = poses[k]
@@ -203,6 +206,24 @@ def expected_tile_lists(scene, view, poses):
             for ty in range(yl[vv] >> 4, (yh[vv] >> 4) + 1):
                 for tx in range(xl[vv] >> 4, (xh[vv] >> 4) + 1):
                     lists.setdefault(ty * ntx + tx, []).append((k, int(vv)))
+    return lists
+
+
+def _tile_lists_subset(scene, view, poses, tiles, ntx):
+    lists = {t: [] for t in tiles}
+    for k, o in enumerate(scene["octrees"]):
+        active, R, p = poses[k]
+        if not active:
+            continue
+        st, xl, xh, yl, yh = leaf_rects(o, view, R, p)
+        vis = (st > 0) & (xl <= xh) & (yl <= yh)
+        rk = leaf_ranks(o, view, R, p)
+        for t in tiles:
+            tx, ty = t % ntx, t // ntx
+            sel = np.nonzero(vis & ((xl >> 4) <= tx) & ((xh >> 4) >= tx) &
+                             ((yl >> 4) <= ty) & ((yh >> 4) >= ty))[0]
+            sel = sel[np.argsort(rk[sel], kind="stable")]
+            lists[t].extend((k, int(v)) for v in sel)
     return lists
 
 

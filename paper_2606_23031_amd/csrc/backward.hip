@@ -64,12 +64,40 @@ __device__ inline void load_bwd_batch(BwdBatch& B, const CompArgs& a,
   }
 }
 
+// Lane exchanges of the reduction below (gfx950).  swap32 / swap16 pair
+// the two registers across lane halves / 16-lane rows so that a + b leaves
+// the upper half (odd rows) with the sum of the second register and the
+// lower half (even rows) with the sum of the first; dpp() reads a lane of
+// the same 16-lane row.
+__device__ inline float swap32_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a),
+                                                  __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline float swap16_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a),
+                                                  __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+template <int CTRL>
+__device__ inline float dpp(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+constexpr int DPP_ROR8 = 0x128;         // row_ror:8  -> lane ^ 8 in a row
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane ^ 7 within 8 lanes
+constexpr int DPP_XOR2 = 0x4E;          // quad_perm [2,3,0,1]
+constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1,0,3,2]
+
 // Reduce one lane-contribution set into the batch slot r.  The 14
 // channels (padded to 16) are summed over the wave with a transposing
 // butterfly: at each exchange a lane keeps half of its channels and adds the
-// partner's copy of them, so 17 shuffles leave lane l holding the full sum
-// of channel l >> 2; lanes with l % 4 == 0 then add their channel into LDS.
-// Must be called wave-uniformly.
+// partner's copy of them (partners lane ^ 32, ^ 16, ^ 8, ^ 7, then ^ 2 and
+// ^ 1 on the last channel; together they span all 64 lanes), which leaves
+// lane l with the full sum of channel l >> 2; lanes with l % 4 == 0 then add
+// their channel into LDS.  Cross-half and cross-row steps use the gfx950
+// permlane swaps, in-row steps DPP, so no exchange goes through LDS.  Must
+// be called wave-uniformly with every lane active.
 __device__ inline void accum_record(BwdBatch& B, uint32_t r, bool hit,
                                     float3 dcol, float3 dnrm,
                                     const float* dg) {
@@ -86,18 +114,31 @@ __device__ inline void accum_record(BwdBatch& B, uint32_t r, bool hit,
 #pragma unroll
     for (int c = 0; c < 16; ++c) v[c] = 0.0f;
   }
+  // lane bit 5: channels 0-7 stay in the lower half, 8-15 in the upper
 #pragma unroll
-  for (int m = 32, n = 8; n >= 1; m >>= 1, n >>= 1) {
-    const bool upper = (lane & m) != 0;
+  for (int i = 0; i < 8; ++i) v[i] = swap32_sum(v[i], v[i + 8]);
+  // lane bit 4 (rows)
 #pragma unroll
-    for (int i = 0; i < n; ++i) {
-      const float send = upper ? v[i] : v[i + n];
-      const float keep = upper ? v[i + n] : v[i];
-      v[i] = keep + __shfl_xor(send, m, 64);
+  for (int i = 0; i < 4; ++i) v[i] = swap16_sum(v[i], v[i + 4]);
+  // lane bit 3: partner lane ^ 8
+  {
+    const bool up = (lane & 8) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float send = up ? v[i] : v[i + 2];
+      const float keep = up ? v[i + 2] : v[i];
+      v[i] = keep + dpp<DPP_ROR8>(send);
     }
   }
-  v[0] += __shfl_xor(v[0], 2, 64);
-  v[0] += __shfl_xor(v[0], 1, 64);
+  // lane bit 2: partner lane ^ 7 (opposite bit 2)
+  {
+    const bool up = (lane & 4) != 0;
+    const float send = up ? v[0] : v[1];
+    const float keep = up ? v[1] : v[0];
+    v[0] = keep + dpp<DPP_HALF_MIRROR>(send);
+  }
+  v[0] += dpp<DPP_XOR2>(v[0]);
+  v[0] += dpp<DPP_XOR1>(v[0]);
   const int ch = lane >> 2;
   if ((lane & 3) == 0 && ch < NACC && v[0] != 0.0f) atomicAdd(&B.acc[ch][r], v[0]);
 }
@@ -155,11 +196,15 @@ __device__ inline void pose12(const VOConst& C, float3 d, float3 go, float3 gd,
                    C.R[b * 3 + 2] * g_o[2]);
 }
 
-template <bool NORMALS>
+// Backward compositing: the forward walk re-run in the same order with the
+// same arithmetic (so T and every stop decision repeat bit for bit), giving
+// dL/dtau_i = T_{i+1} v_i - S_{i+1} with the suffix S formed against the
+// totals, or against the tail sums once T < T_REBASE.
+template <bool NORMALS, int KC>
 __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
   __shared__ BwdBatch B;
   __shared__ float red[(TPB / 64) * 12];
-  const uint32_t gt = blockIdx.x;
+  const uint32_t gt = a.tile_order[blockIdx.x];
   const int tid = threadIdx.x;
   for (int c = 0; c < NACC; ++c) B.acc[c][tid] = 0.0f;
   const int v = view_of_tile(a.views, a.n_views, gt);
@@ -184,7 +229,7 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
   uint32_t n_test = 0, n_piece = 0;
   // upstream gradients and the scalar L
   float3 GC = make_float3(0, 0, 0), GN = make_float3(0, 0, 0);
-  float GD = 0.0f, GT = 0.0f, L = 0.0f;
+  float GD = 0.0f, GT = 0.0f, L = 0.0f, LB = 0.0f, LT = 0.0f;
   if (valid) {
     const dv_out_grads& G = a.gin[v];
     const size_t hw = (size_t)V.w * V.h, o = (size_t)py * V.w + px;
@@ -194,9 +239,12 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
       GN = make_float3(G.normal[o], G.normal[hw + o], G.normal[2 * hw + o]);
     if (G.T) GT = G.T[o];
     const float4 f0 = a.fin0[pix], f1 = a.fin1[pix];
+    LB = (GC.x * a.bg[0] + GC.y * a.bg[1] + GC.z * a.bg[2] + GT) * f1.w;
     L = GC.x * f0.x + GC.y * f0.y + GC.z * f0.z + GD * f0.w +
-        GN.x * f1.x + GN.y * f1.y + GN.z * f1.z +
-        (GC.x * a.bg[0] + GC.y * a.bg[1] + GC.z * a.bg[2] + GT) * f1.w;
+        GN.x * f1.x + GN.y * f1.y + GN.z * f1.z + LB;
+    const float4 f2 = a.fin2[pix], f3 = a.fin3[pix];
+    LT = GC.x * f2.x + GC.y * f2.y + GC.z * f2.z + GD * f2.w +
+         GN.x * f3.x + GN.y * f3.y + GN.z * f3.z + LB;
   }
   const uint32_t a_beg = a.act_beg[gt];
   const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
@@ -207,113 +255,159 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
 
   // ---------------------------------------------------- B1: background
   {
-    float T = 1.0f, P = 0.0f;
+    float T = 1.0f, P = 0.0f, PT = 0.0f;
     bool done = !valid;
-    int qn = 0;
-    float ns = nseg > 0 ? a.seg_se[seg_index(seg0, tid)].x : F_INF;
-    float excl = -F_INF;
     const float3 inv = safe_inv(d);
     const uint32_t beg = a.tile_start[gt], bgend = a.tile_bgend[gt];
-    for (uint32_t base = beg; base < bgend; base += TPB) {
-      const uint32_t nb = min((uint32_t)TPB, bgend - base);
-      load_bwd_batch(B, a, base, nb);
-      __syncthreads();
-      for (uint32_t r = 0; r < nb; ++r) {
-        if (!rect_hits_block(B.rect[r], bx, by)) continue;
-        const float4 geo = B.geo[r];
-        float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
-        float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        bool hit = false;
-        if (!done) {
-          float t0, t1;
-          slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
-          ++n_test;
-          t0 = fmaxf(t0, a.tau_near);
-          if (t1 > t0) {
-            float pa = fmaxf(t0, excl);
-            bool a_seg = excl > t0;
-            while (pa < t1 && !done) {
-              if (pa >= ns) {
-                const size_t qi = seg_index(seg0 + qn, tid);
-                const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
-                const float Vq = GC.x * q0.x + GC.y * q0.y + GC.z * q0.z +
-                                 GD * q0.w + GN.x * q1.x + GN.y * q1.y +
-                                 GN.z * q1.z;
-                const float Tpre = T;
-                P = fmaf(T, Vq, P);
-                T *= q1.w;
-                // keep .z: the piece just before may have added dL/dstart
-                float4 bw = a.seg_bw[qi];
-                bw.x = Tpre;
-                bw.y = L - P;
-                a.seg_bw[qi] = bw;
-                const float ex = a.seg_se[qi].y;
-                if (ex > pa) { pa = ex; a_seg = true; }
-                excl = ex;
-                ++qn;
-                ns = qn < nseg ? a.seg_se[seg_index(seg0 + qn, tid)].x : F_INF;
-                if (T < a.eps) done = true;
-                continue;
-              }
-              const bool b_seg = ns < t1;
-              const float pb = fminf(t1, ns);
-              const float4 cn = B.cn[r];
-              PieceDer pd;
-              const float tau =
-                  (a_seg || b_seg)
-                      ? piece_eval<2>(geo, B.ga[r], B.gb[r], cn.w, d, pa, pb, K,
-                                      invK, a.c, a.inv_c, &pd)
-                      : piece_eval<1>(geo, B.ga[r], B.gb[r], cn.w, d, pa, pb, K,
-                                      invK, a.c, a.inv_c, &pd);
-              ++n_piece;
-              const float e = fast_exp(-tau);
-              const float wgt = T * (1.0f - e);
-              const float4 nr = B.nrm[r];
-              const float mid = 0.5f * (pa + pb);
-              float vi = GC.x * cn.x + GC.y * cn.y + GC.z * cn.z + GD * mid;
-              if (NORMALS) vi += GN.x * nr.x + GN.y * nr.y + GN.z * nr.z;
-              const float Tn = T * e;
-              P = fmaf(wgt, vi, P);
-              const float dtau = Tn * vi - (L - P);
-              hit = true;
-              dcol.x += wgt * GC.x; dcol.y += wgt * GC.y; dcol.z += wgt * GC.z;
-              if (NORMALS) {
-                dnrm.x += wgt * GN.x; dnrm.y += wgt * GN.y; dnrm.z += wgt * GN.z;
-              }
+    auto suffix = [&]() { return T < T_REBASE ? LT - PT : L - P; };
+    // composite one piece of entry r and add its colour/normal/corner
+    // gradients; returns dL/dtau, the piece's weight in wgt
+    auto piece_grad = [&](uint32_t r, float tau, const PieceDer& pd, float pa,
+                          float pb, float3& dcol, float3& dnrm, float* dg,
+                          float& wgt) {
+      const float4 cn = B.cn[r];
+      const float e = fast_exp(-tau);
+      wgt = T * opacity(tau, e);
+      const float wt = T < T_REBASE ? wgt : 0.0f;
+      const float mid = 0.5f * (pa + pb);
+      float vi = GC.x * cn.x + GC.y * cn.y + GC.z * cn.z + GD * mid;
+      if (NORMALS) {
+        const float4 nr = B.nrm[r];
+        vi += GN.x * nr.x + GN.y * nr.y + GN.z * nr.z;
+      }
+      P = fmaf(wgt, vi, P);
+      PT = fmaf(wt, vi, PT);
+      T *= e;
+      const float dtau = T * vi - suffix();
+      dcol.x += wgt * GC.x; dcol.y += wgt * GC.y; dcol.z += wgt * GC.z;
+      if (NORMALS) {
+        dnrm.x += wgt * GN.x; dnrm.y += wgt * GN.y; dnrm.z += wgt * GN.z;
+      }
 #pragma unroll
-              for (int m = 0; m < 8; ++m) dg[m] = fmaf(dtau, pd.dg[m], dg[m]);
-              if (a_seg && qn > 0)
-                a.seg_bw[seg_index(seg0 + qn - 1, tid)].w +=
-                    dtau * pd.dtda + 0.5f * wgt * GD;
-              if (b_seg)
-                a.seg_bw[seg_index(seg0 + qn, tid)].z +=
-                    dtau * pd.dtdb + 0.5f * wgt * GD;
-              T = Tn;
-              if (T < a.eps) done = true;
-              pa = pb;
-              a_seg = false;
+      for (int m = 0; m < 8; ++m) dg[m] = fmaf(dtau, pd.dg[m], dg[m]);
+      if (T < a.eps) done = true;
+      return dtau;
+    };
+    if (n_at == 0) {
+      for (uint32_t base = beg; base < bgend; base += TPB) {
+        const uint32_t nb = min((uint32_t)TPB, bgend - base);
+        load_bwd_batch(B, a, base, nb);
+        __syncthreads();
+        uint64_t wm[4];
+        wave_entry_masks(B.rect, nb, bx, by, wm);
+        for (int c = 0; c < 4; ++c) {
+          uint64_t m = wm[c];
+          while (m != 0 && __ballot(!done) != 0) {
+            const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
+            m &= m - 1;
+            float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
+            float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            bool hit = false;
+            if (!done) {
+              const float4 geo = B.geo[r];
+              float t0, t1;
+              slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+              ++n_test;
+              t0 = fmaxf(t0, a.tau_near);
+              if (t1 > t0) {
+                PieceDer pd;
+                const float tau = piece_eval<1, KC>(geo, B.ga[r], B.gb[r], B.cn[r].w,
+                                                    d, t0, t1, K, invK, a.c,
+                                                    a.inv_c, &pd);
+                ++n_piece;
+                float wgt;
+                piece_grad(r, tau, pd, t0, t1, dcol, dnrm, dg, wgt);
+                hit = true;
+              }
             }
+            accum_record(B, r, hit, dcol, dnrm, dg);
           }
         }
-        accum_record(B, r, hit, dcol, dnrm, dg);
+        flush_batch(B, a, nb);
+        if (__syncthreads_and(done)) break;
       }
-      flush_batch(B, a, nb);
-      if (__syncthreads_and(done)) break;
-    }
-    while (!done && qn < nseg) {
-      const size_t qi = seg_index(seg0 + qn, tid);
-      const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
-      const float Vq = GC.x * q0.x + GC.y * q0.y + GC.z * q0.z + GD * q0.w +
-                       GN.x * q1.x + GN.y * q1.y + GN.z * q1.z;
-      const float Tpre = T;
-      P = fmaf(T, Vq, P);
-      T *= q1.w;
-      float4 bw = a.seg_bw[qi];
-      bw.x = Tpre;
-      bw.y = L - P;
-      a.seg_bw[qi] = bw;
-      ++qn;
-      if (T < a.eps) done = true;
+    } else {
+      int qn = 0;
+      float ns = nseg > 0 ? a.seg_se[seg_index(seg0, tid)].x : F_INF;
+      float excl = -F_INF;
+      auto splice = [&](int qq) {
+        const size_t qi = seg_index(seg0 + qq, tid);
+        const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
+        const float Vq = GC.x * q0.x + GC.y * q0.y + GC.z * q0.z + GD * q0.w +
+                         GN.x * q1.x + GN.y * q1.y + GN.z * q1.z;
+        const float Tpre = T;
+        P = fmaf(T, Vq, P);
+        PT = fmaf(T < T_REBASE ? T : 0.0f, Vq, PT);
+        T *= q1.w;
+        // keep .z: the piece just before may have added dL/dstart
+        float4 bw = a.seg_bw[qi];
+        bw.x = Tpre;
+        bw.y = suffix();
+        a.seg_bw[qi] = bw;
+        if (T < a.eps) done = true;
+      };
+      for (uint32_t base = beg; base < bgend; base += TPB) {
+        const uint32_t nb = min((uint32_t)TPB, bgend - base);
+        load_bwd_batch(B, a, base, nb);
+        __syncthreads();
+        for (uint32_t r = 0; r < nb; ++r) {
+          if (!rect_hits_block(B.rect[r], bx, by)) continue;
+          const float4 geo = B.geo[r];
+          float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
+          float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+          bool hit = false;
+          if (!done) {
+            float t0, t1;
+            slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+            ++n_test;
+            t0 = fmaxf(t0, a.tau_near);
+            if (t1 > t0) {
+              float pa = fmaxf(t0, excl);
+              bool a_seg = excl > t0;
+              while (pa < t1 && !done) {
+                if (pa >= ns) {
+                  const float ex = a.seg_se[seg_index(seg0 + qn, tid)].y;
+                  splice(qn);
+                  if (ex > pa) { pa = ex; a_seg = true; }
+                  excl = ex;
+                  ++qn;
+                  ns = qn < nseg ? a.seg_se[seg_index(seg0 + qn, tid)].x : F_INF;
+                  continue;
+                }
+                const bool b_seg = ns < t1;
+                const float pb = fminf(t1, ns);
+                const float inv_h = B.cn[r].w;
+                PieceDer pd;
+                const float tau =
+                    (a_seg || b_seg)
+                        ? piece_eval<2, KC>(geo, B.ga[r], B.gb[r], inv_h, d, pa, pb,
+                                            K, invK, a.c, a.inv_c, &pd)
+                        : piece_eval<1, KC>(geo, B.ga[r], B.gb[r], inv_h, d, pa, pb,
+                                            K, invK, a.c, a.inv_c, &pd);
+                ++n_piece;
+                float wgt;
+                const float dtau = piece_grad(r, tau, pd, pa, pb, dcol, dnrm, dg, wgt);
+                hit = true;
+                if (a_seg && qn > 0)
+                  a.seg_bw[seg_index(seg0 + qn - 1, tid)].w +=
+                      dtau * pd.dtda + 0.5f * wgt * GD;
+                if (b_seg)
+                  a.seg_bw[seg_index(seg0 + qn, tid)].z +=
+                      dtau * pd.dtdb + 0.5f * wgt * GD;
+                pa = pb;
+                a_seg = false;
+              }
+            }
+          }
+          accum_record(B, r, hit, dcol, dnrm, dg);
+        }
+        flush_batch(B, a, nb);
+        if (__syncthreads_and(done)) break;
+      }
+      while (!done && qn < nseg) {
+        splice(qn);
+        ++qn;
+      }
     }
   }
 
@@ -331,7 +425,9 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
     const VOConst& C = a.vo[v * a.n_oct + koct];
     const float3 dj = mat3_mul(C.Rt, d);
     const float3 inv = safe_inv(dj);
-    float qs = 0, qe = 0, Tpre = 0, Saft = 0, Vq = 0, Tl = 1.0f, Pl = 0.0f;
+    // Vq/Pl: segment total and prefix; VqT/PlT: their tail parts
+    float qs = 0, qe = 0, Tpre = 0, Saft = 0, Vq = 0, VqT = 0, Tl = 1.0f;
+    float Pl = 0.0f, PlT = 0.0f;
     bool qdone = false;
     float3 go = make_float3(0, 0, 0), gd = make_float3(0, 0, 0);
     auto load_q = [&](int qq) {
@@ -342,7 +438,10 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
       qs = se.x; qe = se.y; Tpre = bw.x; Saft = bw.y;
       Vq = GC.x * q0.x + GC.y * q0.y + GC.z * q0.z + GD * q0.w + GN.x * q1.x +
            GN.y * q1.y + GN.z * q1.z;
-      Tl = 1.0f; Pl = 0.0f; qdone = false;
+      const float4 u0 = a.seg_t0[qi], u1 = a.seg_t1[qi];
+      VqT = GC.x * u0.x + GC.y * u0.y + GC.z * u0.z + GD * u0.w + GN.x * u1.x +
+            GN.y * u1.y + GN.z * u1.z;
+      Tl = 1.0f; Pl = 0.0f; PlT = 0.0f; qdone = false;
     };
     auto next_q = [&](int from) {
       for (int i = from; i < nseg; ++i) {
@@ -382,19 +481,22 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
               if (pb > pa && !qdone) {
                 const float4 cn = B.cn[r];
                 PieceDer pd;
-                const float tau = piece_eval<2>(geo, B.ga[r], B.gb[r], cn.w, dj,
-                                                pa, pb, K, invK, a.c, a.inv_c,
-                                                &pd);
+                const float tau = piece_eval<2, KC>(geo, B.ga[r], B.gb[r], cn.w,
+                                                    dj, pa, pb, K, invK, a.c,
+                                                    a.inv_c, &pd);
                 ++n_piece;
                 const float e = fast_exp(-tau);
-                const float wl = Tl * (1.0f - e);
+                const float wl = Tl * opacity(tau, e);
                 const float4 nr = B.nrm[r];
                 const float mid = 0.5f * (pa + pb);
                 float vi = GC.x * cn.x + GC.y * cn.y + GC.z * cn.z + GD * mid;
                 if (NORMALS) vi += GN.x * nr.x + GN.y * nr.y + GN.z * nr.z;
-                const float Tln = Tl * e;
+                const float wlt = Tl < T_REBASE ? wl : 0.0f;
                 Pl = fmaf(wl, vi, Pl);
-                const float dtau = Tpre * Tln * vi - (Tpre * (Vq - Pl) + Saft);
+                PlT = fmaf(wlt, vi, PlT);
+                Tl *= e;
+                const float Sl = Tl < T_REBASE ? VqT - PlT : Vq - Pl;
+                const float dtau = Tpre * Tl * vi - (Tpre * Sl + Saft);
                 const float wt = Tpre * wl;
                 hit = true;
                 dcol.x += wt * GC.x; dcol.y += wt * GC.y; dcol.z += wt * GC.z;
@@ -427,7 +529,6 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
                     add_axis(gd, ax1, -gb_ * pb / di);
                   }
                 }
-                Tl = Tln;
                 if (Tl < a.eps) qdone = true;
               }
               if (t1 > qe) { qe = t0; continue; }
@@ -694,10 +795,14 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   ca.seg_meta = st->seg_meta.as<uint32_t>();
   ca.seg_p0 = st->seg_p0.as<float4>();
   ca.seg_p1 = st->seg_p1.as<float4>();
+  ca.seg_t0 = st->seg_t0.as<float4>();
+  ca.seg_t1 = st->seg_t1.as<float4>();
   ca.seg_bw = segbw.as<float4>();
   ca.pix_nseg = st->pix_nseg.as<uint32_t>();
   ca.fin0 = st->fin0.as<float4>();
   ca.fin1 = st->fin1.as<float4>();
+  ca.fin2 = st->fin2.as<float4>();
+  ca.fin3 = st->fin3.as<float4>();
   ca.gin = gin.as<dv_out_grads>();
   ca.gr_col = gcol.as<float4>();
   ca.gr_nrm = gnrm.as<float4>();
@@ -714,15 +819,17 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   for (int i = 0; i < 3; ++i) ca.bg[i] = op.bg[i];
   ca.mask = op.out_mask;
   ca.counters = (ctx->prof_flags.load() & DV_PROFILE_COUNTERS) ? ctx->counters : nullptr;
+  // schedule the backward by the work each tile took in the forward
+  DV_TRY(alloc_n<uint32_t>(ctx, st->tile_order_bwd, nt, s));
+  DV_TRY(launch_tile_order(nt, nullptr, st->tile_work.as<uint32_t>(),
+                           st->tile_order_bwd.as<uint32_t>(), s));
+  ca.tile_order = st->tile_order_bwd.as<uint32_t>();
   tm_clear.stop();
   StageTimer tm_comp(ctx, ST_COMPOSITE_BWD, s);
   if (nt > 0) {
-    if (normals)
-      hipLaunchKernelGGL(k_composite_bwd<true>, dim3((unsigned)nt), dim3(TPB),
-                         0, s, ca);
-    else
-      hipLaunchKernelGGL(k_composite_bwd<false>, dim3((unsigned)nt), dim3(TPB),
-                         0, s, ca);
+    auto kern = normals ? (op.K == 1 ? k_composite_bwd<true, 1> : k_composite_bwd<true, 0>)
+                        : (op.K == 1 ? k_composite_bwd<false, 1> : k_composite_bwd<false, 0>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
     DV_TRY_HIP(hipGetLastError());
   }
   tm_comp.stop();

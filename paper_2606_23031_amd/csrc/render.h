@@ -20,6 +20,8 @@ struct CompArgs {
   const uint32_t* tile_start;
   const uint32_t* tile_end;
   const uint32_t* tile_bgend;
+  const uint32_t* tile_order;  // launch order of the compositing blocks
+  uint32_t* tile_work;     // forward: measured work per tile
   const uint32_t* pair_val;
   const float4* rec_geo;   // vmin - camera (octree frame), h
   const float4* rec_g8a;   // corner densities 0..3
@@ -34,10 +36,14 @@ struct CompArgs {
   uint32_t* seg_meta;
   float4* seg_p0;          // partial C.rgb, D
   float4* seg_p1;          // partial N.xyz, T
+  float4* seg_t0;          // tail part of seg_p0 (after the rebase), else 0
+  float4* seg_t1;          // tail part of seg_p1.xyz, 0
   float4* seg_bw;          // backward: T_pre, S_after, dL/dstart, dL/dend
   uint32_t* pix_nseg;
   float4* fin0;            // final C.rgb, D
   float4* fin1;            // final N.xyz, T
+  float4* fin2;            // tail part of fin0 (after the rebase), else 0
+  float4* fin3;            // tail part of fin1.xyz, 0
   const dv_outputs* outs;  // per view
   const dv_out_grads* gin; // per view (backward)
   float4* gr_col;          // backward per-record: dL/dc (rgb), 0
@@ -91,6 +97,20 @@ __device__ inline bool rect_hits_block(uint2 rc, int bx, int by) {
   return xl <= bx + 7 && xh >= bx && yl <= by + 7 && yh >= by;
 }
 
+// Entries of a staged batch (nb <= 256) whose pixel rectangle meets the
+// calling wave's 8x8 block, as four wave-uniform 64-bit masks (bit i of
+// m[c] is entry 64 c + i).  Called by every lane of the wave.
+__device__ inline void wave_entry_masks(const uint2* rect, uint32_t nb, int bx,
+                                        int by, uint64_t m[4]) {
+  const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const uint32_t r = (uint32_t)c * 64 + lane;
+    const bool hit = r < nb && rect_hits_block(rect[r], bx, by);
+    m[c] = __ballot(hit);
+  }
+}
+
 __device__ inline int view_of_tile(const ViewConst* views, int n_views,
                                    uint32_t gt) {
   int lo = 0, hi = n_views - 1;
@@ -118,6 +138,35 @@ __device__ inline float explin(float x, float c, float inv_c) {
 }
 __device__ inline float explin_grad(float x, float c, float inv_c) {
   return x > c ? 1.0f : fast_exp(fmaf(x, inv_c, -1.0f));
+}
+
+// Suffix rebase.  The backward needs, per piece, the suffix S = L - P of
+// everything composited after it.  Formed as a difference of running sums
+// it carries an absolute FP32 error ~2^-24 |L|, which swamps the suffix of
+// pieces behind an opaque surface (S ~ T |L|).  Both walks therefore split
+// their running sums the first time T drops below T_REBASE (tested where
+// the stop test is, on bit-identical T): the forward stores the part after
+// the split (the tail) beside the totals, and the backward restarts P at 0
+// against the tail total there, so deep pieces see an error ~2^-24 T_REBASE
+// |L| instead.  Asset segments do the same on their own transmittance.
+// Heaviest-first launch order of the compositing blocks (render.hip):
+// weight end[t] - start[t], or end[t] alone when start is null.
+dv_status launch_tile_order(int64_t nt, const uint32_t* start,
+                            const uint32_t* end, uint32_t* order,
+                            hipStream_t s);
+
+constexpr float T_REBASE = 0.0009765625f;  // 2^-10
+
+// alpha = 1 - exp(-tau).  For small tau the difference 1 - e cancels in
+// FP32 (relative error ~6e-8 / tau), so a 4-term series is used there; the
+// series' truncation error is below 2^-24 relative for tau < 2^-6.
+// Both branches are evaluated and selected (no divergent branch).
+__device__ inline float opacity(float tau, float e) {
+  const float p = fmaf(tau, fmaf(tau, fmaf(tau, -1.0f / 24.0f, 1.0f / 6.0f),
+                                 -0.5f), 1.0f);
+  const float series = tau * p;
+  const float direct = 1.0f - e;
+  return tau < 0.015625f ? series : direct;
 }
 
 __device__ inline float lerpf(float a, float b, float t) {
@@ -178,11 +227,14 @@ struct PieceDer {
 // corner derivatives; 2: also geometry derivatives (samples, ends).  The
 // optical depth takes the same operations in every mode, so forward and
 // backward walks see bit-identical values.
-template <int MODE>
+// KC > 0 fixes K = KC at compile time (same arithmetic as a run-time K).
+template <int MODE, int KC = 0>
 __device__ inline float piece_eval(float4 geo, float4 ga, float4 gb,
                                    float inv_h, float3 d, float a, float b,
-                                   int K, float invK, float c, float inv_c,
+                                   int K_, float invK_, float c, float inv_c,
                                    PieceDer* o) {
+  const int K = KC > 0 ? KC : K_;
+  const float invK = KC > 0 ? 1.0f / (float)KC : invK_;
   const float step = (b - a) * invK;
   float sum = 0.0f, pa = 0.0f, pb = 0.0f;
   if (MODE >= 1) {
@@ -236,11 +288,12 @@ __device__ inline float piece_eval(float4 geo, float4 ga, float4 gb,
   return sum * step;
 }
 
+template <int KC = 0>
 __device__ inline float piece_tau(float4 geo, float4 ga, float4 gb,
                                   float inv_h, float3 d, float a, float b,
                                   int K, float invK, float c, float inv_c) {
-  return piece_eval<0>(geo, ga, gb, inv_h, d, a, b, K, invK, c, inv_c,
-                       nullptr);
+  return piece_eval<0, KC>(geo, ga, gb, inv_h, d, a, b, K, invK, c, inv_c,
+                           nullptr);
 }
 
 // Real spherical harmonics up to degree 3 (Sec. 3.1 view-dependent
@@ -339,5 +392,6 @@ struct dv_fwd_state {
   dv::DBuf tile_start, tile_end, tile_bgend;
   dv::DBuf act_beg, act_oct, act_sub;
   dv::DBuf seg_se, seg_meta, seg_p0, seg_p1, seg_bw, pix_nseg;
-  dv::DBuf fin0, fin1;
+  dv::DBuf fin0, fin1, fin2, fin3, seg_t0, seg_t1;
+  dv::DBuf tile_order, tile_work, tile_order_bwd;
 };

@@ -318,6 +318,54 @@ __global__ void k_actor_ranges(int64_t n, const uint32_t* act_tile,
   sub[e] = make_uint2(a, b);
 }
 
+// Launch order of the compositing blocks: heaviest tiles first, so long
+// tiles start early and short ones fill the tail of the grid.  The weight of
+// tile t is end[t] - start[t] (list length) when start is given, else
+// end[t] (a measured work count).  Tiles are bucketed by weight on a log
+// scale with 8 steps per octave; the order inside a bucket is whatever the
+// LDS atomics give, which changes no result (tiles are independent).  One
+// block of 1024 threads.
+__device__ inline uint32_t weight_bucket(uint32_t w) {
+  if (w == 0) return 0;
+  const uint32_t lz = __builtin_clz(w);
+  const uint32_t mant = lz < 31 ? ((w << (lz + 1)) >> 29) : 0u;
+  return (31u - lz) * 8u + mant;  // 0 .. 255
+}
+
+__global__ void __launch_bounds__(1024) k_tile_order(int n, const uint32_t* start,
+                                                     const uint32_t* end,
+                                                     uint32_t* order) {
+  __shared__ uint32_t cnt[256];
+  __shared__ uint32_t off[256];
+  const int tid = threadIdx.x;
+  if (tid < 256) cnt[tid] = 0;
+  __syncthreads();
+  for (int t = tid; t < n; t += 1024) {
+    const uint32_t w = start ? end[t] - start[t] : end[t];
+    atomicAdd(&cnt[255 - weight_bucket(w)], 1u);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int b = 0; b < 256; ++b) { off[b] = acc; acc += cnt[b]; }
+  }
+  __syncthreads();
+  for (int t = tid; t < n; t += 1024) {
+    const uint32_t w = start ? end[t] - start[t] : end[t];
+    order[atomicAdd(&off[255 - weight_bucket(w)], 1u)] = (uint32_t)t;
+  }
+}
+
+dv_status launch_tile_order(int64_t nt, const uint32_t* start,
+                            const uint32_t* end, uint32_t* order,
+                            hipStream_t s) {
+  if (nt <= 0) return DV_OK;
+  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, (int)nt, start,
+                     end, order);
+  DV_TRY_HIP(hipGetLastError());
+  return DV_OK;
+}
+
 // ------------------------------------------------------------------ composite
 struct Batch {
   float4 geo[TPB];
@@ -408,6 +456,8 @@ __device__ inline int build_segments(const CompArgs& a, uint32_t sbase,
         a.seg_meta[qi] = (uint32_t)owner | (cur_src << 8) | (nb_src << 18);
         a.seg_p0[qi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         a.seg_p1[qi] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+        a.seg_t0[qi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        a.seg_t1[qi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         ++nseg;
       }
     }
@@ -424,10 +474,15 @@ __device__ inline int next_seg_of(const CompArgs& a, uint32_t seg0, int nseg,
   return nseg;
 }
 
-template <bool NORMALS>
+// Forward compositing, one 256-thread block per 16x16 tile (each wave an
+// 8x8 quadrant).  Sums are kept twice: over all pieces, and over the tail
+// (pieces entered with T < T_REBASE), which the backward needs for its
+// suffixes.  KC = 1 fixes one sample per piece at compile time.
+template <bool NORMALS, int KC>
 __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
   __shared__ Batch B;
-  const uint32_t gt = blockIdx.x;
+  __shared__ uint32_t blk_work;
+  const uint32_t gt = a.tile_order[blockIdx.x];
   const int tid = threadIdx.x;
   const int v = view_of_tile(a.views, a.n_views, gt);
   const ViewConst& V = a.views[v];
@@ -468,8 +523,18 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
     const float3 dj = mat3_mul(C.Rt, d);
     const float3 inv = safe_inv(dj);
     float qs = 0, qe = 0;
+    // p0/p1: partial state of segment q; t0/t1: its tail part
     float4 p0 = make_float4(0, 0, 0, 0), p1 = make_float4(0, 0, 0, 1);
+    float4 t0s = make_float4(0, 0, 0, 0);
+    float3 t1s = make_float3(0, 0, 0);
     bool qdone = false;
+    auto store_q = [&](int qq) {
+      const size_t qi = seg_index(seg0 + qq, tid);
+      a.seg_p0[qi] = p0;
+      a.seg_p1[qi] = p1;
+      a.seg_t0[qi] = t0s;
+      a.seg_t1[qi] = make_float4(t1s.x, t1s.y, t1s.z, 0.0f);
+    };
     if (has) {
       const float2 se = a.seg_se[seg_index(seg0 + q, tid)];
       qs = se.x; qe = se.y;
@@ -489,33 +554,35 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
         while (true) {
           if (qe <= t0) {
             // segment q finished: store and move to the next one of j
-            a.seg_p0[seg_index(seg0 + q, tid)] = p0;
-            a.seg_p1[seg_index(seg0 + q, tid)] = p1;
+            store_q(q);
             q = next_seg_of(a, seg0, nseg, q + 1, j, tid);
             if (q >= nseg) { has = false; break; }
             const float2 se = a.seg_se[seg_index(seg0 + q, tid)];
             qs = se.x; qe = se.y;
             p0 = make_float4(0, 0, 0, 0); p1 = make_float4(0, 0, 0, 1);
+            t0s = make_float4(0, 0, 0, 0); t1s = make_float3(0, 0, 0);
             qdone = false;
             continue;
           }
           const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
           if (pb > pa && !qdone) {
             const float4 cn = B.cn[r];
-            const float tau = piece_tau(geo, B.ga[r], B.gb[r], cn.w, dj, pa,
-                                        pb, K, invK, a.c, a.inv_c);
+            const float tau = piece_tau<KC>(geo, B.ga[r], B.gb[r], cn.w, dj, pa,
+                                            pb, K, invK, a.c, a.inv_c);
             ++n_piece;
             const float e = fast_exp(-tau);
-            const float wgt = p1.w * (1.0f - e);
-            p0.x = fmaf(wgt, cn.x, p0.x);
-            p0.y = fmaf(wgt, cn.y, p0.y);
-            p0.z = fmaf(wgt, cn.z, p0.z);
-            p0.w = fmaf(wgt, 0.5f * (pa + pb), p0.w);
+            const float wgt = p1.w * opacity(tau, e);
+            const float wt = p1.w < T_REBASE ? wgt : 0.0f;
+            const float mid = 0.5f * (pa + pb);
+            p0.x = fmaf(wgt, cn.x, p0.x); t0s.x = fmaf(wt, cn.x, t0s.x);
+            p0.y = fmaf(wgt, cn.y, p0.y); t0s.y = fmaf(wt, cn.y, t0s.y);
+            p0.z = fmaf(wgt, cn.z, p0.z); t0s.z = fmaf(wt, cn.z, t0s.z);
+            p0.w = fmaf(wgt, mid, p0.w); t0s.w = fmaf(wt, mid, t0s.w);
             if (NORMALS) {
               const float4 nr = B.nrm[r];
-              p1.x = fmaf(wgt, nr.x, p1.x);
-              p1.y = fmaf(wgt, nr.y, p1.y);
-              p1.z = fmaf(wgt, nr.z, p1.z);
+              p1.x = fmaf(wgt, nr.x, p1.x); t1s.x = fmaf(wt, nr.x, t1s.x);
+              p1.y = fmaf(wgt, nr.y, p1.y); t1s.y = fmaf(wt, nr.y, t1s.y);
+              p1.z = fmaf(wgt, nr.z, p1.z); t1s.z = fmaf(wt, nr.z, t1s.z);
             }
             p1.w *= e;
             if (p1.w < a.eps) qdone = true;
@@ -529,88 +596,136 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
       }
       if (!__syncthreads_or(has)) break;
     }
-    if (has) {
-      a.seg_p0[seg_index(seg0 + q, tid)] = p0;
-      a.seg_p1[seg_index(seg0 + q, tid)] = p1;
-    }
+    if (has) store_q(q);
   }
 
   // ---------------------------------------------------- phase 2: background
+  // totals C3/D/N3 and tail sums CT/DT/NT
   float3 C3 = make_float3(0, 0, 0), N3 = make_float3(0, 0, 0);
-  float D = 0.0f, T = 1.0f;
+  float3 CT = make_float3(0, 0, 0), NT = make_float3(0, 0, 0);
+  float D = 0.0f, DT = 0.0f, T = 1.0f;
   bool done = !valid;
-  int qn = 0;
-  float ns = nseg > 0 ? a.seg_se[seg_index(seg0, tid)].x : F_INF;
-  float excl = -F_INF;
   const float3 inv = safe_inv(d);
-  auto splice = [&](int qq) {
-    const size_t qi = seg_index(seg0 + qq, tid);
-    const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
-    C3.x = fmaf(T, q0.x, C3.x); C3.y = fmaf(T, q0.y, C3.y);
-    C3.z = fmaf(T, q0.z, C3.z); D = fmaf(T, q0.w, D);
+  auto add_piece = [&](uint32_t r, const float4& geo, float pa, float pb) {
+    const float4 cn = B.cn[r];
+    const float tau = piece_tau<KC>(geo, B.ga[r], B.gb[r], cn.w, d, pa, pb, K,
+                                    invK, a.c, a.inv_c);
+    ++n_piece;
+    const float e = fast_exp(-tau);
+    const float wgt = T * opacity(tau, e);
+    const float wt = T < T_REBASE ? wgt : 0.0f;
+    const float mid = 0.5f * (pa + pb);
+    C3.x = fmaf(wgt, cn.x, C3.x); CT.x = fmaf(wt, cn.x, CT.x);
+    C3.y = fmaf(wgt, cn.y, C3.y); CT.y = fmaf(wt, cn.y, CT.y);
+    C3.z = fmaf(wgt, cn.z, C3.z); CT.z = fmaf(wt, cn.z, CT.z);
+    D = fmaf(wgt, mid, D); DT = fmaf(wt, mid, DT);
     if (NORMALS) {
-      N3.x = fmaf(T, q1.x, N3.x); N3.y = fmaf(T, q1.y, N3.y);
-      N3.z = fmaf(T, q1.z, N3.z);
+      const float4 nr = B.nrm[r];
+      N3.x = fmaf(wgt, nr.x, N3.x); NT.x = fmaf(wt, nr.x, NT.x);
+      N3.y = fmaf(wgt, nr.y, N3.y); NT.y = fmaf(wt, nr.y, NT.y);
+      N3.z = fmaf(wgt, nr.z, N3.z); NT.z = fmaf(wt, nr.z, NT.z);
     }
-    T *= q1.w;
-    excl = a.seg_se[qi].y;
+    T *= e;
+    if (T < a.eps) done = true;
   };
   const uint32_t beg = a.tile_start[gt], bgend = a.tile_bgend[gt];
-  for (uint32_t base = beg; base < bgend; base += TPB) {
-    const uint32_t nb = min((uint32_t)TPB, bgend - base);
-    load_batch(B, a, base, nb);
-    __syncthreads();
-    for (uint32_t r = 0; r < nb && !done; ++r) {
-      if (!rect_hits_block(B.rect[r], bx, by)) continue;
-      const float4 geo = B.geo[r];
-      float t0, t1;
-      slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
-      ++n_test;
-      t0 = fmaxf(t0, a.tau_near);
-      if (!(t1 > t0)) continue;
-      float pa = fmaxf(t0, excl);
-      while (pa < t1 && !done) {
-        if (pa >= ns) {
-          splice(qn);
-          pa = fmaxf(pa, excl);
-          ++qn;
-          ns = qn < nseg ? a.seg_se[seg_index(seg0 + qn, tid)].x : F_INF;
-          if (T < a.eps) done = true;
-          continue;
+  if (n_at == 0) {
+    // no actor box meets the tile: a plain walk, entries picked from the
+    // wave's rectangle masks
+    for (uint32_t base = beg; base < bgend; base += TPB) {
+      const uint32_t nb = min((uint32_t)TPB, bgend - base);
+      load_batch(B, a, base, nb);
+      __syncthreads();
+      uint64_t wm[4];
+      wave_entry_masks(B.rect, nb, bx, by, wm);
+      for (int c = 0; c < 4; ++c) {
+        uint64_t m = wm[c];
+        while (m != 0 && __ballot(!done) != 0) {
+          const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
+          m &= m - 1;
+          if (!done) {
+            const float4 geo = B.geo[r];
+            float t0, t1;
+            slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+            ++n_test;
+            t0 = fmaxf(t0, a.tau_near);
+            if (t1 > t0) add_piece(r, geo, t0, t1);
+          }
         }
-        const float pb = fminf(t1, ns);
-        const float4 cn = B.cn[r];
-        const float tau = piece_tau(geo, B.ga[r], B.gb[r], cn.w, d, pa, pb, K,
-                                    invK, a.c, a.inv_c);
-        ++n_piece;
-        const float e = fast_exp(-tau);
-        const float wgt = T * (1.0f - e);
-        C3.x = fmaf(wgt, cn.x, C3.x);
-        C3.y = fmaf(wgt, cn.y, C3.y);
-        C3.z = fmaf(wgt, cn.z, C3.z);
-        D = fmaf(wgt, 0.5f * (pa + pb), D);
-        if (NORMALS) {
-          const float4 nr = B.nrm[r];
-          N3.x = fmaf(wgt, nr.x, N3.x);
-          N3.y = fmaf(wgt, nr.y, N3.y);
-          N3.z = fmaf(wgt, nr.z, N3.z);
-        }
-        T *= e;
-        if (T < a.eps) done = true;
-        pa = pb;
       }
+      if (__syncthreads_and(done)) break;
     }
-    if (__syncthreads_and(done)) break;
-  }
-  while (!done && qn < nseg) {
-    splice(qn);
-    ++qn;
-    if (T < a.eps) done = true;
+  } else {
+    int qn = 0;
+    float ns = nseg > 0 ? a.seg_se[seg_index(seg0, tid)].x : F_INF;
+    float excl = -F_INF;
+    auto splice = [&](int qq) {
+      const size_t qi = seg_index(seg0 + qq, tid);
+      const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
+      const float ts = T < T_REBASE ? T : 0.0f;
+      C3.x = fmaf(T, q0.x, C3.x); CT.x = fmaf(ts, q0.x, CT.x);
+      C3.y = fmaf(T, q0.y, C3.y); CT.y = fmaf(ts, q0.y, CT.y);
+      C3.z = fmaf(T, q0.z, C3.z); CT.z = fmaf(ts, q0.z, CT.z);
+      D = fmaf(T, q0.w, D); DT = fmaf(ts, q0.w, DT);
+      if (NORMALS) {
+        N3.x = fmaf(T, q1.x, N3.x); NT.x = fmaf(ts, q1.x, NT.x);
+        N3.y = fmaf(T, q1.y, N3.y); NT.y = fmaf(ts, q1.y, NT.y);
+        N3.z = fmaf(T, q1.z, N3.z); NT.z = fmaf(ts, q1.z, NT.z);
+      }
+      T *= q1.w;
+      excl = a.seg_se[qi].y;
+      if (T < a.eps) done = true;
+    };
+    for (uint32_t base = beg; base < bgend; base += TPB) {
+      const uint32_t nb = min((uint32_t)TPB, bgend - base);
+      load_batch(B, a, base, nb);
+      __syncthreads();
+      for (uint32_t r = 0; r < nb && !done; ++r) {
+        if (!rect_hits_block(B.rect[r], bx, by)) continue;
+        const float4 geo = B.geo[r];
+        float t0, t1;
+        slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+        ++n_test;
+        t0 = fmaxf(t0, a.tau_near);
+        if (!(t1 > t0)) continue;
+        float pa = fmaxf(t0, excl);
+        while (pa < t1 && !done) {
+          if (pa >= ns) {
+            splice(qn);
+            pa = fmaxf(pa, excl);
+            ++qn;
+            ns = qn < nseg ? a.seg_se[seg_index(seg0 + qn, tid)].x : F_INF;
+            continue;
+          }
+          const float pb = fminf(t1, ns);
+          add_piece(r, geo, pa, pb);
+          pa = pb;
+        }
+      }
+      if (__syncthreads_and(done)) break;
+    }
+    while (!done && qn < nseg) {
+      splice(qn);
+      ++qn;
+    }
   }
   count_work(a.counters, 0, n_test, n_piece);
+  // per-tile work (slab tests + 4 per piece), the backward's schedule key
+  {
+    uint32_t w = n_test + 4u * n_piece;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
+    if (tid == 0) blk_work = 0;
+    __syncthreads();
+    if ((tid & 63) == 0) atomicAdd(&blk_work, w);
+    __syncthreads();
+    if (tid == 0) a.tile_work[gt] = blk_work;
+  }
   if (!valid) return;
   a.fin0[pix] = make_float4(C3.x, C3.y, C3.z, D);
   a.fin1[pix] = make_float4(N3.x, N3.y, N3.z, T);
+  a.fin2[pix] = make_float4(CT.x, CT.y, CT.z, DT);
+  a.fin3[pix] = make_float4(NT.x, NT.y, NT.z, 0.0f);
   const dv_outputs& O = a.outs[v];
   const size_t hw = (size_t)V.w * V.h, o = (size_t)py * V.w + px;
   if ((a.mask & DV_OUT_RGB) && O.rgb) {
@@ -1066,6 +1181,11 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
                        n_oct, st->act_sub.as<uint2>());
     DV_TRY_HIP(hipGetLastError());
   }
+  DV_TRY(alloc_n<uint32_t>(ctx, st->tile_order, nt, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->tile_work, nt, s));
+  DV_TRY(launch_tile_order(nt, st->tile_start.as<uint32_t>(),
+                            st->tile_end.as<uint32_t>(),
+                            st->tile_order.as<uint32_t>(), s));
   tm_dir.stop();
   // per-pixel scratch
   const size_t nslots = (size_t)3 * na * TPB;
@@ -1073,9 +1193,13 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   DV_TRY(alloc_n<uint32_t>(ctx, st->seg_meta, nslots, s));
   DV_TRY(alloc_n<float4>(ctx, st->seg_p0, nslots, s));
   DV_TRY(alloc_n<float4>(ctx, st->seg_p1, nslots, s));
+  DV_TRY(alloc_n<float4>(ctx, st->seg_t0, nslots, s));
+  DV_TRY(alloc_n<float4>(ctx, st->seg_t1, nslots, s));
   DV_TRY(alloc_n<uint32_t>(ctx, st->pix_nseg, (size_t)nt * TPB, s));
   DV_TRY(alloc_n<float4>(ctx, st->fin0, (size_t)nt * TPB, s));
   DV_TRY(alloc_n<float4>(ctx, st->fin1, (size_t)nt * TPB, s));
+  DV_TRY(alloc_n<float4>(ctx, st->fin2, (size_t)nt * TPB, s));
+  DV_TRY(alloc_n<float4>(ctx, st->fin3, (size_t)nt * TPB, s));
   CompArgs ca;
   std::memset(&ca, 0, sizeof(ca));
   ca.views = st->views_d.as<ViewConst>();
@@ -1085,6 +1209,8 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   ca.tile_start = st->tile_start.as<uint32_t>();
   ca.tile_end = st->tile_end.as<uint32_t>();
   ca.tile_bgend = st->tile_bgend.as<uint32_t>();
+  ca.tile_order = st->tile_order.as<uint32_t>();
+  ca.tile_work = st->tile_work.as<uint32_t>();
   ca.pair_val = st->pair_val.as<uint32_t>();
   ca.rec_geo = st->rec_geo.as<float4>();
   ca.rec_g8a = st->rec_g8a.as<float4>();
@@ -1099,9 +1225,13 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   ca.seg_meta = st->seg_meta.as<uint32_t>();
   ca.seg_p0 = st->seg_p0.as<float4>();
   ca.seg_p1 = st->seg_p1.as<float4>();
+  ca.seg_t0 = st->seg_t0.as<float4>();
+  ca.seg_t1 = st->seg_t1.as<float4>();
   ca.pix_nseg = st->pix_nseg.as<uint32_t>();
   ca.fin0 = st->fin0.as<float4>();
   ca.fin1 = st->fin1.as<float4>();
+  ca.fin2 = st->fin2.as<float4>();
+  ca.fin3 = st->fin3.as<float4>();
   ca.outs = st->outs_d.as<dv_outputs>();
   ca.n_actors = n_oct - 1;
   ca.K = op.K;
@@ -1114,12 +1244,10 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   ca.counters = (ctx->prof_flags.load() & DV_PROFILE_COUNTERS) ? ctx->counters : nullptr;
   StageTimer tm_comp(ctx, ST_COMPOSITE_FWD, s);
   if (nt > 0) {
-    if (op.out_mask & DV_OUT_NORMAL)
-      hipLaunchKernelGGL(k_composite_fwd<true>, dim3((unsigned)nt), dim3(TPB), 0,
-                         s, ca);
-    else
-      hipLaunchKernelGGL(k_composite_fwd<false>, dim3((unsigned)nt), dim3(TPB),
-                         0, s, ca);
+    const bool nrm = (op.out_mask & DV_OUT_NORMAL) != 0;
+    auto kern = nrm ? (op.K == 1 ? k_composite_fwd<true, 1> : k_composite_fwd<true, 0>)
+                    : (op.K == 1 ? k_composite_fwd<false, 1> : k_composite_fwd<false, 0>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
   }
   DV_TRY_HIP(hipGetLastError());
   return DV_OK;

@@ -28,6 +28,11 @@ INNER_LO = np.array([-102.4, -102.4, -1.6])
 INNER_HI = np.array([102.4, 102.4, 33.6])
 V_FAR = -10.0
 CAR = np.array([4.5, 1.9, 1.6])
+# car centre height: the body rests 1.37 cm above the ground, which keeps the
+# horizontal faces of the actor box (centre +- 2.7 m) off the background's
+# 0.1 m grid planes; a box face lying exactly on a leaf face makes the image a
+# kinked function of the actor's height
+CAR_Z = 0.8 + 0.0137
 
 
 def soft_prior(d, s, v_close, v_far=V_FAR):
@@ -311,8 +316,8 @@ def car_tracks(rng, n, t_end=10.0, lane_ys=(-4.0, 4.0), x_start=-30.0,
         yaw = np.deg2rad(rng.uniform(-5.0, 5.0))
         v = speeds[lane]
         tracks.append(dict(t=np.array([0.0, t_end]), yaw=np.array([yaw, yaw]),
-                           trans=np.array([[x0, y, 0.8],
-                                           [x0 + v * t_end, y, 0.8]])))
+                           trans=np.array([[x0, y, CAR_Z],
+                                           [x0 + v * t_end, y, CAR_Z]])))
     return tracks
 
 
