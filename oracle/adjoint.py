@@ -24,9 +24,12 @@ _GW_CENTRE = F.trilinear_weight_grads(np.full(3, 0.5))       # [8,3]
 
 
 def new_accumulators(ctx):
-    acc = dict(corner=[], dcol=[], dnw=[], dR=[], dp=[])
+    # corner_abs: sum of |per-piece contribution| per corner, the scale of
+    # the summands behind each corner gradient (bookkeeping for error bars)
+    acc = dict(corner=[], corner_abs=[], dcol=[], dnw=[], dR=[], dp=[])
     for k, o in enumerate(ctx.scene["octrees"]):
         acc["corner"].append(np.zeros(o["corner_density"].shape[0]))
+        acc["corner_abs"].append(np.zeros(o["corner_density"].shape[0]))
         n = o["level"].shape[0]
         acc["dcol"].append(np.zeros((n, 3)))
         acc["dnw"].append(np.zeros((n, 3)))
@@ -66,6 +69,7 @@ def ray_adjoint(ctx, o, d, gC, gD, gN, gT, acc):
         # corner densities through the samples
         dg8 = W[i].T @ dgq[i]                          # [8]
         np.add.at(acc["corner"][k], oct_["corner_idx"][:, vv], dg8)
+        np.add.at(acc["corner_abs"][k], oct_["corner_idx"][:, vv], np.abs(dg8))
         acc["dcol"][k][vv] += w[i] * gC
         acc["dnw"][k][vv] += w[i] * gN
         # geometry: samples and piece ends
@@ -100,7 +104,7 @@ def ray_adjoint(ctx, o, d, gC, gD, gN, gT, acc):
 def finalize(ctx, acc):
     """Per-leaf colour and normal gradients -> SH coefficients, corners
     (through normals) and poses (SH direction, normal rotation)."""
-    out = dict(corner=[], sh=[], dR=[], dp=[])
+    out = dict(corner=[], corner_abs=[], sh=[], dR=[], dp=[])
     for k, o in enumerate(ctx.scene["octrees"]):
         ent = ctx.oct[k]
         dcol = acc["dcol"][k] * (ent["raw"] > 0)
@@ -108,6 +112,7 @@ def finalize(ctx, acc):
         Y = SH.basis(ent["wdir"], deg)                  # [N,S]
         out["sh"].append(np.einsum("ns,nc->scn", Y, dcol))
         corner = acc["corner"][k].copy()
+        corner_abs = acc["corner_abs"][k].copy()
         dR, dp = acc["dR"][k].copy(), acc["dp"][k].copy()
         R, p = ent["R"], ent["p"]
         # normals: n_w = R n_loc, n_loc = -v/|v|, v = grad of trilinear
@@ -125,6 +130,8 @@ def finalize(ctx, acc):
             dv = np.where(ok[:, None], -proj / np.where(ok, nrm, 1.0)[:, None], 0.0)
             dg8 = dv @ _GW_CENTRE.T                     # [n,8]
             np.add.at(corner, o["corner_idx"][:, nz].T.ravel(), dg8.ravel())
+            np.add.at(corner_abs, o["corner_idx"][:, nz].T.ravel(),
+                      np.abs(dg8).ravel())
         if k >= 1:
             cz = np.nonzero(np.abs(dcol).sum(1) > 0)[0]
             if cz.size:
@@ -135,6 +142,7 @@ def finalize(ctx, acc):
                 dR += np.outer(ctx.cam - p, dP)
                 dp += -R @ dP
         out["corner"].append(corner)
+        out["corner_abs"].append(corner_abs)
         out["dR"].append(dR)
         out["dp"].append(dp)
     return out

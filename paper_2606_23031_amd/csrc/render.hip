@@ -227,34 +227,29 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
   (void)v;
 }
 
+// Records stay where the preprocess put them (slot order: view, octree,
+// leaf).  For the depth-sorted order i -> slot order[i], record each slot's
+// (view, octree) id and the tile count of sorted record i.
 __global__ void k_gather(int64_t n, const uint64_t* __restrict__ keys,
-                         const uint32_t* __restrict__ vals, int rank_bits,
-                         const float4* s_geo, const float4* s_g8a,
-                         const float4* s_g8b, const float4* s_cn,
-                         const float4* s_nrm, const uint32_t* s_vox,
-                         const uint64_t* s_rect, float4* r_geo, float4* r_g8a,
-                         float4* r_g8b, float4* r_cn, float4* r_nrm,
-                         uint32_t* r_vox, uint32_t* r_seg, uint32_t* r_count,
-                         uint64_t* r_rect) {
+                         const uint32_t* __restrict__ order, int rank_bits,
+                         const uint64_t* __restrict__ rect,
+                         uint32_t* __restrict__ rseg,
+                         uint32_t* __restrict__ r_count) {
   const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (i >= n) return;
-  const uint32_t sl = vals[i];
-  r_geo[i] = s_geo[sl];
-  r_g8a[i] = s_g8a[sl];
-  r_g8b[i] = s_g8b[sl];
-  r_cn[i] = s_cn[sl];
-  r_nrm[i] = s_nrm[sl];
-  r_vox[i] = s_vox[sl];
-  r_seg[i] = (uint32_t)(keys[i] >> rank_bits);
-  const uint64_t rc = s_rect[sl];
+  const uint32_t sl = order[i];
+  rseg[sl] = (uint32_t)(keys[i] >> rank_bits);
+  const uint64_t rc = rect[sl];
   const uint32_t tx0 = (rc & 0xFFFF) >> 4, tx1 = ((rc >> 16) & 0xFFFF) >> 4;
   const uint32_t ty0 = ((rc >> 32) & 0xFFFF) >> 4, ty1 = (rc >> 48) >> 4;
   r_count[i] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-  r_rect[i] = rc;
 }
 
+// Pair p of the depth-sorted record list: key = global tile, value = the
+// record's slot (pairs come out in depth order within every tile).
 __global__ void k_emit(int64_t n_pairs, int64_t n_rec,
                        const uint32_t* __restrict__ off,
+                       const uint32_t* __restrict__ order,
                        const uint64_t* __restrict__ rect,
                        const uint32_t* __restrict__ seg, int n_oct,
                        const ViewConst* __restrict__ views,
@@ -267,14 +262,15 @@ __global__ void k_emit(int64_t n_pairs, int64_t n_rec,
     int64_t mid = (lo + hi + 1) >> 1;
     if ((int64_t)off[mid] <= p) lo = mid; else hi = mid - 1;
   }
-  const uint64_t rc = rect[lo];
+  const uint32_t sl = order[lo];
+  const uint64_t rc = rect[sl];
   const uint32_t tx0 = (rc & 0xFFFF) >> 4, tx1 = ((rc >> 16) & 0xFFFF) >> 4;
   const uint32_t ty0 = ((rc >> 32) & 0xFFFF) >> 4;
   const uint32_t wdt = tx1 - tx0 + 1;
   const uint32_t i = (uint32_t)(p - off[lo]);
-  const ViewConst& V = views[seg[lo] / n_oct];
+  const ViewConst& V = views[seg[sl] / n_oct];
   pkey[p] = V.tile_base + (ty0 + i / wdt) * V.ntx + (tx0 + i % wdt);
-  pval[p] = (uint32_t)lo;
+  pval[p] = sl;
 }
 
 __global__ void k_tile_bounds(int64_t n, const uint32_t* __restrict__ key,
@@ -1034,27 +1030,29 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   }
   const int64_t nv = (int64_t)n_vis;
   // pass 1: records in slot order
-  DBuf keys, vals, keys2, vals2, s_geo, s_g8a, s_g8b, s_cn, s_nrm, s_vox, s_rect;
+  // the record arrays of the state, in slot order
+  DBuf keys, vals, keys2, vals2;
   DV_TRY(alloc_n<uint64_t>(ctx, keys, nv, s));
   DV_TRY(alloc_n<uint32_t>(ctx, vals, nv, s));
   DV_TRY(alloc_n<uint64_t>(ctx, keys2, nv, s));
   DV_TRY(alloc_n<uint32_t>(ctx, vals2, nv, s));
-  DV_TRY(alloc_n<float4>(ctx, s_geo, nv, s));
-  DV_TRY(alloc_n<float4>(ctx, s_g8a, nv, s));
-  DV_TRY(alloc_n<float4>(ctx, s_g8b, nv, s));
-  DV_TRY(alloc_n<float4>(ctx, s_cn, nv, s));
-  DV_TRY(alloc_n<float4>(ctx, s_nrm, nv, s));
-  DV_TRY(alloc_n<uint32_t>(ctx, s_vox, nv, s));
-  DV_TRY(alloc_n<uint64_t>(ctx, s_rect, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, st->rec_geo, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, st->rec_g8a, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, st->rec_g8b, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, st->rec_cn, nv, s));
+  DV_TRY(alloc_n<float4>(ctx, st->rec_nrm, nv, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->rec_vox, nv, s));
+  DV_TRY(alloc_n<uint64_t>(ctx, st->rec_rect, nv, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->rec_seg, nv, s));
   pa.keys = keys.as<uint64_t>();
   pa.vals = vals.as<uint32_t>();
-  pa.s_geo = s_geo.as<float4>();
-  pa.s_g8a = s_g8a.as<float4>();
-  pa.s_g8b = s_g8b.as<float4>();
-  pa.s_cn = s_cn.as<float4>();
-  pa.s_nrm = s_nrm.as<float4>();
-  pa.s_vox = s_vox.as<uint32_t>();
-  pa.s_rect = s_rect.as<uint64_t>();
+  pa.s_geo = st->rec_geo.as<float4>();
+  pa.s_g8a = st->rec_g8a.as<float4>();
+  pa.s_g8b = st->rec_g8b.as<float4>();
+  pa.s_cn = st->rec_cn.as<float4>();
+  pa.s_nrm = st->rec_nrm.as<float4>();
+  pa.s_vox = st->rec_vox.as<uint32_t>();
+  pa.s_rect = st->rec_rect.as<uint64_t>();
   {
     StageTimer tm(ctx, ST_PREPROCESS, s);
     if (n_items > 0 && nv > 0)
@@ -1071,30 +1069,15 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   }
   uint64_t* ks = alt ? keys2.as<uint64_t>() : keys.as<uint64_t>();
   uint32_t* vs = alt ? vals2.as<uint32_t>() : vals.as<uint32_t>();
-  // records in sorted order
+  // per sorted record: slot's (view, octree) id, tile count and offset
   DBuf r_count, r_off;
-  DBuf& r_rect = st->rec_rect;
-  DV_TRY(alloc_n<float4>(ctx, st->rec_geo, nv, s));
-  DV_TRY(alloc_n<float4>(ctx, st->rec_g8a, nv, s));
-  DV_TRY(alloc_n<float4>(ctx, st->rec_g8b, nv, s));
-  DV_TRY(alloc_n<float4>(ctx, st->rec_cn, nv, s));
-  DV_TRY(alloc_n<float4>(ctx, st->rec_nrm, nv, s));
-  DV_TRY(alloc_n<uint32_t>(ctx, st->rec_vox, nv, s));
-  DV_TRY(alloc_n<uint32_t>(ctx, st->rec_seg, nv, s));
   DV_TRY(alloc_n<uint32_t>(ctx, r_count, nv, s));
   DV_TRY(alloc_n<uint32_t>(ctx, r_off, nv, s));
-  DV_TRY(alloc_n<uint64_t>(ctx, r_rect, nv, s));
   StageTimer tm_gather(ctx, ST_GATHER, s);
   if (nv > 0)
     hipLaunchKernelGGL(k_gather, dim3(grid_for(nv, TPB)), dim3(TPB), 0, s, nv,
-                       ks, vs, st->rank_bits, s_geo.as<float4>(),
-                       s_g8a.as<float4>(), s_g8b.as<float4>(), s_cn.as<float4>(),
-                       s_nrm.as<float4>(), s_vox.as<uint32_t>(),
-                       s_rect.as<uint64_t>(), st->rec_geo.as<float4>(),
-                       st->rec_g8a.as<float4>(), st->rec_g8b.as<float4>(),
-                       st->rec_cn.as<float4>(), st->rec_nrm.as<float4>(),
-                       st->rec_vox.as<uint32_t>(), st->rec_seg.as<uint32_t>(),
-                       r_count.as<uint32_t>(), r_rect.as<uint64_t>());
+                       ks, vs, st->rank_bits, st->rec_rect.as<uint64_t>(),
+                       st->rec_seg.as<uint32_t>(), r_count.as<uint32_t>());
   DV_TRY_HIP(hipGetLastError());
   DV_TRY(exclusive_scan_u32(ctx, r_count.as<uint32_t>(), r_off.as<uint32_t>(),
                             total.as<uint64_t>(), nv, s));
@@ -1114,9 +1097,8 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   }
   st->n_pairs = (int64_t)n_pairs;
   const int64_t np = (int64_t)n_pairs;
-  // free slot-order buffers early
-  s_geo.reset(); s_g8a.reset(); s_g8b.reset(); s_cn.reset(); s_nrm.reset();
-  s_vox.reset(); s_rect.reset();
+  keys.reset();
+  keys2.reset();
   DBuf pkey, pkey2, pval2;
   DV_TRY(alloc_n<uint32_t>(ctx, pkey, np, s));
   DV_TRY(alloc_n<uint32_t>(ctx, st->pair_val, np, s));
@@ -1125,7 +1107,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   StageTimer tm_emit(ctx, ST_EMIT, s);
   if (np > 0)
     hipLaunchKernelGGL(k_emit, dim3(grid_for(np, TPB)), dim3(TPB), 0, s, np, nv,
-                       r_off.as<uint32_t>(), r_rect.as<uint64_t>(),
+                       r_off.as<uint32_t>(), vs, st->rec_rect.as<uint64_t>(),
                        st->rec_seg.as<uint32_t>(), n_oct,
                        st->views_d.as<ViewConst>(), pkey.as<uint32_t>(),
                        st->pair_val.as<uint32_t>());

@@ -119,16 +119,18 @@ def test_c3_crop_gradients(tmp_path):
     # the bar applies per gradient kind over all octrees / actors together:
     # octrees seen only far behind the crop's car carry FP64 gradients of
     # 1e-16 and below, where FP32 transmittance has underflowed to 0
-    gc, rc, gs, rs = [], [], [], []
+    gc, rc, mc, gs, rs = [], [], [], [], []
     for k, o in enumerate(sub["octrees"]):
         keep = o["_keep"]
         if len(keep) == 0:
             continue
         gc.append(acc[k]["corner"].cpu().numpy())
         rc.append(ref["corner"][k])
+        mc.append(ref["corner_abs"][k])
         gs.append(acc[k]["sh"].cpu().numpy()[:, :, keep].ravel())
         rs.append(np.asarray(ref["sh"][k]).ravel())
-    worst = {"corner": _close("corner (all octrees)", np.concatenate(gc), np.concatenate(rc)),
+    worst = {"corner": _close("corner (all octrees)", np.concatenate(gc), np.concatenate(rc),
+                              mag=np.concatenate(mc)),
              "sh": _close("sh (all octrees)", np.concatenate(gs), np.concatenate(rs))}
     p0 = pg.cpu().numpy()[0]
     refR = np.stack([ref["dR"][i + 1] for i in range(na)])
@@ -137,7 +139,7 @@ def test_c3_crop_gradients(tmp_path):
     worst["dp"] = _close("dp (all actors)", p0[:, 9:], refp)
     # and the crop's own car by itself
     worst[f"corner[{kcar}]"] = _close(f"corner[{kcar}]", acc[kcar]["corner"].cpu().numpy(),
-                                      ref["corner"][kcar])
+                                      ref["corner"][kcar], mag=ref["corner_abs"][kcar])
     # other views carry zero upstream gradient: no pose gradient there
     assert float(pg[1:].abs().max()) == 0.0
     bad = {k: w for k, w in worst.items() if w > 1.0}
