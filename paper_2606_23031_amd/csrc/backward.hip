@@ -288,80 +288,58 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
       if (T < a.eps) done = true;
       return dtau;
     };
-    if (n_at == 0) {
-      for (uint32_t base = beg; base < bgend; base += TPB) {
-        const uint32_t nb = min((uint32_t)TPB, bgend - base);
-        load_bwd_batch(B, a, base, nb);
-        __syncthreads();
-        uint64_t wm[4];
-        wave_entry_masks(B.rect, nb, bx, by, wm);
-        for (int c = 0; c < 4; ++c) {
-          uint64_t m = wm[c];
-          while (m != 0 && __ballot(!done) != 0) {
-            const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
-            m &= m - 1;
-            float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
-            float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            bool hit = false;
-            if (!done) {
-              const float4 geo = B.geo[r];
-              float t0, t1;
-              slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
-              ++n_test;
-              t0 = fmaxf(t0, a.tau_near);
-              if (t1 > t0) {
-                PieceDer pd;
-                const float tau = piece_eval<1, KC>(geo, B.ga[r], B.gb[r], B.cn[r].w,
-                                                    d, t0, t1, K, invK, a.c,
-                                                    a.inv_c, &pd);
-                ++n_piece;
-                float wgt;
-                piece_grad(r, tau, pd, t0, t1, dcol, dnrm, dg, wgt);
-                hit = true;
-              }
-            }
-            accum_record(B, r, hit, dcol, dnrm, dg);
-          }
-        }
-        flush_batch(B, a, nb);
-        if (__syncthreads_and(done)) break;
-      }
-    } else {
-      int qn = 0;
-      float ns = nseg > 0 ? a.seg_se[seg_index(seg0, tid)].x : F_INF;
-      float excl = -F_INF;
-      auto splice = [&](int qq) {
-        const size_t qi = seg_index(seg0 + qq, tid);
-        const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
-        const float Vq = GC.x * q0.x + GC.y * q0.y + GC.z * q0.z + GD * q0.w +
-                         GN.x * q1.x + GN.y * q1.y + GN.z * q1.z;
-        const float Tpre = T;
-        P = fmaf(T, Vq, P);
-        PT = fmaf(T < T_REBASE ? T : 0.0f, Vq, PT);
-        T *= q1.w;
-        // keep .z: the piece just before may have added dL/dstart
-        float4 bw = a.seg_bw[qi];
-        bw.x = Tpre;
-        bw.y = suffix();
-        a.seg_bw[qi] = bw;
-        if (T < a.eps) done = true;
-      };
-      for (uint32_t base = beg; base < bgend; base += TPB) {
-        const uint32_t nb = min((uint32_t)TPB, bgend - base);
-        load_bwd_batch(B, a, base, nb);
-        __syncthreads();
-        for (uint32_t r = 0; r < nb; ++r) {
-          if (!rect_hits_block(B.rect[r], bx, by)) continue;
-          const float4 geo = B.geo[r];
+    // waves none of whose pixels has an ownership segment take the plain
+    // walk (wave-uniform), the others splice segments as they come
+    const bool wseg = __ballot(nseg > 0) != 0;
+    int qn = 0;
+    float ns = nseg > 0 ? a.seg_se[seg_index(seg0, tid)].x : F_INF;
+    float excl = -F_INF;
+    auto splice = [&](int qq) {
+      const size_t qi = seg_index(seg0 + qq, tid);
+      const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
+      const float Vq = GC.x * q0.x + GC.y * q0.y + GC.z * q0.z + GD * q0.w +
+                       GN.x * q1.x + GN.y * q1.y + GN.z * q1.z;
+      const float Tpre = T;
+      P = fmaf(T, Vq, P);
+      PT = fmaf(T < T_REBASE ? T : 0.0f, Vq, PT);
+      T *= q1.w;
+      // keep .z: the piece just before may have added dL/dstart
+      float4 bw = a.seg_bw[qi];
+      bw.x = Tpre;
+      bw.y = suffix();
+      a.seg_bw[qi] = bw;
+      if (T < a.eps) done = true;
+    };
+    for (uint32_t base = beg; base < bgend; base += TPB) {
+      const uint32_t nb = min((uint32_t)TPB, bgend - base);
+      load_bwd_batch(B, a, base, nb);
+      __syncthreads();
+      uint64_t wm[4];
+      wave_entry_masks(B.rect, nb, bx, by, wm);
+      for (int c = 0; c < 4; ++c) {
+        uint64_t m = wm[c];
+        while (m != 0 && __ballot(!done) != 0) {
+          const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
+          m &= m - 1;
           float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
           float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
           bool hit = false;
           if (!done) {
+            const float4 geo = B.geo[r];
             float t0, t1;
             slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
             ++n_test;
             t0 = fmaxf(t0, a.tau_near);
-            if (t1 > t0) {
+            if (t1 > t0 && !wseg) {
+              PieceDer pd;
+              const float tau = piece_eval<1, KC>(geo, B.ga[r], B.gb[r], B.cn[r].w,
+                                                  d, t0, t1, K, invK, a.c,
+                                                  a.inv_c, &pd);
+              ++n_piece;
+              float wgt;
+              piece_grad(r, tau, pd, t0, t1, dcol, dnrm, dg, wgt);
+              hit = true;
+            } else if (t1 > t0) {
               float pa = fmaxf(t0, excl);
               bool a_seg = excl > t0;
               while (pa < t1 && !done) {
@@ -401,13 +379,13 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
           }
           accum_record(B, r, hit, dcol, dnrm, dg);
         }
-        flush_batch(B, a, nb);
-        if (__syncthreads_and(done)) break;
       }
-      while (!done && qn < nseg) {
-        splice(qn);
-        ++qn;
-      }
+      flush_batch(B, a, nb);
+      if (__syncthreads_and(done)) break;
+    }
+    while (!done && qn < nseg) {
+      splice(qn);
+      ++qn;
     }
   }
 

@@ -625,65 +625,51 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
     if (T < a.eps) done = true;
   };
   const uint32_t beg = a.tile_start[gt], bgend = a.tile_bgend[gt];
-  if (n_at == 0) {
-    // no actor box meets the tile: a plain walk, entries picked from the
-    // wave's rectangle masks
-    for (uint32_t base = beg; base < bgend; base += TPB) {
-      const uint32_t nb = min((uint32_t)TPB, bgend - base);
-      load_batch(B, a, base, nb);
-      __syncthreads();
-      uint64_t wm[4];
-      wave_entry_masks(B.rect, nb, bx, by, wm);
-      for (int c = 0; c < 4; ++c) {
-        uint64_t m = wm[c];
-        while (m != 0 && __ballot(!done) != 0) {
-          const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
-          m &= m - 1;
-          if (!done) {
-            const float4 geo = B.geo[r];
-            float t0, t1;
-            slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
-            ++n_test;
-            t0 = fmaxf(t0, a.tau_near);
-            if (t1 > t0) add_piece(r, geo, t0, t1);
-          }
-        }
-      }
-      if (__syncthreads_and(done)) break;
+  // Waves none of whose pixels has an ownership segment take the plain walk
+  // (a wave-uniform choice); the others splice segments as they come.
+  const bool wseg = __ballot(nseg > 0) != 0;
+  int qn = 0;
+  float ns = nseg > 0 ? a.seg_se[seg_index(seg0, tid)].x : F_INF;
+  float excl = -F_INF;
+  auto splice = [&](int qq) {
+    const size_t qi = seg_index(seg0 + qq, tid);
+    const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
+    const float ts = T < T_REBASE ? T : 0.0f;
+    C3.x = fmaf(T, q0.x, C3.x); CT.x = fmaf(ts, q0.x, CT.x);
+    C3.y = fmaf(T, q0.y, C3.y); CT.y = fmaf(ts, q0.y, CT.y);
+    C3.z = fmaf(T, q0.z, C3.z); CT.z = fmaf(ts, q0.z, CT.z);
+    D = fmaf(T, q0.w, D); DT = fmaf(ts, q0.w, DT);
+    if (NORMALS) {
+      N3.x = fmaf(T, q1.x, N3.x); NT.x = fmaf(ts, q1.x, NT.x);
+      N3.y = fmaf(T, q1.y, N3.y); NT.y = fmaf(ts, q1.y, NT.y);
+      N3.z = fmaf(T, q1.z, N3.z); NT.z = fmaf(ts, q1.z, NT.z);
     }
-  } else {
-    int qn = 0;
-    float ns = nseg > 0 ? a.seg_se[seg_index(seg0, tid)].x : F_INF;
-    float excl = -F_INF;
-    auto splice = [&](int qq) {
-      const size_t qi = seg_index(seg0 + qq, tid);
-      const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
-      const float ts = T < T_REBASE ? T : 0.0f;
-      C3.x = fmaf(T, q0.x, C3.x); CT.x = fmaf(ts, q0.x, CT.x);
-      C3.y = fmaf(T, q0.y, C3.y); CT.y = fmaf(ts, q0.y, CT.y);
-      C3.z = fmaf(T, q0.z, C3.z); CT.z = fmaf(ts, q0.z, CT.z);
-      D = fmaf(T, q0.w, D); DT = fmaf(ts, q0.w, DT);
-      if (NORMALS) {
-        N3.x = fmaf(T, q1.x, N3.x); NT.x = fmaf(ts, q1.x, NT.x);
-        N3.y = fmaf(T, q1.y, N3.y); NT.y = fmaf(ts, q1.y, NT.y);
-        N3.z = fmaf(T, q1.z, N3.z); NT.z = fmaf(ts, q1.z, NT.z);
-      }
-      T *= q1.w;
-      excl = a.seg_se[qi].y;
-      if (T < a.eps) done = true;
-    };
-    for (uint32_t base = beg; base < bgend; base += TPB) {
-      const uint32_t nb = min((uint32_t)TPB, bgend - base);
-      load_batch(B, a, base, nb);
-      __syncthreads();
-      for (uint32_t r = 0; r < nb && !done; ++r) {
-        if (!rect_hits_block(B.rect[r], bx, by)) continue;
+    T *= q1.w;
+    excl = a.seg_se[qi].y;
+    if (T < a.eps) done = true;
+  };
+  for (uint32_t base = beg; base < bgend; base += TPB) {
+    const uint32_t nb = min((uint32_t)TPB, bgend - base);
+    load_batch(B, a, base, nb);
+    __syncthreads();
+    uint64_t wm[4];
+    wave_entry_masks(B.rect, nb, bx, by, wm);
+    for (int c = 0; c < 4; ++c) {
+      uint64_t m = wm[c];
+      while (m != 0 && __ballot(!done) != 0) {
+        const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
+        if (done) continue;
         const float4 geo = B.geo[r];
         float t0, t1;
         slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
         ++n_test;
         t0 = fmaxf(t0, a.tau_near);
         if (!(t1 > t0)) continue;
+        if (!wseg) {
+          add_piece(r, geo, t0, t1);
+          continue;
+        }
         float pa = fmaxf(t0, excl);
         while (pa < t1 && !done) {
           if (pa >= ns) {
@@ -698,12 +684,12 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
           pa = pb;
         }
       }
-      if (__syncthreads_and(done)) break;
     }
-    while (!done && qn < nseg) {
-      splice(qn);
-      ++qn;
-    }
+    if (__syncthreads_and(done)) break;
+  }
+  while (!done && qn < nseg) {
+    splice(qn);
+    ++qn;
   }
   count_work(a.counters, 0, n_test, n_piece);
   // per-tile work (slab tests + 4 per piece), the backward's schedule key
