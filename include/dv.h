@@ -157,6 +157,10 @@ typedef struct {
   int64_t n_tiles;              /* 16x16 tiles over all windows            */
   int32_t key_bits;             /* bits of the record sort key             */
   int32_t tile_bits;            /* bits of the pair sort key               */
+  int64_t n_items;              /* compositing work items: one per tile,
+                                   several for a tile whose background list
+                                   is split into chunks                    */
+  int64_t n_chunk_slots;        /* chunks of the split tiles               */
 } dv_state_info;
 
 /* ---------------------------------------------------------------- context */

@@ -97,7 +97,8 @@ constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1,0,3,2]
 // lane l with the full sum of channel l >> 2; lanes with l % 4 == 0 then add
 // their channel into LDS.  Cross-half and cross-row steps use the gfx950
 // permlane swaps, in-row steps DPP, so no exchange goes through LDS.  Must
-// be called wave-uniformly with every lane active.
+// be called wave-uniformly with every lane active; lanes without a hit pass
+// zero contributions.
 __device__ inline void accum_record(BwdBatch& B, uint32_t r, bool hit,
                                     float3 dcol, float3 dnrm,
                                     const float* dg) {
@@ -110,10 +111,6 @@ __device__ inline void accum_record(BwdBatch& B, uint32_t r, bool hit,
   for (int m = 0; m < 8; ++m) v[6 + m] = dg[m];
   v[14] = 0.0f;
   v[15] = 0.0f;
-  if (!hit) {
-#pragma unroll
-    for (int c = 0; c < 16; ++c) v[c] = 0.0f;
-  }
   // lane bit 5: channels 0-7 stay in the lower half, 8-15 in the upper
 #pragma unroll
   for (int i = 0; i < 8; ++i) v[i] = swap32_sum(v[i], v[i + 8]);
@@ -196,201 +193,294 @@ __device__ inline void pose12(const VOConst& C, float3 d, float3 go, float3 gd,
                    C.R[b * 3 + 2] * g_o[2]);
 }
 
-// Backward compositing: the forward walk re-run in the same order with the
-// same arithmetic (so T and every stop decision repeat bit for bit), giving
-// dL/dtau_i = T_{i+1} v_i - S_{i+1} with the suffix S formed against the
-// totals, or against the tail sums once T < T_REBASE.
+// Upstream gradients of the pixel.
+struct PixGrad {
+  float3 GC, GN;
+  float GD, GT;
+};
+template <bool NORMALS>
+__device__ inline PixGrad pixel_grads(const CompArgs& a, const PixSetup& P) {
+  PixGrad g;
+  g.GC = make_float3(0, 0, 0);
+  g.GN = make_float3(0, 0, 0);
+  g.GD = 0.0f;
+  g.GT = 0.0f;
+  if (!P.valid) return g;
+  const ViewConst& V = a.views[P.v];
+  const dv_out_grads& G = a.gin[P.v];
+  const size_t hw = (size_t)V.w * V.h, o = (size_t)P.py * V.w + P.px;
+  if (G.rgb) g.GC = make_float3(G.rgb[o], G.rgb[hw + o], G.rgb[2 * hw + o]);
+  if (G.depth) g.GD = G.depth[o];
+  if (NORMALS && G.normal)
+    g.GN = make_float3(G.normal[o], G.normal[hw + o], G.normal[2 * hw + o]);
+  if (G.T) g.GT = G.T[o];
+  return g;
+}
+// Upstream-weighted value of a (C.rgb, D) and (N.xyz, -) pair.
+__device__ inline float gdot(const PixGrad& g, float4 c, float4 n) {
+  return g.GC.x * c.x + g.GC.y * c.y + g.GC.z * c.z + g.GD * c.w +
+         g.GN.x * n.x + g.GN.y * n.y + g.GN.z * n.z;
+}
+
+__global__ void k_seg_bw_init(int64_t n, float4* seg_bw) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i < n) seg_bw[i] = make_float4(-1.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// Backward, part 1 (tiles of several chunks): per pixel and chunk, the
+// transmittance in front of the chunk and the part of L behind it,
+// S_after_c = sum_{c' > c} T_<c' V_c' + T (C_bg.G_C + G_T), summed from the
+// back so that no difference of large sums is formed.
+template <bool NORMALS>
+__global__ void __launch_bounds__(TPB) k_chunk_prep(CompArgs a) {
+  const uint32_t gt = blockIdx.x;
+  const uint32_t nck = a.tile_nck[gt];
+  if (nck <= 1) return;
+  const int tid = threadIdx.x;
+  const PixSetup P = pixel_setup(a, gt, tid);
+  if (!P.valid) return;
+  const PixGrad g = pixel_grads<NORMALS>(a, P);
+  const size_t s0 = (size_t)a.tile_pbase[gt] * TPB + tid;
+  const float4* part = a.chunk_part + s0 * 4;
+  float T = 1.0f;
+  for (uint32_t c = 0; c < nck; ++c) {
+    a.chunk_tps[s0 + (size_t)c * TPB] = make_float2(T, 0.0f);
+    T *= part[(size_t)c * TPB * 4 + 1].w;
+  }
+  float S = (g.GC.x * a.bg[0] + g.GC.y * a.bg[1] + g.GC.z * a.bg[2] + g.GT) * T;
+  for (uint32_t c = nck; c-- > 0;) {
+    const size_t q = (size_t)c * TPB;
+    const float Tp = a.chunk_tps[s0 + q].x;
+    a.chunk_tps[s0 + q] = make_float2(Tp, S);
+    const float Vc = gdot(g, part[q * 4], part[q * 4 + 1]);
+    S = fmaf(Tp, Vc, S);
+  }
+}
+
+// Backward, part 2: the forward walk of one work item re-run in the same
+// order with the same arithmetic (so the chunk-local T and every stop
+// decision repeat bit for bit), giving for each background piece
+//   dL/dtau_i = T_pre (T_{i+1} v_i - S_{i+1}) - S_after,
+// where T, S are chunk-local (the suffix against the chunk's totals, or
+// against its tail sums once T < T_REBASE), T_pre the transmittance in front
+// of the chunk and S_after the part of L behind it (a tile of one chunk:
+// T_pre = 1, S_after = its background term).  Per-record colour, normal and
+// corner gradients are summed over the wave and block, then added once per
+// record and batch; spliced segments get T_pre and S_after of their own for
+// k_actor_bwd.
 template <bool NORMALS, int KC>
-__global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
+__global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
   __shared__ BwdBatch B;
-  __shared__ float red[(TPB / 64) * 12];
-  const uint32_t gt = a.tile_order[blockIdx.x];
+  // the order holds every id below the grid size; ids past the item count
+  // are unused
+  const uint32_t item = a.order[blockIdx.x];
+  if (item >= a.plan_counts[0]) return;
+  const uint32_t gt = a.item_tile[item], chunk = a.item_chunk[item];
+  const uint32_t nck = a.tile_nck[gt];
   const int tid = threadIdx.x;
   for (int c = 0; c < NACC; ++c) B.acc[c][tid] = 0.0f;
-  const int v = view_of_tile(a.views, a.n_views, gt);
-  const ViewConst& V = a.views[v];
-  const uint32_t lt = gt - V.tile_base;
-  const int px = (int)(lt % V.ntx) * TILE + tile_px(tid);
-  const int py = (int)(lt / V.ntx) * TILE + tile_py(tid);
-  const int bx = (int)(lt % V.ntx) * TILE + (((tid >> 6) & 1) << 3);
-  const int by = (int)(lt / V.ntx) * TILE + (((tid >> 6) >> 1) << 3);
-  const bool valid = px < V.w && py < V.h;
-  float3 d;
-  {
-    const float dx = ((float)(V.x0 + px) + 0.5f - V.fcx) * V.inv_fx;
-    const float dy = ((float)(V.y0 + py) + 0.5f - V.fcy) * V.inv_fy;
-    d = mat3_mul(V.Rc, make_float3(dx, dy, 1.0f));
-    const float inv = 1.0f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
-    d = make_float3(d.x * inv, d.y * inv, d.z * inv);
-  }
+  const PixSetup P = pixel_setup(a, gt, tid);
+  const int bx = P.bx, by = P.by;
+  const bool valid = P.valid;
+  const float3 d = P.d;
+  const size_t pix = P.pix;
   const int K = a.K;
   const float invK = 1.0f / (float)K;
-  const size_t pix = (size_t)gt * TPB + tid;
   uint32_t n_test = 0, n_piece = 0;
-  // upstream gradients and the scalar L
-  float3 GC = make_float3(0, 0, 0), GN = make_float3(0, 0, 0);
-  float GD = 0.0f, GT = 0.0f, L = 0.0f, LB = 0.0f, LT = 0.0f;
+  const PixGrad g = pixel_grads<NORMALS>(a, P);
+  const float3 GC = g.GC, GN = g.GN;
+  const float GD = g.GD;
+  // chunk totals V / VT (upstream-weighted) and the chunk's surroundings
+  float V = 0.0f, VT = 0.0f, Tpre = 1.0f, Saft = 0.0f;
   if (valid) {
-    const dv_out_grads& G = a.gin[v];
-    const size_t hw = (size_t)V.w * V.h, o = (size_t)py * V.w + px;
-    if (G.rgb) GC = make_float3(G.rgb[o], G.rgb[hw + o], G.rgb[2 * hw + o]);
-    if (G.depth) GD = G.depth[o];
-    if (NORMALS && G.normal)
-      GN = make_float3(G.normal[o], G.normal[hw + o], G.normal[2 * hw + o]);
-    if (G.T) GT = G.T[o];
-    const float4 f0 = a.fin0[pix], f1 = a.fin1[pix];
-    LB = (GC.x * a.bg[0] + GC.y * a.bg[1] + GC.z * a.bg[2] + GT) * f1.w;
-    L = GC.x * f0.x + GC.y * f0.y + GC.z * f0.z + GD * f0.w +
-        GN.x * f1.x + GN.y * f1.y + GN.z * f1.z + LB;
-    const float4 f2 = a.fin2[pix], f3 = a.fin3[pix];
-    LT = GC.x * f2.x + GC.y * f2.y + GC.z * f2.z + GD * f2.w +
-         GN.x * f3.x + GN.y * f3.y + GN.z * f3.z + LB;
+    if (nck == 1) {
+      const float4 f1 = a.fin1[pix];
+      V = gdot(g, a.fin0[pix], f1);
+      VT = gdot(g, a.fin2[pix], a.fin3[pix]);
+      Saft = (GC.x * a.bg[0] + GC.y * a.bg[1] + GC.z * a.bg[2] + g.GT) * f1.w;
+    } else {
+      const size_t sl = ((size_t)a.tile_pbase[gt] + chunk) * TPB + tid;
+      const float4* part = a.chunk_part + sl * 4;
+      V = gdot(g, part[0], part[1]);
+      VT = gdot(g, part[2], part[3]);
+      const float2 tps = a.chunk_tps[sl];
+      Tpre = tps.x;
+      Saft = tps.y;
+    }
   }
   const uint32_t a_beg = a.act_beg[gt];
   const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
   const uint32_t seg0 = 3 * a_beg + n_at;
   const int nseg = (n_at > 0 && valid) ? (int)a.pix_nseg[pix] : 0;
-  for (int q = 0; q < nseg; ++q)
-    a.seg_bw[seg_index(seg0 + q, tid)] = make_float4(-1.0f, 0.0f, 0.0f, 0.0f);
 
-  // ---------------------------------------------------- B1: background
-  {
-    float T = 1.0f, P = 0.0f, PT = 0.0f;
-    bool done = !valid;
-    const float3 inv = safe_inv(d);
-    const uint32_t beg = a.tile_start[gt], bgend = a.tile_bgend[gt];
-    auto suffix = [&]() { return T < T_REBASE ? LT - PT : L - P; };
-    // composite one piece of entry r and add its colour/normal/corner
-    // gradients; returns dL/dtau, the piece's weight in wgt
-    auto piece_grad = [&](uint32_t r, float tau, const PieceDer& pd, float pa,
-                          float pb, float3& dcol, float3& dnrm, float* dg,
-                          float& wgt) {
-      const float4 cn = B.cn[r];
-      const float e = fast_exp(-tau);
-      wgt = T * opacity(tau, e);
-      const float wt = T < T_REBASE ? wgt : 0.0f;
-      const float mid = 0.5f * (pa + pb);
-      float vi = GC.x * cn.x + GC.y * cn.y + GC.z * cn.z + GD * mid;
-      if (NORMALS) {
-        const float4 nr = B.nrm[r];
-        vi += GN.x * nr.x + GN.y * nr.y + GN.z * nr.z;
-      }
-      P = fmaf(wgt, vi, P);
-      PT = fmaf(wt, vi, PT);
-      T *= e;
-      const float dtau = T * vi - suffix();
-      dcol.x += wgt * GC.x; dcol.y += wgt * GC.y; dcol.z += wgt * GC.z;
-      if (NORMALS) {
-        dnrm.x += wgt * GN.x; dnrm.y += wgt * GN.y; dnrm.z += wgt * GN.z;
-      }
-#pragma unroll
-      for (int m = 0; m < 8; ++m) dg[m] = fmaf(dtau, pd.dg[m], dg[m]);
-      if (T < a.eps) done = true;
-      return dtau;
-    };
-    // waves none of whose pixels has an ownership segment take the plain
-    // walk (wave-uniform), the others splice segments as they come
-    const bool wseg = __ballot(nseg > 0) != 0;
-    int qn = 0;
-    float ns = nseg > 0 ? a.seg_se[seg_index(seg0, tid)].x : F_INF;
-    float excl = -F_INF;
-    auto splice = [&](int qq) {
-      const size_t qi = seg_index(seg0 + qq, tid);
-      const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
-      const float Vq = GC.x * q0.x + GC.y * q0.y + GC.z * q0.z + GD * q0.w +
-                       GN.x * q1.x + GN.y * q1.y + GN.z * q1.z;
-      const float Tpre = T;
-      P = fmaf(T, Vq, P);
-      PT = fmaf(T < T_REBASE ? T : 0.0f, Vq, PT);
-      T *= q1.w;
-      // keep .z: the piece just before may have added dL/dstart
-      float4 bw = a.seg_bw[qi];
-      bw.x = Tpre;
-      bw.y = suffix();
-      a.seg_bw[qi] = bw;
-      if (T < a.eps) done = true;
-    };
-    for (uint32_t base = beg; base < bgend; base += TPB) {
-      const uint32_t nb = min((uint32_t)TPB, bgend - base);
-      load_bwd_batch(B, a, base, nb);
-      __syncthreads();
-      uint64_t wm[4];
-      wave_entry_masks(B.rect, nb, bx, by, wm);
-      for (int c = 0; c < 4; ++c) {
-        uint64_t m = wm[c];
-        while (m != 0 && __ballot(!done) != 0) {
-          const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
-          m &= m - 1;
-          float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
-          float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-          bool hit = false;
-          if (!done) {
-            const float4 geo = B.geo[r];
-            float t0, t1;
-            slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
-            ++n_test;
-            t0 = fmaxf(t0, a.tau_near);
-            if (t1 > t0 && !wseg) {
-              PieceDer pd;
-              const float tau = piece_eval<1, KC>(geo, B.ga[r], B.gb[r], B.cn[r].w,
-                                                  d, t0, t1, K, invK, a.c,
-                                                  a.inv_c, &pd);
-              ++n_piece;
-              float wgt;
-              piece_grad(r, tau, pd, t0, t1, dcol, dnrm, dg, wgt);
-              hit = true;
-            } else if (t1 > t0) {
-              float pa = fmaxf(t0, excl);
-              bool a_seg = excl > t0;
-              while (pa < t1 && !done) {
-                if (pa >= ns) {
-                  const float ex = a.seg_se[seg_index(seg0 + qn, tid)].y;
-                  splice(qn);
-                  if (ex > pa) { pa = ex; a_seg = true; }
-                  excl = ex;
-                  ++qn;
-                  ns = qn < nseg ? a.seg_se[seg_index(seg0 + qn, tid)].x : F_INF;
-                  continue;
-                }
-                const bool b_seg = ns < t1;
-                const float pb = fminf(t1, ns);
-                const float inv_h = B.cn[r].w;
-                PieceDer pd;
-                const float tau =
-                    (a_seg || b_seg)
-                        ? piece_eval<2, KC>(geo, B.ga[r], B.gb[r], inv_h, d, pa, pb,
-                                            K, invK, a.c, a.inv_c, &pd)
-                        : piece_eval<1, KC>(geo, B.ga[r], B.gb[r], inv_h, d, pa, pb,
-                                            K, invK, a.c, a.inv_c, &pd);
-                ++n_piece;
-                float wgt;
-                const float dtau = piece_grad(r, tau, pd, pa, pb, dcol, dnrm, dg, wgt);
-                hit = true;
-                if (a_seg && qn > 0)
-                  a.seg_bw[seg_index(seg0 + qn - 1, tid)].w +=
-                      dtau * pd.dtda + 0.5f * wgt * GD;
-                if (b_seg)
-                  a.seg_bw[seg_index(seg0 + qn, tid)].z +=
-                      dtau * pd.dtdb + 0.5f * wgt * GD;
-                pa = pb;
-                a_seg = false;
+  float T = 1.0f, P_ = 0.0f, PT = 0.0f;
+  bool done = !valid;
+  const float3 inv = safe_inv(d);
+  uint32_t beg, bgend;
+  chunk_range(a.tile_start[gt], a.tile_bgend[gt], nck, chunk, beg, bgend);
+  float Bc, Bn;
+  chunk_bounds(a, gt, nck, chunk, tid, Bc, Bn);
+  auto suffix = [&]() { return T < T_REBASE ? VT - PT : V - P_; };
+  // composite one piece of entry r and add its colour/normal/corner
+  // gradients; returns dL/dtau, the piece's (global) weight in wg
+  auto piece_grad = [&](uint32_t r, float tau, const PieceDer& pd, float pa,
+                        float pb, float3& dcol, float3& dnrm, float* dg,
+                        float& wg) {
+    const float4 cn = B.cn[r];
+    const float e = fast_exp(-tau);
+    const float wgt = T * opacity(tau, e);
+    const float wt = T < T_REBASE ? wgt : 0.0f;
+    const float mid = 0.5f * (pa + pb);
+    float vi = GC.x * cn.x + GC.y * cn.y + GC.z * cn.z + GD * mid;
+    if (NORMALS) {
+      const float4 nr = B.nrm[r];
+      vi += GN.x * nr.x + GN.y * nr.y + GN.z * nr.z;
+    }
+    P_ = fmaf(wgt, vi, P_);
+    PT = fmaf(wt, vi, PT);
+    T *= e;
+    const float dtau = Tpre * (T * vi - suffix()) - Saft;
+    wg = Tpre * wgt;
+    dcol.x += wg * GC.x; dcol.y += wg * GC.y; dcol.z += wg * GC.z;
+    if (NORMALS) {
+      dnrm.x += wg * GN.x; dnrm.y += wg * GN.y; dnrm.z += wg * GN.z;
+    }
+    add_corner_grads<KC>(pd, dtau, dg);
+    if (T < a.eps) done = true;
+    return dtau;
+  };
+  // waves none of whose pixels has an ownership segment take the plain
+  // walk (wave-uniform), the others splice segments as they come
+  const bool wseg = __ballot(nseg > 0) != 0;
+  int qn = 0;
+  while (qn < nseg && a.seg_se[seg_index(seg0 + qn, tid)].x < Bc) ++qn;
+  float excl = qn > 0 ? a.seg_se[seg_index(seg0 + qn - 1, tid)].y : -F_INF;
+  float ns = qn < nseg ? a.seg_se[seg_index(seg0 + qn, tid)].x : F_INF;
+  auto splice = [&](int qq) {
+    const size_t qi = seg_index(seg0 + qq, tid);
+    const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
+    const float Vq = gdot(g, q0, q1);
+    const float Tseg = Tpre * T;
+    P_ = fmaf(T, Vq, P_);
+    PT = fmaf(T < T_REBASE ? T : 0.0f, Vq, PT);
+    T *= q1.w;
+    // .x/.y only: .z (from the piece in front) and .w (from the piece
+    // behind, possibly another chunk's block) are added separately
+    float* bw = reinterpret_cast<float*>(a.seg_bw + qi);
+    bw[0] = Tseg;
+    bw[1] = fmaf(Tpre, suffix(), Saft);
+    if (T < a.eps) done = true;
+  };
+  for (uint32_t base = beg; base < bgend; base += TPB) {
+    const uint32_t nb = min((uint32_t)TPB, bgend - base);
+    load_bwd_batch(B, a, base, nb);
+    __syncthreads();
+    uint64_t wm[4];
+    wave_entry_masks(B.rect, nb, bx, by, wm);
+    for (int c = 0; c < 4; ++c) {
+      uint64_t m = wm[c];
+      while (m != 0 && __ballot(!done) != 0) {
+        const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
+        float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
+        float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        bool hit = false;
+        if (!done) {
+          const float4 geo = B.geo[r];
+          float t0, t1;
+          slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+          ++n_test;
+          t0 = fmaxf(t0, a.tau_near);
+          if (t1 > t0 && !wseg) {
+            PieceDer pd;
+            const float tau = piece_eval<1, KC>(geo, B.ga[r], B.gb[r], B.cn[r].w,
+                                                d, t0, t1, K, invK, a.c,
+                                                a.inv_c, &pd);
+            ++n_piece;
+            float wg;
+            piece_grad(r, tau, pd, t0, t1, dcol, dnrm, dg, wg);
+            hit = true;
+          } else if (t1 > t0) {
+            float pa = fmaxf(t0, excl);
+            bool a_seg = excl > t0;
+            while (pa < t1 && !done) {
+              if (pa >= ns) {
+                const float ex = a.seg_se[seg_index(seg0 + qn, tid)].y;
+                splice(qn);
+                if (ex > pa) { pa = ex; a_seg = true; }
+                excl = ex;
+                ++qn;
+                ns = qn < nseg ? a.seg_se[seg_index(seg0 + qn, tid)].x : F_INF;
+                continue;
               }
+              const bool b_seg = ns < t1;
+              const float pb = fminf(t1, ns);
+              const float inv_h = B.cn[r].w;
+              PieceDer pd;
+              const float tau =
+                  (a_seg || b_seg)
+                      ? piece_eval<2, KC>(geo, B.ga[r], B.gb[r], inv_h, d, pa, pb,
+                                          K, invK, a.c, a.inv_c, &pd)
+                      : piece_eval<1, KC>(geo, B.ga[r], B.gb[r], inv_h, d, pa, pb,
+                                          K, invK, a.c, a.inv_c, &pd);
+              ++n_piece;
+              float wg;
+              const float dtau = piece_grad(r, tau, pd, pa, pb, dcol, dnrm, dg, wg);
+              hit = true;
+              if (a_seg && qn > 0)
+                a.seg_bw[seg_index(seg0 + qn - 1, tid)].w +=
+                    dtau * pd.dtda + 0.5f * wg * GD;
+              if (b_seg)
+                a.seg_bw[seg_index(seg0 + qn, tid)].z +=
+                    dtau * pd.dtdb + 0.5f * wg * GD;
+              pa = pb;
+              a_seg = false;
             }
           }
-          accum_record(B, r, hit, dcol, dnrm, dg);
         }
+        accum_record(B, r, hit, dcol, dnrm, dg);
       }
-      flush_batch(B, a, nb);
-      if (__syncthreads_and(done)) break;
     }
-    while (!done && qn < nseg) {
-      splice(qn);
-      ++qn;
-    }
+    flush_batch(B, a, nb);
+    if (__syncthreads_and(done)) break;
   }
+  // segments before the next chunk's boundary (all, in the last chunk)
+  while (!done && qn < nseg && a.seg_se[seg_index(seg0 + qn, tid)].x < Bn) {
+    splice(qn);
+    ++qn;
+  }
+  count_work(a.counters, 2, n_test, n_piece);
+}
 
-  // ---------------------------------------------------- B2: actors
-  for (int j = 0; j < n_at; ++j) {
+// Backward, part 3 (tiles with actor boxes, after every part 2 item):
+// pieces of the asset segments (their T_pre, S_after from the splice), then
+// the box faces that bound segments, into the pose gradients.
+template <bool NORMALS, int KC>
+__global__ void __launch_bounds__(TPB) k_actor_bwd(CompArgs a) {
+  __shared__ BwdBatch B;
+  __shared__ float red[(TPB / 64) * 12];
+  const uint32_t e = a.actor_order[blockIdx.x];
+  const uint32_t gt = a.act_tile[e];
+  const uint32_t a_beg = a.act_beg[gt];
+  const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
+  const int jsel = (int)(e - a_beg);
+  const int tid = threadIdx.x;
+  for (int c = 0; c < NACC; ++c) B.acc[c][tid] = 0.0f;
+  const PixSetup P = pixel_setup(a, gt, tid);
+  const int v = P.v, bx = P.bx, by = P.by;
+  const bool valid = P.valid;
+  const float3 d = P.d;
+  const int K = a.K;
+  const float invK = 1.0f / (float)K;
+  uint32_t n_test = 0, n_piece = 0;
+  const PixGrad g = pixel_grads<NORMALS>(a, P);
+  const float3 GC = g.GC, GN = g.GN;
+  const float GD = g.GD;
+  const uint32_t seg0 = 3 * a_beg + n_at;
+  const int nseg = valid ? (int)a.pix_nseg[P.pix] : 0;
+
+  // ---------------------------------------------------- B2: actor jsel
+  for (int j = jsel; j == jsel; ++j) {
     // first spliced segment of slot j
     int q = nseg;
     for (int i = 0; i < nseg; ++i) {
@@ -429,17 +519,30 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
       return nseg;
     };
     if (has) load_q(q);
+    // last spliced segment of actor j on this ray: once it is done the lane
+    // has nothing left in this list
+    int qlast = -1;
+    for (int i = nseg - 1; i >= 0 && qlast < 0; --i) {
+      const size_t qi = seg_index(seg0 + i, tid);
+      if ((int)(a.seg_meta[qi] & 0xFF) == j && a.seg_bw[qi].x >= 0.0f) qlast = i;
+    }
+    auto live = [&]() { return has && !(qdone && q == qlast); };
     const uint2 sub = a.act_sub[a_beg + j];
     for (uint32_t base = sub.x; base < sub.y; base += TPB) {
       const uint32_t nb = min((uint32_t)TPB, sub.y - base);
       load_bwd_batch(B, a, base, nb);
       __syncthreads();
-      for (uint32_t r = 0; r < nb; ++r) {
-        if (!rect_hits_block(B.rect[r], bx, by)) continue;
+      uint64_t wm[4];
+      wave_entry_masks(B.rect, nb, bx, by, wm);
+      for (int wc = 0; wc < 4; ++wc) {
+      uint64_t m = wm[wc];
+      while (m != 0 && __ballot(live()) != 0) {
+        const uint32_t r = (uint32_t)wc * 64 + (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
         float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
         float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         bool hit = false;
-        if (has) {
+        if (live()) {
           const float4 geo = B.geo[r];
           float t0, t1;
           int ax0, ax1;
@@ -481,8 +584,7 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
                 if (NORMALS) {
                   dnrm.x += wt * GN.x; dnrm.y += wt * GN.y; dnrm.z += wt * GN.z;
                 }
-#pragma unroll
-                for (int m = 0; m < 8; ++m) dg[m] = fmaf(dtau, pd.dg[m], dg[m]);
+                add_corner_grads<KC>(pd, dtau, dg);
                 if (a.pose_grad) {
                   go.x = fmaf(dtau, pd.dx.x, go.x);
                   go.y = fmaf(dtau, pd.dx.y, go.y);
@@ -516,8 +618,9 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
         }
         accum_record(B, r, hit, dcol, dnrm, dg);
       }
+      }
       flush_batch(B, a, nb);
-      if (!__syncthreads_or(has)) break;
+      if (!__syncthreads_or(live())) break;
     }
     if (a.pose_grad) {
       float p12[12];
@@ -529,6 +632,24 @@ __global__ void __launch_bounds__(TPB) k_composite_bwd(CompArgs a) {
 
   count_work(a.counters, 2, n_test, n_piece);
 
+}
+
+// Backward, part 4 (tiles with actor boxes, after every part 3 block): the
+// box faces that bound segments, from the end-point derivatives gathered on
+// the segments, into the pose gradients.
+template <bool NORMALS>
+__global__ void __launch_bounds__(TPB) k_box_bwd(CompArgs a) {
+  __shared__ float red[(TPB / 64) * 12];
+  const uint32_t gt = blockIdx.x;
+  const uint32_t a_beg = a.act_beg[gt];
+  const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
+  if (n_at == 0 || !a.pose_grad) return;
+  const int tid = threadIdx.x;
+  const PixSetup P = pixel_setup(a, gt, tid);
+  const int v = P.v;
+  const float3 d = P.d;
+  const uint32_t seg0 = 3 * a_beg + n_at;
+  const int nseg = P.valid ? (int)a.pix_nseg[P.pix] : 0;
   // ---------------------------------------------------- B3: box faces
   if (a.pose_grad) {
     for (int j = 0; j < n_at; ++j) {
@@ -750,6 +871,13 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   DV_TRY(fill_f32(gg8b.as<float>(), 0.0f, 4 * nv, s));
   const size_t nslots = (size_t)3 * st->n_apairs * TPB;
   DV_TRY(alloc_n<float4>(ctx, segbw, nslots, s));
+  if (nslots > 0) {
+    hipLaunchKernelGGL(k_seg_bw_init, dim3(grid_for((int64_t)nslots, TPB)),
+                       dim3(TPB), 0, s, (int64_t)nslots, segbw.as<float4>());
+    DV_TRY_HIP(hipGetLastError());
+  }
+  DBuf tps;
+  DV_TRY(alloc_n<float2>(ctx, tps, st->max_slots * TPB, s));
   CompArgs ca;
   std::memset(&ca, 0, sizeof(ca));
   ca.views = st->views_d.as<ViewConst>();
@@ -797,17 +925,39 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   for (int i = 0; i < 3; ++i) ca.bg[i] = op.bg[i];
   ca.mask = op.out_mask;
   ca.counters = (ctx->prof_flags.load() & DV_PROFILE_COUNTERS) ? ctx->counters : nullptr;
-  // schedule the backward by the work each tile took in the forward
-  DV_TRY(alloc_n<uint32_t>(ctx, st->tile_order_bwd, nt, s));
-  DV_TRY(launch_tile_order(nt, nullptr, st->tile_work.as<uint32_t>(),
-                           st->tile_order_bwd.as<uint32_t>(), s));
-  ca.tile_order = st->tile_order_bwd.as<uint32_t>();
+  ca.item_tile = st->item_tile.as<uint32_t>();
+  ca.item_chunk = st->item_chunk.as<uint32_t>();
+  ca.tile_nck = st->tile_nck.as<uint32_t>();
+  ca.tile_pbase = st->tile_pbase.as<uint32_t>();
+  ca.plan_counts = st->plan_counts.as<uint32_t>();
+  ca.chunk_b = st->chunk_b.as<float>();
+  ca.chunk_part = st->chunk_part.as<float4>();
+  ca.chunk_tps = tps.as<float2>();
+  // the same work items as the forward, ordered by the work each took there
+  DV_TRY(alloc_n<uint32_t>(ctx, st->order_bwd, st->max_items, s));
+  DV_TRY(launch_order_by_weight(st->max_items, nullptr, st->item_work.as<uint32_t>(),
+                                st->order_bwd.as<uint32_t>(), s));
+  ca.order = st->order_bwd.as<uint32_t>();
+  ca.actor_order = st->actor_order.as<uint32_t>();
+  ca.act_tile = st->act_tile.as<uint32_t>();
   tm_clear.stop();
   StageTimer tm_comp(ctx, ST_COMPOSITE_BWD, s);
   if (nt > 0) {
-    auto kern = normals ? (op.K == 1 ? k_composite_bwd<true, 1> : k_composite_bwd<true, 0>)
-                        : (op.K == 1 ? k_composite_bwd<false, 1> : k_composite_bwd<false, 0>);
-    hipLaunchKernelGGL(kern, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
+    const bool k1 = op.K == 1;
+    auto kp = normals ? k_chunk_prep<true> : k_chunk_prep<false>;
+    hipLaunchKernelGGL(kp, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
+    auto kern = normals ? (k1 ? k_composite_bwd<true, 1> : k_composite_bwd<true, 0>)
+                        : (k1 ? k_composite_bwd<false, 1> : k_composite_bwd<false, 0>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)st->max_items), dim3(TPB), 0, s, ca);
+    if (st->n_apairs > 0) {
+      auto ka = normals ? (k1 ? k_actor_bwd<true, 1> : k_actor_bwd<true, 0>)
+                        : (k1 ? k_actor_bwd<false, 1> : k_actor_bwd<false, 0>);
+      hipLaunchKernelGGL(ka, dim3((unsigned)st->n_apairs), dim3(TPB), 0, s, ca);
+      if (ca.pose_grad) {
+        auto kb = normals ? k_box_bwd<true> : k_box_bwd<false>;
+        hipLaunchKernelGGL(kb, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
+      }
+    }
     DV_TRY_HIP(hipGetLastError());
   }
   tm_comp.stop();

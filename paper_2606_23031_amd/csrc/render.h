@@ -20,8 +20,19 @@ struct CompArgs {
   const uint32_t* tile_start;
   const uint32_t* tile_end;
   const uint32_t* tile_bgend;
-  const uint32_t* tile_order;  // launch order of the compositing blocks
-  uint32_t* tile_work;     // forward: measured work per tile
+  // work items: every tile's background list in 1 or more chunks
+  const uint32_t* order;       // launch order -> item id
+  const uint32_t* actor_order; // launch order of the actor kernels -> pair
+  const uint32_t* act_tile;    // (tile, actor) pair -> tile
+  const uint32_t* item_tile;   // item id -> tile
+  const uint32_t* item_chunk;  // item id -> chunk index in its tile
+  const uint32_t* tile_nck;    // chunks per tile
+  const uint32_t* tile_pbase;  // first chunk slot of a tile with nck > 1
+  const uint32_t* plan_counts; // [0] items, [1] chunk slots
+  float* chunk_b;          // per (chunk slot, pixel): depth boundary B_c
+  float4* chunk_part;      // per (chunk slot, pixel): 4 x float4 partials
+  float2* chunk_tps;       // backward: per (chunk slot, pixel): T_pre, S_after
+  uint32_t* item_work;     // forward: measured work per item
   const uint32_t* pair_val;
   const float4* rec_geo;   // vmin - camera (octree frame), h
   const float4* rec_g8a;   // corner densities 0..3
@@ -149,11 +160,26 @@ __device__ inline float explin_grad(float x, float c, float inv_c) {
 // the split (the tail) beside the totals, and the backward restarts P at 0
 // against the tail total there, so deep pieces see an error ~2^-24 T_REBASE
 // |L| instead.  Asset segments do the same on their own transmittance.
-// Heaviest-first launch order of the compositing blocks (render.hip):
-// weight end[t] - start[t], or end[t] alone when start is null.
-dv_status launch_tile_order(int64_t nt, const uint32_t* start,
-                            const uint32_t* end, uint32_t* order,
-                            hipStream_t s);
+// Heaviest-first launch order (render.hip) of n items of weight
+// w[i] - (w0 ? w0[i] : 0).
+dv_status launch_order_by_weight(int64_t n, const uint32_t* w0, const uint32_t* w,
+                                 uint32_t* order, hipStream_t s);
+
+// Background entries per chunk: a tile whose list is longer than 1.5
+// chunks is split into ceil(len / CHUNK) equal chunks, each composited by
+// its own block into per-pixel partial states that are merged in order.
+constexpr uint32_t CHUNK = 1024;
+__host__ __device__ inline uint32_t chunks_of(uint32_t len) {
+  return len > CHUNK + CHUNK / 2 ? (len + CHUNK - 1) / CHUNK : 1u;
+}
+// Entry range [cb, ce) of chunk c of nck over [beg, end).
+__device__ inline void chunk_range(uint32_t beg, uint32_t end, uint32_t nck,
+                                   uint32_t c, uint32_t& cb, uint32_t& ce) {
+  const uint32_t len = end - beg;
+  const uint32_t cs = (len + nck - 1) / nck;
+  cb = min(end, beg + c * cs);
+  ce = min(end, cb + cs);
+}
 
 constexpr float T_REBASE = 0.0009765625f;  // 2^-10
 
@@ -214,10 +240,13 @@ __device__ inline float3 safe_inv(float3 d) {
   return make_float3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
 }
 
-// Derivatives of the optical depth of one piece.
+// Derivatives of the optical depth of one piece.  With one sample per
+// piece (KC = 1) the corner derivatives are kept factored as coef times the
+// trilinear weights of (ux, uy, uz); add_corner_grads expands them.
 struct PieceDer {
   float dtda, dtdb;       // d tau / d(a), d(b)
-  float dg[8];            // d tau / d corner value
+  float dg[8];            // d tau / d corner value (KC != 1)
+  float coef, ux, uy, uz; // KC == 1: d tau / d g and the sample's cell coords
   float3 dx;              // sum_q d tau / d x_q
   float3 dxt;             // sum_q tau_q d tau / d x_q
 };
@@ -238,8 +267,10 @@ __device__ inline float piece_eval(float4 geo, float4 ga, float4 gb,
   const float step = (b - a) * invK;
   float sum = 0.0f, pa = 0.0f, pb = 0.0f;
   if (MODE >= 1) {
+    if (KC != 1) {
 #pragma unroll
-    for (int m = 0; m < 8; ++m) o->dg[m] = 0.0f;
+      for (int m = 0; m < 8; ++m) o->dg[m] = 0.0f;
+    }
     o->dx = make_float3(0, 0, 0);
     o->dxt = make_float3(0, 0, 0);
   }
@@ -249,10 +280,15 @@ __device__ inline float piece_eval(float4 geo, float4 ga, float4 gb,
     const float uy = clamp01(fmaf(tq, d.y, -geo.y) * inv_h);
     const float uz = clamp01(fmaf(tq, d.z, -geo.z) * inv_h);
     const float g = trilerp(ga, gb, ux, uy, uz);
-    sum += explin(g, c, inv_c);
+    // (the activation is positive, so the first sum equals the sample)
+    if (q == 0) sum = explin(g, c, inv_c);
+    else sum += explin(g, c, inv_c);
     if (MODE >= 1) {
       const float coef = step * explin_grad(g, c, inv_c);
       const float vx = 1.0f - ux, vy = 1.0f - uy, vz = 1.0f - uz;
+      if (KC == 1) {
+        o->coef = coef; o->ux = ux; o->uy = uy; o->uz = uz;
+      } else {
       o->dg[0] = fmaf(coef, vx * vy * vz, o->dg[0]);
       o->dg[1] = fmaf(coef, ux * vy * vz, o->dg[1]);
       o->dg[2] = fmaf(coef, vx * uy * vz, o->dg[2]);
@@ -261,6 +297,7 @@ __device__ inline float piece_eval(float4 geo, float4 ga, float4 gb,
       o->dg[5] = fmaf(coef, ux * vy * uz, o->dg[5]);
       o->dg[6] = fmaf(coef, vx * uy * uz, o->dg[6]);
       o->dg[7] = fmaf(coef, ux * uy * uz, o->dg[7]);
+      }
       if (MODE >= 2) {
         const float f = ((float)q + 0.5f) * invK;
         const float gx = vy * vz * (ga.y - ga.x) + uy * vz * (ga.w - ga.z) +
@@ -288,12 +325,78 @@ __device__ inline float piece_eval(float4 geo, float4 ga, float4 gb,
   return sum * step;
 }
 
+// dg[m] += dtau * d tau / d corner m.
+template <int KC>
+__device__ inline void add_corner_grads(const PieceDer& pd, float dtau,
+                                        float* dg) {
+  if (KC == 1) {
+    const float s = dtau * pd.coef;
+    const float vx = 1.0f - pd.ux, vy = 1.0f - pd.uy, vz = 1.0f - pd.uz;
+    const float s0 = s * vz, s1 = s * pd.uz;
+    const float w00 = vx * vy, w10 = pd.ux * vy, w01 = vx * pd.uy,
+                w11 = pd.ux * pd.uy;
+    dg[0] = fmaf(s0, w00, dg[0]); dg[1] = fmaf(s0, w10, dg[1]);
+    dg[2] = fmaf(s0, w01, dg[2]); dg[3] = fmaf(s0, w11, dg[3]);
+    dg[4] = fmaf(s1, w00, dg[4]); dg[5] = fmaf(s1, w10, dg[5]);
+    dg[6] = fmaf(s1, w01, dg[6]); dg[7] = fmaf(s1, w11, dg[7]);
+  } else {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) dg[m] = fmaf(dtau, pd.dg[m], dg[m]);
+  }
+}
+
 template <int KC = 0>
 __device__ inline float piece_tau(float4 geo, float4 ga, float4 gb,
                                   float inv_h, float3 d, float a, float b,
                                   int K, float invK, float c, float inv_c) {
   return piece_eval<0, KC>(geo, ga, gb, inv_h, d, a, b, K, invK, c, inv_c,
                            nullptr);
+}
+
+// Pixel of thread tid in tile gt and its unit ray direction.
+struct PixSetup {
+  int v;
+  int px, py, bx, by;
+  bool valid;
+  float3 d;
+  size_t pix;
+};
+__device__ inline PixSetup pixel_setup(const CompArgs& a, uint32_t gt, int tid) {
+  PixSetup P;
+  P.v = view_of_tile(a.views, a.n_views, gt);
+  const ViewConst& V = a.views[P.v];
+  const uint32_t lt = gt - V.tile_base;
+  P.px = (int)(lt % V.ntx) * TILE + tile_px(tid);
+  P.py = (int)(lt / V.ntx) * TILE + tile_py(tid);
+  P.bx = (int)(lt % V.ntx) * TILE + (((tid >> 6) & 1) << 3);
+  P.by = (int)(lt / V.ntx) * TILE + (((tid >> 6) >> 1) << 3);
+  P.valid = P.px < V.w && P.py < V.h;
+  const float dx = ((float)(V.x0 + P.px) + 0.5f - V.fcx) * V.inv_fx;
+  const float dy = ((float)(V.y0 + P.py) + 0.5f - V.fcy) * V.inv_fy;
+  float3 d = mat3_mul(V.Rc, make_float3(dx, dy, 1.0f));
+  const float inv = 1.0f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+  P.d = make_float3(d.x * inv, d.y * inv, d.z * inv);
+  P.pix = (size_t)gt * TPB + tid;
+  return P;
+}
+
+// Depth boundaries of a chunked tile's background walk.  Chunk c > 0
+// starts at B'_c = min over c' >= c of B_c' (B_c: entry depth of the
+// pixel's first non-empty chord in chunk c, +inf if none).  Ownership
+// segments starting before B'_c belong to earlier chunks (spliced by the
+// chunk before, at its end), the others to chunk c or later.  Chords along
+// one ray are disjoint and in depth order, so this splits the sequential
+// walk exactly.
+__device__ inline void chunk_bounds(const CompArgs& a, uint32_t gt, uint32_t nck,
+                                    uint32_t c, int tid, float& Bc, float& Bn) {
+  Bc = -F_INF;
+  Bn = F_INF;
+  if (nck <= 1) return;
+  const size_t sb = (size_t)a.tile_pbase[gt] * TPB + tid;
+  float m = F_INF;
+  for (uint32_t k = nck - 1; k > c; --k) m = fminf(m, a.chunk_b[sb + (size_t)k * TPB]);
+  Bn = m;
+  if (c > 0) Bc = fminf(m, a.chunk_b[sb + (size_t)c * TPB]);
 }
 
 // Real spherical harmonics up to degree 3 (Sec. 3.1 view-dependent
@@ -393,5 +496,8 @@ struct dv_fwd_state {
   dv::DBuf act_beg, act_oct, act_sub;
   dv::DBuf seg_se, seg_meta, seg_p0, seg_p1, seg_bw, pix_nseg;
   dv::DBuf fin0, fin1, fin2, fin3, seg_t0, seg_t1;
-  dv::DBuf tile_order, tile_work, tile_order_bwd;
+  dv::DBuf order_fwd, order_bwd, item_tile, item_chunk, item_work;
+  dv::DBuf tile_nck, tile_ibase, tile_pbase, plan_counts;
+  dv::DBuf chunk_b, chunk_part, actor_order, act_tile;
+  int64_t max_items = 0, max_slots = 0;
 };

@@ -314,13 +314,10 @@ __global__ void k_actor_ranges(int64_t n, const uint32_t* act_tile,
   sub[e] = make_uint2(a, b);
 }
 
-// Launch order of the compositing blocks: heaviest tiles first, so long
-// tiles start early and short ones fill the tail of the grid.  The weight of
-// tile t is end[t] - start[t] (list length) when start is given, else
-// end[t] (a measured work count).  Tiles are bucketed by weight on a log
+// Launch orders: heaviest work first, so long items start early and short
+// ones fill the tail of the grid.  Items are bucketed by weight on a log
 // scale with 8 steps per octave; the order inside a bucket is whatever the
-// LDS atomics give, which changes no result (tiles are independent).  One
-// block of 1024 threads.
+// LDS atomics give, which changes no result (items are independent).
 __device__ inline uint32_t weight_bucket(uint32_t w) {
   if (w == 0) return 0;
   const uint32_t lz = __builtin_clz(w);
@@ -328,17 +325,104 @@ __device__ inline uint32_t weight_bucket(uint32_t w) {
   return (31u - lz) * 8u + mant;  // 0 .. 255
 }
 
-__global__ void __launch_bounds__(1024) k_tile_order(int n, const uint32_t* start,
-                                                     const uint32_t* end,
-                                                     uint32_t* order) {
+// Exclusive prefix sum over the 1024 threads of a block (x per thread);
+// returns the thread's offset, *total receives the sum.
+__device__ inline uint32_t block_scan_1024(uint32_t x, uint32_t* wsum,
+                                           uint32_t* total) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint32_t incl = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int i = 0; i < 16; ++i) { const uint32_t t = wsum[i]; wsum[i] = acc; acc += t; }
+    wsum[16] = acc;
+  }
+  __syncthreads();
+  *total = wsum[16];
+  return wsum[w] + incl - x;
+}
+
+// One block of 1024 threads: order items 0..n-1 by weight w[i] - (w0 ?
+// w0[i] : 0), heaviest first.
+__global__ void __launch_bounds__(1024) k_order_by_weight(int64_t n, const uint32_t* w0,
+                                                          const uint32_t* w,
+                                                          uint32_t* order) {
   __shared__ uint32_t cnt[256];
   __shared__ uint32_t off[256];
   const int tid = threadIdx.x;
   if (tid < 256) cnt[tid] = 0;
   __syncthreads();
-  for (int t = tid; t < n; t += 1024) {
-    const uint32_t w = start ? end[t] - start[t] : end[t];
-    atomicAdd(&cnt[255 - weight_bucket(w)], 1u);
+  for (int64_t i = tid; i < n; i += 1024)
+    atomicAdd(&cnt[255 - weight_bucket(w[i] - (w0 ? w0[i] : 0u))], 1u);
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int b = 0; b < 256; ++b) { off[b] = acc; acc += cnt[b]; }
+  }
+  __syncthreads();
+  for (int64_t i = tid; i < n; i += 1024)
+    order[atomicAdd(&off[255 - weight_bucket(w[i] - (w0 ? w0[i] : 0u))], 1u)] = (uint32_t)i;
+}
+
+dv_status launch_order_by_weight(int64_t n, const uint32_t* w0, const uint32_t* w,
+                                 uint32_t* order, hipStream_t s) {
+  if (n <= 0) return DV_OK;
+  hipLaunchKernelGGL(k_order_by_weight, dim3(1), dim3(1024), 0, s, n, w0, w, order);
+  DV_TRY_HIP(hipGetLastError());
+  return DV_OK;
+}
+
+// Work items of the compositing kernels.  Tile t's background list
+// [start, bgend) becomes chunks_of(len) items (ids tile_ibase[t] + c);
+// tiles split into more than one chunk get consecutive chunk slots from
+// tile_pbase[t] for their partial states.  The launch order puts the
+// longest chunks first.  counts[0] = items, counts[1] = chunk slots.  One
+// block of 1024 threads, each owning a contiguous run of tiles.
+__global__ void __launch_bounds__(1024) k_plan_items(
+    int64_t n_tiles, const uint32_t* start, const uint32_t* bgend,
+    uint32_t* tile_nck, uint32_t* tile_ibase, uint32_t* tile_pbase,
+    uint32_t* item_tile, uint32_t* item_chunk, uint32_t* order,
+    uint32_t* counts) {
+  __shared__ uint32_t wsum[17];
+  __shared__ uint32_t cnt[256];
+  __shared__ uint32_t off[256];
+  const int tid = threadIdx.x;
+  const int64_t per = (n_tiles + 1023) / 1024;
+  const int64_t t0 = min(n_tiles, (int64_t)tid * per), t1 = min(n_tiles, t0 + per);
+  uint32_t ni = 0, nsl = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const uint32_t k = chunks_of(bgend[t] - start[t]);
+    ni += k;
+    if (k > 1) nsl += k;
+  }
+  if (tid < 256) cnt[tid] = 0;
+  uint32_t n_items, n_slots;
+  uint32_t ib = block_scan_1024(ni, wsum, &n_items);
+  __syncthreads();
+  uint32_t pb = block_scan_1024(nsl, wsum, &n_slots);
+  if (tid == 0) { counts[0] = n_items; counts[1] = n_slots; }
+  const uint32_t ib0 = ib;
+  for (int64_t t = t0; t < t1; ++t) {
+    const uint32_t len = bgend[t] - start[t];
+    const uint32_t k = chunks_of(len);
+    tile_nck[t] = k;
+    tile_ibase[t] = ib;
+    tile_pbase[t] = pb;
+    for (uint32_t c = 0; c < k; ++c) {
+      uint32_t cb, ce;
+      chunk_range(0, len, k, c, cb, ce);
+      item_tile[ib + c] = (uint32_t)t;
+      item_chunk[ib + c] = c;
+      atomicAdd(&cnt[255 - weight_bucket(ce - cb)], 1u);
+    }
+    ib += k;
+    if (k > 1) pb += k;
   }
   __syncthreads();
   if (tid == 0) {
@@ -346,20 +430,17 @@ __global__ void __launch_bounds__(1024) k_tile_order(int n, const uint32_t* star
     for (int b = 0; b < 256; ++b) { off[b] = acc; acc += cnt[b]; }
   }
   __syncthreads();
-  for (int t = tid; t < n; t += 1024) {
-    const uint32_t w = start ? end[t] - start[t] : end[t];
-    order[atomicAdd(&off[255 - weight_bucket(w)], 1u)] = (uint32_t)t;
+  ib = ib0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const uint32_t len = bgend[t] - start[t];
+    const uint32_t k = chunks_of(len);
+    for (uint32_t c = 0; c < k; ++c) {
+      uint32_t cb, ce;
+      chunk_range(0, len, k, c, cb, ce);
+      order[atomicAdd(&off[255 - weight_bucket(ce - cb)], 1u)] = ib + c;
+    }
+    ib += k;
   }
-}
-
-dv_status launch_tile_order(int64_t nt, const uint32_t* start,
-                            const uint32_t* end, uint32_t* order,
-                            hipStream_t s) {
-  if (nt <= 0) return DV_OK;
-  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, (int)nt, start,
-                     end, order);
-  DV_TRY_HIP(hipGetLastError());
-  return DV_OK;
 }
 
 // ------------------------------------------------------------------ composite
@@ -470,48 +551,68 @@ __device__ inline int next_seg_of(const CompArgs& a, uint32_t seg0, int nseg,
   return nseg;
 }
 
-// Forward compositing, one 256-thread block per 16x16 tile (each wave an
-// 8x8 quadrant).  Sums are kept twice: over all pieces, and over the tail
-// (pieces entered with T < T_REBASE), which the backward needs for its
-// suffixes.  KC = 1 fixes one sample per piece at compile time.
-template <bool NORMALS, int KC>
-__global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
-  __shared__ Batch B;
-  __shared__ uint32_t blk_work;
-  const uint32_t gt = a.tile_order[blockIdx.x];
-  const int tid = threadIdx.x;
-  const int v = view_of_tile(a.views, a.n_views, gt);
-  const ViewConst& V = a.views[v];
-  const uint32_t lt = gt - V.tile_base;
-  const int px = (int)(lt % V.ntx) * TILE + tile_px(tid);
-  const int py = (int)(lt / V.ntx) * TILE + tile_py(tid);
-  const int bx = (int)(lt % V.ntx) * TILE + (((tid >> 6) & 1) << 3);
-  const int by = (int)(lt / V.ntx) * TILE + (((tid >> 6) >> 1) << 3);
-  const bool valid = px < V.w && py < V.h;
-  float3 d;
-  {
-    const float dx = ((float)(V.x0 + px) + 0.5f - V.fcx) * V.inv_fx;
-    const float dy = ((float)(V.y0 + py) + 0.5f - V.fcy) * V.inv_fy;
-    d = mat3_mul(V.Rc, make_float3(dx, dy, 1.0f));
-    const float inv = 1.0f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
-    d = make_float3(d.x * inv, d.y * inv, d.z * inv);
+// Final composite with the background colour (Eq. 2) into the outputs.
+__device__ inline void write_outputs(const CompArgs& a, const ViewConst& V, int v,
+                                     int px, int py, float3 C3, float D,
+                                     float3 N3, float T) {
+  const dv_outputs& O = a.outs[v];
+  const size_t hw = (size_t)V.w * V.h, o = (size_t)py * V.w + px;
+  if ((a.mask & DV_OUT_RGB) && O.rgb) {
+    O.rgb[o] = fmaf(T, a.bg[0], C3.x);
+    O.rgb[hw + o] = fmaf(T, a.bg[1], C3.y);
+    O.rgb[2 * hw + o] = fmaf(T, a.bg[2], C3.z);
   }
-  const int K = a.K;
-  const float invK = 1.0f / (float)K;
-  const size_t pix = (size_t)gt * TPB + tid;
-  uint32_t n_test = 0, n_piece = 0;
+  if ((a.mask & DV_OUT_DEPTH) && O.depth) O.depth[o] = D;
+  if ((a.mask & DV_OUT_NORMAL) && O.normal) {
+    O.normal[o] = N3.x;
+    O.normal[hw + o] = N3.y;
+    O.normal[2 * hw + o] = N3.z;
+  }
+  if ((a.mask & DV_OUT_T) && O.T) O.T[o] = T;
+}
 
-  // ---------------------------------------------------- actor segments
+__global__ void k_sub_len(int64_t n, const uint2* sub, uint32_t* len) {
+  const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (e < n) len[e] = sub[e].y - sub[e].x;
+}
+
+// Forward, part 1a (tiles with actor boxes): per pixel, the ownership
+// segments of the actor boxes its ray meets.
+__global__ void __launch_bounds__(TPB) k_build_segments(CompArgs a) {
+  const uint32_t gt = blockIdx.x;
   const uint32_t a_beg = a.act_beg[gt];
   const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
-  const uint32_t sbase = 3 * a_beg;
-  const uint32_t seg0 = sbase + n_at;
+  if (n_at == 0) return;
+  const int tid = threadIdx.x;
+  const PixSetup P = pixel_setup(a, gt, tid);
   int nseg = 0;
-  if (n_at > 0 && valid) nseg = build_segments(a, sbase, n_at, a_beg, v, d, tid);
-  if (n_at > 0) a.pix_nseg[pix] = (uint32_t)nseg;
+  if (P.valid) nseg = build_segments(a, 3 * a_beg, n_at, a_beg, P.v, P.d, tid);
+  a.pix_nseg[P.pix] = (uint32_t)nseg;
+}
 
-  // ---------------------------------------------------- phase 1: actors
-  for (int j = 0; j < n_at; ++j) {
+// Forward, part 1b: one block per (tile, actor) pair: every segment of that
+// actor on the tile's rays composited into a partial state (C, D, N, T)
+// with its tail sums.  Actors are independent here, so the pairs of a tile
+// run as separate blocks.
+template <bool NORMALS, int KC>
+__global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
+  __shared__ Batch B;
+  const uint32_t e = a.actor_order[blockIdx.x];
+  const uint32_t gt = a.act_tile[e];
+  const uint32_t a_beg = a.act_beg[gt];
+  const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
+  const int jsel = (int)(e - a_beg);
+  const int tid = threadIdx.x;
+  const PixSetup P = pixel_setup(a, gt, tid);
+  const int v = P.v, bx = P.bx, by = P.by;
+  const float3 d = P.d;
+  const int K = a.K;
+  const float invK = 1.0f / (float)K;
+  uint32_t n_test = 0, n_piece = 0;
+  const uint32_t seg0 = 3 * a_beg + n_at;
+  const int nseg = P.valid ? (int)a.pix_nseg[P.pix] : 0;
+
+  for (int j = jsel; j == jsel; ++j) {
     int q = next_seg_of(a, seg0, nseg, 0, j, tid);
     bool has = q < nseg;
     if (!__syncthreads_or(has)) continue;
@@ -535,13 +636,25 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
       const float2 se = a.seg_se[seg_index(seg0 + q, tid)];
       qs = se.x; qe = se.y;
     }
+    // last segment of actor j on this ray: once it is done (T below the
+    // stop threshold) the lane has nothing left in this list
+    int qlast = -1;
+    for (int i = nseg - 1; i >= 0 && qlast < 0; --i)
+      if ((int)(a.seg_meta[seg_index(seg0 + i, tid)] & 0xFF) == j) qlast = i;
+    auto live = [&]() { return has && !(qdone && q == qlast); };
     const uint2 sub = a.act_sub[a_beg + j];
     for (uint32_t base = sub.x; base < sub.y; base += TPB) {
       const uint32_t nb = min((uint32_t)TPB, sub.y - base);
       load_batch(B, a, base, nb);
       __syncthreads();
-      for (uint32_t r = 0; r < nb && has; ++r) {
-        if (!rect_hits_block(B.rect[r], bx, by)) continue;
+      uint64_t wm[4];
+      wave_entry_masks(B.rect, nb, bx, by, wm);
+      for (int c = 0; c < 4; ++c) {
+      uint64_t m = wm[c];
+      while (m != 0 && __ballot(live()) != 0) {
+        const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
+        if (!live()) continue;
         const float4 geo = B.geo[r];
         float t0, t1;
         slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
@@ -590,12 +703,86 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
           break;
         }
       }
-      if (!__syncthreads_or(has)) break;
+      }
+      if (!__syncthreads_or(live())) break;
     }
     if (has) store_q(q);
   }
 
-  // ---------------------------------------------------- phase 2: background
+  count_work(a.counters, 0, n_test, n_piece);
+}
+
+// Forward, part 2 (chunked tiles, chunks c > 0): B_c of every pixel, the
+// entry depth of its first non-empty chord among the chunk's entries.
+__global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a) {
+  __shared__ Batch B;
+  if (blockIdx.x >= a.plan_counts[0]) return;
+  const uint32_t k = a.order[blockIdx.x];
+  const uint32_t gt = a.item_tile[k], c = a.item_chunk[k];
+  const uint32_t nck = a.tile_nck[gt];
+  if (nck <= 1 || c == 0) return;
+  const int tid = threadIdx.x;
+  const PixSetup P = pixel_setup(a, gt, tid);
+  const float3 inv = safe_inv(P.d);
+  uint32_t cb, ce;
+  chunk_range(a.tile_start[gt], a.tile_bgend[gt], nck, c, cb, ce);
+  float Bc = F_INF;
+  bool found = !P.valid;
+  for (uint32_t base = cb; base < ce; base += TPB) {
+    const uint32_t nb = min((uint32_t)TPB, ce - base);
+    load_batch(B, a, base, nb);
+    __syncthreads();
+    uint64_t wm[4];
+    wave_entry_masks(B.rect, nb, P.bx, P.by, wm);
+    for (int q = 0; q < 4; ++q) {
+      uint64_t m = wm[q];
+      while (m != 0 && __ballot(!found) != 0) {
+        const uint32_t r = (uint32_t)q * 64 + (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
+        if (found) continue;
+        const float4 geo = B.geo[r];
+        float t0, t1;
+        slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+        t0 = fmaxf(t0, a.tau_near);
+        if (t1 > t0) { Bc = t0; found = true; }
+      }
+    }
+    if (__syncthreads_and(found)) break;
+  }
+  a.chunk_b[((size_t)a.tile_pbase[gt] + c) * TPB + tid] = Bc;
+}
+
+// Forward, part 3: the background walk of one work item (a tile, or one
+// chunk of a long tile), one 256-thread block per item (each wave an 8x8
+// quadrant), asset segments spliced in as the walk reaches them.  Sums are
+// kept twice: over all pieces, and over the tail (pieces entered with
+// T < T_REBASE), which the backward needs for its suffixes.  A tile of one
+// chunk writes the outputs; a chunk writes its partial state (T starts at
+// 1 in every chunk, and so does the stop test) for k_chunk_merge.
+// KC = 1 fixes one sample per piece at compile time.
+template <bool NORMALS, int KC>
+__global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs a) {
+  __shared__ Batch B;
+  __shared__ uint32_t blk_work;
+  if (blockIdx.x >= a.plan_counts[0]) return;
+  const uint32_t item = a.order[blockIdx.x];
+  const uint32_t gt = a.item_tile[item], chunk = a.item_chunk[item];
+  const uint32_t nck = a.tile_nck[gt];
+  const int tid = threadIdx.x;
+  const PixSetup P = pixel_setup(a, gt, tid);
+  const int v = P.v, px = P.px, py = P.py, bx = P.bx, by = P.by;
+  const bool valid = P.valid;
+  const float3 d = P.d;
+  const size_t pix = P.pix;
+  const ViewConst& V = a.views[v];
+  const int K = a.K;
+  const float invK = 1.0f / (float)K;
+  uint32_t n_test = 0, n_piece = 0;
+  const uint32_t a_beg = a.act_beg[gt];
+  const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
+  const uint32_t seg0 = 3 * a_beg + n_at;
+  const int nseg = (n_at > 0 && valid) ? (int)a.pix_nseg[pix] : 0;
+
   // totals C3/D/N3 and tail sums CT/DT/NT
   float3 C3 = make_float3(0, 0, 0), N3 = make_float3(0, 0, 0);
   float3 CT = make_float3(0, 0, 0), NT = make_float3(0, 0, 0);
@@ -624,13 +811,17 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
     T *= e;
     if (T < a.eps) done = true;
   };
-  const uint32_t beg = a.tile_start[gt], bgend = a.tile_bgend[gt];
+  uint32_t beg, bgend;
+  chunk_range(a.tile_start[gt], a.tile_bgend[gt], nck, chunk, beg, bgend);
+  float Bc, Bn;
+  chunk_bounds(a, gt, nck, chunk, tid, Bc, Bn);
   // Waves none of whose pixels has an ownership segment take the plain walk
   // (a wave-uniform choice); the others splice segments as they come.
   const bool wseg = __ballot(nseg > 0) != 0;
   int qn = 0;
-  float ns = nseg > 0 ? a.seg_se[seg_index(seg0, tid)].x : F_INF;
-  float excl = -F_INF;
+  while (qn < nseg && a.seg_se[seg_index(seg0 + qn, tid)].x < Bc) ++qn;
+  float excl = qn > 0 ? a.seg_se[seg_index(seg0 + qn - 1, tid)].y : -F_INF;
+  float ns = qn < nseg ? a.seg_se[seg_index(seg0 + qn, tid)].x : F_INF;
   auto splice = [&](int qq) {
     const size_t qi = seg_index(seg0 + qq, tid);
     const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
@@ -687,41 +878,66 @@ __global__ void __launch_bounds__(TPB) k_composite_fwd(CompArgs a) {
     }
     if (__syncthreads_and(done)) break;
   }
-  while (!done && qn < nseg) {
+  // segments before the next chunk's boundary (all, in the last chunk)
+  while (!done && qn < nseg && a.seg_se[seg_index(seg0 + qn, tid)].x < Bn) {
     splice(qn);
     ++qn;
   }
   count_work(a.counters, 0, n_test, n_piece);
-  // per-tile work (slab tests + 4 per piece), the backward's schedule key
+  // measured work (slab tests + 4 per piece, at least 1), the backward's
+  // schedule key
   {
-    uint32_t w = n_test + 4u * n_piece;
+    uint32_t w = n_test + 4u * n_piece + (tid == 0 ? 1u : 0u);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
     if (tid == 0) blk_work = 0;
     __syncthreads();
     if ((tid & 63) == 0) atomicAdd(&blk_work, w);
     __syncthreads();
-    if (tid == 0) a.tile_work[gt] = blk_work;
+    if (tid == 0) a.item_work[item] = blk_work;
   }
   if (!valid) return;
+  if (nck > 1) {
+    float4* part = a.chunk_part + (((size_t)a.tile_pbase[gt] + chunk) * TPB + tid) * 4;
+    part[0] = make_float4(C3.x, C3.y, C3.z, D);
+    part[1] = make_float4(N3.x, N3.y, N3.z, T);
+    part[2] = make_float4(CT.x, CT.y, CT.z, DT);
+    part[3] = make_float4(NT.x, NT.y, NT.z, 0.0f);
+    return;
+  }
   a.fin0[pix] = make_float4(C3.x, C3.y, C3.z, D);
   a.fin1[pix] = make_float4(N3.x, N3.y, N3.z, T);
   a.fin2[pix] = make_float4(CT.x, CT.y, CT.z, DT);
   a.fin3[pix] = make_float4(NT.x, NT.y, NT.z, 0.0f);
-  const dv_outputs& O = a.outs[v];
-  const size_t hw = (size_t)V.w * V.h, o = (size_t)py * V.w + px;
-  if ((a.mask & DV_OUT_RGB) && O.rgb) {
-    O.rgb[o] = fmaf(T, a.bg[0], C3.x);
-    O.rgb[hw + o] = fmaf(T, a.bg[1], C3.y);
-    O.rgb[2 * hw + o] = fmaf(T, a.bg[2], C3.z);
+  write_outputs(a, V, v, px, py, C3, D, N3, T);
+}
+
+// Forward, part 4 (tiles of several chunks): merge the chunk partials in
+// order, C = sum_c T_<c C_c, T = prod_c T_c, and write the outputs.
+__global__ void __launch_bounds__(TPB) k_chunk_merge(CompArgs a) {
+  const uint32_t gt = blockIdx.x;
+  const uint32_t nck = a.tile_nck[gt];
+  if (nck <= 1) return;
+  const int tid = threadIdx.x;
+  const PixSetup P = pixel_setup(a, gt, tid);
+  if (!P.valid) return;
+  const ViewConst& V = a.views[P.v];
+  float3 C3 = make_float3(0, 0, 0), N3 = make_float3(0, 0, 0);
+  float D = 0.0f, T = 1.0f;
+  const float4* part = a.chunk_part + ((size_t)a.tile_pbase[gt] * TPB + tid) * 4;
+  for (uint32_t c = 0; c < nck; ++c) {
+    const float4 p0 = part[(size_t)c * TPB * 4], p1 = part[(size_t)c * TPB * 4 + 1];
+    C3.x = fmaf(T, p0.x, C3.x); C3.y = fmaf(T, p0.y, C3.y);
+    C3.z = fmaf(T, p0.z, C3.z); D = fmaf(T, p0.w, D);
+    N3.x = fmaf(T, p1.x, N3.x); N3.y = fmaf(T, p1.y, N3.y);
+    N3.z = fmaf(T, p1.z, N3.z);
+    T *= p1.w;
   }
-  if ((a.mask & DV_OUT_DEPTH) && O.depth) O.depth[o] = D;
-  if ((a.mask & DV_OUT_NORMAL) && O.normal) {
-    O.normal[o] = N3.x;
-    O.normal[hw + o] = N3.y;
-    O.normal[2 * hw + o] = N3.z;
-  }
-  if ((a.mask & DV_OUT_T) && O.T) O.T[o] = T;
+  a.fin0[P.pix] = make_float4(C3.x, C3.y, C3.z, D);
+  a.fin1[P.pix] = make_float4(N3.x, N3.y, N3.z, T);
+  a.fin2[P.pix] = make_float4(0, 0, 0, 0);
+  a.fin3[P.pix] = make_float4(0, 0, 0, 0);
+  write_outputs(a, V, P.v, P.px, P.py, C3, D, N3, T);
 }
 
 // ------------------------------------------------------------------ host
@@ -1130,7 +1346,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   DV_TRY_HIP(hipGetLastError());
   // actor lists
   const int64_t na = st->n_apairs;
-  DBuf atile;
+  DBuf& atile = st->act_tile;
   DV_TRY(alloc_n<uint32_t>(ctx, st->act_beg, nt + 1, s));
   DV_TRY(alloc_n<uint32_t>(ctx, st->act_oct, na, s));
   DV_TRY(alloc_n<uint2>(ctx, st->act_sub, na, s));
@@ -1149,11 +1365,40 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
                        n_oct, st->act_sub.as<uint2>());
     DV_TRY_HIP(hipGetLastError());
   }
-  DV_TRY(alloc_n<uint32_t>(ctx, st->tile_order, nt, s));
-  DV_TRY(alloc_n<uint32_t>(ctx, st->tile_work, nt, s));
-  DV_TRY(launch_tile_order(nt, st->tile_start.as<uint32_t>(),
-                            st->tile_end.as<uint32_t>(),
-                            st->tile_order.as<uint32_t>(), s));
+  // work items: tiles, long background lists split into chunks
+  st->max_items = nt + st->n_pairs / CHUNK + 1;
+  st->max_slots = 2 * (st->n_pairs / CHUNK) + 1;
+  DV_TRY(alloc_n<uint32_t>(ctx, st->order_fwd, st->max_items, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->item_tile, st->max_items, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->item_chunk, st->max_items, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->item_work, st->max_items, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->tile_nck, nt, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->tile_ibase, nt, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->tile_pbase, nt, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->plan_counts, 2, s));
+  DV_TRY(alloc_n<float>(ctx, st->chunk_b, st->max_slots * TPB, s));
+  DV_TRY(alloc_n<float4>(ctx, st->chunk_part, st->max_slots * TPB * 4, s));
+  DV_TRY(fill_u32(st->item_work.as<uint32_t>(), 0u, st->max_items, s));
+  // (tile, actor) pairs by the length of their lists, heaviest first
+  if (na > 0) {
+    DBuf sublen;
+    DV_TRY(alloc_n<uint32_t>(ctx, sublen, na, s));
+    DV_TRY(alloc_n<uint32_t>(ctx, st->actor_order, na, s));
+    hipLaunchKernelGGL(k_sub_len, dim3(grid_for(na, TPB)), dim3(TPB), 0, s, na,
+                       st->act_sub.as<uint2>(), sublen.as<uint32_t>());
+    DV_TRY_HIP(hipGetLastError());
+    DV_TRY(launch_order_by_weight(na, nullptr, sublen.as<uint32_t>(),
+                                  st->actor_order.as<uint32_t>(), s));
+  }
+  if (nt > 0) {
+    hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(1024), 0, s, nt,
+                       st->tile_start.as<uint32_t>(), st->tile_bgend.as<uint32_t>(),
+                       st->tile_nck.as<uint32_t>(), st->tile_ibase.as<uint32_t>(),
+                       st->tile_pbase.as<uint32_t>(), st->item_tile.as<uint32_t>(),
+                       st->item_chunk.as<uint32_t>(), st->order_fwd.as<uint32_t>(),
+                       st->plan_counts.as<uint32_t>());
+    DV_TRY_HIP(hipGetLastError());
+  }
   tm_dir.stop();
   // per-pixel scratch
   const size_t nslots = (size_t)3 * na * TPB;
@@ -1177,8 +1422,17 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   ca.tile_start = st->tile_start.as<uint32_t>();
   ca.tile_end = st->tile_end.as<uint32_t>();
   ca.tile_bgend = st->tile_bgend.as<uint32_t>();
-  ca.tile_order = st->tile_order.as<uint32_t>();
-  ca.tile_work = st->tile_work.as<uint32_t>();
+  ca.order = st->order_fwd.as<uint32_t>();
+  ca.actor_order = st->actor_order.as<uint32_t>();
+  ca.act_tile = st->act_tile.as<uint32_t>();
+  ca.item_tile = st->item_tile.as<uint32_t>();
+  ca.item_chunk = st->item_chunk.as<uint32_t>();
+  ca.tile_nck = st->tile_nck.as<uint32_t>();
+  ca.tile_pbase = st->tile_pbase.as<uint32_t>();
+  ca.plan_counts = st->plan_counts.as<uint32_t>();
+  ca.chunk_b = st->chunk_b.as<float>();
+  ca.chunk_part = st->chunk_part.as<float4>();
+  ca.item_work = st->item_work.as<uint32_t>();
   ca.pair_val = st->pair_val.as<uint32_t>();
   ca.rec_geo = st->rec_geo.as<float4>();
   ca.rec_g8a = st->rec_g8a.as<float4>();
@@ -1213,9 +1467,19 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   StageTimer tm_comp(ctx, ST_COMPOSITE_FWD, s);
   if (nt > 0) {
     const bool nrm = (op.out_mask & DV_OUT_NORMAL) != 0;
-    auto kern = nrm ? (op.K == 1 ? k_composite_fwd<true, 1> : k_composite_fwd<true, 0>)
-                    : (op.K == 1 ? k_composite_fwd<false, 1> : k_composite_fwd<false, 0>);
-    hipLaunchKernelGGL(kern, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
+    const bool k1 = op.K == 1;
+    if (st->n_apairs > 0) {
+      hipLaunchKernelGGL(k_build_segments, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
+      auto ka = nrm ? (k1 ? k_actor_fwd<true, 1> : k_actor_fwd<true, 0>)
+                    : (k1 ? k_actor_fwd<false, 1> : k_actor_fwd<false, 0>);
+      hipLaunchKernelGGL(ka, dim3((unsigned)st->n_apairs), dim3(TPB), 0, s, ca);
+    }
+    const unsigned ni = (unsigned)st->max_items;
+    hipLaunchKernelGGL(k_chunk_bounds, dim3(ni), dim3(TPB), 0, s, ca);
+    auto kern = nrm ? (k1 ? k_composite_fwd<true, 1> : k_composite_fwd<true, 0>)
+                    : (k1 ? k_composite_fwd<false, 1> : k_composite_fwd<false, 0>);
+    hipLaunchKernelGGL(kern, dim3(ni), dim3(TPB), 0, s, ca);
+    hipLaunchKernelGGL(k_chunk_merge, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
   }
   DV_TRY_HIP(hipGetLastError());
   return DV_OK;
@@ -1320,6 +1584,16 @@ dv_status dv_fwd_state_info(const dv_fwd_state* st, dv_state_info* info) {
   info->n_tiles = st->n_tiles;
   info->key_bits = st->key_bits;
   info->tile_bits = st->tile_bits;
+  info->n_items = 0;
+  info->n_chunk_slots = 0;
+  if (st->n_tiles > 0) {
+    uint32_t c[2] = {0, 0};
+    DV_TRY_HIP(hipSetDevice(st->ctx->device));
+    DV_TRY_HIP(hipStreamSynchronize(st->stream));
+    DV_TRY_HIP(hipMemcpy(c, st->plan_counts.p, sizeof(c), hipMemcpyDeviceToHost));
+    info->n_items = c[0];
+    info->n_chunk_slots = c[1];
+  }
   return DV_OK;
 }
 

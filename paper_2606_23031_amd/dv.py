@@ -94,7 +94,8 @@ class dv_state_info(C.Structure):
     _fields_ = [("n_views", C.c_int32), ("n_visible", C.c_int64),
                 ("n_pairs", C.c_int64), ("n_actor_pairs", C.c_int64),
                 ("n_tiles", C.c_int64), ("key_bits", C.c_int32),
-                ("tile_bits", C.c_int32)]
+                ("tile_bits", C.c_int32), ("n_items", C.c_int64),
+                ("n_chunk_slots", C.c_int64)]
 
 
 NUM_STAGES = 12

@@ -92,3 +92,29 @@ def actor_scene(seed=0, n_actors=2, deg=1, overlap=False, K=1, bg_levels=(2, 24,
                 explin_c=1.1)
     return dict(scene=dict(octrees=octs, tracks=tracks), views=[view],
                 opts=opts)
+
+
+def dense_scene(seed=0, n_actors=2, level=5, deg=1):
+    """Background cube [-2,2]^3 fully tiled by (2^level)^3 leaves of low
+    density (rays cross all of them), with actor cubes inside: a small view
+    whose tile lists exceed the compositing chunk length, so long lists are
+    split into chunks that are merged back."""
+    rng = np.random.default_rng(seed)
+    bg = random_octree(rng, (-2.0, -2.0, -2.0), 4.0, level, 0, level, deg,
+                       g_mean=-2.5, g_std=0.7)
+    octs = [bg]
+    tracks = [None]
+    centres = [(-0.6, 0.3, 0.113), (0.7, -0.4, -0.187), (0.1, 0.2, 0.521)]
+    for i in range(n_actors):
+        a = random_octree(rng, (-0.5, -0.5, -0.5), 1.0, 2, 10, 4, deg,
+                          g_mean=0.5, g_std=1.5,
+                          box=((-0.45, -0.4, -0.35), (0.45, 0.4, 0.35)))
+        octs.append(a)
+        c = np.array(centres[i])
+        tracks.append(moving_track(0.2 + 0.3 * i, 0.5 + 0.3 * i, c, c + (0.3, 0.1, 0.0)))
+    eye = np.array([4.2, 2.1, 1.7])
+    view = make_view(64, 48, 50.0, look_at_c2w(eye, (0.0, 0.0, 0.0)), t=2.5)
+    opts = dict(K=1, eps_stop=0.0, tau_near=0.0, bg=(0.1, 0.2, 0.3),
+                explin_c=1.1)
+    return dict(scene=dict(octrees=octs, tracks=tracks), views=[view],
+                opts=opts)

@@ -10,7 +10,7 @@ import pytest
 
 from oracle import adjoint as AD
 from oracle import render as RD
-from scenes import actor_scene
+from scenes import actor_scene, dense_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -97,3 +97,18 @@ def test_backward_without_pose_buffer(ctx):
     acc, _, ref, _ = _run(ctx, cfg, seed=4, pose=False)
     for k in range(len(acc)):
         _close(f"corner[{k}]", acc[k]["corner"].cpu().numpy(), ref["corner"][k])
+
+
+def test_backward_chunked_tiles(ctx):
+    # tile lists split into chunks: chunk-local walks with T_pre / S_after
+    # from the merged partials, segments spliced by the chunk that holds
+    # them, the pieces around a segment possibly in different chunks
+    cfg = dense_scene(seed=1, deg=1)
+    acc, pg, ref, _ = _run(ctx, cfg, mask_normals=True, seed=1)
+    for k in range(len(acc)):
+        _close(f"corner[{k}]", acc[k]["corner"].cpu().numpy(), ref["corner"][k])
+        _close(f"sh[{k}]", acc[k]["sh"].cpu().numpy(), ref["sh"][k])
+    p = pg.cpu().numpy()[0]
+    for i in range(len(acc) - 1):
+        _close(f"dR[{i}]", p[i, :9].reshape(3, 3), ref["dR"][i + 1])
+        _close(f"dp[{i}]", p[i, 9:], ref["dp"][i + 1])

@@ -12,7 +12,7 @@ from oracle import render as RD
 from oracle import binning as B
 from oracle import geometry as G
 from synth import make_config, make_view, look_at_c2w
-from scenes import actor_scene, empty_octree, random_octree
+from scenes import actor_scene, dense_scene, empty_octree, random_octree
 
 pytestmark = pytest.mark.gpu
 
@@ -90,6 +90,29 @@ def test_actor_scene_parity(ctx, seed, overlap, K):
     ref = _oracle(cfg["scene"], v, cfg["opts"])
     _compare(res[0], ref)
     _lists_equal(ctx, st, cfg["scene"], v)
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-4])
+def test_chunked_tiles_parity(ctx, eps):
+    # every tile's list (2.7k-4.2k entries) is split into chunks whose
+    # partial states are merged; asset segments fall inside chunks and on
+    # chunk boundaries.  With eps > 0 a chunk tests the stop on its own T,
+    # which moves a colour by at most eps.
+    from gpu_helpers import render_gpu
+    from paper_2606_23031_amd import dv
+    cfg = dense_scene(seed=0)
+    v = cfg["views"][0]
+    opts = dict(cfg["opts"], eps_stop=eps)
+    res, st, _ = render_gpu(ctx, cfg["scene"], [v], opts, keep=True)
+    info = dv.dv_fwd_state_info(st)
+    assert info["n_items"] > info["n_tiles"] and info["n_chunk_slots"] > 0
+    ref = _oracle(cfg["scene"], v, dict(opts, eps_stop=0.0))
+    if eps == 0.0:
+        _compare(res[0], ref)
+        _lists_equal(ctx, st, cfg["scene"], v)
+    else:
+        assert np.abs(res[0]["rgb"] - ref["rgb"]).max() <= eps + TOL
+    dv.dv_fwd_state_release(st)
 
 
 def test_empty_scene_returns_background(ctx):
