@@ -241,6 +241,7 @@ def serve_run(dv, ctx, sc, opts, views, rate, batched, seed):
 
 
 KERNEL_OF_STAGE = {"composite_fwd": "dv::k_composite_fwd", "composite_bwd": "dv::k_composite_bwd",
+                   "actor_fwd": "dv::k_actor_fwd", "actor_bwd": "dv::k_actor_bwd",
                    "record_bwd": "dv::k_record_bwd", "preprocess": "dv::k_preprocess<1>",
                    "emit_pairs": "dv::k_emit", "gather_scan": "dv::k_gather"}
 
@@ -266,11 +267,11 @@ def stored_traffic(stage, workload):
 def roofline(stage, ms, calls, info, counters, scene_stats):
     """Roofline entry for the dominant stage (per launch)."""
     per = ms / max(calls, 1) / 1e3   # seconds per launch
-    if stage in ("composite_fwd", "composite_bwd"):
-        if stage == "composite_fwd":
-            flops = FLOP_TEST * counters["entries_fwd"] + FLOP_PIECE_FWD * counters["pieces_fwd"]
-        else:
-            flops = FLOP_TEST * counters["entries_bwd"] + FLOP_PIECE_BWD * counters["pieces_bwd"]
+    if stage in ("composite_fwd", "composite_bwd", "actor_fwd", "actor_bwd"):
+        suf = {"composite_fwd": "fwd", "composite_bwd": "bwd",
+               "actor_fwd": "actor_fwd", "actor_bwd": "actor_bwd"}[stage]
+        per_piece = FLOP_PIECE_FWD if suf.endswith("fwd") else FLOP_PIECE_BWD
+        flops = FLOP_TEST * counters["entries_" + suf] + per_piece * counters["pieces_" + suf]
         ach = flops / per / 1e12
         return dict(bound="alu", achieved=ach, peak=PEAK_FP32_TFLOPS,
                     unit="TFLOP/s", frac=ach / PEAK_FP32_TFLOPS, traffic=None,

@@ -182,14 +182,19 @@ const char* dv_version(void);
  * adds their durations and optionally resets. */
 #define DV_PROFILE_EVENTS 1
 #define DV_PROFILE_COUNTERS 2
-#define DV_NUM_STAGES 12
+#define DV_NUM_STAGES 14
 typedef struct {
   double ms[DV_NUM_STAGES];     /* summed device time per stage            */
   int64_t calls[DV_NUM_STAGES]; /* number of timed intervals               */
-  int64_t entries_fwd;          /* (pixel, entry) slab tests, forward      */
-  int64_t pieces_fwd;           /* pieces composited, forward              */
+  int64_t entries_fwd;          /* (pixel, entry) slab tests, background
+                                   walk, forward                           */
+  int64_t pieces_fwd;           /* pieces composited, same                 */
   int64_t entries_bwd;          /* same, backward re-walk                  */
   int64_t pieces_bwd;
+  int64_t entries_actor_fwd;    /* slab tests of asset-segment walks       */
+  int64_t pieces_actor_fwd;
+  int64_t entries_actor_bwd;
+  int64_t pieces_actor_bwd;
 } dv_stage_times;
 dv_status dv_ctx_set_profiling(dv_ctx* ctx, int32_t flags);
 dv_status dv_ctx_stage_times(dv_ctx* ctx, dv_stage_times* out, int32_t reset);

@@ -630,7 +630,7 @@ __global__ void __launch_bounds__(TPB) k_actor_bwd(CompArgs a) {
     }
   }
 
-  count_work(a.counters, 2, n_test, n_piece);
+  count_work(a.counters, 6, n_test, n_piece);
 
 }
 
@@ -940,16 +940,19 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   ca.order = st->order_bwd.as<uint32_t>();
   ca.actor_order = st->actor_order.as<uint32_t>();
   ca.act_tile = st->act_tile.as<uint32_t>();
-  tm_clear.stop();
-  StageTimer tm_comp(ctx, ST_COMPOSITE_BWD, s);
   if (nt > 0) {
     const bool k1 = op.K == 1;
     auto kp = normals ? k_chunk_prep<true> : k_chunk_prep<false>;
     hipLaunchKernelGGL(kp, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
-    auto kern = normals ? (k1 ? k_composite_bwd<true, 1> : k_composite_bwd<true, 0>)
-                        : (k1 ? k_composite_bwd<false, 1> : k_composite_bwd<false, 0>);
-    hipLaunchKernelGGL(kern, dim3((unsigned)st->max_items), dim3(TPB), 0, s, ca);
+    tm_clear.stop();
+    {
+      StageTimer tm_comp(ctx, ST_COMPOSITE_BWD, s);
+      auto kern = normals ? (k1 ? k_composite_bwd<true, 1> : k_composite_bwd<true, 0>)
+                          : (k1 ? k_composite_bwd<false, 1> : k_composite_bwd<false, 0>);
+      hipLaunchKernelGGL(kern, dim3((unsigned)st->max_items), dim3(TPB), 0, s, ca);
+    }
     if (st->n_apairs > 0) {
+      StageTimer tm_act(ctx, ST_ACTOR_BWD, s);
       auto ka = normals ? (k1 ? k_actor_bwd<true, 1> : k_actor_bwd<true, 0>)
                         : (k1 ? k_actor_bwd<false, 1> : k_actor_bwd<false, 0>);
       hipLaunchKernelGGL(ka, dim3((unsigned)st->n_apairs), dim3(TPB), 0, s, ca);
@@ -960,7 +963,7 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
     }
     DV_TRY_HIP(hipGetLastError());
   }
-  tm_comp.stop();
+  tm_clear.stop();
   StageTimer tm_rec(ctx, ST_RECORD_BWD, s);
   if (nv > 0) {
     if (ca.pose_grad)

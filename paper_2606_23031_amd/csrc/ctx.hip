@@ -165,7 +165,7 @@ void StageTimer::stop() {
 static const char* kStageNames[DV_NUM_STAGES] = {
     "preprocess", "sort_records", "gather_scan", "emit_pairs", "sort_pairs",
     "tile_directory", "composite_fwd", "bwd_clear", "composite_bwd",
-    "record_bwd", "host_sync", "other"};
+    "record_bwd", "host_sync", "other", "actor_fwd", "actor_bwd"};
 
 }  // namespace dv
 
@@ -212,8 +212,8 @@ dv_status dv_ctx_set_profiling(dv_ctx* ctx, int32_t flags) {
   if (!ctx) return DV_ERR_INVALID;
   DV_TRY_HIP(hipSetDevice(ctx->device));
   if ((flags & DV_PROFILE_COUNTERS) && !ctx->counters) {
-    DV_TRY_HIP(hipMalloc((void**)&ctx->counters, 4 * sizeof(unsigned long long)));
-    DV_TRY_HIP(hipMemset(ctx->counters, 0, 4 * sizeof(unsigned long long)));
+    DV_TRY_HIP(hipMalloc((void**)&ctx->counters, 8 * sizeof(unsigned long long)));
+    DV_TRY_HIP(hipMemset(ctx->counters, 0, 8 * sizeof(unsigned long long)));
   }
   ctx->prof_flags = flags;
   return DV_OK;
@@ -239,13 +239,17 @@ dv_status dv_ctx_stage_times(dv_ctx* ctx, dv_stage_times* out, int32_t reset) {
     out->calls[i] = ctx->prof_calls[i];
   }
   if (ctx->counters) {
-    unsigned long long c[4];
+    unsigned long long c[8];
     DV_TRY_HIP(hipDeviceSynchronize());
     DV_TRY_HIP(hipMemcpy(c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost));
     out->entries_fwd = (int64_t)c[0];
     out->pieces_fwd = (int64_t)c[1];
     out->entries_bwd = (int64_t)c[2];
     out->pieces_bwd = (int64_t)c[3];
+    out->entries_actor_fwd = (int64_t)c[4];
+    out->pieces_actor_fwd = (int64_t)c[5];
+    out->entries_actor_bwd = (int64_t)c[6];
+    out->pieces_actor_bwd = (int64_t)c[7];
     if (reset) DV_TRY_HIP(hipMemset(ctx->counters, 0, sizeof(c)));
   }
   if (reset) {

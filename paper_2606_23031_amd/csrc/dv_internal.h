@@ -96,7 +96,7 @@ namespace dv {
 enum Stage {
   ST_PREPROCESS = 0, ST_SORT_RECORDS, ST_GATHER, ST_EMIT, ST_SORT_PAIRS,
   ST_TILE_DIR, ST_COMPOSITE_FWD, ST_BWD_CLEAR, ST_COMPOSITE_BWD,
-  ST_RECORD_BWD, ST_HOST_SYNC, ST_OTHER
+  ST_RECORD_BWD, ST_HOST_SYNC, ST_OTHER, ST_ACTOR_FWD, ST_ACTOR_BWD
 };
 }  // namespace dv
 
@@ -119,7 +119,7 @@ struct dv_ctx {
   std::vector<Interval> prof_pending;
   double prof_ms[DV_NUM_STAGES] = {0};
   int64_t prof_calls[DV_NUM_STAGES] = {0};
-  unsigned long long* counters = nullptr;  // device [4]
+  unsigned long long* counters = nullptr;  // device [8]
 };
 
 namespace dv {

@@ -709,7 +709,7 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
     if (has) store_q(q);
   }
 
-  count_work(a.counters, 0, n_test, n_piece);
+  count_work(a.counters, 4, n_test, n_piece);
 }
 
 // Forward, part 2 (chunked tiles, chunks c > 0): B_c of every pixel, the
@@ -1464,21 +1464,28 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   for (int i = 0; i < 3; ++i) ca.bg[i] = op.bg[i];
   ca.mask = op.out_mask;
   ca.counters = (ctx->prof_flags.load() & DV_PROFILE_COUNTERS) ? ctx->counters : nullptr;
-  StageTimer tm_comp(ctx, ST_COMPOSITE_FWD, s);
   if (nt > 0) {
     const bool nrm = (op.out_mask & DV_OUT_NORMAL) != 0;
     const bool k1 = op.K == 1;
     if (st->n_apairs > 0) {
+      StageTimer tm_act(ctx, ST_ACTOR_FWD, s);
       hipLaunchKernelGGL(k_build_segments, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
       auto ka = nrm ? (k1 ? k_actor_fwd<true, 1> : k_actor_fwd<true, 0>)
                     : (k1 ? k_actor_fwd<false, 1> : k_actor_fwd<false, 0>);
       hipLaunchKernelGGL(ka, dim3((unsigned)st->n_apairs), dim3(TPB), 0, s, ca);
     }
     const unsigned ni = (unsigned)st->max_items;
-    hipLaunchKernelGGL(k_chunk_bounds, dim3(ni), dim3(TPB), 0, s, ca);
-    auto kern = nrm ? (k1 ? k_composite_fwd<true, 1> : k_composite_fwd<true, 0>)
-                    : (k1 ? k_composite_fwd<false, 1> : k_composite_fwd<false, 0>);
-    hipLaunchKernelGGL(kern, dim3(ni), dim3(TPB), 0, s, ca);
+    {
+      StageTimer tm_ch(ctx, ST_OTHER, s);
+      hipLaunchKernelGGL(k_chunk_bounds, dim3(ni), dim3(TPB), 0, s, ca);
+    }
+    {
+      StageTimer tm_comp(ctx, ST_COMPOSITE_FWD, s);
+      auto kern = nrm ? (k1 ? k_composite_fwd<true, 1> : k_composite_fwd<true, 0>)
+                      : (k1 ? k_composite_fwd<false, 1> : k_composite_fwd<false, 0>);
+      hipLaunchKernelGGL(kern, dim3(ni), dim3(TPB), 0, s, ca);
+    }
+    StageTimer tm_m(ctx, ST_OTHER, s);
     hipLaunchKernelGGL(k_chunk_merge, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
   }
   DV_TRY_HIP(hipGetLastError());

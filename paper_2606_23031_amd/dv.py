@@ -98,14 +98,16 @@ class dv_state_info(C.Structure):
                 ("n_chunk_slots", C.c_int64)]
 
 
-NUM_STAGES = 12
+NUM_STAGES = 14
 
 
 class dv_stage_times(C.Structure):
     _fields_ = [("ms", C.c_double * NUM_STAGES),
                 ("calls", C.c_int64 * NUM_STAGES),
                 ("entries_fwd", C.c_int64), ("pieces_fwd", C.c_int64),
-                ("entries_bwd", C.c_int64), ("pieces_bwd", C.c_int64)]
+                ("entries_bwd", C.c_int64), ("pieces_bwd", C.c_int64),
+                ("entries_actor_fwd", C.c_int64), ("pieces_actor_fwd", C.c_int64),
+                ("entries_actor_bwd", C.c_int64), ("pieces_actor_bwd", C.c_int64)]
 
 
 class dv_serve_opts(C.Structure):
@@ -237,7 +239,11 @@ def dv_ctx_stage_times(ctx, reset=True):
     out = {_lib.dv_stage_name(i).decode(): (t.ms[i], t.calls[i])
            for i in range(NUM_STAGES)}
     out["_counters"] = dict(entries_fwd=t.entries_fwd, pieces_fwd=t.pieces_fwd,
-                            entries_bwd=t.entries_bwd, pieces_bwd=t.pieces_bwd)
+                            entries_bwd=t.entries_bwd, pieces_bwd=t.pieces_bwd,
+                            entries_actor_fwd=t.entries_actor_fwd,
+                            pieces_actor_fwd=t.pieces_actor_fwd,
+                            entries_actor_bwd=t.entries_actor_bwd,
+                            pieces_actor_bwd=t.pieces_actor_bwd)
     return out
 
 
