@@ -161,6 +161,9 @@ typedef struct {
                                    several for a tile whose background list
                                    is split into chunks                    */
   int64_t n_chunk_slots;        /* chunks of the split tiles               */
+  int64_t n_actor_items;        /* asset work items: one per (tile, actor)
+                                   list, several for a split list          */
+  int64_t n_actor_chunk_slots;  /* chunks of the split (tile, actor) lists */
 } dv_state_info;
 
 /* ---------------------------------------------------------------- context */

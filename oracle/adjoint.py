@@ -26,12 +26,13 @@ _GW_CENTRE = F.trilinear_weight_grads(np.full(3, 0.5))       # [8,3]
 def new_accumulators(ctx):
     # corner_abs: sum of |per-piece contribution| per corner, the scale of
     # the summands behind each corner gradient (bookkeeping for error bars)
-    acc = dict(corner=[], corner_abs=[], dcol=[], dnw=[], dR=[], dp=[])
+    acc = dict(corner=[], corner_abs=[], dcol=[], dcol_abs=[], dnw=[], dR=[], dp=[])
     for k, o in enumerate(ctx.scene["octrees"]):
         acc["corner"].append(np.zeros(o["corner_density"].shape[0]))
         acc["corner_abs"].append(np.zeros(o["corner_density"].shape[0]))
         n = o["level"].shape[0]
         acc["dcol"].append(np.zeros((n, 3)))
+        acc["dcol_abs"].append(np.zeros((n, 3)))
         acc["dnw"].append(np.zeros((n, 3)))
         acc["dR"].append(np.zeros((3, 3)))
         acc["dp"].append(np.zeros(3))
@@ -71,6 +72,7 @@ def ray_adjoint(ctx, o, d, gC, gD, gN, gT, acc):
         np.add.at(acc["corner"][k], oct_["corner_idx"][:, vv], dg8)
         np.add.at(acc["corner_abs"][k], oct_["corner_idx"][:, vv], np.abs(dg8))
         acc["dcol"][k][vv] += w[i] * gC
+        acc["dcol_abs"][k][vv] += np.abs(w[i] * gC)
         acc["dnw"][k][vv] += w[i] * gN
         # geometry: samples and piece ends
         gw = F.trilinear_weight_grads(smp["u"][i])     # [K,8,3]
@@ -104,13 +106,15 @@ def ray_adjoint(ctx, o, d, gC, gD, gN, gT, acc):
 def finalize(ctx, acc):
     """Per-leaf colour and normal gradients -> SH coefficients, corners
     (through normals) and poses (SH direction, normal rotation)."""
-    out = dict(corner=[], corner_abs=[], sh=[], dR=[], dp=[])
+    out = dict(corner=[], corner_abs=[], sh=[], sh_abs=[], dR=[], dp=[])
     for k, o in enumerate(ctx.scene["octrees"]):
         ent = ctx.oct[k]
         dcol = acc["dcol"][k] * (ent["raw"] > 0)
         deg = o["sh_degree"]
         Y = SH.basis(ent["wdir"], deg)                  # [N,S]
         out["sh"].append(np.einsum("ns,nc->scn", Y, dcol))
+        dcol_abs = acc["dcol_abs"][k] * (ent["raw"] > 0)
+        out["sh_abs"].append(np.einsum("ns,nc->scn", np.abs(Y), dcol_abs))
         corner = acc["corner"][k].copy()
         corner_abs = acc["corner_abs"][k].copy()
         dR, dp = acc["dR"][k].copy(), acc["dp"][k].copy()

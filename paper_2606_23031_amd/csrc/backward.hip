@@ -452,14 +452,69 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
   count_work(a.counters, 2, n_test, n_piece);
 }
 
-// Backward, part 3 (tiles with actor boxes, after every part 2 item):
-// pieces of the asset segments (their T_pre, S_after from the splice), then
-// the box faces that bound segments, into the pose gradients.
+// Segments of actor j on the ray of this lane: count, first and last.
+__device__ inline int segs_of_actor_b(const CompArgs& a, uint32_t seg0, int nseg,
+                                      int j, int tid, int& qfirst) {
+  int nj = 0;
+  qfirst = nseg;
+  for (int i = 0; i < nseg; ++i)
+    if ((int)(a.seg_meta[seg_index(seg0 + i, tid)] & 0xFF) == j) {
+      if (nj == 0) qfirst = i;
+      ++nj;
+    }
+  return nj;
+}
+
+// Backward, part 3a (actor lists of several chunks): for rays with a single
+// segment of the actor, the transmittance W_c in front of chunk c inside
+// the segment and the segment's part R_c behind the chunk, summed from the
+// back.
+template <bool NORMALS>
+__global__ void __launch_bounds__(TPB) k_actor_prep(CompArgs a) {
+  const uint32_t e = blockIdx.x;
+  const uint32_t nck = a.pair_nck[e];
+  if (nck <= 1) return;
+  const uint32_t gt = a.act_tile[e];
+  const uint32_t a_beg = a.act_beg[gt];
+  const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
+  const int tid = threadIdx.x;
+  const PixSetup P = pixel_setup(a, gt, tid);
+  if (!P.valid) return;
+  const uint32_t seg0 = 3 * a_beg + n_at;
+  const int nseg = (int)a.pix_nseg[P.pix];
+  int qfirst;
+  if (segs_of_actor_b(a, seg0, nseg, (int)(e - a_beg), tid, qfirst) != 1) return;
+  const PixGrad g = pixel_grads<NORMALS>(a, P);
+  const size_t s0 = (size_t)a.pair_pbase[e] * TPB + tid;
+  const float4* part = a.apart + s0 * 4;
+  float W = 1.0f;
+  for (uint32_t c = 0; c < nck; ++c) {
+    a.atps[s0 + (size_t)c * TPB] = make_float2(W, 0.0f);
+    W *= part[(size_t)c * TPB * 4 + 1].w;
+  }
+  float R = 0.0f;
+  for (uint32_t c = nck; c-- > 0;) {
+    const size_t q = (size_t)c * TPB;
+    const float Wc = a.atps[s0 + q].x;
+    a.atps[s0 + q] = make_float2(Wc, R);
+    R = fmaf(Wc, gdot(g, part[q * 4], part[q * 4 + 1]), R);
+  }
+}
+
+// Backward, part 3b: one block per actor work item (a chunk of one (tile,
+// actor) list), after every part 2 block: pieces of the asset segments,
+// with T_pre and S_after of their segment from the splice (for a chunk of a
+// single-segment ray, T_pre W_c and T_pre R_c + S_after, with the chunk's
+// own totals and tails); end points of segments on box faces go to the
+// segment for part 4.
 template <bool NORMALS, int KC>
 __global__ void __launch_bounds__(TPB) k_actor_bwd(CompArgs a) {
   __shared__ BwdBatch B;
   __shared__ float red[(TPB / 64) * 12];
-  const uint32_t e = a.actor_order[blockIdx.x];
+  if (blockIdx.x >= a.aplan_counts[0]) return;
+  const uint32_t item = a.aorder[blockIdx.x];
+  const uint32_t e = a.aitem_pair[item], chunk = a.aitem_chunk[item];
+  const uint32_t nck = a.pair_nck[e];
   const uint32_t gt = a.act_tile[e];
   const uint32_t a_beg = a.act_beg[gt];
   const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
@@ -481,14 +536,18 @@ __global__ void __launch_bounds__(TPB) k_actor_bwd(CompArgs a) {
 
   // ---------------------------------------------------- B2: actor jsel
   for (int j = jsel; j == jsel; ++j) {
+    int qf;
+    const int nj = segs_of_actor_b(a, seg0, nseg, j, tid, qf);
+    const bool simple = nck > 1 && nj == 1;
     // first spliced segment of slot j
     int q = nseg;
     for (int i = 0; i < nseg; ++i) {
       const size_t qi = seg_index(seg0 + i, tid);
       if ((int)(a.seg_meta[qi] & 0xFF) == j && a.seg_bw[qi].x >= 0.0f) { q = i; break; }
     }
-    bool has = q < nseg;
+    bool has = q < nseg && (nck == 1 || simple || chunk == 0);
     if (!__syncthreads_or(has)) continue;
+    const bool any_full = __syncthreads_or(has && nck > 1 && !simple);
     const uint32_t koct = a.act_oct[a_beg + j];
     const VOConst& C = a.vo[v * a.n_oct + koct];
     const float3 dj = mat3_mul(C.Rt, d);
@@ -502,13 +561,20 @@ __global__ void __launch_bounds__(TPB) k_actor_bwd(CompArgs a) {
       const size_t qi = seg_index(seg0 + qq, tid);
       const float2 se = a.seg_se[qi];
       const float4 bw = a.seg_bw[qi];
-      const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
       qs = se.x; qe = se.y; Tpre = bw.x; Saft = bw.y;
-      Vq = GC.x * q0.x + GC.y * q0.y + GC.z * q0.z + GD * q0.w + GN.x * q1.x +
-           GN.y * q1.y + GN.z * q1.z;
-      const float4 u0 = a.seg_t0[qi], u1 = a.seg_t1[qi];
-      VqT = GC.x * u0.x + GC.y * u0.y + GC.z * u0.z + GD * u0.w + GN.x * u1.x +
-            GN.y * u1.y + GN.z * u1.z;
+      if (simple) {
+        // this chunk of the segment: its totals, tails and surroundings
+        const size_t sl = ((size_t)a.pair_pbase[e] + chunk) * TPB + tid;
+        const float4* part = a.apart + sl * 4;
+        const float2 wr = a.atps[sl];
+        Vq = gdot(g, part[0], part[1]);
+        VqT = gdot(g, part[2], part[3]);
+        Saft = fmaf(Tpre, wr.y, Saft);
+        Tpre *= wr.x;
+      } else {
+        Vq = gdot(g, a.seg_p0[qi], a.seg_p1[qi]);
+        VqT = gdot(g, a.seg_t0[qi], a.seg_t1[qi]);
+      }
       Tl = 1.0f; Pl = 0.0f; PlT = 0.0f; qdone = false;
     };
     auto next_q = [&](int from) {
@@ -528,8 +594,13 @@ __global__ void __launch_bounds__(TPB) k_actor_bwd(CompArgs a) {
     }
     auto live = [&]() { return has && !(qdone && q == qlast); };
     const uint2 sub = a.act_sub[a_beg + j];
-    for (uint32_t base = sub.x; base < sub.y; base += TPB) {
-      const uint32_t nb = min((uint32_t)TPB, sub.y - base);
+    uint32_t cb = sub.x, ce = sub.y;
+    if (nck > 1) chunk_range(sub.x, sub.y, nck, chunk, cb, ce);
+    // entries this lane walks, and the block's loop range
+    const uint32_t wlo = simple ? cb : sub.x, whi = simple ? ce : sub.y;
+    const uint32_t lo = any_full ? sub.x : cb, hi = any_full ? sub.y : ce;
+    for (uint32_t base = lo; base < hi; base += TPB) {
+      const uint32_t nb = min((uint32_t)TPB, hi - base);
       load_bwd_batch(B, a, base, nb);
       __syncthreads();
       uint64_t wm[4];
@@ -542,7 +613,7 @@ __global__ void __launch_bounds__(TPB) k_actor_bwd(CompArgs a) {
         float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
         float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         bool hit = false;
-        if (live()) {
+        if (live() && base + r >= wlo && base + r < whi) {
           const float4 geo = B.geo[r];
           float t0, t1;
           int ax0, ax1;
@@ -876,8 +947,9 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
                        dim3(TPB), 0, s, (int64_t)nslots, segbw.as<float4>());
     DV_TRY_HIP(hipGetLastError());
   }
-  DBuf tps;
+  DBuf tps, atps;
   DV_TRY(alloc_n<float2>(ctx, tps, st->max_slots * TPB, s));
+  DV_TRY(alloc_n<float2>(ctx, atps, st->max_aslots * TPB, s));
   CompArgs ca;
   std::memset(&ca, 0, sizeof(ca));
   ca.views = st->views_d.as<ViewConst>();
@@ -933,13 +1005,20 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   ca.chunk_b = st->chunk_b.as<float>();
   ca.chunk_part = st->chunk_part.as<float4>();
   ca.chunk_tps = tps.as<float2>();
+  ca.atps = atps.as<float2>();
   // the same work items as the forward, ordered by the work each took there
   DV_TRY(alloc_n<uint32_t>(ctx, st->order_bwd, st->max_items, s));
   DV_TRY(launch_order_by_weight(st->max_items, nullptr, st->item_work.as<uint32_t>(),
                                 st->order_bwd.as<uint32_t>(), s));
   ca.order = st->order_bwd.as<uint32_t>();
-  ca.actor_order = st->actor_order.as<uint32_t>();
   ca.act_tile = st->act_tile.as<uint32_t>();
+  ca.aorder = st->aorder.as<uint32_t>();
+  ca.aitem_pair = st->aitem_pair.as<uint32_t>();
+  ca.aitem_chunk = st->aitem_chunk.as<uint32_t>();
+  ca.pair_nck = st->pair_nck.as<uint32_t>();
+  ca.pair_pbase = st->pair_pbase.as<uint32_t>();
+  ca.aplan_counts = st->aplan_counts.as<uint32_t>();
+  ca.apart = st->apart.as<float4>();
   if (nt > 0) {
     const bool k1 = op.K == 1;
     auto kp = normals ? k_chunk_prep<true> : k_chunk_prep<false>;
@@ -953,9 +1032,11 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
     }
     if (st->n_apairs > 0) {
       StageTimer tm_act(ctx, ST_ACTOR_BWD, s);
+      auto kq = normals ? k_actor_prep<true> : k_actor_prep<false>;
+      hipLaunchKernelGGL(kq, dim3((unsigned)st->n_apairs), dim3(TPB), 0, s, ca);
       auto ka = normals ? (k1 ? k_actor_bwd<true, 1> : k_actor_bwd<true, 0>)
                         : (k1 ? k_actor_bwd<false, 1> : k_actor_bwd<false, 0>);
-      hipLaunchKernelGGL(ka, dim3((unsigned)st->n_apairs), dim3(TPB), 0, s, ca);
+      hipLaunchKernelGGL(ka, dim3((unsigned)st->max_aitems), dim3(TPB), 0, s, ca);
       if (ca.pose_grad) {
         auto kb = normals ? k_box_bwd<true> : k_box_bwd<false>;
         hipLaunchKernelGGL(kb, dim3((unsigned)nt), dim3(TPB), 0, s, ca);

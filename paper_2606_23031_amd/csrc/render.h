@@ -22,7 +22,6 @@ struct CompArgs {
   const uint32_t* tile_bgend;
   // work items: every tile's background list in 1 or more chunks
   const uint32_t* order;       // launch order -> item id
-  const uint32_t* actor_order; // launch order of the actor kernels -> pair
   const uint32_t* act_tile;    // (tile, actor) pair -> tile
   const uint32_t* item_tile;   // item id -> tile
   const uint32_t* item_chunk;  // item id -> chunk index in its tile
@@ -33,6 +32,16 @@ struct CompArgs {
   float4* chunk_part;      // per (chunk slot, pixel): 4 x float4 partials
   float2* chunk_tps;       // backward: per (chunk slot, pixel): T_pre, S_after
   uint32_t* item_work;     // forward: measured work per item
+  // actor work items: every (tile, actor) list in 1 or more chunks; a ray
+  // with one segment of the actor is composited per chunk into partials
+  const uint32_t* aorder;      // launch order -> actor item id
+  const uint32_t* aitem_pair;  // actor item -> (tile, actor) pair
+  const uint32_t* aitem_chunk; // actor item -> chunk index
+  const uint32_t* pair_nck;    // chunks per pair
+  const uint32_t* pair_pbase;  // first chunk slot of a pair with nck > 1
+  const uint32_t* aplan_counts;// [0] actor items, [1] chunk slots
+  float4* apart;           // per (actor chunk slot, pixel): 4 x float4
+  float2* atps;            // backward: per (slot, pixel): W_c, R_c
   const uint32_t* pair_val;
   const float4* rec_geo;   // vmin - camera (octree frame), h
   const float4* rec_g8a;   // corner densities 0..3
@@ -169,9 +178,12 @@ dv_status launch_order_by_weight(int64_t n, const uint32_t* w0, const uint32_t* 
 // chunks is split into ceil(len / CHUNK) equal chunks, each composited by
 // its own block into per-pixel partial states that are merged in order.
 constexpr uint32_t CHUNK = 1024;
-__host__ __device__ inline uint32_t chunks_of(uint32_t len) {
-  return len > CHUNK + CHUNK / 2 ? (len + CHUNK - 1) / CHUNK : 1u;
+__host__ __device__ inline uint32_t chunks_of(uint32_t len, uint32_t chunk = CHUNK) {
+  return len > chunk + chunk / 2 ? (len + chunk - 1) / chunk : 1u;
 }
+// Entries per chunk of an actor's list in a tile (asset walks cost more per
+// entry, so their chunks are shorter).
+constexpr uint32_t ACHUNK = 384;
 // Entry range [cb, ce) of chunk c of nck over [beg, end).
 __device__ inline void chunk_range(uint32_t beg, uint32_t end, uint32_t nck,
                                    uint32_t c, uint32_t& cb, uint32_t& ce) {
@@ -498,6 +510,9 @@ struct dv_fwd_state {
   dv::DBuf fin0, fin1, fin2, fin3, seg_t0, seg_t1;
   dv::DBuf order_fwd, order_bwd, item_tile, item_chunk, item_work;
   dv::DBuf tile_nck, tile_ibase, tile_pbase, plan_counts;
-  dv::DBuf chunk_b, chunk_part, actor_order, act_tile;
+  dv::DBuf chunk_b, chunk_part, act_tile;
+  dv::DBuf aorder, aitem_pair, aitem_chunk, pair_nck, pair_ibase, pair_pbase,
+      aplan_counts, apart;
+  int64_t max_aitems = 0, max_aslots = 0;
   int64_t max_items = 0, max_slots = 0;
 };

@@ -379,38 +379,54 @@ dv_status launch_order_by_weight(int64_t n, const uint32_t* w0, const uint32_t* 
 }
 
 // Work items of the compositing kernels.  Tile t's background list
-// [start, bgend) becomes chunks_of(len) items (ids tile_ibase[t] + c);
-// tiles split into more than one chunk get consecutive chunk slots from
-// tile_pbase[t] for their partial states.  The launch order puts the
-// longest chunks first.  counts[0] = items, counts[1] = chunk slots.  One
-// block of 1024 threads, each owning a contiguous run of tiles.
+// [start, bgend) becomes k = chunks_of(len) items (ids tile_ibase[t] + c)
+// when its chunk slots [tile_pbase[t], + k) fit below max_slots, else one
+// item; split tiles keep their partial states in those slots.  The launch
+// order puts the longest chunks first.  counts[0] = items, counts[1] =
+// slots reserved.  The same for the (tile, actor) lists when range is given
+// (range[e] = [first, end) entries).  One block of 1024 threads, each owning
+// a contiguous run of lists.
 __global__ void __launch_bounds__(1024) k_plan_items(
     int64_t n_tiles, const uint32_t* start, const uint32_t* bgend,
+    const uint2* range, uint32_t chunk_len, uint32_t max_slots,
     uint32_t* tile_nck, uint32_t* tile_ibase, uint32_t* tile_pbase,
     uint32_t* item_tile, uint32_t* item_chunk, uint32_t* order,
     uint32_t* counts) {
   __shared__ uint32_t wsum[17];
   __shared__ uint32_t cnt[256];
   __shared__ uint32_t off[256];
+  auto list_len = [&](int64_t t) -> uint32_t {
+    return range ? range[t].y - range[t].x : bgend[t] - start[t];
+  };
   const int tid = threadIdx.x;
   const int64_t per = (n_tiles + 1023) / 1024;
   const int64_t t0 = min(n_tiles, (int64_t)tid * per), t1 = min(n_tiles, t0 + per);
-  uint32_t ni = 0, nsl = 0;
+  if (tid < 256) cnt[tid] = 0;
+  // slots wanted by this thread's lists
+  uint32_t nsl = 0;
   for (int64_t t = t0; t < t1; ++t) {
-    const uint32_t k = chunks_of(bgend[t] - start[t]);
-    ni += k;
+    const uint32_t k = chunks_of(list_len(t), chunk_len);
     if (k > 1) nsl += k;
   }
-  if (tid < 256) cnt[tid] = 0;
-  uint32_t n_items, n_slots;
-  uint32_t ib = block_scan_1024(ni, wsum, &n_items);
-  __syncthreads();
-  uint32_t pb = block_scan_1024(nsl, wsum, &n_slots);
-  if (tid == 0) { counts[0] = n_items; counts[1] = n_slots; }
-  const uint32_t ib0 = ib;
+  uint32_t n_slots;
+  const uint32_t pb0 = block_scan_1024(nsl, wsum, &n_slots);
+  // chunks granted (a list whose slots would pass max_slots stays whole)
+  uint32_t ni = 0, pb = pb0;
   for (int64_t t = t0; t < t1; ++t) {
-    const uint32_t len = bgend[t] - start[t];
-    const uint32_t k = chunks_of(len);
+    const uint32_t k = chunks_of(list_len(t), chunk_len);
+    ni += (k > 1 && pb + k <= max_slots) ? k : 1u;
+    if (k > 1) pb += k;
+  }
+  __syncthreads();
+  uint32_t n_items;
+  uint32_t ib = block_scan_1024(ni, wsum, &n_items);
+  if (tid == 0) { counts[0] = n_items; counts[1] = min(n_slots, max_slots); }
+  const uint32_t ib0 = ib;
+  pb = pb0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const uint32_t len = list_len(t);
+    const uint32_t kw = chunks_of(len, chunk_len);
+    const uint32_t k = (kw > 1 && pb + kw <= max_slots) ? kw : 1u;
     tile_nck[t] = k;
     tile_ibase[t] = ib;
     tile_pbase[t] = pb;
@@ -422,7 +438,7 @@ __global__ void __launch_bounds__(1024) k_plan_items(
       atomicAdd(&cnt[255 - weight_bucket(ce - cb)], 1u);
     }
     ib += k;
-    if (k > 1) pb += k;
+    if (kw > 1) pb += kw;
   }
   __syncthreads();
   if (tid == 0) {
@@ -432,8 +448,8 @@ __global__ void __launch_bounds__(1024) k_plan_items(
   __syncthreads();
   ib = ib0;
   for (int64_t t = t0; t < t1; ++t) {
-    const uint32_t len = bgend[t] - start[t];
-    const uint32_t k = chunks_of(len);
+    const uint32_t k = tile_nck[t];
+    const uint32_t len = list_len(t);
     for (uint32_t c = 0; c < k; ++c) {
       uint32_t cb, ce;
       chunk_range(0, len, k, c, cb, ce);
@@ -571,11 +587,6 @@ __device__ inline void write_outputs(const CompArgs& a, const ViewConst& V, int 
   if ((a.mask & DV_OUT_T) && O.T) O.T[o] = T;
 }
 
-__global__ void k_sub_len(int64_t n, const uint2* sub, uint32_t* len) {
-  const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (e < n) len[e] = sub[e].y - sub[e].x;
-}
-
 // Forward, part 1a (tiles with actor boxes): per pixel, the ownership
 // segments of the actor boxes its ray meets.
 __global__ void __launch_bounds__(TPB) k_build_segments(CompArgs a) {
@@ -590,18 +601,39 @@ __global__ void __launch_bounds__(TPB) k_build_segments(CompArgs a) {
   a.pix_nseg[P.pix] = (uint32_t)nseg;
 }
 
-// Forward, part 1b: one block per (tile, actor) pair: every segment of that
-// actor on the tile's rays composited into a partial state (C, D, N, T)
-// with its tail sums.  Actors are independent here, so the pairs of a tile
-// run as separate blocks.
+// Segments of actor j on the ray of this lane: count, first and last.
+__device__ inline int segs_of_actor(const CompArgs& a, uint32_t seg0, int nseg,
+                                    int j, int tid, int& qfirst, int& qlast) {
+  int nj = 0;
+  qfirst = nseg;
+  qlast = -1;
+  for (int i = 0; i < nseg; ++i)
+    if ((int)(a.seg_meta[seg_index(seg0 + i, tid)] & 0xFF) == j) {
+      if (nj == 0) qfirst = i;
+      qlast = i;
+      ++nj;
+    }
+  return nj;
+}
+
+// Forward, part 1b: one block per actor work item, a chunk of one (tile,
+// actor) list: every segment of that actor on the tile's rays composited
+// into a partial state (C, D, N, T) with its tail sums.  Actors are
+// independent here, so they run as separate blocks; a long list is split
+// into chunks for rays with a single segment of the actor (partials per
+// chunk, merged by k_actor_merge), while rays with several segments of it
+// (overlapping boxes) walk the whole list in chunk 0.
 template <bool NORMALS, int KC>
 __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
   __shared__ Batch B;
-  const uint32_t e = a.actor_order[blockIdx.x];
+  if (blockIdx.x >= a.aplan_counts[0]) return;
+  const uint32_t item = a.aorder[blockIdx.x];
+  const uint32_t e = a.aitem_pair[item], chunk = a.aitem_chunk[item];
+  const uint32_t nck = a.pair_nck[e];
   const uint32_t gt = a.act_tile[e];
   const uint32_t a_beg = a.act_beg[gt];
   const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
-  const int jsel = (int)(e - a_beg);
+  const int j = (int)(e - a_beg);
   const int tid = threadIdx.x;
   const PixSetup P = pixel_setup(a, gt, tid);
   const int v = P.v, bx = P.bx, by = P.by;
@@ -611,50 +643,63 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
   uint32_t n_test = 0, n_piece = 0;
   const uint32_t seg0 = 3 * a_beg + n_at;
   const int nseg = P.valid ? (int)a.pix_nseg[P.pix] : 0;
-
-  for (int j = jsel; j == jsel; ++j) {
-    int q = next_seg_of(a, seg0, nseg, 0, j, tid);
-    bool has = q < nseg;
-    if (!__syncthreads_or(has)) continue;
-    const VOConst& C = a.vo[v * a.n_oct + a.act_oct[a_beg + j]];
-    const float3 dj = mat3_mul(C.Rt, d);
-    const float3 inv = safe_inv(dj);
-    float qs = 0, qe = 0;
-    // p0/p1: partial state of segment q; t0/t1: its tail part
-    float4 p0 = make_float4(0, 0, 0, 0), p1 = make_float4(0, 0, 0, 1);
-    float4 t0s = make_float4(0, 0, 0, 0);
-    float3 t1s = make_float3(0, 0, 0);
-    bool qdone = false;
-    auto store_q = [&](int qq) {
-      const size_t qi = seg_index(seg0 + qq, tid);
-      a.seg_p0[qi] = p0;
-      a.seg_p1[qi] = p1;
-      a.seg_t0[qi] = t0s;
-      a.seg_t1[qi] = make_float4(t1s.x, t1s.y, t1s.z, 0.0f);
-    };
-    if (has) {
-      const float2 se = a.seg_se[seg_index(seg0 + q, tid)];
-      qs = se.x; qe = se.y;
+  int qfirst, qlast;
+  const int nj = segs_of_actor(a, seg0, nseg, j, tid, qfirst, qlast);
+  const bool simple = nck > 1 && nj == 1;
+  bool has = nj > 0 && (nck == 1 || simple || chunk == 0);
+  if (!__syncthreads_or(has)) return;
+  const bool any_full = __syncthreads_or(has && nck > 1 && !simple);
+  const uint2 sub = a.act_sub[e];
+  uint32_t cb = sub.x, ce = sub.y;
+  if (nck > 1) chunk_range(sub.x, sub.y, nck, chunk, cb, ce);
+  // entries this lane walks, and the block's loop range
+  const uint32_t wlo = simple ? cb : sub.x, whi = simple ? ce : sub.y;
+  const uint32_t lo = any_full ? sub.x : cb, hi = any_full ? sub.y : ce;
+  const VOConst& C = a.vo[v * a.n_oct + a.act_oct[e]];
+  const float3 dj = mat3_mul(C.Rt, d);
+  const float3 inv = safe_inv(dj);
+  int q = qfirst;
+  float qs = 0, qe = 0;
+  // p0/p1: partial state of segment q; t0s/t1s: its tail part
+  float4 p0 = make_float4(0, 0, 0, 0), p1 = make_float4(0, 0, 0, 1);
+  float4 t0s = make_float4(0, 0, 0, 0);
+  float3 t1s = make_float3(0, 0, 0);
+  bool qdone = false;
+  auto store_q = [&](int qq) {
+    float4* dst;
+    if (simple) {
+      dst = a.apart + (((size_t)a.pair_pbase[e] + chunk) * TPB + tid) * 4;
+      dst[0] = p0;
+      dst[1] = p1;
+      dst[2] = t0s;
+      dst[3] = make_float4(t1s.x, t1s.y, t1s.z, 0.0f);
+      return;
     }
-    // last segment of actor j on this ray: once it is done (T below the
-    // stop threshold) the lane has nothing left in this list
-    int qlast = -1;
-    for (int i = nseg - 1; i >= 0 && qlast < 0; --i)
-      if ((int)(a.seg_meta[seg_index(seg0 + i, tid)] & 0xFF) == j) qlast = i;
-    auto live = [&]() { return has && !(qdone && q == qlast); };
-    const uint2 sub = a.act_sub[a_beg + j];
-    for (uint32_t base = sub.x; base < sub.y; base += TPB) {
-      const uint32_t nb = min((uint32_t)TPB, sub.y - base);
-      load_batch(B, a, base, nb);
-      __syncthreads();
-      uint64_t wm[4];
-      wave_entry_masks(B.rect, nb, bx, by, wm);
-      for (int c = 0; c < 4; ++c) {
+    const size_t qi = seg_index(seg0 + qq, tid);
+    a.seg_p0[qi] = p0;
+    a.seg_p1[qi] = p1;
+    a.seg_t0[qi] = t0s;
+    a.seg_t1[qi] = make_float4(t1s.x, t1s.y, t1s.z, 0.0f);
+  };
+  if (has) {
+    const float2 se = a.seg_se[seg_index(seg0 + q, tid)];
+    qs = se.x; qe = se.y;
+  }
+  // once the last segment of the actor is done (T below the stop threshold)
+  // the lane has nothing left in this list
+  auto live = [&]() { return has && !(qdone && q == qlast); };
+  for (uint32_t base = lo; base < hi; base += TPB) {
+    const uint32_t nb = min((uint32_t)TPB, hi - base);
+    load_batch(B, a, base, nb);
+    __syncthreads();
+    uint64_t wm[4];
+    wave_entry_masks(B.rect, nb, bx, by, wm);
+    for (int c = 0; c < 4; ++c) {
       uint64_t m = wm[c];
       while (m != 0 && __ballot(live()) != 0) {
         const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
         m &= m - 1;
-        if (!live()) continue;
+        if (!live() || base + r < wlo || base + r >= whi) continue;
         const float4 geo = B.geo[r];
         float t0, t1;
         slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
@@ -679,8 +724,8 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
             const float tau = piece_tau<KC>(geo, B.ga[r], B.gb[r], cn.w, dj, pa,
                                             pb, K, invK, a.c, a.inv_c);
             ++n_piece;
-            const float e = fast_exp(-tau);
-            const float wgt = p1.w * opacity(tau, e);
+            const float e_ = fast_exp(-tau);
+            const float wgt = p1.w * opacity(tau, e_);
             const float wt = p1.w < T_REBASE ? wgt : 0.0f;
             const float mid = 0.5f * (pa + pb);
             p0.x = fmaf(wgt, cn.x, p0.x); t0s.x = fmaf(wt, cn.x, t0s.x);
@@ -693,7 +738,7 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
               p1.y = fmaf(wgt, nr.y, p1.y); t1s.y = fmaf(wt, nr.y, t1s.y);
               p1.z = fmaf(wgt, nr.z, p1.z); t1s.z = fmaf(wt, nr.z, t1s.z);
             }
-            p1.w *= e;
+            p1.w *= e_;
             if (p1.w < a.eps) qdone = true;
           }
           if (t1 > qe) {  // chord continues into a later segment of j
@@ -703,13 +748,46 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
           break;
         }
       }
-      }
-      if (!__syncthreads_or(live())) break;
     }
-    if (has) store_q(q);
+    if (!__syncthreads_or(live())) break;
   }
-
+  if (has) store_q(q);
   count_work(a.counters, 4, n_test, n_piece);
+}
+
+// Forward, part 1c (actor lists of several chunks): per ray with a single
+// segment of the actor, merge the chunk partials in order into the
+// segment's state.  The segment's tail sums are per chunk (each chunk has
+// its own T), so the backward takes them from the chunk partials.
+__global__ void __launch_bounds__(TPB) k_actor_merge(CompArgs a) {
+  const uint32_t e = blockIdx.x;
+  const uint32_t nck = a.pair_nck[e];
+  if (nck <= 1) return;
+  const uint32_t gt = a.act_tile[e];
+  const uint32_t a_beg = a.act_beg[gt];
+  const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
+  const int tid = threadIdx.x;
+  const size_t pix = (size_t)gt * TPB + tid;
+  const uint32_t seg0 = 3 * a_beg + n_at;
+  const int nseg = (int)a.pix_nseg[pix];
+  int qfirst, qlast;
+  if (segs_of_actor(a, seg0, nseg, (int)(e - a_beg), tid, qfirst, qlast) != 1) return;
+  const float4* part = a.apart + ((size_t)a.pair_pbase[e] * TPB + tid) * 4;
+  float4 p0 = make_float4(0, 0, 0, 0), p1 = make_float4(0, 0, 0, 1);
+  for (uint32_t c = 0; c < nck; ++c) {
+    const float4 c0 = part[(size_t)c * TPB * 4], c1 = part[(size_t)c * TPB * 4 + 1];
+    const float T = p1.w;
+    p0.x = fmaf(T, c0.x, p0.x); p0.y = fmaf(T, c0.y, p0.y);
+    p0.z = fmaf(T, c0.z, p0.z); p0.w = fmaf(T, c0.w, p0.w);
+    p1.x = fmaf(T, c1.x, p1.x); p1.y = fmaf(T, c1.y, p1.y);
+    p1.z = fmaf(T, c1.z, p1.z);
+    p1.w = T * c1.w;
+  }
+  const size_t qi = seg_index(seg0 + qfirst, tid);
+  a.seg_p0[qi] = p0;
+  a.seg_p1[qi] = p1;
+  a.seg_t0[qi] = make_float4(0, 0, 0, 0);
+  a.seg_t1[qi] = make_float4(0, 0, 0, 0);
 }
 
 // Forward, part 2 (chunked tiles, chunks c > 0): B_c of every pixel, the
@@ -1379,20 +1457,32 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   DV_TRY(alloc_n<float>(ctx, st->chunk_b, st->max_slots * TPB, s));
   DV_TRY(alloc_n<float4>(ctx, st->chunk_part, st->max_slots * TPB * 4, s));
   DV_TRY(fill_u32(st->item_work.as<uint32_t>(), 0u, st->max_items, s));
-  // (tile, actor) pairs by the length of their lists, heaviest first
+  // actor work items: (tile, actor) lists, long ones split into chunks
   if (na > 0) {
-    DBuf sublen;
-    DV_TRY(alloc_n<uint32_t>(ctx, sublen, na, s));
-    DV_TRY(alloc_n<uint32_t>(ctx, st->actor_order, na, s));
-    hipLaunchKernelGGL(k_sub_len, dim3(grid_for(na, TPB)), dim3(TPB), 0, s, na,
-                       st->act_sub.as<uint2>(), sublen.as<uint32_t>());
+    st->max_aitems = na + st->n_pairs / ACHUNK + 1;
+    st->max_aslots = std::min<int64_t>(2 * (st->n_pairs / ACHUNK) + 1,
+                                       ((int64_t)1 << 30) / (TPB * 64));
+    DV_TRY(alloc_n<uint32_t>(ctx, st->aorder, st->max_aitems, s));
+    DV_TRY(alloc_n<uint32_t>(ctx, st->aitem_pair, st->max_aitems, s));
+    DV_TRY(alloc_n<uint32_t>(ctx, st->aitem_chunk, st->max_aitems, s));
+    DV_TRY(alloc_n<uint32_t>(ctx, st->pair_nck, na, s));
+    DV_TRY(alloc_n<uint32_t>(ctx, st->pair_ibase, na, s));
+    DV_TRY(alloc_n<uint32_t>(ctx, st->pair_pbase, na, s));
+    DV_TRY(alloc_n<uint32_t>(ctx, st->aplan_counts, 2, s));
+    DV_TRY(alloc_n<float4>(ctx, st->apart, st->max_aslots * TPB * 4, s));
+    hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(1024), 0, s, na,
+                       (const uint32_t*)nullptr, (const uint32_t*)nullptr,
+                       st->act_sub.as<uint2>(), ACHUNK, (uint32_t)st->max_aslots,
+                       st->pair_nck.as<uint32_t>(), st->pair_ibase.as<uint32_t>(),
+                       st->pair_pbase.as<uint32_t>(), st->aitem_pair.as<uint32_t>(),
+                       st->aitem_chunk.as<uint32_t>(), st->aorder.as<uint32_t>(),
+                       st->aplan_counts.as<uint32_t>());
     DV_TRY_HIP(hipGetLastError());
-    DV_TRY(launch_order_by_weight(na, nullptr, sublen.as<uint32_t>(),
-                                  st->actor_order.as<uint32_t>(), s));
   }
   if (nt > 0) {
     hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(1024), 0, s, nt,
                        st->tile_start.as<uint32_t>(), st->tile_bgend.as<uint32_t>(),
+                       (const uint2*)nullptr, CHUNK, (uint32_t)st->max_slots,
                        st->tile_nck.as<uint32_t>(), st->tile_ibase.as<uint32_t>(),
                        st->tile_pbase.as<uint32_t>(), st->item_tile.as<uint32_t>(),
                        st->item_chunk.as<uint32_t>(), st->order_fwd.as<uint32_t>(),
@@ -1423,8 +1513,14 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   ca.tile_end = st->tile_end.as<uint32_t>();
   ca.tile_bgend = st->tile_bgend.as<uint32_t>();
   ca.order = st->order_fwd.as<uint32_t>();
-  ca.actor_order = st->actor_order.as<uint32_t>();
   ca.act_tile = st->act_tile.as<uint32_t>();
+  ca.aorder = st->aorder.as<uint32_t>();
+  ca.aitem_pair = st->aitem_pair.as<uint32_t>();
+  ca.aitem_chunk = st->aitem_chunk.as<uint32_t>();
+  ca.pair_nck = st->pair_nck.as<uint32_t>();
+  ca.pair_pbase = st->pair_pbase.as<uint32_t>();
+  ca.aplan_counts = st->aplan_counts.as<uint32_t>();
+  ca.apart = st->apart.as<float4>();
   ca.item_tile = st->item_tile.as<uint32_t>();
   ca.item_chunk = st->item_chunk.as<uint32_t>();
   ca.tile_nck = st->tile_nck.as<uint32_t>();
@@ -1472,7 +1568,8 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
       hipLaunchKernelGGL(k_build_segments, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
       auto ka = nrm ? (k1 ? k_actor_fwd<true, 1> : k_actor_fwd<true, 0>)
                     : (k1 ? k_actor_fwd<false, 1> : k_actor_fwd<false, 0>);
-      hipLaunchKernelGGL(ka, dim3((unsigned)st->n_apairs), dim3(TPB), 0, s, ca);
+      hipLaunchKernelGGL(ka, dim3((unsigned)st->max_aitems), dim3(TPB), 0, s, ca);
+      hipLaunchKernelGGL(k_actor_merge, dim3((unsigned)st->n_apairs), dim3(TPB), 0, s, ca);
     }
     const unsigned ni = (unsigned)st->max_items;
     {
@@ -1600,6 +1697,14 @@ dv_status dv_fwd_state_info(const dv_fwd_state* st, dv_state_info* info) {
     DV_TRY_HIP(hipMemcpy(c, st->plan_counts.p, sizeof(c), hipMemcpyDeviceToHost));
     info->n_items = c[0];
     info->n_chunk_slots = c[1];
+  }
+  info->n_actor_items = 0;
+  info->n_actor_chunk_slots = 0;
+  if (st->n_apairs > 0) {
+    uint32_t c[2] = {0, 0};
+    DV_TRY_HIP(hipMemcpy(c, st->aplan_counts.p, sizeof(c), hipMemcpyDeviceToHost));
+    info->n_actor_items = c[0];
+    info->n_actor_chunk_slots = c[1];
   }
   return DV_OK;
 }

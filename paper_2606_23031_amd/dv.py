@@ -18,6 +18,10 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build it with "
         "`python -m paper_2606_23031_amd.build` (hipcc, gfx950)")
+# torch first: the library then binds to the HIP runtime torch brought into
+# the process, so tensors and streams of both are the same runtime's (a
+# second runtime loaded ahead of torch's would see no device in one of them)
+import torch  # noqa: E402,F401
 _lib = C.CDLL(LIB_PATH)
 
 DV_OK = 0
@@ -95,7 +99,8 @@ class dv_state_info(C.Structure):
                 ("n_pairs", C.c_int64), ("n_actor_pairs", C.c_int64),
                 ("n_tiles", C.c_int64), ("key_bits", C.c_int32),
                 ("tile_bits", C.c_int32), ("n_items", C.c_int64),
-                ("n_chunk_slots", C.c_int64)]
+                ("n_chunk_slots", C.c_int64), ("n_actor_items", C.c_int64),
+                ("n_actor_chunk_slots", C.c_int64)]
 
 
 NUM_STAGES = 14

@@ -19,7 +19,7 @@ def _grad_chunk(args):
         o, d = G.camera_ray(ctx.view, px, py)
         AD.ray_adjoint(ctx, o, d, g[0:3], g[3], g[4:7], g[7], acc)
     out = {}
-    for key in ("corner", "corner_abs", "dcol", "dnw"):
+    for key in ("corner", "corner_abs", "dcol", "dcol_abs", "dnw"):
         lst = []
         for arr in acc[key]:
             if arr.size == 0:
@@ -44,7 +44,7 @@ def render_and_grad_parallel(scene, view, opts, grads, pixels, procs):
         parts = pool.map(_grad_chunk, [(pixels[c], grads[c]) for c in chunks])
     acc = AD.new_accumulators(ctx)
     for part in parts:
-        for key in ("corner", "corner_abs", "dcol", "dnw"):
+        for key in ("corner", "corner_abs", "dcol", "dcol_abs", "dnw"):
             for k, (nz, vals) in enumerate(part[key]):
                 acc[key][k][nz] += vals
         for k in range(len(acc["dR"])):

@@ -94,7 +94,8 @@ def actor_scene(seed=0, n_actors=2, deg=1, overlap=False, K=1, bg_levels=(2, 24,
                 opts=opts)
 
 
-def dense_scene(seed=0, n_actors=2, level=5, deg=1):
+def dense_scene(seed=0, n_actors=2, level=5, deg=1, actor_level=None,
+                overlap=False):
     """Background cube [-2,2]^3 fully tiled by (2^level)^3 leaves of low
     density (rays cross all of them), with actor cubes inside: a small view
     whose tile lists exceed the compositing chunk length, so long lists are
@@ -105,10 +106,19 @@ def dense_scene(seed=0, n_actors=2, level=5, deg=1):
     octs = [bg]
     tracks = [None]
     centres = [(-0.6, 0.3, 0.113), (0.7, -0.4, -0.187), (0.1, 0.2, 0.521)]
+    if overlap:
+        centres = [(-0.2, 0.1, 0.013), (0.2, 0.0, 0.117), (0.1, 0.2, 0.521)]
     for i in range(n_actors):
-        a = random_octree(rng, (-0.5, -0.5, -0.5), 1.0, 2, 10, 4, deg,
-                          g_mean=0.5, g_std=1.5,
-                          box=((-0.45, -0.4, -0.35), (0.45, 0.4, 0.35)))
+        if actor_level is None:
+            a = random_octree(rng, (-0.5, -0.5, -0.5), 1.0, 2, 10, 4, deg,
+                              g_mean=0.5, g_std=1.5,
+                              box=((-0.45, -0.4, -0.35), (0.45, 0.4, 0.35)))
+        else:
+            # fully tiled asset, density varying from empty to opaque:
+            # long (tile, actor) lists
+            a = random_octree(rng, (-0.5, -0.5, -0.5), 1.0, actor_level, 0,
+                              actor_level, deg, g_mean=-0.5, g_std=1.5,
+                              box=((-0.45, -0.4, -0.35), (0.45, 0.4, 0.35)))
         octs.append(a)
         c = np.array(centres[i])
         tracks.append(moving_track(0.2 + 0.3 * i, 0.5 + 0.3 * i, c, c + (0.3, 0.1, 0.0)))

@@ -105,10 +105,40 @@ def test_backward_chunked_tiles(ctx):
     # them, the pieces around a segment possibly in different chunks
     cfg = dense_scene(seed=1, deg=1)
     acc, pg, ref, _ = _run(ctx, cfg, mask_normals=True, seed=1)
+    _dense_bar(acc, pg, ref)
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_backward_chunked_actor_lists(ctx, overlap):
+    # split (tile, actor) lists: chunk-local asset walks with W_c / R_c of
+    # the segment, single-segment rays per chunk, two-segment rays whole
+    cfg = dense_scene(seed=3, actor_level=4, overlap=overlap)
+    acc, pg, ref, _ = _run(ctx, cfg, mask_normals=True, seed=3)
+    _dense_bar(acc, pg, ref)
+
+
+def _dense_bar(acc, pg, ref):
+    """Scenes whose rays cross thousands of small leaves: each tensor within
+    1e-3 relative in the 2-norm, and every significant element within 1e-2
+    of the sum of |contributions| behind it.  Among thousands of chords some
+    only graze a leaf; a chord of length l at distance t carries a relative
+    FP32 error ~2^-24 t / l (the camera-relative leaf position itself is
+    rounded to that), which reaches 1e-3 for l ~ 5e-4 t and can be the only
+    contribution to a small leaf's gradient.  The elementwise bar is there
+    to catch structural mistakes (a wrong chunk boundary or splice moves an
+    element by its own size), the norm bar holds the tensor to 1e-3."""
+    from test_gpu_fullsize import _close as close_sum
+    worst = {}
     for k in range(len(acc)):
-        _close(f"corner[{k}]", acc[k]["corner"].cpu().numpy(), ref["corner"][k])
-        _close(f"sh[{k}]", acc[k]["sh"].cpu().numpy(), ref["sh"][k])
+        worst[f"corner[{k}]"] = close_sum(f"corner[{k}]", acc[k]["corner"].cpu().numpy(),
+                                          ref["corner"][k], mag=ref["corner_abs"][k],
+                                          rel_elem=1e-2)
+        worst[f"sh[{k}]"] = close_sum(f"sh[{k}]", acc[k]["sh"].cpu().numpy(),
+                                      ref["sh"][k], mag=ref["sh_abs"][k], rel_elem=1e-2)
     p = pg.cpu().numpy()[0]
     for i in range(len(acc) - 1):
-        _close(f"dR[{i}]", p[i, :9].reshape(3, 3), ref["dR"][i + 1])
-        _close(f"dp[{i}]", p[i, 9:], ref["dp"][i + 1])
+        worst[f"dR[{i}]"] = close_sum(f"dR[{i}]", p[i, :9].reshape(3, 3), ref["dR"][i + 1],
+                                      rel_elem=1e-2)
+        worst[f"dp[{i}]"] = close_sum(f"dp[{i}]", p[i, 9:], ref["dp"][i + 1], rel_elem=1e-2)
+    bad = {k: w for k, w in worst.items() if w > 1.0}
+    assert not bad, bad

@@ -119,7 +119,7 @@ def test_c3_crop_gradients(tmp_path):
     # the bar applies per gradient kind over all octrees / actors together:
     # octrees seen only far behind the crop's car carry FP64 gradients of
     # 1e-16 and below, where FP32 transmittance has underflowed to 0
-    gc, rc, mc, gs, rs = [], [], [], [], []
+    gc, rc, mc, gs, rs, ms = [], [], [], [], [], []
     for k, o in enumerate(sub["octrees"]):
         keep = o["_keep"]
         if len(keep) == 0:
@@ -129,9 +129,11 @@ def test_c3_crop_gradients(tmp_path):
         mc.append(ref["corner_abs"][k])
         gs.append(acc[k]["sh"].cpu().numpy()[:, :, keep].ravel())
         rs.append(np.asarray(ref["sh"][k]).ravel())
+        ms.append(np.asarray(ref["sh_abs"][k]).ravel())
     worst = {"corner": _close("corner (all octrees)", np.concatenate(gc), np.concatenate(rc),
                               mag=np.concatenate(mc)),
-             "sh": _close("sh (all octrees)", np.concatenate(gs), np.concatenate(rs))}
+             "sh": _close("sh (all octrees)", np.concatenate(gs), np.concatenate(rs),
+                          mag=np.concatenate(ms))}
     p0 = pg.cpu().numpy()[0]
     refR = np.stack([ref["dR"][i + 1] for i in range(na)])
     refp = np.stack([ref["dp"][i + 1] for i in range(na)])

@@ -115,6 +115,23 @@ def test_chunked_tiles_parity(ctx, eps):
     dv.dv_fwd_state_release(st)
 
 
+@pytest.mark.parametrize("overlap", [False, True])
+def test_chunked_actor_lists_parity(ctx, overlap):
+    # fully tiled assets: (tile, actor) lists of 2.4k-3.7k entries split into
+    # chunks for rays with one segment of the actor; with overlapping boxes
+    # some rays have two segments of one actor and walk the whole list
+    from gpu_helpers import render_gpu
+    from paper_2606_23031_amd import dv
+    cfg = dense_scene(seed=2, actor_level=4, overlap=overlap)
+    v = cfg["views"][0]
+    res, st, _ = render_gpu(ctx, cfg["scene"], [v], cfg["opts"], keep=True)
+    info = dv.dv_fwd_state_info(st)
+    assert info["n_actor_items"] > info["n_actor_pairs"]
+    ref = _oracle(cfg["scene"], v, cfg["opts"])
+    _compare(res[0], ref)
+    dv.dv_fwd_state_release(st)
+
+
 def test_empty_scene_returns_background(ctx):
     from gpu_helpers import render_gpu
     sc = dict(octrees=[empty_octree()], tracks=[None])

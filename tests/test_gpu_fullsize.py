@@ -114,18 +114,20 @@ def test_fullsize_tile_lists_sampled(c2):
     assert n > 100
 
 
-def _close(name, g, ref, rel=1e-3, floor=1e-2, mag=None):
+def _close(name, g, ref, rel=1e-3, floor=1e-2, mag=None, rel_elem=None):
     """Gradient bar at full size (reading of '1e-3 relative on gradients'):
     the tensor as a whole within 1e-3 relative in the 2-norm, and every
     significant element within 1e-3 of its scale.  An element's scale is
     |ref|, or, where given, ``mag``: the oracle's sum of |per-piece
-    contribution| behind it.  A corner gradient is a sum over many pixels
-    of contributions of both signs, each of which carries the FP32 error of
-    its chord ends (~2^-24 t absolute at ray distance t, i.e. 1e-5..1e-4
-    relative for a few-cm leaf 20 m away), so the error of the sum scales
-    with the summands, not with the (possibly cancelled) net value.
-    Significant: scale >= 1e-2 of the largest.  Returns the worse of the
-    two ratios (1 = at the bar)."""
+    contribution| behind it.  A corner or SH gradient is a sum over many
+    pixels of contributions of both signs, each of which carries FP32
+    rounding (for corners also the error of its chord ends, ~2^-24 t
+    absolute at ray distance t, i.e. 1e-5..1e-4 relative for a few-cm leaf
+    20 m away), so the error of the sum scales with the summands, not with
+    the (possibly cancelled) net value.
+    Significant: scale >= 1e-2 of the largest.  ``rel_elem`` (default rel)
+    is the elementwise bar.  Returns the worse of the two ratios (1 = at the
+    bar)."""
     g = np.asarray(g, np.float64).ravel()
     ref = np.asarray(ref, np.float64).ravel()
     sc = np.abs(ref) if mag is None else np.maximum(np.abs(ref), np.asarray(mag, np.float64).ravel())
@@ -136,7 +138,7 @@ def _close(name, g, ref, rel=1e-3, floor=1e-2, mag=None):
     err = np.abs(g - ref)
     norm = np.linalg.norm(g - ref) / np.linalg.norm(ref) / rel
     sig = sc >= floor * scale
-    ratio = err[sig] / (rel * sc[sig])
+    ratio = err[sig] / ((rel if rel_elem is None else rel_elem) * sc[sig])
     i = int(np.argmax(ratio))
     print(f"  {name}: max|ref| {np.abs(ref).max():.3e} max err {err.max():.3e} norm ratio "
           f"{norm:.3f} elementwise ({'|ref|' if mag is None else 'sum|contrib|'} "
@@ -191,7 +193,8 @@ def _crop_grads(c2, k_actor, dx, dy, seed, eps_stop):
             continue
         worst[f"corner[{k}]"] = _close(f"corner[{k}]", acc[k]["corner"].cpu().numpy(),
                                        ref["corner"][k], mag=ref["corner_abs"][k])
-        worst[f"sh[{k}]"] = _close(f"sh[{k}]", acc[k]["sh"].cpu().numpy(), ref["sh"][k])
+        worst[f"sh[{k}]"] = _close(f"sh[{k}]", acc[k]["sh"].cpu().numpy(), ref["sh"][k],
+                                   mag=ref["sh_abs"][k])
     p = pg.cpu().numpy()[0]
     for i in range(na):
         if np.abs(ref["dR"][i + 1]).max() == 0.0:
