@@ -496,6 +496,8 @@ struct dv_fwd_state {
   int key_bits = 0, tile_bits = 0, rank_bits = 0;
   std::vector<uint32_t> act_beg_h, act_oct_h, act_tile_h;
   std::vector<int64_t> seg_start_h;
+  std::vector<int64_t> seg_pstart_h;   // starts padded to multiples of 64
+  std::vector<int32_t> seg_len_h;
   // host copies uploaded asynchronously by backward calls; kept until the
   // state is retired (after its stream has passed them)
   std::vector<std::vector<dv_out_grads>> grads_keep;

@@ -90,11 +90,46 @@ __host__ __device__ inline Rect bin_box(const double A[9], const double b[3],
   return r;
 }
 
+// Conservative pre-test for bin_box: true only when every box inside the
+// ball of radius rad about c (octree frame) is rejected by bin_box.  The
+// ball lies behind Z = 0 (all corners behind: no coverage), or it is
+// farther from the camera than the near radius (the transformed corners'
+// bounding box sits in the cube of half-size rad about the centre, so its
+// distance is at least |X| - sqrt(3) rad) and lies behind the plane Z = e
+// or outside one of the four planes through the camera that bound the
+// window widened by 2 px.  Projected points then fall more than 2 px
+// outside the window, where the pixel rule of bin_box leaves an empty
+// rectangle; rounding of the FP64 corner arithmetic is many orders below
+// that margin.  Requires fx, fy > 0.
+__host__ __device__ inline bool ball_culled(const double A[9], const double b[3],
+                                            const double c[3], double rad,
+                                            double fx, double fy, double cx,
+                                            double cy, int x0, int y0, int w,
+                                            int h, double rnear2) {
+  const double X = ((A[0] * c[0] + A[1] * c[1]) + A[2] * c[2]) + b[0];
+  const double Y = ((A[3] * c[0] + A[4] * c[1]) + A[5] * c[2]) + b[1];
+  const double Z = ((A[6] * c[0] + A[7] * c[1]) + A[8] * c[2]) + b[2];
+  const double r = rad * (1.0 + 1e-6) + 1e-9;
+  if (Z + r < 0.0) return true;
+  const double dist = sqrt((X * X + Y * Y) + Z * Z) - 1.7320508075688772 * r;
+  if (!(dist > sqrt(rnear2) * (1.0 + 1e-6) + 1e-9)) return false;
+  if (Z + r < Z_EPS_D) return true;
+  const double l = cx - (x0 - 2.0), rr = (x0 + w + 2.0) - cx;
+  const double t = cy - (y0 - 2.0), bb = (y0 + h + 2.0) - cy;
+  if (fx * X + l * Z + r * sqrt(fx * fx + l * l) < 0.0) return true;
+  if (-fx * X + rr * Z + r * sqrt(fx * fx + rr * rr) < 0.0) return true;
+  if (fy * Y + t * Z + r * sqrt(fy * fy + t * t) < 0.0) return true;
+  if (-fy * Y + bb * Z + r * sqrt(fy * fy + bb * bb) < 0.0) return true;
+  return false;
+}
+
 struct PreArgs {
   const ViewConst* views;
   const VOConst* vo;
   const OctDev* oct;
-  const int64_t* seg_start;
+  const int64_t* seg_start;   // padded: segments start on multiples of 64
+  const int32_t* seg_len;     // leaves per segment
+  uint64_t* wave_mask;        // visibility ballot per wave (pass 0 -> 1)
   int32_t n_seg;
   int32_t n_oct;
   int64_t n_items;
@@ -112,44 +147,68 @@ struct PreArgs {
   uint64_t* s_rect;
 };
 
+// Segments (view, octree) start on multiples of 64 items, so each wave
+// holds leaves of one segment: the segment search and the per-segment
+// constants are wave-uniform (scalar loads).  Pass 0 stores each wave's
+// visibility ballot and the block counts; pass 1 reads the ballots back,
+// skips invisible waves and bins again only the visible lanes.
 template <int PASS>
 __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
-  __shared__ uint32_t wtot[TPB / 64];
-  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  bool vis = false;
-  int s = 0, vox = 0;
-  Rect r{0, 1, 0, 1, 0};
-  int l = 0, ii = 0, jj = 0, kk = 0;
-  if (t < p.n_items) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t t0 = (int64_t)blockIdx.x * TPB + w * 64;
+  const int64_t wave = (int64_t)blockIdx.x * (TPB / 64) + w;
+  uint64_t m = 0;
+  uint32_t woff = 0;
+  if (PASS == 1) {
+    const uint64_t* bm = p.wave_mask + (int64_t)blockIdx.x * (TPB / 64);
+    for (int i = 0; i < w; ++i) woff += (uint32_t)__popcll(bm[i]);
+    m = bm[w];
+    if (!((m >> lane) & 1ull)) return;
+  }
+  int s = 0;
+  if (t0 < p.n_items) {
     int lo = 0, hi = p.n_seg - 1;
     while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (p.seg_start[mid] <= t) lo = mid; else hi = mid - 1;
+      const int mid = (lo + hi + 1) >> 1;
+      if (p.seg_start[mid] <= t0) lo = mid; else hi = mid - 1;
     }
     s = lo;
-    vox = (int)(t - p.seg_start[s]);
-    const int v = s / p.n_oct, k = s % p.n_oct;
-    const ViewConst& V = p.views[v];
-    const VOConst& C = p.vo[s];
-    const OctDev& O = p.oct[k];
+  }
+  const int vox = (int)(t0 - p.seg_start[s]) + lane;
+  const int v = s / p.n_oct, k = s % p.n_oct;
+  const ViewConst& V = p.views[v];
+  const VOConst& C = p.vo[s];
+  const OctDev& O = p.oct[k];
+  bool vis = false;
+  Rect r{0, 1, 0, 1, 0};
+  int l = 0, ii = 0, jj = 0, kk = 0;
+  if (t0 < p.n_items && vox < p.seg_len[s]) {
     unpack_geo(O.geo[vox], l, ii, jj, kk);
     const double h = ldexp(O.root_size, -l);
-    double blo[3], bhi[3];
+    double blo[3], bhi[3], ctr[3];
     const int ijk[3] = {ii, jj, kk};
     for (int a = 0; a < 3; ++a) {
       blo[a] = O.root_min[a] + (double)ijk[a] * h;
       bhi[a] = O.root_min[a] + (double)(ijk[a] + 1) * h;
+      ctr[a] = O.root_min[a] + ((double)ijk[a] + 0.5) * h;
     }
-    r = bin_box(C.A, C.b, blo, bhi, V.fx, V.fy, V.cx, V.cy, V.x0, V.y0, V.w,
-                V.h, V.rnear2);
-    vis = r.status != 0 && r.xl <= r.xh && r.yl <= r.yh;
+    if (PASS == 1 ||
+        !ball_culled(C.A, C.b, ctr, 0.8660254037844386 * h, V.fx, V.fy, V.cx,
+                     V.cy, V.x0, V.y0, V.w, V.h, V.rnear2)) {
+      r = bin_box(C.A, C.b, blo, bhi, V.fx, V.fy, V.cx, V.cy, V.x0, V.y0,
+                  V.w, V.h, V.rnear2);
+      vis = r.status != 0 && r.xl <= r.xh && r.yl <= r.yh;
+    }
   }
-  const uint64_t m = __ballot(vis);
-  const uint32_t wcount = (uint32_t)__popcll(m);
-  if (lane == 0) wtot[w] = wcount;
-  __syncthreads();
   if (PASS == 0) {
+    __shared__ uint32_t wtot[TPB / 64];
+    m = __ballot(vis);
+    if (lane == 0) {
+      p.wave_mask[wave] = m;
+      wtot[w] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
       uint32_t tot = 0;
       for (int i = 0; i < TPB / 64; ++i) tot += wtot[i];
@@ -157,14 +216,8 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
     }
     return;
   }
-  uint32_t woff = 0;
-  for (int i = 0; i < w; ++i) woff += wtot[i];
-  if (!vis) return;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint32_t slot = p.block_off[blockIdx.x] + woff + (uint32_t)__popcll(m & lt);
-  const int v = s / p.n_oct, k = s % p.n_oct;
-  const VOConst& C = p.vo[s];
-  const OctDev& O = p.oct[k];
   // depth rank: BSP painter's order from the quantised camera position
   const int L = O.max_level;
   const int ijk[3] = {ii, jj, kk};
@@ -1173,7 +1226,16 @@ dv_status setup_state(dv_fwd_state* st, const dv_scene* sc,
         C.boxhi[a] = (float)(bhi[a] - P[a]);
       }
       const size_t sidx = (size_t)v * n_oct + k;
-      const int64_t cnt = active ? sc->desc[k].n_voxels : 0;
+      int64_t cnt = active ? sc->desc[k].n_voxels : 0;
+      if (cnt > 0) {
+        // no leaf of an octree whose root cube is culled can be binned
+        const ViewConst& V = st->views_h[v];
+        double ctr[3];
+        for (int a = 0; a < 3; ++a) ctr[a] = od.root_min[a] + 0.5 * od.root_size;
+        if (ball_culled(C.A, C.b, ctr, 0.8660254037844386 * od.root_size, V.fx,
+                        V.fy, V.cx, V.cy, V.x0, V.y0, V.w, V.h, V.rnear2))
+          cnt = 0;
+      }
       seg_start[sidx + 1] = seg_start[sidx] + cnt;
       items += cnt;
       if (k > 0 && active) {
@@ -1239,22 +1301,34 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   const std::vector<uint32_t>& act_tile = st->act_tile_h;
   const int n_views = st->n_views, n_oct = st->n_oct;
   const dv_render_opts& op = st->opts;
-  const int64_t n_items = seg_start.back();
   const int n_seg = n_views * n_oct;
+  // item space: each segment padded to a multiple of 64 leaves
+  std::vector<int64_t>& pstart = st->seg_pstart_h;
+  std::vector<int32_t>& seg_len = st->seg_len_h;
+  pstart.assign((size_t)n_seg + 1, 0);
+  seg_len.assign((size_t)n_seg, 0);
+  for (int i = 0; i < n_seg; ++i) {
+    seg_len[i] = (int32_t)(seg_start[i + 1] - seg_start[i]);
+    pstart[i + 1] = pstart[i] + ((seg_len[i] + 63) & ~(int64_t)63);
+  }
+  const int64_t n_items = pstart.back();
   // constants
   DV_TRY(alloc_n<ViewConst>(ctx, st->views_d, n_views, s));
   DV_TRY(alloc_n<VOConst>(ctx, st->vo_d, (size_t)n_seg, s));
   DV_TRY(alloc_n<dv_outputs>(ctx, st->outs_d, n_views, s));
-  DBuf segs_d;
-  DV_TRY(alloc_n<int64_t>(ctx, segs_d, seg_start.size(), s));
+  DBuf segs_d, slen_d;
+  DV_TRY(alloc_n<int64_t>(ctx, segs_d, pstart.size(), s));
+  DV_TRY(alloc_n<int32_t>(ctx, slen_d, (size_t)n_seg, s));
   DV_TRY_HIP(hipMemcpyAsync(st->views_d.p, st->views_h.data(),
                             sizeof(ViewConst) * n_views, hipMemcpyHostToDevice, s));
   DV_TRY_HIP(hipMemcpyAsync(st->vo_d.p, st->vo_h.data(),
                             sizeof(VOConst) * n_seg, hipMemcpyHostToDevice, s));
   DV_TRY_HIP(hipMemcpyAsync(st->outs_d.p, outs, sizeof(dv_outputs) * n_views,
                             hipMemcpyHostToDevice, s));
-  DV_TRY_HIP(hipMemcpyAsync(segs_d.p, seg_start.data(),
-                            sizeof(int64_t) * seg_start.size(),
+  DV_TRY_HIP(hipMemcpyAsync(segs_d.p, pstart.data(),
+                            sizeof(int64_t) * pstart.size(),
+                            hipMemcpyHostToDevice, s));
+  DV_TRY_HIP(hipMemcpyAsync(slen_d.p, seg_len.data(), sizeof(int32_t) * n_seg,
                             hipMemcpyHostToDevice, s));
   // key layout
   int seg_bits = ceil_log2((uint64_t)n_seg);
@@ -1267,7 +1341,8 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   st->tile_bits = ceil_log2((uint64_t)std::max<int64_t>(st->n_tiles, 2));
   // pass 0: visibility counts per block
   const unsigned nblk = grid_for(std::max<int64_t>(n_items, 1), TPB);
-  DBuf bcount, boff, total;
+  DBuf bcount, boff, total, wmask;
+  DV_TRY(alloc_n<uint64_t>(ctx, wmask, (size_t)nblk * (TPB / 64), s));
   DV_TRY(alloc_n<uint32_t>(ctx, bcount, nblk, s));
   DV_TRY(alloc_n<uint32_t>(ctx, boff, nblk, s));
   DV_TRY(alloc_n<uint64_t>(ctx, total, 2, s));
@@ -1277,6 +1352,8 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   pa.vo = st->vo_d.as<VOConst>();
   pa.oct = sc->oct_dev.as<OctDev>();
   pa.seg_start = segs_d.as<int64_t>();
+  pa.seg_len = slen_d.as<int32_t>();
+  pa.wave_mask = wmask.as<uint64_t>();
   pa.n_seg = n_seg;
   pa.n_oct = n_oct;
   pa.n_items = n_items;
