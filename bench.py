@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--v-close", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-saturate", type=int, default=400,
@@ -327,11 +327,24 @@ def main():
     # per-stage device times (HIP events on the stream of each kernel)
     dv.dv_ctx_set_profiling(ctx, dv.PROFILE_EVENTS)
     dv.dv_ctx_stage_times(ctx, reset=True)
+    per_step = []
+    stages = {}
     for _ in range(args.profile_steps):
         step()
-    torch.cuda.synchronize()
-    stages = dv.dv_ctx_stage_times(ctx, reset=True)
-    counters = stages.pop("_counters")
+        torch.cuda.synchronize()
+        st = dv.dv_ctx_stage_times(ctx, reset=True)
+        st.pop("_counters")
+        per_step.append({k: v[0] for k, v in st.items() if v[1] > 0})
+        for k, v in st.items():
+            acc = stages.setdefault(k, [0.0, 0])
+            acc[0] += v[0]
+            acc[1] += v[1]
+    spread = {}
+    for k in stages:
+        if stages[k][1] == 0:
+            continue
+        xs = np.array([d.get(k, 0.0) for d in per_step])
+        spread[k] = [round(float(np.percentile(xs, q)), 4) for q in (50, 10, 90)]
     # work counters in a separate, untimed step
     dv.dv_ctx_set_profiling(ctx, dv.PROFILE_COUNTERS)
     step()
@@ -370,6 +383,7 @@ def main():
         "roofline": rl,
         "stages_ms_per_step": {k: round(v[0] / args.profile_steps, 4)
                                for k, v in stages.items() if v[1] > 0},
+        "stages_ms_p50_p10_p90": spread,
     }
     if args.serve_requests > 0 and args.config == 2:
         sv = serve_views(args.serve_requests, seed=4)

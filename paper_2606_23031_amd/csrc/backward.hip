@@ -508,7 +508,7 @@ __global__ void __launch_bounds__(TPB) k_actor_prep(CompArgs a) {
 // own totals and tails); end points of segments on box faces go to the
 // segment for part 4.
 template <bool NORMALS, int KC>
-__global__ void __launch_bounds__(TPB) k_actor_bwd(CompArgs a) {
+__global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
   __shared__ BwdBatch B;
   __shared__ float red[(TPB / 64) * 12];
   if (blockIdx.x >= a.aplan_counts[0]) return;
@@ -592,13 +592,78 @@ __global__ void __launch_bounds__(TPB) k_actor_bwd(CompArgs a) {
       const size_t qi = seg_index(seg0 + i, tid);
       if ((int)(a.seg_meta[qi] & 0xFF) == j && a.seg_bw[qi].x >= 0.0f) qlast = i;
     }
-    auto live = [&]() { return has && !(qdone && q == qlast); };
+    // a lane whose chord reached past its single segment is finished (fast
+    // path below)
+    bool fin = false;
+    auto live = [&]() { return has && !fin && !(qdone && q == qlast); };
     const uint2 sub = a.act_sub[a_beg + j];
     uint32_t cb = sub.x, ce = sub.y;
     if (nck > 1) chunk_range(sub.x, sub.y, nck, chunk, cb, ce);
     // entries this lane walks, and the block's loop range
     const uint32_t wlo = simple ? cb : sub.x, whi = simple ? ce : sub.y;
     const uint32_t lo = any_full ? sub.x : cb, hi = any_full ? sub.y : ce;
+    // waves in which no ray has several segments of this actor walk without
+    // segment advances (as in the forward); their end-point derivatives on
+    // the segment (one piece each) are kept in registers until the end
+    const bool single = __ballot(nj > 1) == 0;
+    float bz = 0.0f, bw_ = 0.0f;
+    bool hz = false, hw = false;
+    // gradients of the piece [pa, pb) of entry r in segment q (chord
+    // [t0, t1) entering and leaving through axes ax0, ax1)
+    auto piece = [&](uint32_t r, const float4& geo, float t0, float t1, int ax0,
+                     int ax1, float pa, float pb, float3& dcol, float3& dnrm,
+                     float* dg) {
+      const float4 cn = B.cn[r];
+      PieceDer pd;
+      const float tau = piece_eval<2, KC>(geo, B.ga[r], B.gb[r], cn.w, dj, pa,
+                                          pb, K, invK, a.c, a.inv_c, &pd);
+      ++n_piece;
+      const float e = fast_exp(-tau);
+      const float wl = Tl * opacity(tau, e);
+      const float4 nr = B.nrm[r];
+      const float mid = 0.5f * (pa + pb);
+      float vi = GC.x * cn.x + GC.y * cn.y + GC.z * cn.z + GD * mid;
+      if (NORMALS) vi += GN.x * nr.x + GN.y * nr.y + GN.z * nr.z;
+      const float wlt = Tl < T_REBASE ? wl : 0.0f;
+      Pl = fmaf(wl, vi, Pl);
+      PlT = fmaf(wlt, vi, PlT);
+      Tl *= e;
+      const float Sl = Tl < T_REBASE ? VqT - PlT : Vq - Pl;
+      const float dtau = Tpre * Tl * vi - (Tpre * Sl + Saft);
+      const float wt = Tpre * wl;
+      dcol.x += wt * GC.x; dcol.y += wt * GC.y; dcol.z += wt * GC.z;
+      if (NORMALS) {
+        dnrm.x += wt * GN.x; dnrm.y += wt * GN.y; dnrm.z += wt * GN.z;
+      }
+      add_corner_grads<KC>(pd, dtau, dg);
+      if (a.pose_grad) {
+        go.x = fmaf(dtau, pd.dx.x, go.x);
+        go.y = fmaf(dtau, pd.dx.y, go.y);
+        go.z = fmaf(dtau, pd.dx.z, go.z);
+        gd.x = fmaf(dtau, pd.dxt.x, gd.x);
+        gd.y = fmaf(dtau, pd.dxt.y, gd.y);
+        gd.z = fmaf(dtau, pd.dxt.z, gd.z);
+        const float ga_ = dtau * pd.dtda + 0.5f * wt * GD;
+        const float gb_ = dtau * pd.dtdb + 0.5f * wt * GD;
+        if (qs > t0) {
+          if (single) { bz += ga_; hz = true; }
+          else a.seg_bw[seg_index(seg0 + q, tid)].z += ga_;
+        } else {
+          const float di = get_axis(dj, ax0);
+          add_axis(go, ax0, -ga_ / di);
+          add_axis(gd, ax0, -ga_ * pa / di);
+        }
+        if (qe < t1) {
+          if (single) { bw_ += gb_; hw = true; }
+          else a.seg_bw[seg_index(seg0 + q, tid)].w += gb_;
+        } else {
+          const float di = get_axis(dj, ax1);
+          add_axis(go, ax1, -gb_ / di);
+          add_axis(gd, ax1, -gb_ * pb / di);
+        }
+      }
+      if (Tl < a.eps) qdone = true;
+    };
     for (uint32_t base = lo; base < hi; base += TPB) {
       const uint32_t nb = min((uint32_t)TPB, hi - base);
       load_bwd_batch(B, a, base, nb);
@@ -621,7 +686,14 @@ __global__ void __launch_bounds__(TPB) k_actor_bwd(CompArgs a) {
                     make_float3(geo.x + geo.w, geo.y + geo.w, geo.z + geo.w),
                     inv, t0, t1, ax0, ax1);
           ++n_test;
-          if (t1 > t0 && t1 > qs) {
+          if (single) {
+            const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
+            if (pb > pa) {
+              piece(r, geo, t0, t1, ax0, ax1, pa, pb, dcol, dnrm, dg);
+              hit = true;
+            }
+            if (t1 > t0 && t1 > qs && (qe <= t0 || t1 > qe)) fin = true;
+          } else if (t1 > t0 && t1 > qs) {
             while (true) {
               if (qe <= t0) {
                 q = next_q(q + 1);
@@ -631,56 +703,8 @@ __global__ void __launch_bounds__(TPB) k_actor_bwd(CompArgs a) {
               }
               const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
               if (pb > pa && !qdone) {
-                const float4 cn = B.cn[r];
-                PieceDer pd;
-                const float tau = piece_eval<2, KC>(geo, B.ga[r], B.gb[r], cn.w,
-                                                    dj, pa, pb, K, invK, a.c,
-                                                    a.inv_c, &pd);
-                ++n_piece;
-                const float e = fast_exp(-tau);
-                const float wl = Tl * opacity(tau, e);
-                const float4 nr = B.nrm[r];
-                const float mid = 0.5f * (pa + pb);
-                float vi = GC.x * cn.x + GC.y * cn.y + GC.z * cn.z + GD * mid;
-                if (NORMALS) vi += GN.x * nr.x + GN.y * nr.y + GN.z * nr.z;
-                const float wlt = Tl < T_REBASE ? wl : 0.0f;
-                Pl = fmaf(wl, vi, Pl);
-                PlT = fmaf(wlt, vi, PlT);
-                Tl *= e;
-                const float Sl = Tl < T_REBASE ? VqT - PlT : Vq - Pl;
-                const float dtau = Tpre * Tl * vi - (Tpre * Sl + Saft);
-                const float wt = Tpre * wl;
+                piece(r, geo, t0, t1, ax0, ax1, pa, pb, dcol, dnrm, dg);
                 hit = true;
-                dcol.x += wt * GC.x; dcol.y += wt * GC.y; dcol.z += wt * GC.z;
-                if (NORMALS) {
-                  dnrm.x += wt * GN.x; dnrm.y += wt * GN.y; dnrm.z += wt * GN.z;
-                }
-                add_corner_grads<KC>(pd, dtau, dg);
-                if (a.pose_grad) {
-                  go.x = fmaf(dtau, pd.dx.x, go.x);
-                  go.y = fmaf(dtau, pd.dx.y, go.y);
-                  go.z = fmaf(dtau, pd.dx.z, go.z);
-                  gd.x = fmaf(dtau, pd.dxt.x, gd.x);
-                  gd.y = fmaf(dtau, pd.dxt.y, gd.y);
-                  gd.z = fmaf(dtau, pd.dxt.z, gd.z);
-                  const float ga_ = dtau * pd.dtda + 0.5f * wt * GD;
-                  const float gb_ = dtau * pd.dtdb + 0.5f * wt * GD;
-                  if (qs > t0) {
-                    a.seg_bw[seg_index(seg0 + q, tid)].z += ga_;
-                  } else {
-                    const float di = get_axis(dj, ax0);
-                    add_axis(go, ax0, -ga_ / di);
-                    add_axis(gd, ax0, -ga_ * pa / di);
-                  }
-                  if (qe < t1) {
-                    a.seg_bw[seg_index(seg0 + q, tid)].w += gb_;
-                  } else {
-                    const float di = get_axis(dj, ax1);
-                    add_axis(go, ax1, -gb_ / di);
-                    add_axis(gd, ax1, -gb_ * pb / di);
-                  }
-                }
-                if (Tl < a.eps) qdone = true;
               }
               if (t1 > qe) { qe = t0; continue; }
               break;
@@ -692,6 +716,11 @@ __global__ void __launch_bounds__(TPB) k_actor_bwd(CompArgs a) {
       }
       flush_batch(B, a, nb);
       if (!__syncthreads_or(live())) break;
+    }
+    if (hz || hw) {
+      float4* sb = a.seg_bw + seg_index(seg0 + q, tid);
+      if (hz) sb->z += bz;
+      if (hw) sb->w += bw_;
     }
     if (a.pose_grad) {
       float p12[12];

@@ -738,9 +738,40 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
     const float2 se = a.seg_se[seg_index(seg0 + q, tid)];
     qs = se.x; qe = se.y;
   }
+  // a lane whose chord reached past its single segment is finished (fast
+  // path below)
+  bool fin = false;
   // once the last segment of the actor is done (T below the stop threshold)
   // the lane has nothing left in this list
-  auto live = [&]() { return has && !(qdone && q == qlast); };
+  auto live = [&]() { return has && !fin && !(qdone && q == qlast); };
+  // composite the piece [pa, pb) of entry r into segment q's partial state
+  auto piece = [&](uint32_t r, const float4& geo, float pa, float pb) {
+    const float4 cn = B.cn[r];
+    const float tau = piece_tau<KC>(geo, B.ga[r], B.gb[r], cn.w, dj, pa, pb, K,
+                                    invK, a.c, a.inv_c);
+    ++n_piece;
+    const float e_ = fast_exp(-tau);
+    const float wgt = p1.w * opacity(tau, e_);
+    const float wt = p1.w < T_REBASE ? wgt : 0.0f;
+    const float mid = 0.5f * (pa + pb);
+    p0.x = fmaf(wgt, cn.x, p0.x); t0s.x = fmaf(wt, cn.x, t0s.x);
+    p0.y = fmaf(wgt, cn.y, p0.y); t0s.y = fmaf(wt, cn.y, t0s.y);
+    p0.z = fmaf(wgt, cn.z, p0.z); t0s.z = fmaf(wt, cn.z, t0s.z);
+    p0.w = fmaf(wgt, mid, p0.w); t0s.w = fmaf(wt, mid, t0s.w);
+    if (NORMALS) {
+      const float4 nr = B.nrm[r];
+      p1.x = fmaf(wgt, nr.x, p1.x); t1s.x = fmaf(wt, nr.x, t1s.x);
+      p1.y = fmaf(wgt, nr.y, p1.y); t1s.y = fmaf(wt, nr.y, t1s.y);
+      p1.z = fmaf(wgt, nr.z, p1.z); t1s.z = fmaf(wt, nr.z, t1s.z);
+    }
+    p1.w *= e_;
+    if (p1.w < a.eps) qdone = true;
+  };
+  // waves in which no ray has several segments of this actor (boxes that do
+  // not overlap along the ray) take a walk without segment advances: the
+  // piece is the chord clipped to [qs, qe), and a chord reaching past qe
+  // ends the lane (later entries lie farther along the ray)
+  const bool single = __ballot(nj > 1) == 0;
   for (uint32_t base = lo; base < hi; base += TPB) {
     const uint32_t nb = min((uint32_t)TPB, hi - base);
     load_batch(B, a, base, nb);
@@ -749,6 +780,22 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
     wave_entry_masks(B.rect, nb, bx, by, wm);
     for (int c = 0; c < 4; ++c) {
       uint64_t m = wm[c];
+      if (single) {
+        while (m != 0 && __ballot(live()) != 0) {
+          const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
+          m &= m - 1;
+          if (live() && base + r >= wlo && base + r < whi) {
+            const float4 geo = B.geo[r];
+            float t0, t1;
+            slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+            ++n_test;
+            const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
+            if (pb > pa) piece(r, geo, pa, pb);
+            if (t1 > t0 && t1 > qs && (qe <= t0 || t1 > qe)) fin = true;
+          }
+        }
+        continue;
+      }
       while (m != 0 && __ballot(live()) != 0) {
         const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
         m &= m - 1;
@@ -772,28 +819,7 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
             continue;
           }
           const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
-          if (pb > pa && !qdone) {
-            const float4 cn = B.cn[r];
-            const float tau = piece_tau<KC>(geo, B.ga[r], B.gb[r], cn.w, dj, pa,
-                                            pb, K, invK, a.c, a.inv_c);
-            ++n_piece;
-            const float e_ = fast_exp(-tau);
-            const float wgt = p1.w * opacity(tau, e_);
-            const float wt = p1.w < T_REBASE ? wgt : 0.0f;
-            const float mid = 0.5f * (pa + pb);
-            p0.x = fmaf(wgt, cn.x, p0.x); t0s.x = fmaf(wt, cn.x, t0s.x);
-            p0.y = fmaf(wgt, cn.y, p0.y); t0s.y = fmaf(wt, cn.y, t0s.y);
-            p0.z = fmaf(wgt, cn.z, p0.z); t0s.z = fmaf(wt, cn.z, t0s.z);
-            p0.w = fmaf(wgt, mid, p0.w); t0s.w = fmaf(wt, mid, t0s.w);
-            if (NORMALS) {
-              const float4 nr = B.nrm[r];
-              p1.x = fmaf(wgt, nr.x, p1.x); t1s.x = fmaf(wt, nr.x, t1s.x);
-              p1.y = fmaf(wgt, nr.y, p1.y); t1s.y = fmaf(wt, nr.y, t1s.y);
-              p1.z = fmaf(wgt, nr.z, p1.z); t1s.z = fmaf(wt, nr.z, t1s.z);
-            }
-            p1.w *= e_;
-            if (p1.w < a.eps) qdone = true;
-          }
+          if (pb > pa && !qdone) piece(r, geo, pa, pb);
           if (t1 > qe) {  // chord continues into a later segment of j
             qe = t0;      // forces the store-and-advance branch above
             continue;
