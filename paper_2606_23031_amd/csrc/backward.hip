@@ -790,15 +790,34 @@ __global__ void __launch_bounds__(TPB) k_box_bwd(CompArgs a) {
 }
 
 // ------------------------------------------------------------------ records
+// SH gradient of one record, added to the [S][3][N] accumulator by plain
+// read-modify-write (the caller guarantees one record per leaf and launch);
+// all loads of a channel are issued before its stores.
+template <int S>
+__device__ inline void sh_grad_rmw(float* gsh, int N, uint32_t vox,
+                                   const float* Y, const float* mc) {
+  const int64_t N3 = 3 * (int64_t)N;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    if (mc[ch] == 0.0f) continue;
+    float* gp = gsh + (int64_t)ch * N + vox;
+    float old[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) old[q] = gp[q * N3];
+#pragma unroll
+    for (int q = 0; q < S; ++q) gp[q * N3] = old[q] + Y[q] * mc[ch];
+  }
+}
+
 template <bool POSE>
 __global__ void __launch_bounds__(TPB)
-k_record_bwd(int64_t n, const uint32_t* rseg, const uint32_t* rvox,
+k_record_bwd(int64_t off, int64_t n, const uint32_t* rseg, const uint32_t* rvox,
              const float4* rgeo, const float4* rcn, const float4* rg8a,
              const float4* rg8b, const float4* gcol, const float4* gnrm,
              const float4* gg8a, const float4* gg8b, const OctDev* oct,
              const OctGrad* og, const VOConst* vo, int n_oct, int n_actors,
              float* pose_grad, bool normals) {
-  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const int64_t i = off + (int64_t)blockIdx.x * TPB + threadIdx.x;
   float p12[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) p12[c] = 0.0f;
@@ -823,13 +842,20 @@ k_record_bwd(int64_t n, const uint32_t* rseg, const uint32_t* rvox,
     const float mc[3] = {cn.x > 0.0f ? dc.x : 0.0f, cn.y > 0.0f ? dc.y : 0.0f,
                          cn.z > 0.0f ? dc.z : 0.0f};
     const int S = (O.sh_degree + 1) * (O.sh_degree + 1);
-    if (G.sh && (mc[0] != 0.0f || mc[1] != 0.0f || mc[2] != 0.0f)) {
+    float* const gsh = G.sh;
+    float* const gcor = G.corner;
+    const int32_t* const cidx = O.corner_idx;
+    if (gsh && (mc[0] != 0.0f || mc[1] != 0.0f || mc[2] != 0.0f)) {
       float Y[16];
       sh_basis(O.sh_degree, wx, wy, wz, Y);
-      for (int q = 0; q < S; ++q)
-        for (int ch = 0; ch < 3; ++ch)
-          if (mc[ch] != 0.0f)
-            atomicAdd(G.sh + ((int64_t)q * 3 + ch) * N + vox, Y[q] * mc[ch]);
+      // one launch covers the records of one view, where a leaf has at most
+      // one record: plain read-modify-write, coalesced over consecutive leaves
+      switch (O.sh_degree) {
+        case 0: sh_grad_rmw<1>(gsh, N, vox, Y, mc); break;
+        case 1: sh_grad_rmw<4>(gsh, N, vox, Y, mc); break;
+        case 2: sh_grad_rmw<9>(gsh, N, vox, Y, mc); break;
+        default: sh_grad_rmw<16>(gsh, N, vox, Y, mc); break;
+      }
     }
     if (POSE && k > 0 && (mc[0] != 0.0f || mc[1] != 0.0f || mc[2] != 0.0f)) {
       float gx[16], gy[16], gz[16];
@@ -890,10 +916,14 @@ k_record_bwd(int64_t n, const uint32_t* rseg, const uint32_t* rvox,
         }
       }
     }
-    if (G.corner) {
-      for (int m = 0; m < 8; ++m)
-        if (dg[m] != 0.0f)
-          atomicAdd(G.corner + O.corner_idx[(int64_t)m * N + vox], dg[m]);
+    if (gcor && (dg[0] != 0.0f || dg[1] != 0.0f || dg[2] != 0.0f ||
+                     dg[3] != 0.0f || dg[4] != 0.0f || dg[5] != 0.0f ||
+                     dg[6] != 0.0f || dg[7] != 0.0f)) {
+      int32_t ci[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) ci[m] = cidx[(int64_t)m * N + vox];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) atomicAdd(gcor + ci[m], dg[m]);
     }
   }
   if (!POSE) return;
@@ -1075,27 +1105,19 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   }
   tm_clear.stop();
   StageTimer tm_rec(ctx, ST_RECORD_BWD, s);
-  if (nv > 0) {
-    if (ca.pose_grad)
-      hipLaunchKernelGGL(k_record_bwd<true>, dim3(grid_for(nv, TPB)), dim3(TPB),
-                         0, s, nv, st->rec_seg.as<uint32_t>(),
-                         st->rec_vox.as<uint32_t>(), st->rec_geo.as<float4>(),
-                         st->rec_cn.as<float4>(), st->rec_g8a.as<float4>(),
-                         st->rec_g8b.as<float4>(), gcol.as<float4>(),
-                         gnrm.as<float4>(), gg8a.as<float4>(), gg8b.as<float4>(),
-                         scene->oct_dev.as<OctDev>(), ogd.as<OctGrad>(),
-                         st->vo_d.as<VOConst>(), n_oct, st->n_actors,
-                         ca.pose_grad, normals);
-    else
-      hipLaunchKernelGGL(k_record_bwd<false>, dim3(grid_for(nv, TPB)), dim3(TPB),
-                         0, s, nv, st->rec_seg.as<uint32_t>(),
-                         st->rec_vox.as<uint32_t>(), st->rec_geo.as<float4>(),
-                         st->rec_cn.as<float4>(), st->rec_g8a.as<float4>(),
-                         st->rec_g8b.as<float4>(), gcol.as<float4>(),
-                         gnrm.as<float4>(), gg8a.as<float4>(), gg8b.as<float4>(),
-                         scene->oct_dev.as<OctDev>(), ogd.as<OctGrad>(),
-                         st->vo_d.as<VOConst>(), n_oct, st->n_actors,
-                         (float*)nullptr, normals);
+  // one launch per view (a leaf has at most one record per view)
+  for (int v = 0; v < st->n_views && nv > 0; ++v) {
+    const int64_t r0 = (int64_t)st->view_slot_h[v], r1 = (int64_t)st->view_slot_h[v + 1];
+    if (r1 <= r0) continue;
+    auto kr = ca.pose_grad ? k_record_bwd<true> : k_record_bwd<false>;
+    hipLaunchKernelGGL(kr, dim3(grid_for(r1 - r0, TPB)), dim3(TPB), 0, s, r0, r1,
+                       st->rec_seg.as<uint32_t>(), st->rec_vox.as<uint32_t>(),
+                       st->rec_geo.as<float4>(), st->rec_cn.as<float4>(),
+                       st->rec_g8a.as<float4>(), st->rec_g8b.as<float4>(),
+                       gcol.as<float4>(), gnrm.as<float4>(), gg8a.as<float4>(),
+                       gg8b.as<float4>(), scene->oct_dev.as<OctDev>(),
+                       ogd.as<OctGrad>(), st->vo_d.as<VOConst>(), n_oct,
+                       st->n_actors, ca.pose_grad, normals);
     DV_TRY_HIP(hipGetLastError());
   }
   return DV_OK;

@@ -498,6 +498,7 @@ struct dv_fwd_state {
   std::vector<int64_t> seg_start_h;
   std::vector<int64_t> seg_pstart_h;   // starts padded to multiples of 64
   std::vector<int32_t> seg_len_h;
+  std::vector<uint64_t> view_slot_h;   // first record slot per view, total last
   // host copies uploaded asynchronously by backward calls; kept until the
   // state is retired (after its stream has passed them)
   std::vector<std::vector<dv_out_grads>> grads_keep;

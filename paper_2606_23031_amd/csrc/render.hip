@@ -1309,14 +1309,44 @@ dv_status setup_state(dv_fwd_state* st, const dv_scene* sc,
 
 // One pinned host word per calling thread for device->host counts, so
 // concurrent renders on different streams never wait for each other.
-static uint64_t* pinned_word() {
+static uint64_t* pinned_words(size_t n) {
   static thread_local uint64_t* w = nullptr;
-  if (!w && hipHostMalloc((void**)&w, 64, hipHostMallocDefault) != hipSuccess) {
-    (void)hipGetLastError();
-    set_error("pinned host allocation failed");
+  static thread_local size_t cap = 0;
+  if (n > cap) {
+    if (w) (void)hipHostFree(w);
     w = nullptr;
+    cap = 0;
+    const size_t want = std::max<size_t>(n, 8);
+    if (hipHostMalloc((void**)&w, want * sizeof(uint64_t), hipHostMallocDefault) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      set_error("pinned host allocation failed");
+      w = nullptr;
+      return nullptr;
+    }
+    cap = want;
   }
   return w;
+}
+static uint64_t* pinned_word() { return pinned_words(1); }
+
+// First record slot of every view (records are in slot order: view,
+// octree, leaf), and the record total at index n_views.  A view's first
+// item starts a wave, so its slot is the block offset plus the ballots of
+// the block's earlier waves.
+__global__ void k_view_slots(int n_views, int n_oct, const int64_t* pstart,
+                             int64_t n_items, const uint32_t* block_off,
+                             const uint64_t* wave_mask, const uint64_t* total,
+                             uint64_t* out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > n_views) return;
+  const int64_t it = v < n_views ? pstart[(size_t)v * n_oct] : n_items;
+  if (it >= n_items) { out[v] = total[0]; return; }
+  const int64_t b = it / TPB;
+  const int w = (int)((it / 64) % (TPB / 64));
+  uint64_t sl = block_off[b];
+  for (int i = 0; i < w; ++i) sl += (uint64_t)__popcll(wave_mask[b * (TPB / 64) + i]);
+  out[v] = sl;
 }
 
 // Enqueue the whole forward pass on stream s.  Two host synchronisations
@@ -1367,7 +1397,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   st->tile_bits = ceil_log2((uint64_t)std::max<int64_t>(st->n_tiles, 2));
   // pass 0: visibility counts per block
   const unsigned nblk = grid_for(std::max<int64_t>(n_items, 1), TPB);
-  DBuf bcount, boff, total, wmask;
+  DBuf bcount, boff, total, wmask, vslot;
   DV_TRY(alloc_n<uint64_t>(ctx, wmask, (size_t)nblk * (TPB / 64), s));
   DV_TRY(alloc_n<uint32_t>(ctx, bcount, nblk, s));
   DV_TRY(alloc_n<uint32_t>(ctx, boff, nblk, s));
@@ -1395,15 +1425,23 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
     DV_TRY_HIP(hipGetLastError());
     DV_TRY(exclusive_scan_u32(ctx, bcount.as<uint32_t>(), boff.as<uint32_t>(),
                               total.as<uint64_t>(), nblk, s));
+    DV_TRY(alloc_n<uint64_t>(ctx, vslot, (size_t)n_views + 1, s));
+    hipLaunchKernelGGL(k_view_slots, dim3(grid_for(n_views + 1, TPB)), dim3(TPB),
+                       0, s, n_views, n_oct, segs_d.as<int64_t>(), n_items,
+                       boff.as<uint32_t>(), wmask.as<uint64_t>(),
+                       total.as<uint64_t>(), vslot.as<uint64_t>());
+    DV_TRY_HIP(hipGetLastError());
   }
   uint64_t n_vis = 0;
   {
-    uint64_t* pin = pinned_word();
+    uint64_t* pin = pinned_words((size_t)n_views + 1);
     if (!pin) return DV_ERR_OOM;
     StageTimer tm(ctx, ST_HOST_SYNC, s);
-    DV_TRY_HIP(hipMemcpyAsync(pin, total.p, 8, hipMemcpyDeviceToHost, s));
+    DV_TRY_HIP(hipMemcpyAsync(pin, vslot.p, sizeof(uint64_t) * (n_views + 1),
+                              hipMemcpyDeviceToHost, s));
     DV_TRY_HIP(hipStreamSynchronize(s));
-    n_vis = *pin;
+    n_vis = pin[n_views];
+    st->view_slot_h.assign(pin, pin + n_views + 1);
   }
   st->n_vis = (int64_t)n_vis;
   if (n_vis >= 0xFFFFFFFFull) {
