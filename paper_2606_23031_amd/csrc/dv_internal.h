@@ -86,6 +86,13 @@ struct DBuf {
     p = nullptr; bytes = 0;
   }
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+  // non-owning view of part of another buffer
+  void view_of(void* q, size_t n) {
+    reset();
+    pool = nullptr;
+    p = q;
+    bytes = n;
+  }
 };
 
 }  // namespace dv

@@ -28,7 +28,7 @@ struct CompArgs {
   const uint32_t* tile_nck;    // chunks per tile
   const uint32_t* tile_pbase;  // first chunk slot of a tile with nck > 1
   const uint32_t* plan_counts; // [0] items, [1] chunk slots
-  float* chunk_b;          // per (chunk slot, pixel): depth boundary B_c
+  float* chunk_b;          // per (chunk slot, part, pixel): first chord depth
   float4* chunk_part;      // per (chunk slot, pixel): 4 x float4 partials
   float2* chunk_tps;       // backward: per (chunk slot, pixel): T_pre, S_after
   uint32_t* item_work;     // forward: measured work per item
@@ -399,16 +399,26 @@ __device__ inline PixSetup pixel_setup(const CompArgs& a, uint32_t gt, int tid) 
 // chunk before, at its end), the others to chunk c or later.  Chords along
 // one ray are disjoint and in depth order, so this splits the sequential
 // walk exactly.
+// B_c is searched by CB_SPLIT blocks over consecutive parts of the chunk;
+// the first part (in list order) with a chord gives it.
+constexpr int CB_SPLIT = 4;
+__device__ inline float chunk_first(const CompArgs& a, size_t slot, int tid) {
+  const float* p = a.chunk_b + slot * CB_SPLIT * TPB + tid;
+  float b = p[0];
+  for (int q = 1; q < CB_SPLIT; ++q)
+    if (b == F_INF) b = p[(size_t)q * TPB];
+  return b;
+}
 __device__ inline void chunk_bounds(const CompArgs& a, uint32_t gt, uint32_t nck,
                                     uint32_t c, int tid, float& Bc, float& Bn) {
   Bc = -F_INF;
   Bn = F_INF;
   if (nck <= 1) return;
-  const size_t sb = (size_t)a.tile_pbase[gt] * TPB + tid;
+  const size_t pb = a.tile_pbase[gt];
   float m = F_INF;
-  for (uint32_t k = nck - 1; k > c; --k) m = fminf(m, a.chunk_b[sb + (size_t)k * TPB]);
+  for (uint32_t k = nck - 1; k > c; --k) m = fminf(m, chunk_first(a, pb + k, tid));
   Bn = m;
-  if (c > 0) Bc = fminf(m, a.chunk_b[sb + (size_t)c * TPB]);
+  if (c > 0) Bc = fminf(m, chunk_first(a, pb + c, tid));
 }
 
 // Real spherical harmonics up to degree 3 (Sec. 3.1 view-dependent
@@ -513,6 +523,7 @@ struct dv_fwd_state {
   dv::DBuf fin0, fin1, fin2, fin3, seg_t0, seg_t1;
   dv::DBuf order_fwd, order_bwd, item_tile, item_chunk, item_work;
   dv::DBuf tile_nck, tile_ibase, tile_pbase, plan_counts;
+  dv::DBuf host_tables;   // one upload: views, constants, segments, actor CSR
   dv::DBuf chunk_b, chunk_part, act_tile;
   dv::DBuf aorder, aitem_pair, aitem_chunk, pair_nck, pair_ibase, pair_pbase,
       aplan_counts, apart;

@@ -437,8 +437,8 @@ dv_status launch_order_by_weight(int64_t n, const uint32_t* w0, const uint32_t* 
 // item; split tiles keep their partial states in those slots.  The launch
 // order puts the longest chunks first.  counts[0] = items, counts[1] =
 // slots reserved.  The same for the (tile, actor) lists when range is given
-// (range[e] = [first, end) entries).  One block of 1024 threads, each owning
-// a contiguous run of lists.
+// (range[e] = [first, end) entries).  One block of 1024 threads, walking the
+// lists in rounds of 1024 consecutive ones (coalesced) with running totals.
 __global__ void __launch_bounds__(1024) k_plan_items(
     int64_t n_tiles, const uint32_t* start, const uint32_t* bgend,
     const uint2* range, uint32_t chunk_len, uint32_t max_slots,
@@ -452,63 +452,53 @@ __global__ void __launch_bounds__(1024) k_plan_items(
     return range ? range[t].y - range[t].x : bgend[t] - start[t];
   };
   const int tid = threadIdx.x;
-  const int64_t per = (n_tiles + 1023) / 1024;
-  const int64_t t0 = min(n_tiles, (int64_t)tid * per), t1 = min(n_tiles, t0 + per);
   if (tid < 256) cnt[tid] = 0;
-  // slots wanted by this thread's lists
-  uint32_t nsl = 0;
-  for (int64_t t = t0; t < t1; ++t) {
-    const uint32_t k = chunks_of(list_len(t), chunk_len);
-    if (k > 1) nsl += k;
-  }
-  uint32_t n_slots;
-  const uint32_t pb0 = block_scan_1024(nsl, wsum, &n_slots);
-  // chunks granted (a list whose slots would pass max_slots stays whole)
-  uint32_t ni = 0, pb = pb0;
-  for (int64_t t = t0; t < t1; ++t) {
-    const uint32_t k = chunks_of(list_len(t), chunk_len);
-    ni += (k > 1 && pb + k <= max_slots) ? k : 1u;
-    if (k > 1) pb += k;
-  }
-  __syncthreads();
-  uint32_t n_items;
-  uint32_t ib = block_scan_1024(ni, wsum, &n_items);
-  if (tid == 0) { counts[0] = n_items; counts[1] = min(n_slots, max_slots); }
-  const uint32_t ib0 = ib;
-  pb = pb0;
-  for (int64_t t = t0; t < t1; ++t) {
-    const uint32_t len = list_len(t);
-    const uint32_t kw = chunks_of(len, chunk_len);
+  // rounds of 1024 consecutive lists (thread tid: list r0 + tid), running
+  // totals of wanted slots and of items carried from round to round
+  uint32_t pbc = 0, ibc = 0;
+  for (int64_t r0 = 0; r0 < n_tiles; r0 += 1024) {
+    const int64_t t = r0 + tid;
+    const bool in = t < n_tiles;
+    const uint32_t len = in ? list_len(t) : 0u;
+    const uint32_t kw = in ? chunks_of(len, chunk_len) : 0u;
+    uint32_t ts, ti;
+    const uint32_t pb = pbc + block_scan_1024(kw > 1 ? kw : 0u, wsum, &ts);
+    // chunks granted (a list whose slots would pass max_slots stays whole)
     const uint32_t k = (kw > 1 && pb + kw <= max_slots) ? kw : 1u;
-    tile_nck[t] = k;
-    tile_ibase[t] = ib;
-    tile_pbase[t] = pb;
-    for (uint32_t c = 0; c < k; ++c) {
-      uint32_t cb, ce;
-      chunk_range(0, len, k, c, cb, ce);
-      item_tile[ib + c] = (uint32_t)t;
-      item_chunk[ib + c] = c;
-      atomicAdd(&cnt[255 - weight_bucket(ce - cb)], 1u);
+    __syncthreads();
+    const uint32_t ib = ibc + block_scan_1024(in ? k : 0u, wsum, &ti);
+    if (in) {
+      tile_nck[t] = k;
+      tile_ibase[t] = ib;
+      tile_pbase[t] = pb;
+      for (uint32_t c = 0; c < k; ++c) {
+        uint32_t cb, ce;
+        chunk_range(0, len, k, c, cb, ce);
+        item_tile[ib + c] = (uint32_t)t;
+        item_chunk[ib + c] = c;
+        atomicAdd(&cnt[255 - weight_bucket(ce - cb)], 1u);
+      }
     }
-    ib += k;
-    if (kw > 1) pb += kw;
+    pbc += ts;
+    ibc += ti;
+    __syncthreads();
   }
-  __syncthreads();
+  if (tid == 0) { counts[0] = ibc; counts[1] = min(pbc, max_slots); }
   if (tid == 0) {
     uint32_t acc = 0;
     for (int b = 0; b < 256; ++b) { off[b] = acc; acc += cnt[b]; }
   }
   __syncthreads();
-  ib = ib0;
-  for (int64_t t = t0; t < t1; ++t) {
-    const uint32_t k = tile_nck[t];
+  // heaviest first: items by descending weight bucket (each thread reads
+  // back the lists it wrote)
+  for (int64_t t = tid; t < n_tiles; t += 1024) {
+    const uint32_t k = tile_nck[t], ib = tile_ibase[t];
     const uint32_t len = list_len(t);
     for (uint32_t c = 0; c < k; ++c) {
       uint32_t cb, ce;
       chunk_range(0, len, k, c, cb, ce);
       order[atomicAdd(&off[255 - weight_bucket(ce - cb)], 1u)] = ib + c;
     }
-    ib += k;
   }
 }
 
@@ -873,8 +863,9 @@ __global__ void __launch_bounds__(TPB) k_actor_merge(CompArgs a) {
 // entry depth of its first non-empty chord among the chunk's entries.
 __global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a) {
   __shared__ Batch B;
-  if (blockIdx.x >= a.plan_counts[0]) return;
-  const uint32_t k = a.order[blockIdx.x];
+  const uint32_t part = blockIdx.x % CB_SPLIT;
+  if (blockIdx.x / CB_SPLIT >= a.plan_counts[0]) return;
+  const uint32_t k = a.order[blockIdx.x / CB_SPLIT];
   const uint32_t gt = a.item_tile[k], c = a.item_chunk[k];
   const uint32_t nck = a.tile_nck[gt];
   if (nck <= 1 || c == 0) return;
@@ -883,6 +874,13 @@ __global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a) {
   const float3 inv = safe_inv(P.d);
   uint32_t cb, ce;
   chunk_range(a.tile_start[gt], a.tile_bgend[gt], nck, c, cb, ce);
+  {
+    // this block's part of the chunk
+    const uint32_t len = ce - cb;
+    const uint32_t pb = cb + (uint32_t)((uint64_t)len * part / CB_SPLIT);
+    ce = cb + (uint32_t)((uint64_t)len * (part + 1) / CB_SPLIT);
+    cb = pb;
+  }
   float Bc = F_INF;
   bool found = !P.valid;
   for (uint32_t base = cb; base < ce; base += TPB) {
@@ -906,7 +904,7 @@ __global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a) {
     }
     if (__syncthreads_and(found)) break;
   }
-  a.chunk_b[((size_t)a.tile_pbase[gt] + c) * TPB + tid] = Bc;
+  a.chunk_b[(((size_t)a.tile_pbase[gt] + c) * CB_SPLIT + part) * TPB + tid] = Bc;
 }
 
 // Forward, part 3: the background walk of one work item (a tile, or one
@@ -1330,6 +1328,53 @@ static uint64_t* pinned_words(size_t n) {
 }
 static uint64_t* pinned_word() { return pinned_words(1); }
 
+// Pinned staging for the per-call host tables (one per host thread).  An
+// event after each upload guards reuse: the next call waits for it (a call
+// normally synchronises its stream long before).
+struct HostStage {
+  uint8_t* p = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+static HostStage& host_stage() {
+  static thread_local HostStage h;
+  return h;
+}
+static uint8_t* stage_acquire(size_t bytes) {
+  HostStage& h = host_stage();
+  if (h.pending) {
+    (void)hipEventSynchronize(h.ev);
+    h.pending = false;
+  }
+  if (!h.ev && hipEventCreateWithFlags(&h.ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("event creation failed");
+    h.ev = nullptr;
+    return nullptr;
+  }
+  if (bytes > h.cap) {
+    if (h.p) (void)hipHostFree(h.p);
+    h.p = nullptr;
+    h.cap = 0;
+    const size_t want = std::max<size_t>(bytes + bytes / 2, 1 << 16);
+    if (hipHostMalloc((void**)&h.p, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("pinned host allocation failed");
+      h.p = nullptr;
+      return nullptr;
+    }
+    h.cap = want;
+  }
+  return h.p;
+}
+static dv_status stage_release(hipStream_t s) {
+  HostStage& h = host_stage();
+  DV_TRY_HIP(hipEventRecord(h.ev, s));
+  h.pending = true;
+  return DV_OK;
+}
+
 // First record slot of every view (records are in slot order: view,
 // octree, leaf), and the record total at index n_views.  A view's first
 // item starts a wave, so its slot is the block offset plus the ballots of
@@ -1368,24 +1413,37 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
     pstart[i + 1] = pstart[i] + ((seg_len[i] + 63) & ~(int64_t)63);
   }
   const int64_t n_items = pstart.back();
-  // constants
-  DV_TRY(alloc_n<ViewConst>(ctx, st->views_d, n_views, s));
-  DV_TRY(alloc_n<VOConst>(ctx, st->vo_d, (size_t)n_seg, s));
-  DV_TRY(alloc_n<dv_outputs>(ctx, st->outs_d, n_views, s));
+  // host-side tables, uploaded in one copy from pinned staging: views,
+  // (view, octree) constants, output planes, padded segment starts and
+  // lengths, the actor-tile CSR
+  const int64_t nt = st->n_tiles, na = st->n_apairs;
   DBuf segs_d, slen_d;
-  DV_TRY(alloc_n<int64_t>(ctx, segs_d, pstart.size(), s));
-  DV_TRY(alloc_n<int32_t>(ctx, slen_d, (size_t)n_seg, s));
-  DV_TRY_HIP(hipMemcpyAsync(st->views_d.p, st->views_h.data(),
-                            sizeof(ViewConst) * n_views, hipMemcpyHostToDevice, s));
-  DV_TRY_HIP(hipMemcpyAsync(st->vo_d.p, st->vo_h.data(),
-                            sizeof(VOConst) * n_seg, hipMemcpyHostToDevice, s));
-  DV_TRY_HIP(hipMemcpyAsync(st->outs_d.p, outs, sizeof(dv_outputs) * n_views,
-                            hipMemcpyHostToDevice, s));
-  DV_TRY_HIP(hipMemcpyAsync(segs_d.p, pstart.data(),
-                            sizeof(int64_t) * pstart.size(),
-                            hipMemcpyHostToDevice, s));
-  DV_TRY_HIP(hipMemcpyAsync(slen_d.p, seg_len.data(), sizeof(int32_t) * n_seg,
-                            hipMemcpyHostToDevice, s));
+  {
+    const void* src[8] = {st->views_h.data(), st->vo_h.data(), outs,
+                          pstart.data(), seg_len.data(), st->act_beg_h.data(),
+                          st->act_oct_h.data(), act_tile.data()};
+    const size_t len[8] = {sizeof(ViewConst) * n_views, sizeof(VOConst) * n_seg,
+                           sizeof(dv_outputs) * n_views,
+                           sizeof(int64_t) * pstart.size(), sizeof(int32_t) * n_seg,
+                           4 * (size_t)(nt + 1), 4 * (size_t)na, 4 * (size_t)na};
+    DBuf* dst[8] = {&st->views_d, &st->vo_d, &st->outs_d, &segs_d, &slen_d,
+                    &st->act_beg, &st->act_oct, &st->act_tile};
+    size_t off[8], total = 0;
+    for (int i = 0; i < 8; ++i) {
+      off[i] = total;
+      total += (len[i] + 255) & ~(size_t)255;
+    }
+    DV_TRY(alloc_n<uint8_t>(ctx, st->host_tables, total, s));
+    uint8_t* stage = stage_acquire(total);
+    if (!stage) return DV_ERR_OOM;
+    for (int i = 0; i < 8; ++i)
+      if (len[i]) std::memcpy(stage + off[i], src[i], len[i]);
+    DV_TRY_HIP(hipMemcpyAsync(st->host_tables.p, stage, total,
+                              hipMemcpyHostToDevice, s));
+    DV_TRY(stage_release(s));
+    for (int i = 0; i < 8; ++i)
+      dst[i]->view_of(st->host_tables.as<uint8_t>() + off[i], len[i]);
+  }
   // key layout
   int seg_bits = ceil_log2((uint64_t)n_seg);
   st->rank_bits = 3 * sc->max_level_all;
@@ -1548,7 +1606,6 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   pval2.reset();
   // tile directory
   StageTimer tm_dir(ctx, ST_TILE_DIR, s);
-  const int64_t nt = st->n_tiles;
   DV_TRY(alloc_n<uint32_t>(ctx, st->tile_start, nt, s));
   DV_TRY(alloc_n<uint32_t>(ctx, st->tile_end, nt, s));
   DV_TRY(alloc_n<uint32_t>(ctx, st->tile_bgend, nt, s));
@@ -1564,19 +1621,9 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
                      n_oct, st->tile_bgend.as<uint32_t>());
   DV_TRY_HIP(hipGetLastError());
   // actor lists
-  const int64_t na = st->n_apairs;
   DBuf& atile = st->act_tile;
-  DV_TRY(alloc_n<uint32_t>(ctx, st->act_beg, nt + 1, s));
-  DV_TRY(alloc_n<uint32_t>(ctx, st->act_oct, na, s));
   DV_TRY(alloc_n<uint2>(ctx, st->act_sub, na, s));
-  DV_TRY(alloc_n<uint32_t>(ctx, atile, na, s));
-  DV_TRY_HIP(hipMemcpyAsync(st->act_beg.p, st->act_beg_h.data(),
-                            4 * (size_t)(nt + 1), hipMemcpyHostToDevice, s));
   if (na > 0) {
-    DV_TRY_HIP(hipMemcpyAsync(st->act_oct.p, st->act_oct_h.data(), 4 * (size_t)na,
-                              hipMemcpyHostToDevice, s));
-    DV_TRY_HIP(hipMemcpyAsync(atile.p, act_tile.data(), 4 * (size_t)na,
-                              hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_actor_ranges, dim3(grid_for(na, TPB)), dim3(TPB), 0, s,
                        na, atile.as<uint32_t>(), st->act_oct.as<uint32_t>(),
                        st->tile_bgend.as<uint32_t>(), st->tile_end.as<uint32_t>(),
@@ -1595,7 +1642,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   DV_TRY(alloc_n<uint32_t>(ctx, st->tile_ibase, nt, s));
   DV_TRY(alloc_n<uint32_t>(ctx, st->tile_pbase, nt, s));
   DV_TRY(alloc_n<uint32_t>(ctx, st->plan_counts, 2, s));
-  DV_TRY(alloc_n<float>(ctx, st->chunk_b, st->max_slots * TPB, s));
+  DV_TRY(alloc_n<float>(ctx, st->chunk_b, st->max_slots * CB_SPLIT * TPB, s));
   DV_TRY(alloc_n<float4>(ctx, st->chunk_part, st->max_slots * TPB * 4, s));
   DV_TRY(fill_u32(st->item_work.as<uint32_t>(), 0u, st->max_items, s));
   // actor work items: (tile, actor) lists, long ones split into chunks
@@ -1715,7 +1762,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
     const unsigned ni = (unsigned)st->max_items;
     {
       StageTimer tm_ch(ctx, ST_OTHER, s);
-      hipLaunchKernelGGL(k_chunk_bounds, dim3(ni), dim3(TPB), 0, s, ca);
+      hipLaunchKernelGGL(k_chunk_bounds, dim3(ni * CB_SPLIT), dim3(TPB), 0, s, ca);
     }
     {
       StageTimer tm_comp(ctx, ST_COMPOSITE_FWD, s);
