@@ -99,11 +99,52 @@ constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1,0,3,2]
 // permlane swaps, in-row steps DPP, so no exchange goes through LDS.  Must
 // be called wave-uniformly with every lane active; lanes without a hit pass
 // zero contributions.
+// Without normals the 11 live channels (colour, corners) go through a
+// 12-slot version of the same butterfly: 6, 3, then 2 (one pad) and 1
+// values per lane; lane l ends with slot 6 h5 + 3 h4 + 2 h3 + h2 (h_i: bit
+// i of l; h3 = h2 = 1 is the pad).
+template <bool NORMALS>
 __device__ inline void accum_record(BwdBatch& B, uint32_t r, bool hit,
                                     float3 dcol, float3 dnrm,
                                     const float* dg) {
   if (__ballot(hit) == 0) return;
   const int lane = threadIdx.x & 63;
+  if (!NORMALS) {
+    float v[12];
+    v[0] = dcol.x; v[1] = dcol.y; v[2] = dcol.z;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[3 + m] = dg[m];
+    v[11] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[i] = swap32_sum(v[i], v[i + 6]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) v[i] = swap16_sum(v[i], v[i + 3]);
+    v[3] = 0.0f;
+    {
+      const bool up = (lane & 8) != 0;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const float send = up ? v[i] : v[i + 2];
+        const float keep = up ? v[i + 2] : v[i];
+        v[i] = keep + dpp<DPP_ROR8>(send);
+      }
+    }
+    {
+      const bool up = (lane & 4) != 0;
+      const float send = up ? v[0] : v[1];
+      const float keep = up ? v[1] : v[0];
+      v[0] = keep + dpp<DPP_HALF_MIRROR>(send);
+    }
+    v[0] += dpp<DPP_XOR2>(v[0]);
+    v[0] += dpp<DPP_XOR1>(v[0]);
+    const int slot = 6 * ((lane >> 5) & 1) + 3 * ((lane >> 4) & 1) +
+                     2 * ((lane >> 3) & 1) + ((lane >> 2) & 1);
+    const bool pad = (lane & 12) == 12 || slot >= 11;
+    // slots 0-2: colour (channels 0-2), 3-10: corners (channels 6-13)
+    const int ch = slot < 3 ? slot : slot + 3;
+    if ((lane & 3) == 0 && !pad && v[0] != 0.0f) atomicAdd(&B.acc[ch][r], v[0]);
+    return;
+  }
   float v[16];
   v[0] = dcol.x; v[1] = dcol.y; v[2] = dcol.z;
   v[3] = dnrm.x; v[4] = dnrm.y; v[5] = dnrm.z;
@@ -438,7 +479,7 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
             }
           }
         }
-        accum_record(B, r, hit, dcol, dnrm, dg);
+        accum_record<NORMALS>(B, r, hit, dcol, dnrm, dg);
       }
     }
     flush_batch(B, a, nb);
@@ -711,7 +752,7 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
             }
           }
         }
-        accum_record(B, r, hit, dcol, dnrm, dg);
+        accum_record<NORMALS>(B, r, hit, dcol, dnrm, dg);
       }
       }
       flush_batch(B, a, nb);
