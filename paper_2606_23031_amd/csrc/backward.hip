@@ -364,9 +364,11 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
   auto suffix = [&]() { return T < T_REBASE ? VT - PT : V - P_; };
   // composite one piece of entry r and add its colour/normal/corner
   // gradients; returns dL/dtau, the piece's (global) weight in wg
+  // set: the piece's gradients replace dcol/dnrm/dg (the plain walk's one
+  // piece per entry) instead of adding to them
   auto piece_grad = [&](uint32_t r, float tau, const PieceDer& pd, float pa,
                         float pb, float3& dcol, float3& dnrm, float* dg,
-                        float& wg) {
+                        float& wg, bool set) {
     const float4 cn = B.cn[r];
     const float e = fast_exp(-tau);
     const float wgt = T * opacity(tau, e);
@@ -382,11 +384,17 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
     T *= e;
     const float dtau = Tpre * (T * vi - suffix()) - Saft;
     wg = Tpre * wgt;
-    dcol.x += wg * GC.x; dcol.y += wg * GC.y; dcol.z += wg * GC.z;
-    if (NORMALS) {
-      dnrm.x += wg * GN.x; dnrm.y += wg * GN.y; dnrm.z += wg * GN.z;
+    if (set) {
+      dcol = make_float3(wg * GC.x, wg * GC.y, wg * GC.z);
+      if (NORMALS) dnrm = make_float3(wg * GN.x, wg * GN.y, wg * GN.z);
+      set_corner_grads<KC>(pd, dtau, dg);
+    } else {
+      dcol.x += wg * GC.x; dcol.y += wg * GC.y; dcol.z += wg * GC.z;
+      if (NORMALS) {
+        dnrm.x += wg * GN.x; dnrm.y += wg * GN.y; dnrm.z += wg * GN.z;
+      }
+      add_corner_grads<KC>(pd, dtau, dg);
     }
-    add_corner_grads<KC>(pd, dtau, dg);
     if (T < a.eps) done = true;
     return dtau;
   };
@@ -420,6 +428,33 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
     wave_entry_masks(B.rect, nb, bx, by, wm);
     for (int c = 0; c < 4; ++c) {
       uint64_t m = wm[c];
+      if (!wseg) {
+        // plain walk: a lane without a chord (or done) takes the empty piece
+        // a = b = 0, whose tau = 0 leaves T and the sums as they are and
+        // whose gradients are zero, so every lane runs the same code
+        while (m != 0 && __ballot(!done) != 0) {
+          const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
+          m &= m - 1;
+          const float4 geo = B.geo[r];
+          float t0, t1;
+          slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+          n_test += done ? 0u : 1u;
+          t0 = fmaxf(t0, a.tau_near);
+          const bool hit = !done && t1 > t0;
+          if (__ballot(hit) == 0) continue;
+          const float pa = hit ? t0 : 0.0f, pb = hit ? t1 : 0.0f;
+          PieceDer pd;
+          const float tau = piece_eval<1, KC>(geo, B.ga[r], B.gb[r], B.cn[r].w,
+                                              d, pa, pb, K, invK, a.c, a.inv_c,
+                                              &pd);
+          n_piece += hit ? 1u : 0u;
+          float3 dcol, dnrm = make_float3(0, 0, 0);
+          float dg[8], wg;
+          piece_grad(r, tau, pd, pa, pb, dcol, dnrm, dg, wg, true);
+          accum_record<NORMALS>(B, r, hit, dcol, dnrm, dg);
+        }
+        continue;
+      }
       while (m != 0 && __ballot(!done) != 0) {
         const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
         m &= m - 1;
@@ -432,16 +467,7 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
           slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
           ++n_test;
           t0 = fmaxf(t0, a.tau_near);
-          if (t1 > t0 && !wseg) {
-            PieceDer pd;
-            const float tau = piece_eval<1, KC>(geo, B.ga[r], B.gb[r], B.cn[r].w,
-                                                d, t0, t1, K, invK, a.c,
-                                                a.inv_c, &pd);
-            ++n_piece;
-            float wg;
-            piece_grad(r, tau, pd, t0, t1, dcol, dnrm, dg, wg);
-            hit = true;
-          } else if (t1 > t0) {
+          if (t1 > t0) {
             float pa = fmaxf(t0, excl);
             bool a_seg = excl > t0;
             while (pa < t1 && !done) {
@@ -466,7 +492,8 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
                                           K, invK, a.c, a.inv_c, &pd);
               ++n_piece;
               float wg;
-              const float dtau = piece_grad(r, tau, pd, pa, pb, dcol, dnrm, dg, wg);
+              const float dtau =
+                  piece_grad(r, tau, pd, pa, pb, dcol, dnrm, dg, wg, false);
               hit = true;
               if (a_seg && qn > 0)
                 a.seg_bw[seg_index(seg0 + qn - 1, tid)].w +=

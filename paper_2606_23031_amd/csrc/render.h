@@ -357,6 +357,24 @@ __device__ inline void add_corner_grads(const PieceDer& pd, float dtau,
   }
 }
 
+// dg[m] = dtau * d tau / d corner m.
+template <int KC>
+__device__ inline void set_corner_grads(const PieceDer& pd, float dtau,
+                                        float* dg) {
+  if (KC == 1) {
+    const float s = dtau * pd.coef;
+    const float vx = 1.0f - pd.ux, vy = 1.0f - pd.uy, vz = 1.0f - pd.uz;
+    const float s0 = s * vz, s1 = s * pd.uz;
+    const float w00 = vx * vy, w10 = pd.ux * vy, w01 = vx * pd.uy,
+                w11 = pd.ux * pd.uy;
+    dg[0] = s0 * w00; dg[1] = s0 * w10; dg[2] = s0 * w01; dg[3] = s0 * w11;
+    dg[4] = s1 * w00; dg[5] = s1 * w10; dg[6] = s1 * w01; dg[7] = s1 * w11;
+  } else {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) dg[m] = dtau * pd.dg[m];
+  }
+}
+
 template <int KC = 0>
 __device__ inline float piece_tau(float4 geo, float4 ga, float4 gb,
                                   float inv_h, float3 d, float a, float b,
