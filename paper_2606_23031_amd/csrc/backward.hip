@@ -48,17 +48,25 @@ struct BwdBatch {
   float acc[NACC][TPB];
 };
 
+// NORMALS = false: the normal slot carries the leaf's far corner instead.
+template <bool NORMALS>
 __device__ inline void load_bwd_batch(BwdBatch& B, const CompArgs& a,
                                       uint32_t base, uint32_t n) {
   const int tid = threadIdx.x;
   if ((uint32_t)tid < n) {
     const uint32_t r = a.pair_val[base + tid];
+    const float4 geo = a.rec_geo[r];
     B.rid[tid] = r;
-    B.geo[tid] = a.rec_geo[r];
+    B.geo[tid] = geo;
     B.ga[tid] = a.rec_g8a[r];
     B.gb[tid] = a.rec_g8b[r];
     B.cn[tid] = a.rec_cn[r];
-    B.nrm[tid] = a.rec_nrm[r];
+    if (NORMALS) {
+      B.nrm[tid] = a.rec_nrm[r];
+    } else {
+      const float3 hi = leaf_hi(geo);
+      B.nrm[tid] = make_float4(hi.x, hi.y, hi.z, 0.0f);
+    }
     const uint64_t rc = a.rec_rect[r];
     B.rect[tid] = make_uint2((uint32_t)rc, (uint32_t)(rc >> 32));
   }
@@ -328,6 +336,7 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
   const int K = a.K;
   const float invK = 1.0f / (float)K;
   uint32_t n_test = 0, n_piece = 0;
+  uint32_t w_test = 0, w_piece = 0;  // wave-level counts (plain walk)
   const PixGrad g = pixel_grads<NORMALS>(a, P);
   const float3 GC = g.GC, GN = g.GN;
   const float GD = g.GD;
@@ -422,7 +431,7 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
   };
   for (uint32_t base = beg; base < bgend; base += TPB) {
     const uint32_t nb = min((uint32_t)TPB, bgend - base);
-    load_bwd_batch(B, a, base, nb);
+    load_bwd_batch<NORMALS>(B, a, base, nb);
     __syncthreads();
     uint64_t wm[4];
     wave_entry_masks(B.rect, nb, bx, by, wm);
@@ -432,22 +441,25 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
         // plain walk: a lane without a chord (or done) takes the empty piece
         // a = b = 0, whose tau = 0 leaves T and the sums as they are and
         // whose gradients are zero, so every lane runs the same code
-        while (m != 0 && __ballot(!done) != 0) {
+        while (m != 0) {
+          const uint64_t live = __ballot(!done);
+          if (live == 0) break;
           const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
           m &= m - 1;
+          w_test += (uint32_t)__popcll(live);
           const float4 geo = B.geo[r];
           float t0, t1;
-          slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
-          n_test += done ? 0u : 1u;
+          batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
           t0 = fmaxf(t0, a.tau_near);
           const bool hit = !done && t1 > t0;
-          if (__ballot(hit) == 0) continue;
+          const uint64_t hm = __ballot(hit);
+          if (hm == 0) continue;
+          w_piece += (uint32_t)__popcll(hm);
           const float pa = hit ? t0 : 0.0f, pb = hit ? t1 : 0.0f;
           PieceDer pd;
           const float tau = piece_eval<1, KC>(geo, B.ga[r], B.gb[r], B.cn[r].w,
                                               d, pa, pb, K, invK, a.c, a.inv_c,
                                               &pd);
-          n_piece += hit ? 1u : 0u;
           float3 dcol, dnrm = make_float3(0, 0, 0);
           float dg[8], wg;
           piece_grad(r, tau, pd, pa, pb, dcol, dnrm, dg, wg, true);
@@ -464,7 +476,7 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
         if (!done) {
           const float4 geo = B.geo[r];
           float t0, t1;
-          slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+          batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
           ++n_test;
           t0 = fmaxf(t0, a.tau_near);
           if (t1 > t0) {
@@ -516,6 +528,10 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
   while (!done && qn < nseg && a.seg_se[seg_index(seg0 + qn, tid)].x < Bn) {
     splice(qn);
     ++qn;
+  }
+  if ((tid & 63) == 0) {
+    n_test += w_test;
+    n_piece += w_piece;
   }
   count_work(a.counters, 2, n_test, n_piece);
 }
@@ -734,7 +750,7 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
     };
     for (uint32_t base = lo; base < hi; base += TPB) {
       const uint32_t nb = min((uint32_t)TPB, hi - base);
-      load_bwd_batch(B, a, base, nb);
+      load_bwd_batch<NORMALS>(B, a, base, nb);
       __syncthreads();
       uint64_t wm[4];
       wave_entry_masks(B.rect, nb, bx, by, wm);

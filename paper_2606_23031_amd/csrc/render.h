@@ -221,15 +221,37 @@ __device__ inline float trilerp(float4 ga, float4 gb, float ux, float uy,
 
 __device__ inline float clamp01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
 
-// Slab test against an axis-aligned box [lo, lo + h] given relative to the
-// ray origin, with precomputed reciprocal direction.
-__device__ inline void slab(float3 lo, float h, float3 inv, float& t0,
-                            float& t1) {
-  float ax = lo.x * inv.x, bx = (lo.x + h) * inv.x;
-  float ay = lo.y * inv.y, by = (lo.y + h) * inv.y;
-  float az = lo.z * inv.z, bz = (lo.z + h) * inv.z;
+// Slab test against an axis-aligned box [lo, hi] given relative to the ray
+// origin, with precomputed reciprocal direction.
+__device__ inline void slab2(float3 lo, float3 hi, float3 inv, float& t0,
+                             float& t1) {
+  float ax = lo.x * inv.x, bx = hi.x * inv.x;
+  float ay = lo.y * inv.y, by = hi.y * inv.y;
+  float az = lo.z * inv.z, bz = hi.z * inv.z;
   t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fminf(az, bz));
   t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
+}
+// Far corner lo + h of a leaf record (the same FP32 sums wherever formed).
+__device__ inline float3 leaf_hi(const float4& geo) {
+  return make_float3(geo.x + geo.w, geo.y + geo.w, geo.z + geo.w);
+}
+// The box [lo, lo + h].
+__device__ inline void slab(float3 lo, float h, float3 inv, float& t0,
+                            float& t1) {
+  slab2(lo, make_float3(lo.x + h, lo.y + h, lo.z + h), inv, t0, t1);
+}
+// Slab test of batch entry r (far corner from the batch when NORMALS is
+// false, formed here otherwise: identical values).
+template <bool NORMALS, class BatchT>
+__device__ inline void batch_slab(const BatchT& B, uint32_t r, const float4& geo,
+                                  float3 inv, float& t0, float& t1) {
+  const float3 lo = make_float3(geo.x, geo.y, geo.z);
+  if (NORMALS) {
+    slab2(lo, leaf_hi(geo), inv, t0, t1);
+  } else {
+    const float4 hi = B.nrm[r];
+    slab2(lo, make_float3(hi.x, hi.y, hi.z), inv, t0, t1);
+  }
 }
 
 // Same, also reporting the axes that define entry and exit.

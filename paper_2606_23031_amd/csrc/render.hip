@@ -512,20 +512,30 @@ struct Batch {
   uint2 rect[TPB];
 };
 
+// NORMALS = false: the normal slot carries the leaf's far corner instead
+// (see batch_slab).
+template <bool NORMALS>
 __device__ inline void load_batch(Batch& B, const CompArgs& a, uint32_t base,
                                   uint32_t n) {
   const int tid = threadIdx.x;
   if ((uint32_t)tid < n) {
     const uint32_t r = a.pair_val[base + tid];
-    B.geo[tid] = a.rec_geo[r];
+    const float4 geo = a.rec_geo[r];
+    B.geo[tid] = geo;
     B.ga[tid] = a.rec_g8a[r];
     B.gb[tid] = a.rec_g8b[r];
     B.cn[tid] = a.rec_cn[r];
-    B.nrm[tid] = a.rec_nrm[r];
+    if (NORMALS) {
+      B.nrm[tid] = a.rec_nrm[r];
+    } else {
+      const float3 hi = leaf_hi(geo);
+      B.nrm[tid] = make_float4(hi.x, hi.y, hi.z, 0.0f);
+    }
     const uint64_t rc = a.rec_rect[r];
     B.rect[tid] = make_uint2((uint32_t)rc, (uint32_t)(rc >> 32));
   }
 }
+
 
 __device__ inline uint32_t src_code(int slot, int axis) {
   return ((uint32_t)slot << 2) | (uint32_t)axis;
@@ -764,7 +774,7 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
   const bool single = __ballot(nj > 1) == 0;
   for (uint32_t base = lo; base < hi; base += TPB) {
     const uint32_t nb = min((uint32_t)TPB, hi - base);
-    load_batch(B, a, base, nb);
+    load_batch<NORMALS>(B, a, base, nb);
     __syncthreads();
     uint64_t wm[4];
     wave_entry_masks(B.rect, nb, bx, by, wm);
@@ -885,7 +895,7 @@ __global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a) {
   bool found = !P.valid;
   for (uint32_t base = cb; base < ce; base += TPB) {
     const uint32_t nb = min((uint32_t)TPB, ce - base);
-    load_batch(B, a, base, nb);
+    load_batch<false>(B, a, base, nb);
     __syncthreads();
     uint64_t wm[4];
     wave_entry_masks(B.rect, nb, P.bx, P.by, wm);
@@ -897,7 +907,7 @@ __global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a) {
         if (found) continue;
         const float4 geo = B.geo[r];
         float t0, t1;
-        slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+        batch_slab<false>(B, r, geo, inv, t0, t1);
         t0 = fmaxf(t0, a.tau_near);
         if (t1 > t0) { Bc = t0; found = true; }
       }
@@ -933,6 +943,7 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
   const int K = a.K;
   const float invK = 1.0f / (float)K;
   uint32_t n_test = 0, n_piece = 0;
+  uint32_t w_test = 0, w_piece = 0;  // wave-level counts (plain walk)
   const uint32_t a_beg = a.act_beg[gt];
   const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
   const uint32_t seg0 = 3 * a_beg + n_at;
@@ -948,7 +959,6 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
     const float4 cn = B.cn[r];
     const float tau = piece_tau<KC>(geo, B.ga[r], B.gb[r], cn.w, d, pa, pb, K,
                                     invK, a.c, a.inv_c);
-    ++n_piece;
     const float e = fast_exp(-tau);
     const float wgt = T * opacity(tau, e);
     const float wt = T < T_REBASE ? wgt : 0.0f;
@@ -996,26 +1006,40 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
   };
   for (uint32_t base = beg; base < bgend; base += TPB) {
     const uint32_t nb = min((uint32_t)TPB, bgend - base);
-    load_batch(B, a, base, nb);
+    load_batch<NORMALS>(B, a, base, nb);
     __syncthreads();
     uint64_t wm[4];
     wave_entry_masks(B.rect, nb, bx, by, wm);
     for (int c = 0; c < 4; ++c) {
       uint64_t m = wm[c];
+      if (!wseg) {
+        // plain walk; tests and pieces counted from the wave's ballots
+        while (m != 0) {
+          const uint64_t live = __ballot(!done);
+          if (live == 0) break;
+          const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
+          m &= m - 1;
+          w_test += (uint32_t)__popcll(live);
+          const float4 geo = B.geo[r];
+          float t0, t1;
+          batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
+          t0 = fmaxf(t0, a.tau_near);
+          const bool hit = !done && t1 > t0;
+          w_piece += (uint32_t)__popcll(__ballot(hit));
+          if (hit) add_piece(r, geo, t0, t1);
+        }
+        continue;
+      }
       while (m != 0 && __ballot(!done) != 0) {
         const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
         m &= m - 1;
         if (done) continue;
         const float4 geo = B.geo[r];
         float t0, t1;
-        slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+        batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
         ++n_test;
         t0 = fmaxf(t0, a.tau_near);
         if (!(t1 > t0)) continue;
-        if (!wseg) {
-          add_piece(r, geo, t0, t1);
-          continue;
-        }
         float pa = fmaxf(t0, excl);
         while (pa < t1 && !done) {
           if (pa >= ns) {
@@ -1027,6 +1051,7 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
           }
           const float pb = fminf(t1, ns);
           add_piece(r, geo, pa, pb);
+          ++n_piece;
           pa = pb;
         }
       }
@@ -1037,6 +1062,10 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
   while (!done && qn < nseg && a.seg_se[seg_index(seg0 + qn, tid)].x < Bn) {
     splice(qn);
     ++qn;
+  }
+  if ((tid & 63) == 0) {
+    n_test += w_test;
+    n_piece += w_piece;
   }
   count_work(a.counters, 0, n_test, n_piece);
   // measured work (slab tests + 4 per piece, at least 1), the backward's
