@@ -766,9 +766,14 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
           const float4 geo = B.geo[r];
           float t0, t1;
           int ax0, ax1;
-          slab_axes(make_float3(geo.x, geo.y, geo.z),
-                    make_float3(geo.x + geo.w, geo.y + geo.w, geo.z + geo.w),
-                    inv, t0, t1, ax0, ax1);
+          float3 hi;
+          if (NORMALS) {
+            hi = leaf_hi(geo);
+          } else {
+            const float4 h4 = B.nrm[r];
+            hi = make_float3(h4.x, h4.y, h4.z);
+          }
+          slab_axes(make_float3(geo.x, geo.y, geo.z), hi, inv, t0, t1, ax0, ax1);
           ++n_test;
           if (single) {
             const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);

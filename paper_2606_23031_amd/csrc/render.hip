@@ -749,7 +749,6 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
     const float4 cn = B.cn[r];
     const float tau = piece_tau<KC>(geo, B.ga[r], B.gb[r], cn.w, dj, pa, pb, K,
                                     invK, a.c, a.inv_c);
-    ++n_piece;
     const float e_ = fast_exp(-tau);
     const float wgt = p1.w * opacity(tau, e_);
     const float wt = p1.w < T_REBASE ? wgt : 0.0f;
@@ -787,10 +786,13 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
           if (live() && base + r >= wlo && base + r < whi) {
             const float4 geo = B.geo[r];
             float t0, t1;
-            slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+            batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
             ++n_test;
             const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
-            if (pb > pa) piece(r, geo, pa, pb);
+            if (pb > pa) {
+              piece(r, geo, pa, pb);
+              ++n_piece;
+            }
             if (t1 > t0 && t1 > qs && (qe <= t0 || t1 > qe)) fin = true;
           }
         }
@@ -802,7 +804,7 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
         if (!live() || base + r < wlo || base + r >= whi) continue;
         const float4 geo = B.geo[r];
         float t0, t1;
-        slab(make_float3(geo.x, geo.y, geo.z), geo.w, inv, t0, t1);
+        batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
         ++n_test;
         if (!(t1 > t0) || t1 <= qs) continue;
         while (true) {
@@ -819,7 +821,10 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
             continue;
           }
           const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
-          if (pb > pa && !qdone) piece(r, geo, pa, pb);
+          if (pb > pa && !qdone) {
+            piece(r, geo, pa, pb);
+            ++n_piece;
+          }
           if (t1 > qe) {  // chord continues into a later segment of j
             qe = t0;      // forces the store-and-advance branch above
             continue;
