@@ -733,17 +733,19 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
           if (single) { bz += ga_; hz = true; }
           else a.seg_bw[seg_index(seg0 + q, tid)].z += ga_;
         } else {
-          const float di = get_axis(dj, ax0);
-          add_axis(go, ax0, -ga_ / di);
-          add_axis(gd, ax0, -ga_ * pa / di);
+          // entry face on axis ax0: t = (face - o) / d, so divide by d
+          // (times the reciprocal direction the slab test uses)
+          const float u = ga_ * get_axis(inv, ax0);
+          add_axis(go, ax0, -u);
+          add_axis(gd, ax0, -u * pa);
         }
         if (qe < t1) {
           if (single) { bw_ += gb_; hw = true; }
           else a.seg_bw[seg_index(seg0 + q, tid)].w += gb_;
         } else {
-          const float di = get_axis(dj, ax1);
-          add_axis(go, ax1, -gb_ / di);
-          add_axis(gd, ax1, -gb_ * pb / di);
+          const float u = gb_ * get_axis(inv, ax1);
+          add_axis(go, ax1, -u);
+          add_axis(gd, ax1, -u * pb);
         }
       }
       if (Tl < a.eps) qdone = true;
