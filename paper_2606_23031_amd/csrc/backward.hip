@@ -271,9 +271,19 @@ __device__ inline float gdot(const PixGrad& g, float4 c, float4 n) {
          g.GN.x * n.x + g.GN.y * n.y + g.GN.z * n.z;
 }
 
-__global__ void k_seg_bw_init(int64_t n, float4* seg_bw) {
-  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (i < n) seg_bw[i] = make_float4(-1.0f, 0.0f, 0.0f, 0.0f);
+// Backward values of every segment of every pixel in tiles with actor
+// boxes: (-1: not spliced yet, 0, 0, 0).  Only the pixel's own segments
+// are ever read.
+__global__ void __launch_bounds__(TPB) k_seg_bw_init(CompArgs a) {
+  const uint32_t gt = blockIdx.x;
+  const uint32_t a_beg = a.act_beg[gt];
+  const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
+  if (n_at == 0) return;
+  const int tid = threadIdx.x;
+  const uint32_t seg0 = 3 * a_beg + n_at;
+  const int nseg = (int)a.pix_nseg[(size_t)gt * TPB + tid];
+  for (int q = 0; q < nseg; ++q)
+    a.seg_bw[seg_index(seg0 + q, tid)] = make_float4(-1.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // Backward, part 1 (tiles of several chunks): per pixel and chunk, the
@@ -1081,22 +1091,18 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
                             hipMemcpyHostToDevice, s));
   DV_TRY_HIP(hipMemcpyAsync(ogd.p, og.data(), sizeof(OctGrad) * n_oct,
                             hipMemcpyHostToDevice, s));
-  DV_TRY(alloc_n<float4>(ctx, gcol, nv, s));
-  DV_TRY(alloc_n<float4>(ctx, gnrm, nv, s));
-  DV_TRY(alloc_n<float4>(ctx, gg8a, nv, s));
-  DV_TRY(alloc_n<float4>(ctx, gg8b, nv, s));
+  // per-record gradients in one buffer (colour, corners, normal last, so a
+  // render without normals clears three quarters of it)
+  DBuf grec;
+  DV_TRY(alloc_n<float4>(ctx, grec, 4 * (size_t)nv, s));
+  gcol.view_of(grec.as<float4>(), sizeof(float4) * nv);
+  gg8a.view_of(grec.as<float4>() + nv, sizeof(float4) * nv);
+  gg8b.view_of(grec.as<float4>() + 2 * (size_t)nv, sizeof(float4) * nv);
+  gnrm.view_of(grec.as<float4>() + 3 * (size_t)nv, sizeof(float4) * nv);
   StageTimer tm_clear(ctx, ST_BWD_CLEAR, s);
-  DV_TRY(fill_f32(gcol.as<float>(), 0.0f, 4 * nv, s));
-  DV_TRY(fill_f32(gnrm.as<float>(), 0.0f, 4 * nv, s));
-  DV_TRY(fill_f32(gg8a.as<float>(), 0.0f, 4 * nv, s));
-  DV_TRY(fill_f32(gg8b.as<float>(), 0.0f, 4 * nv, s));
+  DV_TRY(fill_f32(grec.as<float>(), 0.0f, (normals ? 16 : 12) * nv, s));
   const size_t nslots = (size_t)3 * st->n_apairs * TPB;
   DV_TRY(alloc_n<float4>(ctx, segbw, nslots, s));
-  if (nslots > 0) {
-    hipLaunchKernelGGL(k_seg_bw_init, dim3(grid_for((int64_t)nslots, TPB)),
-                       dim3(TPB), 0, s, (int64_t)nslots, segbw.as<float4>());
-    DV_TRY_HIP(hipGetLastError());
-  }
   DBuf tps, atps;
   DV_TRY(alloc_n<float2>(ctx, tps, st->max_slots * TPB, s));
   DV_TRY(alloc_n<float2>(ctx, atps, st->max_aslots * TPB, s));
@@ -1171,6 +1177,8 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   ca.apart = st->apart.as<float4>();
   if (nt > 0) {
     const bool k1 = op.K == 1;
+    if (st->n_apairs > 0)
+      hipLaunchKernelGGL(k_seg_bw_init, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
     auto kp = normals ? k_chunk_prep<true> : k_chunk_prep<false>;
     hipLaunchKernelGGL(kp, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
     tm_clear.stop();
