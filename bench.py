@@ -78,6 +78,9 @@ class Step:
                     for o in scene_dict["octrees"]]
         na = len(scene_dict["octrees"]) - 1
         self.pose = torch.zeros(len(views), max(na, 1), 12, device="cuda")
+        # gradient buffers cleared each step by one multi-tensor launch
+        self.zero_list = ([a["corner"] for a in self.acc] +
+                          [a["sh"] for a in self.acc] + [self.pose])
         self.npix = sum(v["w"] * v["h"] for v in views)
         self.last_info = None
 
@@ -89,10 +92,7 @@ class Step:
         for o, t, g in zip(self.outs, self.targets, self.grads):
             torch.sign(o["rgb"] - t, out=g["rgb"])
             g["rgb"].mul_(1.0 / self.npix / 3.0)
-        for a in self.acc:
-            a["corner"].zero_()
-            a["sh"].zero_()
-        self.pose.zero_()
+        torch._foreach_zero_(self.zero_list)
         dv.dv_render_backward(self.ctx, self.sc, st, self.grads, self.acc,
                               self.pose)
         if info:

@@ -24,12 +24,6 @@ namespace dv {
 
 constexpr int NACC = 14;  // per-record: dcol(3), dnrm(3), dg(8)
 
-__device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 __device__ inline void add_axis(float3& v, int ax, float x) {
   if (ax == 0) v.x += x; else if (ax == 1) v.y += x; else v.z += x;
 }
@@ -107,10 +101,42 @@ constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1,0,3,2]
 // permlane swaps, in-row steps DPP, so no exchange goes through LDS.  Must
 // be called wave-uniformly with every lane active; lanes without a hit pass
 // zero contributions.
-// Without normals the 11 live channels (colour, corners) go through a
-// 12-slot version of the same butterfly: 6, 3, then 2 (one pad) and 1
-// values per lane; lane l ends with slot 6 h5 + 3 h4 + 2 h3 + h2 (h_i: bit
-// i of l; h3 = h2 = 1 is the pad).
+// 12-slot version of the butterfly below: 6, 3, then 2 (one pad) and 1
+// values per lane; lane l ends with the wave sum of slot 6 h5 + 3 h4 + 2 h3
+// + h2 (h_i: bit i of l; lanes with h3 = h2 = 1 hold the pad, 0).  Called
+// wave-uniformly with every lane active.
+__device__ inline float wave_sum12(float* v, int& slot, bool& pad) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) v[i] = swap32_sum(v[i], v[i + 6]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] = swap16_sum(v[i], v[i + 3]);
+  v[3] = 0.0f;
+  {
+    const bool up = (lane & 8) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float send = up ? v[i] : v[i + 2];
+      const float keep = up ? v[i + 2] : v[i];
+      v[i] = keep + dpp<DPP_ROR8>(send);
+    }
+  }
+  {
+    const bool up = (lane & 4) != 0;
+    const float send = up ? v[0] : v[1];
+    const float keep = up ? v[1] : v[0];
+    v[0] = keep + dpp<DPP_HALF_MIRROR>(send);
+  }
+  v[0] += dpp<DPP_XOR2>(v[0]);
+  v[0] += dpp<DPP_XOR1>(v[0]);
+  slot = 6 * ((lane >> 5) & 1) + 3 * ((lane >> 4) & 1) + 2 * ((lane >> 3) & 1) +
+         ((lane >> 2) & 1);
+  pad = (lane & 12) == 12;
+  return v[0];
+}
+
+// Without normals the 11 live channels (colour, corners) go through the
+// 12-slot butterfly (slot 11 is zero).
 template <bool NORMALS>
 __device__ inline void accum_record(BwdBatch& B, uint32_t r, bool hit,
                                     float3 dcol, float3 dnrm,
@@ -123,34 +149,13 @@ __device__ inline void accum_record(BwdBatch& B, uint32_t r, bool hit,
 #pragma unroll
     for (int m = 0; m < 8; ++m) v[3 + m] = dg[m];
     v[11] = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) v[i] = swap32_sum(v[i], v[i + 6]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) v[i] = swap16_sum(v[i], v[i + 3]);
-    v[3] = 0.0f;
-    {
-      const bool up = (lane & 8) != 0;
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const float send = up ? v[i] : v[i + 2];
-        const float keep = up ? v[i + 2] : v[i];
-        v[i] = keep + dpp<DPP_ROR8>(send);
-      }
-    }
-    {
-      const bool up = (lane & 4) != 0;
-      const float send = up ? v[0] : v[1];
-      const float keep = up ? v[1] : v[0];
-      v[0] = keep + dpp<DPP_HALF_MIRROR>(send);
-    }
-    v[0] += dpp<DPP_XOR2>(v[0]);
-    v[0] += dpp<DPP_XOR1>(v[0]);
-    const int slot = 6 * ((lane >> 5) & 1) + 3 * ((lane >> 4) & 1) +
-                     2 * ((lane >> 3) & 1) + ((lane >> 2) & 1);
-    const bool pad = (lane & 12) == 12 || slot >= 11;
+    int slot;
+    bool pad;
+    const float x = wave_sum12(v, slot, pad);
     // slots 0-2: colour (channels 0-2), 3-10: corners (channels 6-13)
     const int ch = slot < 3 ? slot : slot + 3;
-    if ((lane & 3) == 0 && !pad && v[0] != 0.0f) atomicAdd(&B.acc[ch][r], v[0]);
+    if ((lane & 3) == 0 && !pad && slot < 11 && x != 0.0f)
+      atomicAdd(&B.acc[ch][r], x);
     return;
   }
   float v[16];
@@ -213,14 +218,17 @@ __device__ inline void flush_batch(BwdBatch& B, const CompArgs& a,
 }
 
 // Block-reduce 12 floats per thread and add them to dst (one atomic each).
-__device__ inline void block_add12(float* red, const float* v, float* dst) {
+// Called by the whole block.
+__device__ inline void block_add12(float* red, const float* v12, float* dst) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
+  float v[12];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    const float s = wave_sum(v[c]);
-    if (lane == 0) red[w * 12 + c] = s;
-  }
+  for (int c = 0; c < 12; ++c) v[c] = v12[c];
+  int slot;
+  bool pad;
+  const float x = wave_sum12(v, slot, pad);
+  __syncthreads();
+  if ((lane & 3) == 0 && !pad) red[w * 12 + slot] = x;
   __syncthreads();
   if (threadIdx.x < 12) {
     float s = 0.0f;
@@ -857,6 +865,7 @@ __global__ void __launch_bounds__(TPB) k_box_bwd(CompArgs a) {
       const uint32_t koct = a.act_oct[a_beg + j];
       const VOConst& C = a.vo[v * a.n_oct + koct];
       const float3 dj = mat3_mul(C.Rt, d);
+      const float3 inv = safe_inv(dj);
       float3 go = make_float3(0, 0, 0), gd = make_float3(0, 0, 0);
       bool any = false;
       for (int q = 0; q < nseg; ++q) {
@@ -868,16 +877,16 @@ __global__ void __launch_bounds__(TPB) k_box_bwd(CompArgs a) {
         const uint32_t ss = (meta >> 8) & 0x3FF, se_ = (meta >> 18) & 0x3FF;
         if (ss != SRC_NONE && (int)(ss >> 2) == j && bw.z != 0.0f) {
           const int ax = ss & 3;
-          const float di = get_axis(dj, ax);
-          add_axis(go, ax, -bw.z / di);
-          add_axis(gd, ax, -bw.z * se.x / di);
+          const float u = bw.z * get_axis(inv, ax);
+          add_axis(go, ax, -u);
+          add_axis(gd, ax, -u * se.x);
           any = true;
         }
         if (se_ != SRC_NONE && (int)(se_ >> 2) == j && bw.w != 0.0f) {
           const int ax = se_ & 3;
-          const float di = get_axis(dj, ax);
-          add_axis(go, ax, -bw.w / di);
-          add_axis(gd, ax, -bw.w * se.y / di);
+          const float u = bw.w * get_axis(inv, ax);
+          add_axis(go, ax, -u);
+          add_axis(gd, ax, -u * se.y);
           any = true;
         }
       }
@@ -1034,14 +1043,12 @@ k_record_bwd(int64_t off, int64_t n, const uint32_t* rseg, const uint32_t* rvox,
   const bool same = __ballot(seg != s0) == 0;
   if (same) {
     if (s0 == 0xFFFFFFFFu || (int)(s0 % n_oct) == 0) return;
-    float tot[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) tot[c] = wave_sum(p12[c]);
-    if (lane == 0) {
+    int slot;
+    bool pad;
+    const float x = wave_sum12(p12, slot, pad);
+    if ((lane & 3) == 0 && !pad && x != 0.0f) {
       const int v = s0 / n_oct, k = s0 % n_oct;
-      float* dst = pose_grad + ((size_t)v * n_actors + (k - 1)) * 12;
-      for (int c = 0; c < 12; ++c)
-        if (tot[c] != 0.0f) atomicAdd(dst + c, tot[c]);
+      atomicAdd(pose_grad + ((size_t)v * n_actors + (k - 1)) * 12 + slot, x);
     }
   } else if (seg != 0xFFFFFFFFu && (int)(seg % n_oct) > 0) {
     const int v = seg / n_oct, k = seg % n_oct;
