@@ -15,6 +15,8 @@
 // Pose gradients (beyond the paper, which keeps tracks fixed) follow the
 // ray in each actor frame: samples, leaf faces, box faces bounding
 // segments, SH direction and the rotation of normals.
+#include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 
@@ -355,42 +357,51 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
   const float invK = 1.0f / (float)K;
   uint32_t n_test = 0, n_piece = 0;
   uint32_t w_test = 0, w_piece = 0;  // wave-level counts (plain walk)
-  const PixGrad g = pixel_grads<NORMALS>(a, P);
-  const float3 GC = g.GC, GN = g.GN;
-  const float GD = g.GD;
-  // chunk totals V / VT (upstream-weighted) and the chunk's surroundings
-  float V = 0.0f, VT = 0.0f, Tpre = 1.0f, Saft = 0.0f;
+  // upstream gradients scaled by the transmittance T_pre in front of the
+  // chunk (1 for a tile of one chunk), so that
+  //   dL/dtau_i = T_pre (T_{i+1} v_i - S_{i+1}) - S_after
+  // becomes T_{i+1} v'_i - S'_{i+1} - S_after with v' = T_pre v
+  PixGrad g = pixel_grads<NORMALS>(a, P);
+  float Tpre = 1.0f, Saft = 0.0f;
+  // running suffixes S' = V' - sum w v' over the chunk, and the tail's
+  float S = 0.0f, ST = 0.0f;
   if (valid) {
     if (nck == 1) {
       const float4 f1 = a.fin1[pix];
-      V = gdot(g, a.fin0[pix], f1);
-      VT = gdot(g, a.fin2[pix], a.fin3[pix]);
-      Saft = (GC.x * a.bg[0] + GC.y * a.bg[1] + GC.z * a.bg[2] + g.GT) * f1.w;
+      Saft = (g.GC.x * a.bg[0] + g.GC.y * a.bg[1] + g.GC.z * a.bg[2] + g.GT) * f1.w;
+      S = gdot(g, a.fin0[pix], f1);
+      ST = gdot(g, a.fin2[pix], a.fin3[pix]);
     } else {
       const size_t sl = ((size_t)a.tile_pbase[gt] + chunk) * TPB + tid;
       const float4* part = a.chunk_part + sl * 4;
-      V = gdot(g, part[0], part[1]);
-      VT = gdot(g, part[2], part[3]);
       const float2 tps = a.chunk_tps[sl];
       Tpre = tps.x;
       Saft = tps.y;
+      g.GC = make_float3(Tpre * g.GC.x, Tpre * g.GC.y, Tpre * g.GC.z);
+      g.GN = make_float3(Tpre * g.GN.x, Tpre * g.GN.y, Tpre * g.GN.z);
+      g.GD = Tpre * g.GD;
+      S = gdot(g, part[0], part[1]);
+      ST = gdot(g, part[2], part[3]);
     }
   }
+  const float3 GC = g.GC, GN = g.GN;
+  const float GDh = 0.5f * g.GD;  // depth of a piece: (a + b) / 2
   const uint32_t a_beg = a.act_beg[gt];
   const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
   const uint32_t seg0 = 3 * a_beg + n_at;
   const int nseg = (n_at > 0 && valid) ? (int)a.pix_nseg[pix] : 0;
 
-  float T = 1.0f, P_ = 0.0f, PT = 0.0f;
-  bool done = !valid;
+  // an off-window lane starts below the stop threshold (a.eps > 0)
+  float T = valid ? 1.0f : 0.0f;
+  auto live = [&]() { return T >= a.eps; };
   const float3 inv = safe_inv(d);
   uint32_t beg, bgend;
   chunk_range(a.tile_start[gt], a.tile_bgend[gt], nck, chunk, beg, bgend);
   float Bc, Bn;
   chunk_bounds(a, gt, nck, chunk, tid, Bc, Bn);
-  auto suffix = [&]() { return T < T_REBASE ? VT - PT : V - P_; };
+  auto suffix = [&]() { return T < T_REBASE ? ST : S; };
   // composite one piece of entry r and add its colour/normal/corner
-  // gradients; returns dL/dtau, the piece's (global) weight in wg
+  // gradients; returns dL/dtau, the piece's weight w (in the chunk) in wg
   // set: the piece's gradients replace dcol/dnrm/dg (the plain walk's one
   // piece per entry) instead of adding to them
   auto piece_grad = [&](uint32_t r, float tau, const PieceDer& pd, float pa,
@@ -400,29 +411,27 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
     const float e = fast_exp(-tau);
     const float wgt = T * opacity(tau, e);
     const float wt = T < T_REBASE ? wgt : 0.0f;
-    const float mid = 0.5f * (pa + pb);
-    float vi = GC.x * cn.x + GC.y * cn.y + GC.z * cn.z + GD * mid;
+    float vi = fmaf(GDh, pa + pb, fmaf(GC.z, cn.z, fmaf(GC.y, cn.y, GC.x * cn.x)));
     if (NORMALS) {
       const float4 nr = B.nrm[r];
-      vi += GN.x * nr.x + GN.y * nr.y + GN.z * nr.z;
+      vi = fmaf(GN.z, nr.z, fmaf(GN.y, nr.y, fmaf(GN.x, nr.x, vi)));
     }
-    P_ = fmaf(wgt, vi, P_);
-    PT = fmaf(wt, vi, PT);
+    S = fmaf(-wgt, vi, S);
+    ST = fmaf(-wt, vi, ST);
     T *= e;
-    const float dtau = Tpre * (T * vi - suffix()) - Saft;
-    wg = Tpre * wgt;
+    const float dtau = fmaf(T, vi, -suffix()) - Saft;
+    wg = wgt;
     if (set) {
-      dcol = make_float3(wg * GC.x, wg * GC.y, wg * GC.z);
-      if (NORMALS) dnrm = make_float3(wg * GN.x, wg * GN.y, wg * GN.z);
+      dcol = make_float3(wgt * GC.x, wgt * GC.y, wgt * GC.z);
+      if (NORMALS) dnrm = make_float3(wgt * GN.x, wgt * GN.y, wgt * GN.z);
       set_corner_grads<KC>(pd, dtau, dg);
     } else {
-      dcol.x += wg * GC.x; dcol.y += wg * GC.y; dcol.z += wg * GC.z;
+      dcol.x += wgt * GC.x; dcol.y += wgt * GC.y; dcol.z += wgt * GC.z;
       if (NORMALS) {
-        dnrm.x += wg * GN.x; dnrm.y += wg * GN.y; dnrm.z += wg * GN.z;
+        dnrm.x += wgt * GN.x; dnrm.y += wgt * GN.y; dnrm.z += wgt * GN.z;
       }
       add_corner_grads<KC>(pd, dtau, dg);
     }
-    if (T < a.eps) done = true;
     return dtau;
   };
   // waves none of whose pixels has an ownership segment take the plain
@@ -437,15 +446,14 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
     const float4 q0 = a.seg_p0[qi], q1 = a.seg_p1[qi];
     const float Vq = gdot(g, q0, q1);
     const float Tseg = Tpre * T;
-    P_ = fmaf(T, Vq, P_);
-    PT = fmaf(T < T_REBASE ? T : 0.0f, Vq, PT);
+    S = fmaf(-T, Vq, S);
+    ST = fmaf(T < T_REBASE ? -T : 0.0f, Vq, ST);
     T *= q1.w;
     // .x/.y only: .z (from the piece in front) and .w (from the piece
     // behind, possibly another chunk's block) are added separately
     float* bw = reinterpret_cast<float*>(a.seg_bw + qi);
     bw[0] = Tseg;
-    bw[1] = fmaf(Tpre, suffix(), Saft);
-    if (T < a.eps) done = true;
+    bw[1] = suffix() + Saft;
   };
   for (uint32_t base = beg; base < bgend; base += TPB) {
     const uint32_t nb = min((uint32_t)TPB, bgend - base);
@@ -460,16 +468,16 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
         // a = b = 0, whose tau = 0 leaves T and the sums as they are and
         // whose gradients are zero, so every lane runs the same code
         while (m != 0) {
-          const uint64_t live = __ballot(!done);
-          if (live == 0) break;
+          const uint64_t lm = __ballot(live());
+          if (lm == 0) break;
           const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
           m &= m - 1;
-          w_test += (uint32_t)__popcll(live);
+          w_test += (uint32_t)__popcll(lm);
           const float4 geo = B.geo[r];
           float t0, t1;
           batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
           t0 = fmaxf(t0, a.tau_near);
-          const bool hit = !done && t1 > t0;
+          const bool hit = live() && t1 > t0;
           const uint64_t hm = __ballot(hit);
           if (hm == 0) continue;
           w_piece += (uint32_t)__popcll(hm);
@@ -485,13 +493,13 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
         }
         continue;
       }
-      while (m != 0 && __ballot(!done) != 0) {
+      while (m != 0 && __ballot(live()) != 0) {
         const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
         m &= m - 1;
         float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
         float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         bool hit = false;
-        if (!done) {
+        if (live()) {
           const float4 geo = B.geo[r];
           float t0, t1;
           batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
@@ -500,7 +508,7 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
           if (t1 > t0) {
             float pa = fmaxf(t0, excl);
             bool a_seg = excl > t0;
-            while (pa < t1 && !done) {
+            while (pa < t1 && live()) {
               if (pa >= ns) {
                 const float ex = a.seg_se[seg_index(seg0 + qn, tid)].y;
                 splice(qn);
@@ -527,10 +535,10 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
               hit = true;
               if (a_seg && qn > 0)
                 a.seg_bw[seg_index(seg0 + qn - 1, tid)].w +=
-                    dtau * pd.dtda + 0.5f * wg * GD;
+                    dtau * pd.dtda + wg * GDh;
               if (b_seg)
                 a.seg_bw[seg_index(seg0 + qn, tid)].z +=
-                    dtau * pd.dtdb + 0.5f * wg * GD;
+                    dtau * pd.dtdb + wg * GDh;
               pa = pb;
               a_seg = false;
             }
@@ -540,10 +548,10 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
       }
     }
     flush_batch(B, a, nb);
-    if (__syncthreads_and(done)) break;
+    if (!__syncthreads_or(live())) break;
   }
   // segments before the next chunk's boundary (all, in the last chunk)
-  while (!done && qn < nseg && a.seg_se[seg_index(seg0 + qn, tid)].x < Bn) {
+  while (live() && qn < nseg && a.seg_se[seg_index(seg0 + qn, tid)].x < Bn) {
     splice(qn);
     ++qn;
   }
@@ -1153,7 +1161,9 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   ca.n_actors = st->n_actors;
   const dv_render_opts& op = st->opts;
   ca.K = op.K;
-  ca.eps = op.eps_stop;
+  // stop below eps (at least the smallest normal float: an exact walk
+  // stops only where T has underflowed)
+  ca.eps = std::max(op.eps_stop, FLT_MIN);
   ca.tau_near = op.tau_near;
   ca.c = op.explin_c;
   ca.inv_c = 1.0f / op.explin_c;

@@ -2,6 +2,7 @@
 // pair sort, tile directories and the compositing walk (Sec. 3.4, App. A,
 // Alg. 1, Eq. 2).
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 
@@ -957,8 +958,9 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
   // totals C3/D/N3 and tail sums CT/DT/NT
   float3 C3 = make_float3(0, 0, 0), N3 = make_float3(0, 0, 0);
   float3 CT = make_float3(0, 0, 0), NT = make_float3(0, 0, 0);
-  float D = 0.0f, DT = 0.0f, T = 1.0f;
-  bool done = !valid;
+  // an off-window lane starts below the stop threshold (a.eps > 0)
+  float D = 0.0f, DT = 0.0f, T = valid ? 1.0f : 0.0f;
+  auto live = [&]() { return T >= a.eps; };
   const float3 inv = safe_inv(d);
   auto add_piece = [&](uint32_t r, const float4& geo, float pa, float pb) {
     const float4 cn = B.cn[r];
@@ -979,7 +981,6 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
       N3.z = fmaf(wgt, nr.z, N3.z); NT.z = fmaf(wt, nr.z, NT.z);
     }
     T *= e;
-    if (T < a.eps) done = true;
   };
   uint32_t beg, bgend;
   chunk_range(a.tile_start[gt], a.tile_bgend[gt], nck, chunk, beg, bgend);
@@ -1007,7 +1008,6 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
     }
     T *= q1.w;
     excl = a.seg_se[qi].y;
-    if (T < a.eps) done = true;
   };
   for (uint32_t base = beg; base < bgend; base += TPB) {
     const uint32_t nb = min((uint32_t)TPB, bgend - base);
@@ -1020,25 +1020,25 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
       if (!wseg) {
         // plain walk; tests and pieces counted from the wave's ballots
         while (m != 0) {
-          const uint64_t live = __ballot(!done);
-          if (live == 0) break;
+          const uint64_t lm = __ballot(live());
+          if (lm == 0) break;
           const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
           m &= m - 1;
-          w_test += (uint32_t)__popcll(live);
+          w_test += (uint32_t)__popcll(lm);
           const float4 geo = B.geo[r];
           float t0, t1;
           batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
           t0 = fmaxf(t0, a.tau_near);
-          const bool hit = !done && t1 > t0;
+          const bool hit = live() && t1 > t0;
           w_piece += (uint32_t)__popcll(__ballot(hit));
           if (hit) add_piece(r, geo, t0, t1);
         }
         continue;
       }
-      while (m != 0 && __ballot(!done) != 0) {
+      while (m != 0 && __ballot(live()) != 0) {
         const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
         m &= m - 1;
-        if (done) continue;
+        if (!live()) continue;
         const float4 geo = B.geo[r];
         float t0, t1;
         batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
@@ -1046,7 +1046,7 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
         t0 = fmaxf(t0, a.tau_near);
         if (!(t1 > t0)) continue;
         float pa = fmaxf(t0, excl);
-        while (pa < t1 && !done) {
+        while (pa < t1 && live()) {
           if (pa >= ns) {
             splice(qn);
             pa = fmaxf(pa, excl);
@@ -1061,10 +1061,10 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
         }
       }
     }
-    if (__syncthreads_and(done)) break;
+    if (!__syncthreads_or(live())) break;
   }
   // segments before the next chunk's boundary (all, in the last chunk)
-  while (!done && qn < nseg && a.seg_se[seg_index(seg0 + qn, tid)].x < Bn) {
+  while (live() && qn < nseg && a.seg_se[seg_index(seg0 + qn, tid)].x < Bn) {
     splice(qn);
     ++qn;
   }
@@ -1775,7 +1775,9 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   ca.outs = st->outs_d.as<dv_outputs>();
   ca.n_actors = n_oct - 1;
   ca.K = op.K;
-  ca.eps = op.eps_stop;
+  // stop below eps (at least the smallest normal float: an exact walk
+  // stops only where T has underflowed)
+  ca.eps = std::max(op.eps_stop, FLT_MIN);
   ca.tau_near = op.tau_near;
   ca.c = op.explin_c;
   ca.inv_c = 1.0f / op.explin_c;
