@@ -124,6 +124,26 @@ __host__ __device__ inline bool ball_culled(const double A[9], const double b[3]
   return false;
 }
 
+// Colour of one leaf from its SH coefficients ([S][3][N]) and the basis Y
+// at the viewing direction, clamped at 0 after the +0.5 offset; all loads
+// issued before the sums (same summation order as a plain loop).
+template <int S>
+__device__ inline void sh_colour(const float* sh, int N, int vox, const float* Y,
+                                 float col[3]) {
+  float c[3][S];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+    for (int q = 0; q < S; ++q) c[ch][q] = sh[((int64_t)q * 3 + ch) * N + vox];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int q = 0; q < S; ++q) acc = fmaf(Y[q], c[ch][q], acc);
+    col[ch] = fmaxf(acc + 0.5f, 0.0f);
+  }
+}
+
 struct PreArgs {
   const ViewConst* views;
   const VOConst* vo;
@@ -219,9 +239,37 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
   }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint32_t slot = p.block_off[blockIdx.x] + woff + (uint32_t)__popcll(m & lt);
+  // every load first (no store in between, so they are in flight together)
+  const int N = O.n_vox;
+  const float* const dens = O.dens;
+  const int32_t* const cidx = O.corner_idx;
+  int32_t ci[8];
+#pragma unroll
+  for (int c8 = 0; c8 < 8; ++c8) ci[c8] = cidx[(int64_t)c8 * N + vox];
+  // leaf record in the octree frame relative to the camera
+  const int ijk[3] = {ii, jj, kk};
+  const double h = ldexp(O.root_size, -l);
+  double rel[3];
+  for (int a = 0; a < 3; ++a) rel[a] = C.rootrel[a] + (double)ijk[a] * h;
+  // colour from SH at the direction camera -> leaf centre
+  const double cx = rel[0] + 0.5 * h, cy = rel[1] + 0.5 * h, cz = rel[2] + 0.5 * h;
+  const double rn = sqrt(cx * cx + cy * cy + cz * cz);
+  const double inv_r = rn > 0 ? 1.0 / rn : 0.0;
+  float Y[16];
+  sh_basis(O.sh_degree, (float)(cx * inv_r), (float)(cy * inv_r),
+           (float)(cz * inv_r), Y);
+  float col[3];
+  switch (O.sh_degree) {
+    case 0: sh_colour<1>(O.sh, N, vox, Y, col); break;
+    case 1: sh_colour<4>(O.sh, N, vox, Y, col); break;
+    case 2: sh_colour<9>(O.sh, N, vox, Y, col); break;
+    default: sh_colour<16>(O.sh, N, vox, Y, col); break;
+  }
+  float g[8];
+#pragma unroll
+  for (int c8 = 0; c8 < 8; ++c8) g[c8] = dens[ci[c8]];
   // depth rank: BSP painter's order from the quantised camera position
   const int L = O.max_level;
-  const int ijk[3] = {ii, jj, kk};
   uint64_t rank = 0;
   for (int d = 0; d < l; ++d) {
     uint32_t digit = 0;
@@ -234,6 +282,15 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
     }
     rank |= (uint64_t)digit << (3 * (L - 1 - d));
   }
+  // normal: -grad of the trilinear field at the centre, rotated to world
+  const float gx = 0.25f * ((g[1] - g[0]) + (g[3] - g[2]) + (g[5] - g[4]) + (g[7] - g[6]));
+  const float gy = 0.25f * ((g[2] - g[0]) + (g[3] - g[1]) + (g[6] - g[4]) + (g[7] - g[5]));
+  const float gz = 0.25f * ((g[4] - g[0]) + (g[5] - g[1]) + (g[6] - g[2]) + (g[7] - g[3]));
+  const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
+  const float3 nl = gn > 0.0f ? make_float3(-gx / gn, -gy / gn, -gz / gn)
+                              : make_float3(0.0f, 0.0f, 0.0f);
+  const float3 nw = mat3_mul(C.R, nl);
+  // stores
   p.keys[slot] = ((uint64_t)s << p.rank_bits) | rank;
   p.vals[slot] = slot;
   p.s_vox[slot] = (uint32_t)vox;
@@ -241,42 +298,11 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
   p.s_rect[slot] = (uint64_t)(uint32_t)r.xl | ((uint64_t)(uint32_t)r.xh << 16) |
                    ((uint64_t)(uint32_t)r.yl << 32) |
                    ((uint64_t)(uint32_t)r.yh << 48);
-  // leaf record in the octree frame relative to the camera
-  const double h = ldexp(O.root_size, -l);
-  double rel[3];
-  for (int a = 0; a < 3; ++a) rel[a] = C.rootrel[a] + (double)ijk[a] * h;
   p.s_geo[slot] = make_float4((float)rel[0], (float)rel[1], (float)rel[2],
                               (float)h);
-  const int N = O.n_vox;
-  float g[8];
-  for (int c8 = 0; c8 < 8; ++c8)
-    g[c8] = O.dens[O.corner_idx[(int64_t)c8 * N + vox]];
   p.s_g8a[slot] = make_float4(g[0], g[1], g[2], g[3]);
   p.s_g8b[slot] = make_float4(g[4], g[5], g[6], g[7]);
-  // colour from SH at the direction camera -> leaf centre
-  double cx = rel[0] + 0.5 * h, cy = rel[1] + 0.5 * h, cz = rel[2] + 0.5 * h;
-  double rn = sqrt(cx * cx + cy * cy + cz * cz);
-  double inv_r = rn > 0 ? 1.0 / rn : 0.0;
-  float Y[16];
-  sh_basis(O.sh_degree, (float)(cx * inv_r), (float)(cy * inv_r),
-           (float)(cz * inv_r), Y);
-  const int S = (O.sh_degree + 1) * (O.sh_degree + 1);
-  float col[3];
-  for (int ch = 0; ch < 3; ++ch) {
-    float acc = 0.0f;
-    for (int q = 0; q < S; ++q)
-      acc = fmaf(Y[q], O.sh[((int64_t)q * 3 + ch) * N + vox], acc);
-    col[ch] = fmaxf(acc + 0.5f, 0.0f);
-  }
   p.s_cn[slot] = make_float4(col[0], col[1], col[2], (float)(1.0 / h));
-  // normal: -grad of the trilinear field at the centre, rotated to world
-  float gx = 0.25f * ((g[1] - g[0]) + (g[3] - g[2]) + (g[5] - g[4]) + (g[7] - g[6]));
-  float gy = 0.25f * ((g[2] - g[0]) + (g[3] - g[1]) + (g[6] - g[4]) + (g[7] - g[5]));
-  float gz = 0.25f * ((g[4] - g[0]) + (g[5] - g[1]) + (g[6] - g[2]) + (g[7] - g[3]));
-  float gn = sqrtf(gx * gx + gy * gy + gz * gz);
-  float3 nl = gn > 0.0f ? make_float3(-gx / gn, -gy / gn, -gz / gn)
-                        : make_float3(0.0f, 0.0f, 0.0f);
-  float3 nw = mat3_mul(C.R, nl);
   p.s_nrm[slot] = make_float4(nw.x, nw.y, nw.z, 0.0f);
   (void)v;
 }
