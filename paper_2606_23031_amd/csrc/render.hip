@@ -124,6 +124,56 @@ __host__ __device__ inline bool ball_culled(const double A[9], const double b[3]
   return false;
 }
 
+// Spread the low 21 bits of x to every third bit.
+__device__ inline uint64_t spread3(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+// BSP painter's rank of a leaf (level l, index ijk, max level L) from the
+// camera Q (octree frame, QBITS fixed point, clamped to [-1, 2] root
+// sides).  At depth d < l the digit bit of axis a is the leaf's child bit
+// XOR [Q >= the ancestor's splitting plane].  Per axis that is, in closed
+// form: while the camera lies in the depth-d ancestor's slab the bit is the
+// leaf's bit XOR the camera's (0 down to their first difference, 1 there);
+// below it the camera is on one side of every plane, so the bits are the
+// leaf's, inverted when the camera is above.  A camera outside the root
+// slab is on one side of every plane.  The three l-bit strings are
+// interleaved (axis a at bit 3 j + a) and placed at the top of 3 L bits.
+__device__ inline uint64_t bsp_rank(const int ijk[3], int l, int L,
+                                    const int64_t Q[3]) {
+  if (l == 0) return 0;
+  const uint32_t mask = (1u << l) - 1u;
+  uint64_t r = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const uint32_t i = (uint32_t)ijk[a] & mask;
+    uint32_t f;
+    if (Q[a] < 0) {
+      f = i;
+    } else if (Q[a] >= (1ll << QBITS)) {
+      f = ~i & mask;
+    } else {
+      const uint32_t qt = (uint32_t)(Q[a] >> (QBITS - l));
+      const uint32_t dif = qt ^ i;
+      if (dif == 0) {
+        f = 0;
+      } else {
+        const int hb = 31 - __builtin_clz(dif);
+        const uint32_t c = (qt >> hb) & 1u;
+        f = (1u << hb) | ((c ? ~i : i) & ((1u << hb) - 1u));
+      }
+    }
+    r |= spread3(f) << a;
+  }
+  return r << (3 * (L - l));
+}
+
 // Colour of one leaf from its SH coefficients ([S][3][N]) and the basis Y
 // at the viewing direction, clamped at 0 after the +0.5 offset; all loads
 // issued before the sums (same summation order as a plain loop).
@@ -269,19 +319,7 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
 #pragma unroll
   for (int c8 = 0; c8 < 8; ++c8) g[c8] = dens[ci[c8]];
   // depth rank: BSP painter's order from the quantised camera position
-  const int L = O.max_level;
-  uint64_t rank = 0;
-  for (int d = 0; d < l; ++d) {
-    uint32_t digit = 0;
-    for (int a = 0; a < 3; ++a) {
-      const int64_t parent = ijk[a] >> (l - d);
-      const int64_t plane = (2 * parent + 1) << (QBITS - d - 1);
-      const uint32_t flip = C.Q[a] >= plane ? 1u : 0u;
-      const uint32_t bit = (ijk[a] >> (l - d - 1)) & 1;
-      digit |= (bit ^ flip) << a;
-    }
-    rank |= (uint64_t)digit << (3 * (L - 1 - d));
-  }
+  const uint64_t rank = bsp_rank(ijk, l, O.max_level, C.Q);
   // normal: -grad of the trilinear field at the centre, rotated to world
   const float gx = 0.25f * ((g[1] - g[0]) + (g[3] - g[2]) + (g[5] - g[4]) + (g[7] - g[6]));
   const float gy = 0.25f * ((g[2] - g[0]) + (g[3] - g[1]) + (g[6] - g[4]) + (g[7] - g[5]));
