@@ -190,6 +190,8 @@ struct OctDev {
 struct ViewConst {
   double fx, fy, cx, cy;
   double rnear2;            // binning: whole-window radius^2 near the camera
+  double rnear_m;           // sqrt(rnear2), rounded up (culling pre-test)
+  double side_norm[4];      // |normal| of the 4 window side planes (pre-test)
   float inv_fx, inv_fy, fcx, fcy;
   float Rc[9];              // camera -> world rotation (row-major)
   int32_t x0, y0, w, h;

@@ -101,26 +101,26 @@ __host__ __device__ inline Rect bin_box(const double A[9], const double b[3],
 // window widened by 2 px.  Projected points then fall more than 2 px
 // outside the window, where the pixel rule of bin_box leaves an empty
 // rectangle; rounding of the FP64 corner arithmetic is many orders below
-// that margin.  Requires fx, fy > 0.
+// that margin.  Requires fx, fy > 0; the view carries the near radius and
+// the norms of the four side-plane normals (rounded up).
 __host__ __device__ inline bool ball_culled(const double A[9], const double b[3],
                                             const double c[3], double rad,
-                                            double fx, double fy, double cx,
-                                            double cy, int x0, int y0, int w,
-                                            int h, double rnear2) {
+                                            const ViewConst& V) {
   const double X = ((A[0] * c[0] + A[1] * c[1]) + A[2] * c[2]) + b[0];
   const double Y = ((A[3] * c[0] + A[4] * c[1]) + A[5] * c[2]) + b[1];
   const double Z = ((A[6] * c[0] + A[7] * c[1]) + A[8] * c[2]) + b[2];
   const double r = rad * (1.0 + 1e-6) + 1e-9;
   if (Z + r < 0.0) return true;
-  const double dist = sqrt((X * X + Y * Y) + Z * Z) - 1.7320508075688772 * r;
-  if (!(dist > sqrt(rnear2) * (1.0 + 1e-6) + 1e-9)) return false;
+  // |X| > r_near + sqrt(3) r, compared squared (both sides positive)
+  const double reach = V.rnear_m + 1.7320508075688772 * r;
+  if (!((X * X + Y * Y) + Z * Z > reach * reach)) return false;
   if (Z + r < Z_EPS_D) return true;
-  const double l = cx - (x0 - 2.0), rr = (x0 + w + 2.0) - cx;
-  const double t = cy - (y0 - 2.0), bb = (y0 + h + 2.0) - cy;
-  if (fx * X + l * Z + r * sqrt(fx * fx + l * l) < 0.0) return true;
-  if (-fx * X + rr * Z + r * sqrt(fx * fx + rr * rr) < 0.0) return true;
-  if (fy * Y + t * Z + r * sqrt(fy * fy + t * t) < 0.0) return true;
-  if (-fy * Y + bb * Z + r * sqrt(fy * fy + bb * bb) < 0.0) return true;
+  const double l = V.cx - (V.x0 - 2.0), rr = (V.x0 + V.w + 2.0) - V.cx;
+  const double t = V.cy - (V.y0 - 2.0), bb = (V.y0 + V.h + 2.0) - V.cy;
+  if (V.fx * X + l * Z + r * V.side_norm[0] < 0.0) return true;
+  if (-V.fx * X + rr * Z + r * V.side_norm[1] < 0.0) return true;
+  if (V.fy * Y + t * Z + r * V.side_norm[2] < 0.0) return true;
+  if (-V.fy * Y + bb * Z + r * V.side_norm[3] < 0.0) return true;
   return false;
 }
 
@@ -264,9 +264,7 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
       bhi[a] = O.root_min[a] + (double)(ijk[a] + 1) * h;
       ctr[a] = O.root_min[a] + ((double)ijk[a] + 0.5) * h;
     }
-    if (PASS == 1 ||
-        !ball_culled(C.A, C.b, ctr, 0.8660254037844386 * h, V.fx, V.fy, V.cx,
-                     V.cy, V.x0, V.y0, V.w, V.h, V.rnear2)) {
+    if (PASS == 1 || !ball_culled(C.A, C.b, ctr, 0.8660254037844386 * h, V)) {
       r = bin_box(C.A, C.b, blo, bhi, V.fx, V.fy, V.cx, V.cy, V.x0, V.y0,
                   V.w, V.h, V.rnear2);
       vis = r.status != 0 && r.xl <= r.xh && r.yl <= r.yh;
@@ -1268,6 +1266,15 @@ dv_status setup_state(dv_fwd_state* st, const dv_scene* sc,
           m2 = std::max(m2, (1.0 + x * x) + y * y);
         }
       V.rnear2 = (2.0 * Z_EPS_D) * (2.0 * Z_EPS_D) * m2;
+      // for the conservative ball test: sqrt(rnear2) and |n| of the four
+      // window side planes, each rounded up by a relative 1e-6
+      V.rnear_m = std::sqrt(V.rnear2) * (1.0 + 1e-6) + 1e-9;
+      const double l = in.cx - (in.x0 - 2.0), rr = (in.x0 + in.w + 2.0) - in.cx;
+      const double t = in.cy - (in.y0 - 2.0), bb = (in.y0 + in.h + 2.0) - in.cy;
+      V.side_norm[0] = std::sqrt(in.fx * in.fx + l * l) * (1.0 + 1e-6);
+      V.side_norm[1] = std::sqrt(in.fx * in.fx + rr * rr) * (1.0 + 1e-6);
+      V.side_norm[2] = std::sqrt(in.fy * in.fy + t * t) * (1.0 + 1e-6);
+      V.side_norm[3] = std::sqrt(in.fy * in.fy + bb * bb) * (1.0 + 1e-6);
     }
     V.ntx = (in.w + TILE - 1) / TILE;
     V.nty = (in.h + TILE - 1) / TILE;
@@ -1354,8 +1361,7 @@ dv_status setup_state(dv_fwd_state* st, const dv_scene* sc,
         const ViewConst& V = st->views_h[v];
         double ctr[3];
         for (int a = 0; a < 3; ++a) ctr[a] = od.root_min[a] + 0.5 * od.root_size;
-        if (ball_culled(C.A, C.b, ctr, 0.8660254037844386 * od.root_size, V.fx,
-                        V.fy, V.cx, V.cy, V.x0, V.y0, V.w, V.h, V.rnear2))
+        if (ball_culled(C.A, C.b, ctr, 0.8660254037844386 * od.root_size, V))
           cnt = 0;
       }
       seg_start[sidx + 1] = seg_start[sidx] + cnt;
