@@ -908,6 +908,37 @@ __global__ void __launch_bounds__(TPB) k_box_bwd(CompArgs a) {
 }
 
 // ------------------------------------------------------------------ records
+// A record's normal gradient dL/dn (world) in terms of its 8 corner
+// values: n = -grad/|grad| of the trilinear field at the leaf centre, so
+// dL/dg_m = (s_m . dv) with dv = -(I - n n^T) R^T dL/dn / |grad| and s_m the
+// corner's +-1/4 stencil.  Adds to dg; returns false (nothing added) where
+// the gradient or the normal vanishes; nl: the local normal.
+__device__ inline bool normal_to_corners(float4 gn, float4 ga, float4 gb,
+                                         const float* R, float* dg, float* nl) {
+  if (gn.x == 0.0f && gn.y == 0.0f && gn.z == 0.0f) return false;
+  const float g[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+  const float vx = 0.25f * ((g[1] - g[0]) + (g[3] - g[2]) + (g[5] - g[4]) + (g[7] - g[6]));
+  const float vy = 0.25f * ((g[2] - g[0]) + (g[3] - g[1]) + (g[6] - g[4]) + (g[7] - g[5]));
+  const float vz = 0.25f * ((g[4] - g[0]) + (g[5] - g[1]) + (g[6] - g[2]) + (g[7] - g[3]));
+  const float nv = sqrtf(vx * vx + vy * vy + vz * vz);
+  if (!(nv > 0.0f)) return false;
+  nl[0] = -vx / nv; nl[1] = -vy / nv; nl[2] = -vz / nv;
+  // dL/dn_loc = R^T dL/dn_world
+  float dn[3];
+  for (int a2 = 0; a2 < 3; ++a2)
+    dn[a2] = R[0 * 3 + a2] * gn.x + R[1 * 3 + a2] * gn.y + R[2 * 3 + a2] * gn.z;
+  const float pr = dn[0] * nl[0] + dn[1] * nl[1] + dn[2] * nl[2];
+  const float dv[3] = {-(dn[0] - pr * nl[0]) / nv, -(dn[1] - pr * nl[1]) / nv,
+                       -(dn[2] - pr * nl[2]) / nv};
+  for (int m = 0; m < 8; ++m) {
+    const float sx = (m & 1) ? 0.25f : -0.25f;
+    const float sy = (m & 2) ? 0.25f : -0.25f;
+    const float sz = (m & 4) ? 0.25f : -0.25f;
+    dg[m] += sx * dv[0] + sy * dv[1] + sz * dv[2];
+  }
+  return true;
+}
+
 // SH gradient of one record, added to the [S][3][N] accumulator by plain
 // read-modify-write (the caller guarantees one record per leaf and launch);
 // all loads of a channel are issued before its stores.
@@ -927,6 +958,143 @@ __device__ inline void sh_grad_rmw(float* gsh, int N, uint32_t vox,
   }
 }
 
+// SH and corner gradients, leaf-major (renders with several records per
+// leaf): one thread per (octree, leaf) walks the views, finds the leaf's
+// record (if the leaf was visible) from the preprocess ballots — slot =
+// block offset + ballots of the block's earlier waves + lanes below in the
+// wave's ballot — and sums over its records, in registers, Y(dir) dL/dc
+// and the 8 corner gradients (density samples, plus the normal's terms);
+// then one read-modify-write of the [S][3][N] SH accumulator, coalesced
+// over consecutive leaves, and 8 corner atomics per leaf instead of per
+// record.  Leaves of octree k occupy threads [lstart[k], lstart[k] + N_k),
+// lstart 64-aligned, so a wave holds one octree and its lanes share every
+// ballot word.
+struct ShArgs {
+  const int64_t* lstart;   // [n_oct + 1]
+  const int64_t* pstart;   // per (view, octree): first item, 64-aligned
+  const int32_t* seg_len;  // per (view, octree): leaves binned (0: none)
+  const uint64_t* wmask;   // per wave of items: visibility ballot
+  const uint32_t* boff;    // per block of items: first record slot
+  const float4* gcol;      // per record: dL/d colour
+  const float4* rcn;       // per record: colour
+  const float4* rgeo;      // per record: leaf min relative to the camera, h
+  const float4* gg8a;      // per record: dL/d corner values
+  const float4* gg8b;
+  const float4* gnrm;      // per record: dL/d normal (normals rendered)
+  const float4* rg8a;      // per record: corner values
+  const float4* rg8b;
+  const VOConst* vo;
+  const OctDev* oct;
+  const OctGrad* og;
+  int32_t n_oct, n_views;
+  bool normals;
+};
+
+template <int S>
+__device__ inline void sh_leaf(const ShArgs& p, int k, int64_t x0, int lane,
+                               int N, int deg, float* gsh, float* gcor,
+                               const int32_t* cidx) {
+  const int64_t x = x0 + lane;
+  const bool in = x < N;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  float acc[3][S];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+    for (int q = 0; q < S; ++q) acc[ch][q] = 0.0f;
+  float dgs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  bool any = false, anyc = false;
+  for (int v = 0; v < p.n_views; ++v) {
+    const int sg = v * p.n_oct + k;
+    if (p.seg_len[sg] == 0) continue;
+    const int64_t item0 = p.pstart[sg] + x0;   // the wave's first item
+    const uint64_t m = p.wmask[item0 >> 6];
+    if (m == 0) continue;
+    const int64_t blk = item0 / TPB;
+    const int wib = (int)((item0 >> 6) % (TPB / 64));
+    uint32_t base = p.boff[blk];
+    for (int i = 0; i < wib; ++i)
+      base += (uint32_t)__popcll(p.wmask[blk * (TPB / 64) + i]);
+    if (!in || !((m >> lane) & 1ull)) continue;
+    const uint32_t slot = base + (uint32_t)__popcll(m & lt);
+    if (gcor) {
+      const float4 a8 = p.gg8a[slot], b8 = p.gg8b[slot];
+      float dg[8] = {a8.x, a8.y, a8.z, a8.w, b8.x, b8.y, b8.z, b8.w};
+      float nl[3];
+      if (p.normals)
+        normal_to_corners(p.gnrm[slot], p.rg8a[slot], p.rg8b[slot],
+                          p.vo[sg].R, dg, nl);
+#pragma unroll
+      for (int c8 = 0; c8 < 8; ++c8) {
+        dgs[c8] += dg[c8];
+        anyc = anyc || dg[c8] != 0.0f;
+      }
+    }
+    if (!gsh) continue;
+    const float4 dc = p.gcol[slot], cn = p.rcn[slot], geo = p.rgeo[slot];
+    const float mc[3] = {cn.x > 0.0f ? dc.x : 0.0f, cn.y > 0.0f ? dc.y : 0.0f,
+                         cn.z > 0.0f ? dc.z : 0.0f};
+    if (mc[0] == 0.0f && mc[1] == 0.0f && mc[2] == 0.0f) continue;
+    // direction camera -> leaf centre (octree frame)
+    const float cx = geo.x + 0.5f * geo.w, cy = geo.y + 0.5f * geo.w,
+                cz = geo.z + 0.5f * geo.w;
+    const float rn = sqrtf(cx * cx + cy * cy + cz * cz);
+    const float ir = rn > 0.0f ? 1.0f / rn : 0.0f;
+    float Y[16];
+    sh_basis(deg, cx * ir, cy * ir, cz * ir, Y);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+      for (int q = 0; q < S; ++q) acc[ch][q] = fmaf(Y[q], mc[ch], acc[ch][q]);
+    any = true;
+  }
+  if (anyc) {
+    int32_t ci[8];
+#pragma unroll
+    for (int c8 = 0; c8 < 8; ++c8) ci[c8] = cidx[(int64_t)c8 * N + x];
+#pragma unroll
+    for (int c8 = 0; c8 < 8; ++c8) atomicAdd(gcor + ci[c8], dgs[c8]);
+  }
+  if (!any) return;
+  const int64_t N3 = 3 * (int64_t)N;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    float* gp = gsh + (int64_t)ch * N + x;
+    float old[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) old[q] = gp[q * N3];
+#pragma unroll
+    for (int q = 0; q < S; ++q) gp[q * N3] = old[q] + acc[ch][q];
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_leaf_bwd(ShArgs p) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t t0 = (int64_t)blockIdx.x * TPB + w * 64;
+  if (t0 >= p.lstart[p.n_oct]) return;
+  int lo = 0, hi = p.n_oct - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (p.lstart[mid] <= t0) lo = mid; else hi = mid - 1;
+  }
+  const int k = lo;
+  const OctDev& O = p.oct[k];
+  float* const gsh = p.og[k].sh;
+  float* const gcor = p.og[k].corner;
+  if (!gsh && !gcor) return;
+  const int64_t x0 = t0 - p.lstart[k];
+  const int N = O.n_vox;
+  if (x0 >= N) return;
+  const int32_t* const cidx = O.corner_idx;
+  switch (O.sh_degree) {
+    case 0: sh_leaf<1>(p, k, x0, lane, N, 0, gsh, gcor, cidx); break;
+    case 1: sh_leaf<4>(p, k, x0, lane, N, 1, gsh, gcor, cidx); break;
+    case 2: sh_leaf<9>(p, k, x0, lane, N, 2, gsh, gcor, cidx); break;
+    default: sh_leaf<16>(p, k, x0, lane, N, 3, gsh, gcor, cidx); break;
+  }
+}
+
 template <bool POSE>
 __global__ void __launch_bounds__(TPB)
 k_record_bwd(int64_t off, int64_t n, const uint32_t* rseg, const uint32_t* rvox,
@@ -934,7 +1102,7 @@ k_record_bwd(int64_t off, int64_t n, const uint32_t* rseg, const uint32_t* rvox,
              const float4* rg8b, const float4* gcol, const float4* gnrm,
              const float4* gg8a, const float4* gg8b, const OctDev* oct,
              const OctGrad* og, const VOConst* vo, int n_oct, int n_actors,
-             float* pose_grad, bool normals) {
+             float* pose_grad, bool normals, bool leafmajor) {
   const int64_t i = off + (int64_t)blockIdx.x * TPB + threadIdx.x;
   float p12[12];
 #pragma unroll
@@ -960,8 +1128,8 @@ k_record_bwd(int64_t off, int64_t n, const uint32_t* rseg, const uint32_t* rvox,
     const float mc[3] = {cn.x > 0.0f ? dc.x : 0.0f, cn.y > 0.0f ? dc.y : 0.0f,
                          cn.z > 0.0f ? dc.z : 0.0f};
     const int S = (O.sh_degree + 1) * (O.sh_degree + 1);
-    float* const gsh = G.sh;
-    float* const gcor = G.corner;
+    float* const gsh = leafmajor ? nullptr : G.sh;
+    float* const gcor = leafmajor ? nullptr : G.corner;
     const int32_t* const cidx = O.corner_idx;
     if (gsh && (mc[0] != 0.0f || mc[1] != 0.0f || mc[2] != 0.0f)) {
       float Y[16];
@@ -1001,37 +1169,13 @@ k_record_bwd(int64_t off, int64_t n, const uint32_t* rseg, const uint32_t* rvox,
     const float4 a8 = gg8a[i], b8 = gg8b[i];
     float dg[8] = {a8.x, a8.y, a8.z, a8.w, b8.x, b8.y, b8.z, b8.w};
     if (normals) {
-      const float4 gn = gnrm[i];
-      if (gn.x != 0.0f || gn.y != 0.0f || gn.z != 0.0f) {
-        const float4 ga = rg8a[i], gb = rg8b[i];
-        const float g[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
-        float vx = 0.25f * ((g[1] - g[0]) + (g[3] - g[2]) + (g[5] - g[4]) + (g[7] - g[6]));
-        float vy = 0.25f * ((g[2] - g[0]) + (g[3] - g[1]) + (g[6] - g[4]) + (g[7] - g[5]));
-        float vz = 0.25f * ((g[4] - g[0]) + (g[5] - g[1]) + (g[6] - g[2]) + (g[7] - g[3]));
-        const float nv = sqrtf(vx * vx + vy * vy + vz * vz);
-        if (nv > 0.0f) {
-          const float nl[3] = {-vx / nv, -vy / nv, -vz / nv};
-          // dL/dn_loc = R^T dL/dn_world
-          float dn[3];
-          for (int a2 = 0; a2 < 3; ++a2)
-            dn[a2] = C.R[0 * 3 + a2] * gn.x + C.R[1 * 3 + a2] * gn.y +
-                     C.R[2 * 3 + a2] * gn.z;
-          const float pr = dn[0] * nl[0] + dn[1] * nl[1] + dn[2] * nl[2];
-          const float dv[3] = {-(dn[0] - pr * nl[0]) / nv,
-                               -(dn[1] - pr * nl[1]) / nv,
-                               -(dn[2] - pr * nl[2]) / nv};
-          for (int m = 0; m < 8; ++m) {
-            const float sx = (m & 1) ? 0.25f : -0.25f;
-            const float sy = (m & 2) ? 0.25f : -0.25f;
-            const float sz = (m & 4) ? 0.25f : -0.25f;
-            dg[m] += sx * dv[0] + sy * dv[1] + sz * dv[2];
-          }
-          if (POSE && k > 0) {
-            const float gw[3] = {gn.x, gn.y, gn.z};
-            for (int a2 = 0; a2 < 3; ++a2)
-              for (int b = 0; b < 3; ++b) p12[a2 * 3 + b] += gw[a2] * nl[b];
-          }
-        }
+      float nl[3];
+      if (normal_to_corners(gnrm[i], rg8a[i], rg8b[i], C.R, dg, nl) && POSE &&
+          k > 0) {
+        const float4 gn = gnrm[i];
+        const float gw[3] = {gn.x, gn.y, gn.z};
+        for (int a2 = 0; a2 < 3; ++a2)
+          for (int b = 0; b < 3; ++b) p12[a2 * 3 + b] += gw[a2] * nl[b];
       }
     }
     if (gcor && (dg[0] != 0.0f || dg[1] != 0.0f || dg[2] != 0.0f ||
@@ -1098,13 +1242,21 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
     og[k].corner = acc->octrees ? acc->octrees[k].corner : nullptr;
     og[k].sh = acc->octrees ? acc->octrees[k].sh : nullptr;
   }
-  DBuf gin, ogd, gcol, gnrm, gg8a, gg8b, segbw;
+  // leaf-major thread space of the SH backward: octree k from lstart[k]
+  st->lstart_keep.emplace_back((size_t)n_oct + 1, 0);
+  std::vector<int64_t>& lstart = st->lstart_keep.back();
+  for (int k = 0; k < n_oct; ++k)
+    lstart[k + 1] = lstart[k] + ((scene->desc[k].n_voxels + 63) & ~(int64_t)63);
+  DBuf gin, ogd, lsd, gcol, gnrm, gg8a, gg8b, segbw;
   DV_TRY(alloc_n<dv_out_grads>(ctx, gin, st->n_views, s));
   DV_TRY(alloc_n<OctGrad>(ctx, ogd, n_oct, s));
+  DV_TRY(alloc_n<int64_t>(ctx, lsd, (size_t)n_oct + 1, s));
   DV_TRY_HIP(hipMemcpyAsync(gin.p, st->grads_keep.back().data(),
                             sizeof(dv_out_grads) * st->n_views,
                             hipMemcpyHostToDevice, s));
   DV_TRY_HIP(hipMemcpyAsync(ogd.p, og.data(), sizeof(OctGrad) * n_oct,
+                            hipMemcpyHostToDevice, s));
+  DV_TRY_HIP(hipMemcpyAsync(lsd.p, lstart.data(), sizeof(int64_t) * (n_oct + 1),
                             hipMemcpyHostToDevice, s));
   // per-record gradients in one buffer (colour, corners, normal last, so a
   // render without normals clears three quarters of it)
@@ -1221,8 +1373,47 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   }
   tm_clear.stop();
   StageTimer tm_rec(ctx, ST_RECORD_BWD, s);
-  // one launch per view (a leaf has at most one record per view)
-  for (int v = 0; v < st->n_views && nv > 0; ++v) {
+  // leaf-major SH and corner sums when leaves carry several records on
+  // average (several views), else one launch per view over its records
+  const bool leafmajor = st->n_views > 1 && (double)nv >= 1.5 * (double)lstart[n_oct];
+  if (nv > 0 && leafmajor) {
+    if (ca.pose_grad) {
+      hipLaunchKernelGGL(k_record_bwd<true>, dim3(grid_for(nv, TPB)), dim3(TPB), 0,
+                         s, (int64_t)0, nv, st->rec_seg.as<uint32_t>(),
+                         st->rec_vox.as<uint32_t>(), st->rec_geo.as<float4>(),
+                         st->rec_cn.as<float4>(), st->rec_g8a.as<float4>(),
+                         st->rec_g8b.as<float4>(), gcol.as<float4>(),
+                         gnrm.as<float4>(), gg8a.as<float4>(), gg8b.as<float4>(),
+                         scene->oct_dev.as<OctDev>(), ogd.as<OctGrad>(),
+                         st->vo_d.as<VOConst>(), n_oct, st->n_actors,
+                         ca.pose_grad, normals, true);
+      DV_TRY_HIP(hipGetLastError());
+    }
+    ShArgs sa;
+    sa.lstart = lsd.as<int64_t>();
+    sa.pstart = st->seg_pstart_d.as<int64_t>();
+    sa.seg_len = st->seg_len_d.as<int32_t>();
+    sa.wmask = st->pre_wmask.as<uint64_t>();
+    sa.boff = st->pre_boff.as<uint32_t>();
+    sa.gcol = gcol.as<float4>();
+    sa.rcn = st->rec_cn.as<float4>();
+    sa.rgeo = st->rec_geo.as<float4>();
+    sa.gg8a = gg8a.as<float4>();
+    sa.gg8b = gg8b.as<float4>();
+    sa.gnrm = gnrm.as<float4>();
+    sa.rg8a = st->rec_g8a.as<float4>();
+    sa.rg8b = st->rec_g8b.as<float4>();
+    sa.vo = st->vo_d.as<VOConst>();
+    sa.oct = scene->oct_dev.as<OctDev>();
+    sa.og = ogd.as<OctGrad>();
+    sa.n_oct = n_oct;
+    sa.n_views = st->n_views;
+    sa.normals = normals;
+    hipLaunchKernelGGL(k_leaf_bwd, dim3(grid_for(lstart[n_oct], TPB)), dim3(TPB), 0,
+                       s, sa);
+    DV_TRY_HIP(hipGetLastError());
+  }
+  for (int v = 0; v < st->n_views && nv > 0 && !leafmajor; ++v) {
     const int64_t r0 = (int64_t)st->view_slot_h[v], r1 = (int64_t)st->view_slot_h[v + 1];
     if (r1 <= r0) continue;
     auto kr = ca.pose_grad ? k_record_bwd<true> : k_record_bwd<false>;
@@ -1233,7 +1424,7 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
                        gcol.as<float4>(), gnrm.as<float4>(), gg8a.as<float4>(),
                        gg8b.as<float4>(), scene->oct_dev.as<OctDev>(),
                        ogd.as<OctGrad>(), st->vo_d.as<VOConst>(), n_oct,
-                       st->n_actors, ca.pose_grad, normals);
+                       st->n_actors, ca.pose_grad, normals, false);
     DV_TRY_HIP(hipGetLastError());
   }
   return DV_OK;

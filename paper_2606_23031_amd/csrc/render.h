@@ -564,6 +564,11 @@ struct dv_fwd_state {
   dv::DBuf order_fwd, order_bwd, item_tile, item_chunk, item_work;
   dv::DBuf tile_nck, tile_ibase, tile_pbase, plan_counts;
   dv::DBuf host_tables;   // one upload: views, constants, segments, actor CSR
+  // preprocess ballots and block offsets: record slot of any (view,
+  // octree, leaf) item, kept for the leaf-major SH backward
+  dv::DBuf pre_wmask, pre_boff;
+  dv::DBuf seg_pstart_d, seg_len_d;   // views into host_tables
+  std::vector<std::vector<int64_t>> lstart_keep;
   dv::DBuf chunk_b, chunk_part, act_tile;
   dv::DBuf aorder, aitem_pair, aitem_chunk, pair_nck, pair_ibase, pair_pbase,
       aplan_counts, apart;

@@ -1521,7 +1521,8 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   // (view, octree) constants, output planes, padded segment starts and
   // lengths, the actor-tile CSR
   const int64_t nt = st->n_tiles, na = st->n_apairs;
-  DBuf segs_d, slen_d;
+  DBuf& segs_d = st->seg_pstart_d;
+  DBuf& slen_d = st->seg_len_d;
   {
     const void* src[8] = {st->views_h.data(), st->vo_h.data(), outs,
                           pstart.data(), seg_len.data(), st->act_beg_h.data(),
@@ -1559,7 +1560,9 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   st->tile_bits = ceil_log2((uint64_t)std::max<int64_t>(st->n_tiles, 2));
   // pass 0: visibility counts per block
   const unsigned nblk = grid_for(std::max<int64_t>(n_items, 1), TPB);
-  DBuf bcount, boff, total, wmask, vslot;
+  DBuf bcount, total, vslot;
+  DBuf& wmask = st->pre_wmask;
+  DBuf& boff = st->pre_boff;
   DV_TRY(alloc_n<uint64_t>(ctx, wmask, (size_t)nblk * (TPB / 64), s));
   DV_TRY(alloc_n<uint32_t>(ctx, bcount, nblk, s));
   DV_TRY(alloc_n<uint32_t>(ctx, boff, nblk, s));

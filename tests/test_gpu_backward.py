@@ -142,3 +142,74 @@ def _dense_bar(acc, pg, ref):
         worst[f"dp[{i}]"] = close_sum(f"dp[{i}]", p[i, 9:], ref["dp"][i + 1], rel_elem=1e-2)
     bad = {k: w for k, w in worst.items() if w > 1.0}
     assert not bad, bad
+
+
+def test_multiview_leaf_major_equals_views_alone(ctx):
+    """Six views of the actor scene in one launch, with every leaf binned in
+    most of them (more records than 1.5 x the leaves): the SH and corner
+    gradients are then summed per leaf across its records (leaf-major
+    pass).  They must equal the sum of the six views' gradients rendered
+    one view at a time (one record per leaf and launch: the per-record pass
+    the oracle adjoint checks above); pose gradients row by row."""
+    import torch
+    from paper_2606_23031_amd import dv
+    from synth.configs import make_view, look_at_c2w
+    cfg = actor_scene(seed=3, deg=2)
+    scene, opts = cfg["scene"], cfg["opts"]
+    eyes = [(5.0, 2.5, 2.0), (-5.0, 1.5, 1.5), (1.5, -5.0, 2.5),
+            (-2.5, -4.0, -1.5), (4.0, 4.0, -2.5), (0.8, 4.5, 3.5)]
+    views = [make_view(64, 48, 75.0, look_at_c2w(np.array(e), (0.0, 0.0, 0.0)), t=2.5)
+             for e in eyes]
+    mask = dv.DV_OUT_RGB | dv.DV_OUT_DEPTH | dv.DV_OUT_NORMAL | dv.DV_OUT_T
+    copts = dv.make_opts(opts, mask)
+    sc = dv.Scene(ctx, scene)
+    na = len(scene["octrees"]) - 1
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    grads = []
+    for v in views:
+        h, w = v["h"], v["w"]
+        grads.append({k: t.cuda() for k, t in dict(
+            rgb=torch.randn(3, h, w, generator=gen),
+            depth=0.3 * torch.randn(h, w, generator=gen),
+            normal=torch.randn(3, h, w, generator=gen),
+            T=torch.randn(h, w, generator=gen)).items()})
+
+    def zeros():
+        return [dict(corner=torch.zeros(len(o["corner_density"]), device="cuda"),
+                     sh=torch.zeros(o["sh"].shape, device="cuda"))
+                for o in scene["octrees"]]
+
+    outs = dv.alloc_outputs(views, mask)
+    st = dv.dv_render(ctx, sc, views, copts, outs, keep=True)
+    info = dv.dv_fwd_state_info(st)
+    padded = sum((len(o["level"]) + 63) // 64 * 64 for o in scene["octrees"])
+    print(f"  {info['n_visible']} records, {padded} leaf threads")
+    assert info["n_visible"] >= 1.5 * padded  # the leaf-major pass runs
+    acc = zeros()
+    pg = torch.zeros(len(views), na, 12, device="cuda")
+    dv.dv_render_backward(ctx, sc, st, grads, acc, pg)
+    torch.cuda.synchronize()
+    dv.dv_fwd_state_release(st)
+    ref = zeros()
+    pref = torch.zeros(len(views), na, 12, device="cuda")
+    for i, v in enumerate(views):
+        o1 = dv.alloc_outputs([v], mask)
+        s1 = dv.dv_render(ctx, sc, [v], copts, o1, keep=True)
+        a1 = zeros()
+        p1 = torch.zeros(1, na, 12, device="cuda")
+        dv.dv_render_backward(ctx, sc, s1, [grads[i]], a1, p1)
+        torch.cuda.synchronize()
+        dv.dv_fwd_state_release(s1)
+        for k in range(len(ref)):
+            ref[k]["corner"] += a1[k]["corner"]
+            ref[k]["sh"] += a1[k]["sh"]
+        pref[i] = p1[0]
+    for k in range(len(ref)):
+        for key in ("corner", "sh"):
+            x, y = acc[k][key], ref[k][key]
+            scale = float(y.abs().max())
+            err = float((x - y).abs().max())
+            print(f"  octree {k} {key}: max|ref| {scale:.3e} max err {err:.2e}")
+            assert scale > 0.0 and err <= 1e-5 * scale, (k, key)
+    scale = float(pref.abs().max())
+    assert scale > 0.0 and float((pg - pref).abs().max()) <= 1e-5 * scale
