@@ -720,14 +720,18 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
     bool hz = false, hw = false;
     // gradients of the piece [pa, pb) of entry r in segment q (chord
     // [t0, t1) entering and leaving through axes ax0, ax1)
+    // set: the gradients replace dcol/dnrm/dg (one piece per entry) rather
+    // than adding to them; real = false: the empty piece a = b = 0 of a
+    // lane without one (tau = 0 changes no state; dL/dtau is taken as 0, so
+    // every gradient and pose term is zero)
     auto piece = [&](uint32_t r, const float4& geo, float t0, float t1, int ax0,
                      int ax1, float pa, float pb, float3& dcol, float3& dnrm,
-                     float* dg) {
+                     float* dg, bool set, bool real) {
       const float4 cn = B.cn[r];
       PieceDer pd;
       const float tau = piece_eval<2, KC>(geo, B.ga[r], B.gb[r], cn.w, dj, pa,
                                           pb, K, invK, a.c, a.inv_c, &pd);
-      ++n_piece;
+      n_piece += real ? 1u : 0u;
       const float e = fast_exp(-tau);
       const float wl = Tl * opacity(tau, e);
       const float4 nr = B.nrm[r];
@@ -739,13 +743,19 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
       PlT = fmaf(wlt, vi, PlT);
       Tl *= e;
       const float Sl = Tl < T_REBASE ? VqT - PlT : Vq - Pl;
-      const float dtau = Tpre * Tl * vi - (Tpre * Sl + Saft);
+      const float dtau = real ? Tpre * Tl * vi - (Tpre * Sl + Saft) : 0.0f;
       const float wt = Tpre * wl;
-      dcol.x += wt * GC.x; dcol.y += wt * GC.y; dcol.z += wt * GC.z;
-      if (NORMALS) {
-        dnrm.x += wt * GN.x; dnrm.y += wt * GN.y; dnrm.z += wt * GN.z;
+      if (set) {
+        dcol = make_float3(wt * GC.x, wt * GC.y, wt * GC.z);
+        if (NORMALS) dnrm = make_float3(wt * GN.x, wt * GN.y, wt * GN.z);
+        set_corner_grads<KC>(pd, dtau, dg);
+      } else {
+        dcol.x += wt * GC.x; dcol.y += wt * GC.y; dcol.z += wt * GC.z;
+        if (NORMALS) {
+          dnrm.x += wt * GN.x; dnrm.y += wt * GN.y; dnrm.z += wt * GN.z;
+        }
+        add_corner_grads<KC>(pd, dtau, dg);
       }
-      add_corner_grads<KC>(pd, dtau, dg);
       if (a.pose_grad) {
         go.x = fmaf(dtau, pd.dx.x, go.x);
         go.y = fmaf(dtau, pd.dx.y, go.y);
@@ -756,20 +766,20 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
         const float ga_ = dtau * pd.dtda + 0.5f * wt * GD;
         const float gb_ = dtau * pd.dtdb + 0.5f * wt * GD;
         if (qs > t0) {
-          if (single) { bz += ga_; hz = true; }
+          if (single) { bz += ga_; hz = hz || real; }
           else a.seg_bw[seg_index(seg0 + q, tid)].z += ga_;
         } else {
           // entry face on axis ax0: t = (face - o) / d, so divide by d
           // (times the reciprocal direction the slab test uses)
-          const float u = ga_ * get_axis(inv, ax0);
+          const float u = real ? ga_ * get_axis(inv, ax0) : 0.0f;
           add_axis(go, ax0, -u);
           add_axis(gd, ax0, -u * pa);
         }
         if (qe < t1) {
-          if (single) { bw_ += gb_; hw = true; }
+          if (single) { bw_ += gb_; hw = hw || real; }
           else a.seg_bw[seg_index(seg0 + q, tid)].w += gb_;
         } else {
-          const float u = gb_ * get_axis(inv, ax1);
+          const float u = real ? gb_ * get_axis(inv, ax1) : 0.0f;
           add_axis(go, ax1, -u);
           add_axis(gd, ax1, -u * pb);
         }
@@ -784,6 +794,37 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
       wave_entry_masks(B.rect, nb, bx, by, wm);
       for (int wc = 0; wc < 4; ++wc) {
       uint64_t m = wm[wc];
+      if (single) {
+        // one piece per entry at most: straight-line code, lanes without a
+        // piece take the empty one
+        while (m != 0 && __ballot(live()) != 0) {
+          const uint32_t r = (uint32_t)wc * 64 + (uint32_t)__builtin_ctzll(m);
+          m &= m - 1;
+          const bool act = live() && base + r >= wlo && base + r < whi;
+          const float4 geo = B.geo[r];
+          float t0, t1;
+          int ax0, ax1;
+          float3 hi;
+          if (NORMALS) {
+            hi = leaf_hi(geo);
+          } else {
+            const float4 h4 = B.nrm[r];
+            hi = make_float3(h4.x, h4.y, h4.z);
+          }
+          slab_axes(make_float3(geo.x, geo.y, geo.z), hi, inv, t0, t1, ax0, ax1);
+          n_test += act ? 1u : 0u;
+          const float pa0 = fmaxf(t0, qs), pb0 = fminf(t1, qe);
+          const bool hit = act && pb0 > pa0;
+          if (act && t1 > t0 && t1 > qs && (qe <= t0 || t1 > qe)) fin = true;
+          if (__ballot(hit) == 0) continue;
+          const float pa = hit ? pa0 : 0.0f, pb = hit ? pb0 : 0.0f;
+          float3 dcol, dnrm = make_float3(0, 0, 0);
+          float dg[8];
+          piece(r, geo, t0, t1, ax0, ax1, pa, pb, dcol, dnrm, dg, true, hit);
+          accum_record<NORMALS>(B, r, hit, dcol, dnrm, dg);
+        }
+        continue;
+      }
       while (m != 0 && __ballot(live()) != 0) {
         const uint32_t r = (uint32_t)wc * 64 + (uint32_t)__builtin_ctzll(m);
         m &= m - 1;
@@ -803,14 +844,7 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
           }
           slab_axes(make_float3(geo.x, geo.y, geo.z), hi, inv, t0, t1, ax0, ax1);
           ++n_test;
-          if (single) {
-            const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
-            if (pb > pa) {
-              piece(r, geo, t0, t1, ax0, ax1, pa, pb, dcol, dnrm, dg);
-              hit = true;
-            }
-            if (t1 > t0 && t1 > qs && (qe <= t0 || t1 > qe)) fin = true;
-          } else if (t1 > t0 && t1 > qs) {
+          if (t1 > t0 && t1 > qs) {
             while (true) {
               if (qe <= t0) {
                 q = next_q(q + 1);
@@ -820,7 +854,7 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
               }
               const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
               if (pb > pa && !qdone) {
-                piece(r, geo, t0, t1, ax0, ax1, pa, pb, dcol, dnrm, dg);
+                piece(r, geo, t0, t1, ax0, ax1, pa, pb, dcol, dnrm, dg, false, true);
                 hit = true;
               }
               if (t1 > qe) { qe = t0; continue; }
