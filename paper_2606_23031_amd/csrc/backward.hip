@@ -1281,17 +1281,27 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   std::vector<int64_t>& lstart = st->lstart_keep.back();
   for (int k = 0; k < n_oct; ++k)
     lstart[k + 1] = lstart[k] + ((scene->desc[k].n_voxels + 63) & ~(int64_t)63);
-  DBuf gin, ogd, lsd, gcol, gnrm, gg8a, gg8b, segbw;
-  DV_TRY(alloc_n<dv_out_grads>(ctx, gin, st->n_views, s));
-  DV_TRY(alloc_n<OctGrad>(ctx, ogd, n_oct, s));
-  DV_TRY(alloc_n<int64_t>(ctx, lsd, (size_t)n_oct + 1, s));
-  DV_TRY_HIP(hipMemcpyAsync(gin.p, st->grads_keep.back().data(),
-                            sizeof(dv_out_grads) * st->n_views,
-                            hipMemcpyHostToDevice, s));
-  DV_TRY_HIP(hipMemcpyAsync(ogd.p, og.data(), sizeof(OctGrad) * n_oct,
-                            hipMemcpyHostToDevice, s));
-  DV_TRY_HIP(hipMemcpyAsync(lsd.p, lstart.data(), sizeof(int64_t) * (n_oct + 1),
-                            hipMemcpyHostToDevice, s));
+  // one upload: per-view gradient planes, per-octree accumulators, leaf
+  // starts
+  DBuf tabs, gin, ogd, lsd, gcol, gnrm, gg8a, gg8b, segbw;
+  {
+    const void* src[3] = {st->grads_keep.back().data(), og.data(), lstart.data()};
+    const size_t len[3] = {sizeof(dv_out_grads) * st->n_views,
+                           sizeof(OctGrad) * n_oct, sizeof(int64_t) * (n_oct + 1)};
+    DBuf* dst[3] = {&gin, &ogd, &lsd};
+    size_t off[3], total = 0;
+    for (int i = 0; i < 3; ++i) {
+      off[i] = total;
+      total += (len[i] + 255) & ~(size_t)255;
+    }
+    DV_TRY(alloc_n<uint8_t>(ctx, tabs, total, s));
+    uint8_t* stage = stage_acquire(total);
+    if (!stage) return DV_ERR_OOM;
+    for (int i = 0; i < 3; ++i) std::memcpy(stage + off[i], src[i], len[i]);
+    DV_TRY_HIP(hipMemcpyAsync(tabs.p, stage, total, hipMemcpyHostToDevice, s));
+    DV_TRY(stage_release(s));
+    for (int i = 0; i < 3; ++i) dst[i]->view_of(tabs.as<uint8_t>() + off[i], len[i]);
+  }
   // per-record gradients in one buffer (colour, corners, normal last, so a
   // render without normals clears three quarters of it)
   DBuf grec;

@@ -171,6 +171,12 @@ __device__ inline float explin_grad(float x, float c, float inv_c) {
 // |L| instead.  Asset segments do the same on their own transmittance.
 // Heaviest-first launch order (render.hip) of n items of weight
 // w[i] - (w0 ? w0[i] : 0).
+// Pinned staging for small per-call host tables (one buffer per host
+// thread): acquire waits for the previous upload from it, release records
+// an event after the upload just enqueued on s.
+uint8_t* stage_acquire(size_t bytes);
+dv_status stage_release(hipStream_t s);
+
 dv_status launch_order_by_weight(int64_t n, const uint32_t* w0, const uint32_t* w,
                                  uint32_t* order, hipStream_t s);
 

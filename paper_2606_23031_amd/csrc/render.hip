@@ -502,12 +502,37 @@ dv_status launch_order_by_weight(int64_t n, const uint32_t* w0, const uint32_t* 
 // slots reserved.  The same for the (tile, actor) lists when range is given
 // (range[e] = [first, end) entries).  One block of 1024 threads, walking the
 // lists in rounds of 1024 consecutive ones (coalesced) with running totals.
-__global__ void __launch_bounds__(1024) k_plan_items(
-    int64_t n_tiles, const uint32_t* start, const uint32_t* bgend,
-    const uint2* range, uint32_t chunk_len, uint32_t max_slots,
-    uint32_t* tile_nck, uint32_t* tile_ibase, uint32_t* tile_pbase,
-    uint32_t* item_tile, uint32_t* item_chunk, uint32_t* order,
-    uint32_t* counts) {
+struct PlanArgs {
+  int64_t n_tiles;
+  const uint32_t* start;
+  const uint32_t* bgend;
+  const uint2* range;
+  uint32_t chunk_len, max_slots;
+  uint32_t* tile_nck;
+  uint32_t* tile_ibase;
+  uint32_t* tile_pbase;
+  uint32_t* item_tile;
+  uint32_t* item_chunk;
+  uint32_t* order;
+  uint32_t* counts;
+};
+
+// Block b plans list set b (the background lists and the (tile, actor)
+// lists run side by side).
+__global__ void __launch_bounds__(1024) k_plan_items(PlanArgs p0, PlanArgs p1) {
+  const PlanArgs& P = blockIdx.x == 0 ? p0 : p1;
+  const int64_t n_tiles = P.n_tiles;
+  const uint32_t* start = P.start;
+  const uint32_t* bgend = P.bgend;
+  const uint2* range = P.range;
+  const uint32_t chunk_len = P.chunk_len, max_slots = P.max_slots;
+  uint32_t* tile_nck = P.tile_nck;
+  uint32_t* tile_ibase = P.tile_ibase;
+  uint32_t* tile_pbase = P.tile_pbase;
+  uint32_t* item_tile = P.item_tile;
+  uint32_t* item_chunk = P.item_chunk;
+  uint32_t* order = P.order;
+  uint32_t* counts = P.counts;
   __shared__ uint32_t wsum[17];
   __shared__ uint32_t cnt[256];
   __shared__ uint32_t off[256];
@@ -1445,7 +1470,7 @@ static HostStage& host_stage() {
   static thread_local HostStage h;
   return h;
 }
-static uint8_t* stage_acquire(size_t bytes) {
+uint8_t* stage_acquire(size_t bytes) {
   HostStage& h = host_stage();
   if (h.pending) {
     (void)hipEventSynchronize(h.ev);
@@ -1472,7 +1497,7 @@ static uint8_t* stage_acquire(size_t bytes) {
   }
   return h.p;
 }
-static dv_status stage_release(hipStream_t s) {
+dv_status stage_release(hipStream_t s) {
   HostStage& h = host_stage();
   DV_TRY_HIP(hipEventRecord(h.ev, s));
   h.pending = true;
@@ -1753,6 +1778,8 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   DV_TRY(alloc_n<float4>(ctx, st->chunk_part, st->max_slots * TPB * 4, s));
   DV_TRY(fill_u32(st->item_work.as<uint32_t>(), 0u, st->max_items, s));
   // actor work items: (tile, actor) lists, long ones split into chunks
+  PlanArgs plans[2];
+  int n_plans = 0;
   if (na > 0) {
     st->max_aitems = na + st->n_pairs / ACHUNK + 1;
     st->max_aslots = std::min<int64_t>(2 * (st->n_pairs / ACHUNK) + 1,
@@ -1765,23 +1792,28 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
     DV_TRY(alloc_n<uint32_t>(ctx, st->pair_pbase, na, s));
     DV_TRY(alloc_n<uint32_t>(ctx, st->aplan_counts, 2, s));
     DV_TRY(alloc_n<float4>(ctx, st->apart, st->max_aslots * TPB * 4, s));
-    hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(1024), 0, s, na,
-                       (const uint32_t*)nullptr, (const uint32_t*)nullptr,
-                       st->act_sub.as<uint2>(), ACHUNK, (uint32_t)st->max_aslots,
-                       st->pair_nck.as<uint32_t>(), st->pair_ibase.as<uint32_t>(),
-                       st->pair_pbase.as<uint32_t>(), st->aitem_pair.as<uint32_t>(),
-                       st->aitem_chunk.as<uint32_t>(), st->aorder.as<uint32_t>(),
-                       st->aplan_counts.as<uint32_t>());
-    DV_TRY_HIP(hipGetLastError());
+    plans[n_plans++] = PlanArgs{na, nullptr, nullptr, st->act_sub.as<uint2>(), ACHUNK,
+                                (uint32_t)st->max_aslots, st->pair_nck.as<uint32_t>(),
+                                st->pair_ibase.as<uint32_t>(),
+                                st->pair_pbase.as<uint32_t>(),
+                                st->aitem_pair.as<uint32_t>(),
+                                st->aitem_chunk.as<uint32_t>(),
+                                st->aorder.as<uint32_t>(),
+                                st->aplan_counts.as<uint32_t>()};
   }
-  if (nt > 0) {
-    hipLaunchKernelGGL(k_plan_items, dim3(1), dim3(1024), 0, s, nt,
-                       st->tile_start.as<uint32_t>(), st->tile_bgend.as<uint32_t>(),
-                       (const uint2*)nullptr, CHUNK, (uint32_t)st->max_slots,
-                       st->tile_nck.as<uint32_t>(), st->tile_ibase.as<uint32_t>(),
-                       st->tile_pbase.as<uint32_t>(), st->item_tile.as<uint32_t>(),
-                       st->item_chunk.as<uint32_t>(), st->order_fwd.as<uint32_t>(),
-                       st->plan_counts.as<uint32_t>());
+  if (nt > 0)
+    plans[n_plans++] = PlanArgs{nt, st->tile_start.as<uint32_t>(),
+                                st->tile_bgend.as<uint32_t>(), nullptr, CHUNK,
+                                (uint32_t)st->max_slots, st->tile_nck.as<uint32_t>(),
+                                st->tile_ibase.as<uint32_t>(),
+                                st->tile_pbase.as<uint32_t>(),
+                                st->item_tile.as<uint32_t>(),
+                                st->item_chunk.as<uint32_t>(),
+                                st->order_fwd.as<uint32_t>(),
+                                st->plan_counts.as<uint32_t>()};
+  if (n_plans > 0) {
+    hipLaunchKernelGGL(k_plan_items, dim3(n_plans), dim3(1024), 0, s, plans[0],
+                       plans[n_plans - 1]);
     DV_TRY_HIP(hipGetLastError());
   }
   tm_dir.stop();
