@@ -252,12 +252,15 @@ dv_status dv_render(dv_ctx* ctx, const dv_scene* scene, const dv_view* views,
  * segment; pose gradients go beyond the paper, which keeps tracks fixed).
  * Re-walks every pixel's pieces in forward order with identical FP32
  * arithmetic, accumulating gradients of corner densities, SH coefficients
- * and actor poses (R, p) into `acc` (corners and poses with wave-reduced
- * atomics; SH by one kernel launch per view, in which every leaf has at
- * most one record, with plain read-modify-write, so the SH accumulators of
- * different octrees must not overlap).  g: host array [n_views] of device
- * gradient planes.  Corner/SH/pose values must be those used by the
- * forward call. */
+ * and actor poses (R, p) into `acc`.  Poses use wave-reduced atomics.
+ * Corner and SH gradients are added per record (SH by one kernel launch
+ * per view, in which every leaf has at most one record, with plain
+ * read-modify-write; corners by atomics), or, when the launch holds more
+ * than 1.5 records per leaf (several views), per leaf after summing its
+ * records over the views (one SH read-modify-write and 8 corner atomics
+ * per leaf).  Either way the SH accumulators of different octrees must
+ * not overlap.  g: host array [n_views] of device gradient planes.
+ * Corner/SH/pose values must be those used by the forward call. */
 dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
                              const dv_fwd_state* state,
                              const dv_out_grads* g, const dv_param_grads* acc,
