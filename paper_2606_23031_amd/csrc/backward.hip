@@ -493,18 +493,41 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
         }
         continue;
       }
-      while (m != 0 && __ballot(live()) != 0) {
+      while (m != 0) {
+        const uint64_t lm = __ballot(live());
+        if (lm == 0) break;
         const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
         m &= m - 1;
+        const float4 geo = B.geo[r];
+        float t0, t1;
+        batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
+        t0 = fmaxf(t0, a.tau_near);
+        const bool chord = live() && t1 > t0;
+        // when no lane's chord meets a segment (nothing excluded at its
+        // start, no segment starting before its end) every lane has at most
+        // the one piece [t0, t1): the plain walk's straight-line code
+        const bool plain = !chord || (excl <= t0 && ns >= t1);
+        if (__ballot(!plain) == 0) {
+          w_test += (uint32_t)__popcll(lm);
+          const uint64_t hm = __ballot(chord);
+          if (hm == 0) continue;
+          w_piece += (uint32_t)__popcll(hm);
+          const float pa = chord ? t0 : 0.0f, pb = chord ? t1 : 0.0f;
+          PieceDer pd;
+          const float tau = piece_eval<1, KC>(geo, B.ga[r], B.gb[r], B.cn[r].w,
+                                              d, pa, pb, K, invK, a.c, a.inv_c,
+                                              &pd);
+          float3 dcol, dnrm = make_float3(0, 0, 0);
+          float dg[8], wg;
+          piece_grad(r, tau, pd, pa, pb, dcol, dnrm, dg, wg, true);
+          accum_record<NORMALS>(B, r, chord, dcol, dnrm, dg);
+          continue;
+        }
         float3 dcol = make_float3(0, 0, 0), dnrm = make_float3(0, 0, 0);
         float dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         bool hit = false;
         if (live()) {
-          const float4 geo = B.geo[r];
-          float t0, t1;
-          batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
           ++n_test;
-          t0 = fmaxf(t0, a.tau_near);
           if (t1 > t0) {
             float pa = fmaxf(t0, excl);
             bool a_seg = excl > t0;

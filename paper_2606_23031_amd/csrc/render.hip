@@ -1122,15 +1122,26 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
         }
         continue;
       }
-      while (m != 0 && __ballot(live()) != 0) {
+      while (m != 0) {
+        const uint64_t lm = __ballot(live());
+        if (lm == 0) break;
         const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
         m &= m - 1;
-        if (!live()) continue;
         const float4 geo = B.geo[r];
         float t0, t1;
         batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
-        ++n_test;
         t0 = fmaxf(t0, a.tau_near);
+        const bool chord = live() && t1 > t0;
+        // no lane's chord meets a segment: one piece [t0, t1) per chord
+        const bool plain = !chord || (excl <= t0 && ns >= t1);
+        if (__ballot(!plain) == 0) {
+          w_test += (uint32_t)__popcll(lm);
+          w_piece += (uint32_t)__popcll(__ballot(chord));
+          if (chord) add_piece(r, geo, t0, t1);
+          continue;
+        }
+        if (!live()) continue;
+        ++n_test;
         if (!(t1 > t0)) continue;
         float pa = fmaxf(t0, excl);
         while (pa < t1 && live()) {
