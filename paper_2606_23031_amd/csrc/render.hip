@@ -1036,7 +1036,7 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
   const int K = a.K;
   const float invK = 1.0f / (float)K;
   uint32_t n_test = 0, n_piece = 0;
-  uint32_t w_test = 0, w_piece = 0;  // wave-level counts (plain walk)
+  uint32_t w_test = 0, w_piece = 0;  // wave-level counts (straight-line)
   const uint32_t a_beg = a.act_beg[gt];
   const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
   const uint32_t seg0 = 3 * a_beg + n_at;
@@ -1073,9 +1073,9 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
   chunk_range(a.tile_start[gt], a.tile_bgend[gt], nck, chunk, beg, bgend);
   float Bc, Bn;
   chunk_bounds(a, gt, nck, chunk, tid, Bc, Bn);
-  // Waves none of whose pixels has an ownership segment take the plain walk
-  // (a wave-uniform choice); the others splice segments as they come.
-  const bool wseg = __ballot(nseg > 0) != 0;
+  // An entry takes the straight-line iteration (one piece per chord) when no
+  // lane's chord meets a segment, which always holds for lanes without
+  // segments (excl = -inf, ns = +inf); only the other entries splice.
   int qn = 0;
   while (qn < nseg && a.seg_se[seg_index(seg0 + qn, tid)].x < Bc) ++qn;
   float excl = qn > 0 ? a.seg_se[seg_index(seg0 + qn - 1, tid)].y : -F_INF;
@@ -1104,24 +1104,6 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
     wave_entry_masks(B.rect, nb, bx, by, wm);
     for (int c = 0; c < 4; ++c) {
       uint64_t m = wm[c];
-      if (!wseg) {
-        // plain walk; tests and pieces counted from the wave's ballots
-        while (m != 0) {
-          const uint64_t lm = __ballot(live());
-          if (lm == 0) break;
-          const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
-          m &= m - 1;
-          w_test += (uint32_t)__popcll(lm);
-          const float4 geo = B.geo[r];
-          float t0, t1;
-          batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
-          t0 = fmaxf(t0, a.tau_near);
-          const bool hit = live() && t1 > t0;
-          w_piece += (uint32_t)__popcll(__ballot(hit));
-          if (hit) add_piece(r, geo, t0, t1);
-        }
-        continue;
-      }
       while (m != 0) {
         const uint64_t lm = __ballot(live());
         if (lm == 0) break;
