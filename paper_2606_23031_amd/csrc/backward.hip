@@ -1286,6 +1286,7 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   }
   dv_fwd_state* st = const_cast<dv_fwd_state*>(cst);
   DV_TRY_HIP(hipSetDevice(ctx->device));
+  PoolStamp stamp_on_return(ctx);
   reap_states(ctx, false);
   hipStream_t s = (hipStream_t)stream;
   const int64_t nv = st->n_vis, nt = st->n_tiles;

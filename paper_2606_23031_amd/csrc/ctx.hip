@@ -1,4 +1,5 @@
 // Context, error reporting, device memory pool and small fill kernels.
+#include <algorithm>
 #include <cstdarg>
 #include <cstring>
 
@@ -19,13 +20,16 @@ void set_error(const char* fmt, ...) {
 
 const char* get_error() { return g_err.c_str(); }
 
+static thread_local bool t_release_idle = false;
+
+IdleRelease::IdleRelease() { t_release_idle = true; }
+IdleRelease::~IdleRelease() { t_release_idle = false; }
+
 Pool::~Pool() {
   hipSetDevice(device_);
-  for (auto& kv : free_) {
-    hipEventDestroy(kv.second.ev);
-    hipFree(kv.second.p);
-  }
+  for (auto& kv : free_) hipFree(kv.second.p);
   for (auto& kv : live_) hipFree(kv.first);
+  for (auto& kv : ev_refs_) hipEventDestroy(kv.first);
   for (auto e : spare_events_) hipEventDestroy(e);
 }
 
@@ -40,6 +44,17 @@ static size_t round_size(size_t b) {
   return (b + g - 1) / g * g;
 }
 
+// caller holds mu_
+void Pool::drop_event(hipEvent_t ev) {
+  if (!ev) return;
+  auto it = ev_refs_.find(ev);
+  if (it == ev_refs_.end()) return;
+  if (--it->second == 0) {
+    spare_events_.push_back(ev);
+    ev_refs_.erase(it);
+  }
+}
+
 void* Pool::alloc(size_t bytes, hipStream_t s) {
   size_t want = round_size(bytes);
   {
@@ -47,11 +62,12 @@ void* Pool::alloc(size_t bytes, hipStream_t s) {
     auto it = free_.lower_bound(want);
     while (it != free_.end() && it->first <= 2 * want) {
       Block& b = it->second;
-      if (b.stream == s || hipEventQuery(b.ev) == hipSuccess) {
+      if (b.idle || b.stream == s ||
+          (b.ev && hipEventQuery(b.ev) == hipSuccess)) {
         void* p = b.p;
         live_[p] = b.size;
         in_use_ += b.size;
-        spare_events_.push_back(b.ev);
+        drop_event(b.ev);
         free_.erase(it);
         return p;
       }
@@ -81,24 +97,65 @@ void Pool::release(void* p, hipStream_t s) {
   b.p = p;
   b.size = it->second;
   b.stream = s;
-  if (!spare_events_.empty()) {
-    b.ev = spare_events_.back();
-    spare_events_.pop_back();
-  } else {
-    hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
-  }
-  hipEventRecord(b.ev, s);
+  b.ev = nullptr;
+  b.idle = t_release_idle;
   in_use_ -= b.size;
   live_.erase(it);
   free_.emplace(b.size, b);
+  if (!b.idle) {
+    bool seen = false;
+    for (hipStream_t q : pending_) seen = seen || q == s;
+    if (!seen) pending_.push_back(s);
+  }
+}
+
+void Pool::stamp() {
+  std::lock_guard<std::mutex> lk(mu_);
+  for (hipStream_t s : pending_) {
+    hipEvent_t ev = nullptr;
+    if (!spare_events_.empty()) {
+      ev = spare_events_.back();
+      spare_events_.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      ev = nullptr;
+    }
+    if (ev && hipEventRecord(ev, s) != hipSuccess) {
+      // left unstamped: such blocks are reused on their own stream only
+      (void)hipGetLastError();
+      spare_events_.push_back(ev);
+      ev = nullptr;
+    }
+    if (!ev) continue;
+    int n = 0;
+    for (auto& kv : free_) {
+      Block& b = kv.second;
+      if (!b.idle && !b.ev && b.stream == s) {
+        b.ev = ev;
+        ++n;
+      }
+    }
+    if (n > 0) ev_refs_[ev] += n;
+    else spare_events_.push_back(ev);
+  }
+  pending_.clear();
 }
 
 void Pool::trim() {
+  // a block's last use is enqueued before it is freed: the blocks free now
+  // are unused once the device is idle (blocks freed meanwhile are kept)
+  std::vector<void*> snap;
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto& kv : free_) snap.push_back(kv.second.p);
+  }
+  if (hipDeviceSynchronize() != hipSuccess) (void)hipGetLastError();
+  std::sort(snap.begin(), snap.end());
   std::lock_guard<std::mutex> lk(mu_);
   for (auto it = free_.begin(); it != free_.end();) {
-    if (hipEventQuery(it->second.ev) == hipSuccess) {
+    if (std::binary_search(snap.begin(), snap.end(), it->second.p)) {
       hipFree(it->second.p);
-      spare_events_.push_back(it->second.ev);
+      drop_event(it->second.ev);
       it = free_.erase(it);
     } else {
       ++it;

@@ -10,6 +10,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/dv.h"
@@ -37,15 +38,22 @@ const char* get_error();
   } while (0)
 
 // ------------------------------------------------------------------ memory
-// Stream-aware caching pool: a freed block is reusable at once on the stream
-// that freed it (stream order) and on any other stream after the event
-// recorded at free time has completed.
+// Stream-aware caching pool. A freed block is reusable at once on the
+// stream that freed it (stream order). For other streams it waits for a
+// stamp: each library call, as it returns, records one event per stream on
+// which it freed blocks (stamp()) and attaches it to those blocks, and
+// another stream takes such a block once that event has completed. (An
+// event recorded per free would put a marker between kernels in the queue
+// for every buffer; one per call does not.) Blocks freed after their last
+// use is known to be complete (IdleRelease) are reusable by any stream.
 class Pool {
  public:
   explicit Pool(int device) : device_(device) {}
   ~Pool();
   void* alloc(size_t bytes, hipStream_t s);
   void release(void* p, hipStream_t s);
+  // record one event on each stream that freed blocks since the last stamp
+  void stamp();
   void trim();
   size_t bytes_in_use() const { return in_use_; }
 
@@ -54,14 +62,25 @@ class Pool {
     void* p;
     size_t size;
     hipStream_t stream;
-    hipEvent_t ev;
+    hipEvent_t ev;  // stamp event, nullptr until stamped
+    bool idle;      // no use pending on any stream
   };
+  void drop_event(hipEvent_t ev);
   std::mutex mu_;
   std::multimap<size_t, Block> free_;
   std::map<void*, size_t> live_;
+  std::vector<hipStream_t> pending_;            // streams with unstamped frees
+  std::unordered_map<hipEvent_t, int> ev_refs_;  // blocks per stamp event
   std::vector<hipEvent_t> spare_events_;
   size_t in_use_ = 0;
   int device_;
+};
+
+// While alive on a thread, blocks freed by that thread are marked idle: for
+// buffers whose last use has been waited for.
+struct IdleRelease {
+  IdleRelease();
+  ~IdleRelease();
 };
 
 // Owning device buffer returned to the pool on destruction.
@@ -132,6 +151,17 @@ struct dv_ctx {
 namespace dv {
 
 dv_status alloc(dv_ctx* ctx, DBuf& b, size_t bytes, hipStream_t s);
+// Declared first in a library call: on return, after the call's own buffers
+// are freed, stamps the blocks freed during the call.
+struct PoolStamp {
+  dv_ctx* ctx;
+  explicit PoolStamp(dv_ctx* c) : ctx(c) {}
+  ~PoolStamp() {
+    if (ctx && ctx->pool) ctx->pool->stamp();
+  }
+  PoolStamp(const PoolStamp&) = delete;
+  PoolStamp& operator=(const PoolStamp&) = delete;
+};
 // Defer deletion of a forward state until its stream has passed this point.
 void retire_state(dv_ctx* ctx, dv_fwd_state* st);
 // Delete retired states whose work has completed (all of them if wait).

@@ -1941,6 +1941,8 @@ void reap_states(dv_ctx* ctx, bool wait) {
       }
     }
   }
+  // their work has completed: the freed blocks are idle
+  IdleRelease idle;
   for (auto& pr : done) {
     hipEventDestroy(pr.first);
     delete pr.second;
@@ -1976,6 +1978,7 @@ dv_status dv_render(dv_ctx* ctx, const dv_scene* scene, const dv_view* views,
   }
   DV_TRY(check_opts(opts));
   DV_TRY_HIP(hipSetDevice(ctx->device));
+  PoolStamp stamp_on_return(ctx);
   hipStream_t s = (hipStream_t)stream;
   std::unique_ptr<dv_fwd_state> st(new dv_fwd_state());
   st->ctx = ctx;

@@ -142,6 +142,7 @@ dv_status dv_build_scene(dv_ctx* ctx, const dv_octree_desc* octrees,
   }
   *out = nullptr;
   DV_TRY_HIP(hipSetDevice(ctx->device));
+  PoolStamp stamp_on_return(ctx);
   std::unique_ptr<dv_scene> sc(new dv_scene());
   sc->ctx = ctx;
   sc->n_oct = n_octrees;
@@ -244,6 +245,7 @@ void dv_scene_destroy(dv_scene* scene) {
   if (!scene) return;
   hipSetDevice(scene->ctx->device);
   hipDeviceSynchronize();
+  IdleRelease idle;
   delete scene;
 }
 

@@ -263,6 +263,7 @@ dv_status dv_serve_destroy(dv_server* srv) {
   // retired forward states release their buffers with events on the
   // worker streams: free them while those streams still exist
   reap_states(srv->ctx, true);
+  srv->ctx->pool->stamp();
   for (auto s : srv->streams) hipStreamDestroy(s);
   delete srv;
   return DV_OK;
