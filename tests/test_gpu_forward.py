@@ -190,3 +190,31 @@ def test_forward_deterministic(ctx):
     b, _, _ = render_gpu(ctx, cfg["scene"], [v], cfg["opts"])
     for k in ("rgb", "depth", "normal", "T"):
         assert np.array_equal(a[0][k], b[0][k])
+
+
+def test_two_streams_share_the_pool(ctx):
+    """Renders alternating between two streams with no synchronisation in
+    between: buffers freed by a call on one stream are reused by the other
+    only after that call's stamp event, so every result equals the
+    default-stream render bit for bit."""
+    import torch
+    from paper_2606_23031_amd import dv
+    from gpu_helpers import render_gpu
+    cfg = actor_scene(seed=7, n_actors=2, deg=3)
+    v = cfg["views"][0]
+    ref, _, sc = render_gpu(ctx, cfg["scene"], [v], cfg["opts"])
+    mask = dv.DV_OUT_RGB | dv.DV_OUT_DEPTH | dv.DV_OUT_NORMAL | dv.DV_OUT_T
+    copts = dv.make_opts(cfg["opts"], mask)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    results = []
+    for i in range(8):
+        s = streams[i % 2]
+        with torch.cuda.stream(s):
+            outs = dv.alloc_outputs([v], mask)
+            dv.dv_render(ctx, sc, [v], copts, outs, stream=s)
+        results.append(outs[0])
+    torch.cuda.synchronize()
+    for i, o in enumerate(results):
+        for k in ("rgb", "depth", "normal", "T"):
+            got = o[k].cpu().numpy().astype(np.float64)
+            assert np.array_equal(got, ref[0][k]), (i, k)
