@@ -4,7 +4,7 @@ Sec. 3.4 says gradients flow through each voxel segment independently; the
 paper keeps tracks fixed (Sec. 5) and names pose optimisation as future
 work, so the pose gradient here goes beyond it.  With per-piece value
 v_i = G_C.c_i + G_D (a_i+b_i)/2 + G_N.n_i and the scalar
-L = G_C.(C + T C_bg) + G_D D + G_N.N + G_T T, the derivative of L with
+L = G_C.(C + T C_sky) + G_D D + G_N.N + G_T T, the derivative of L with
 respect to the optical depth of piece i is
     dL/dtau_i = T_{i+1} v_i - (L - sum_{j<=i} w_j v_j),
 which needs no division by (1 - alpha).  Pose enters through the ray in
@@ -19,6 +19,7 @@ from . import geometry as G
 from . import field as F
 from . import sh as SH
 from . import render as RD
+from . import sky as SKY
 
 _GW_CENTRE = F.trilinear_weight_grads(np.full(3, 0.5))       # [8,3]
 
@@ -36,11 +37,16 @@ def new_accumulators(ctx):
         acc["dnw"].append(np.zeros((n, 3)))
         acc["dR"].append(np.zeros((3, 3)))
         acc["dp"].append(np.zeros(3))
+    # sky texture gradient (the map is sampled per ray, Eq. 2)
+    acc["sky"] = None if ctx.sky is None else np.zeros_like(ctx.sky)
     return acc
 
 
 def ray_adjoint(ctx, o, d, gC, gD, gN, gT, acc):
     res, pc, smp = RD.render_ray(ctx, o, d)
+    if ctx.sky is not None:
+        # dL/dC_sky = T_final G_C, spread over the four bilinear taps
+        SKY.scatter_grad(acc["sky"], d, res["T"] * np.asarray(gC, np.float64))
     n = res["nproc"]
     if n == 0:
         return res
@@ -106,7 +112,8 @@ def ray_adjoint(ctx, o, d, gC, gD, gN, gT, acc):
 def finalize(ctx, acc):
     """Per-leaf colour and normal gradients -> SH coefficients, corners
     (through normals) and poses (SH direction, normal rotation)."""
-    out = dict(corner=[], corner_abs=[], sh=[], sh_abs=[], dR=[], dp=[])
+    out = dict(corner=[], corner_abs=[], sh=[], sh_abs=[], dR=[], dp=[],
+               sky=acc.get("sky"))
     for k, o in enumerate(ctx.scene["octrees"]):
         ent = ctx.oct[k]
         dcol = acc["dcol"][k] * (ent["raw"] > 0)

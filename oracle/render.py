@@ -27,6 +27,7 @@ import numpy as np
 from . import geometry as G
 from . import field as F
 from . import sh as SH
+from . import sky as SKY
 
 NO_SRC = (-1, -1)
 
@@ -43,6 +44,9 @@ class ViewContext:
         self.tau_near = float(opts.get("tau_near", 0.0))
         self.c = float(opts.get("explin_c", 1.1))
         self.bg = np.asarray(opts.get("bg", (0.0, 0.0, 0.0)), np.float64)
+        # sky environment map [3][H][W] (Sec. 3.1); None: the constant bg
+        sky = opts.get("sky")
+        self.sky = None if sky is None else np.asarray(sky, np.float64)
         self.cam = view["c2w"][:, 3].astype(np.float64)
         self.poses = G.octree_poses(scene, view, pose_override)
         self.oct = []
@@ -194,8 +198,10 @@ def piece_samples(ctx, pc):
                 d_k=d_k, vmin=vmin, h=h, g8=g8)
 
 
-def composite(ctx, pc, smp):
-    """Front-to-back compositing of sorted pieces with the stop test."""
+def composite(ctx, pc, smp, c_sky=None):
+    """Front-to-back compositing of sorted pieces with the stop test, then
+    the sky behind them (Eq. 2): c_sky, else the constant bg."""
+    c_sky = ctx.bg if c_sky is None else c_sky
     n = pc["a"].shape[0]
     e = np.exp(-smp["tau"])
     Tb = np.ones(n)
@@ -215,7 +221,7 @@ def composite(ctx, pc, smp):
     C = (w[:, None] * col).sum(0)
     D = float((w * mid).sum())
     N = (w[:, None] * nw).sum(0)
-    return dict(rgb=C + T * ctx.bg, C=C, depth=D, normal=N, T=T,
+    return dict(rgb=C + T * c_sky, C=C, depth=D, normal=N, T=T,
                 nproc=nproc, e=e[sl], Tb=Tb[sl], w=w, col=col, nw=nw,
                 mid=mid)
 
@@ -223,7 +229,8 @@ def composite(ctx, pc, smp):
 def render_ray(ctx, o, d):
     pc = ray_pieces(ctx, o, d)
     smp = piece_samples(ctx, pc)
-    return composite(ctx, pc, smp), pc, smp
+    c_sky = None if ctx.sky is None else SKY.sample(ctx.sky, d)
+    return composite(ctx, pc, smp, c_sky), pc, smp
 
 
 def window_pixels(view):

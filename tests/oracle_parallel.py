@@ -30,6 +30,7 @@ def _grad_chunk(args):
         out[key] = lst
     out["dR"] = acc["dR"]
     out["dp"] = acc["dp"]
+    out["sky"] = acc["sky"]
     return out
 
 
@@ -50,5 +51,7 @@ def render_and_grad_parallel(scene, view, opts, grads, pixels, procs):
         for k in range(len(acc["dR"])):
             acc["dR"][k] += part["dR"][k]
             acc["dp"][k] += part["dp"][k]
+        if acc["sky"] is not None:
+            acc["sky"] += part["sky"]
     _CTX = None
     return AD.finalize(ctx, acc)
