@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--sky-map", default="512x1024",
+                    help="HxW of the sky environment map timed after the "
+                         "headline step (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-saturate", type=int, default=400,
@@ -60,13 +63,16 @@ def parse():
 class Step:
     """Forward + L1 loss gradient + backward for one batch of views."""
 
-    def __init__(self, ctx, dv, scene_dict, views, opts):
+    def __init__(self, ctx, dv, scene_dict, views, opts, sky=None, sc=None):
         import torch
         self.torch, self.dv, self.ctx = torch, dv, ctx
         self.views = views
         self.mask = dv.DV_OUT_RGB | dv.DV_OUT_DEPTH | dv.DV_OUT_T
-        self.copts = dv.make_opts(opts, self.mask)
-        self.sc = dv.Scene(ctx, scene_dict)
+        # optional sky environment map [3][H][W] and its gradient
+        self.sky = sky
+        self.sky_grad = None if sky is None else torch.zeros_like(sky)
+        self.copts = dv.make_opts(dict(opts, sky=sky), self.mask)
+        self.sc = sc or dv.Scene(ctx, scene_dict)
         self.outs = dv.alloc_outputs(views, self.mask)
         g = torch.Generator(device="cpu").manual_seed(1234)
         self.targets = [torch.rand(3, v["h"], v["w"], generator=g).cuda()
@@ -81,6 +87,8 @@ class Step:
         # gradient buffers cleared each step by one multi-tensor launch
         self.zero_list = ([a["corner"] for a in self.acc] +
                           [a["sh"] for a in self.acc] + [self.pose])
+        if self.sky_grad is not None:
+            self.zero_list.append(self.sky_grad)
         self.npix = sum(v["w"] * v["h"] for v in views)
         self.last_info = None
 
@@ -94,7 +102,7 @@ class Step:
             g["rgb"].mul_(1.0 / self.npix / 3.0)
         torch._foreach_zero_(self.zero_list)
         dv.dv_render_backward(self.ctx, self.sc, st, self.grads, self.acc,
-                              self.pose)
+                              self.pose, sky_grad=self.sky_grad)
         if info:
             self.last_info = dv.dv_fwd_state_info(st)
         dv.dv_fwd_state_release(st)
@@ -385,6 +393,25 @@ def main():
                                for k, v in stages.items() if v[1] > 0},
         "stages_ms_p50_p10_p90": spread,
     }
+    if args.sky_map != "0":
+        # the same step with a sky environment map: bilinear C_sky per pixel
+        # in the composite, T_final G_C scattered into the map's gradient
+        H, W = (int(x) for x in args.sky_map.lower().split("x"))
+        g = torch.Generator(device="cpu").manual_seed(99)
+        sky = torch.rand(3, H, W, generator=g).cuda()
+        sstep = Step(ctx, dv, cfg["scene"], views, cfg["opts"], sky=sky, sc=step.sc)
+        for _ in range(args.warmup):
+            sstep()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            sstep()
+        torch.cuda.synchronize()
+        sms = (time.perf_counter() - t0) / args.steps * 1e3
+        log(f"[bench] with a {H}x{W} sky map: {sms:.3f} ms/step")
+        out["sky"] = {"map": [3, H, W], "ms_per_step": round(sms, 4),
+                      "ms_per_step_constant_bg": round(ms, 4)}
+        del sstep
     if args.serve_requests > 0 and args.config == 2:
         sv = serve_views(args.serve_requests, seed=4)
         log(f"[bench] serving {len(sv)} requests at {args.serve_rate}/s ...")

@@ -114,15 +114,25 @@ typedef struct {
   int32_t K;                    /* midpoint samples per piece, 1..16       */
   float eps_stop;               /* stop a ray once T < eps_stop (Alg. 1)   */
   float tau_near;               /* rays start at tau_near >= 0             */
-  float bg[3];                  /* constant sky colour C_sky (Eq. 2)       */
+  float bg[3];                  /* constant sky colour C_sky (Eq. 2), used
+                                   when sky is NULL                        */
   float explin_c;               /* knee of the exp-linear activation, > 0  */
   uint32_t out_mask;            /* DV_OUT_* bits                           */
+  /* Sky environment map (Sec. 3.1; Eq. 2): device float [3][sky_h][sky_w],
+   * caller-owned, or NULL for the constant bg.  A ray's world direction d
+   * (z up) maps to longitude atan2(d_y, d_x) and colatitude acos(d_z);
+   * u = (lon + pi) / (2 pi) sky_w - 1/2, v = colat / pi sky_h - 1/2 (texel
+   * (i, j) centred at u = i, v = j), sampled bilinearly with columns
+   * wrapping in longitude and rows clamped at the poles.  sky_w, sky_h >= 1
+   * when sky is set (DV_ERR_INVALID otherwise). */
+  const float* sky;
+  int32_t sky_w, sky_h;
 } dv_render_opts;
 
 /* Per-view device output planes (window-sized, float).  Entries not in
  * out_mask may be NULL. */
 typedef struct {
-  float* rgb;                   /* [3][h][w]  C_voxels + T * bg            */
+  float* rgb;                   /* [3][h][w]  C_voxels + T * C_sky         */
   float* depth;                 /* [h][w]     sum w_i (a_i + b_i) / 2      */
   float* normal;                /* [3][h][w]  sum w_i R n_i (world frame)  */
   float* T;                     /* [h][w]     final transmittance          */
@@ -147,6 +157,8 @@ typedef struct {
   const dv_octree_grads* octrees; /* host array [n_octrees]                */
   float* pose;                  /* device [n_views][n_actors][12] or NULL:
                                    dL/dR row-major (9) then dL/dp (3)      */
+  float* sky;                   /* device [3][sky_h][sky_w] or NULL: dL/dsky
+                                   added (atomics); ignored without a map  */
 } dv_param_grads;
 
 typedef struct {

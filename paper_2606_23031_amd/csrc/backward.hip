@@ -316,13 +316,116 @@ __global__ void __launch_bounds__(TPB) k_chunk_prep(CompArgs a) {
     a.chunk_tps[s0 + (size_t)c * TPB] = make_float2(T, 0.0f);
     T *= part[(size_t)c * TPB * 4 + 1].w;
   }
-  float S = (g.GC.x * a.bg[0] + g.GC.y * a.bg[1] + g.GC.z * a.bg[2] + g.GT) * T;
+  const float3 cs = sky_colour(a, P.d);
+  float S = (g.GC.x * cs.x + g.GC.y * cs.y + g.GC.z * cs.z + g.GT) * T;
   for (uint32_t c = nck; c-- > 0;) {
     const size_t q = (size_t)c * TPB;
     const float Tp = a.chunk_tps[s0 + q].x;
     a.chunk_tps[s0 + q] = make_float2(Tp, S);
     const float Vc = gdot(g, part[q * 4], part[q * 4 + 1]);
     S = fmaf(Tp, Vc, S);
+  }
+}
+
+// Sky map gradient (Eq. 2): the pixel's C_sky enters C with weight
+// T_final, so dL/dC_sky = T_final G_C, spread over the four bilinear taps.
+// One block per tile; T_final is the product of the chunks' transmittances
+// for a chunked tile. A tile's pixels fall on a few neighbouring texels, so
+// the block sums its taps in LDS over its texel footprint (columns counted
+// from a reference column, so the footprint may straddle the wrap) and adds
+// each texel once to the map's gradient; a footprint larger than the LDS
+// table adds every tap directly.
+constexpr int SKY_LDS = 256;  // texels per block table
+template <bool NORMALS>
+__global__ void __launch_bounds__(TPB) k_sky_bwd(CompArgs a) {
+  __shared__ float tab[3][SKY_LDS];
+  __shared__ int box[4];  // min row, max row, min column, max column
+  const uint32_t gt = blockIdx.x;
+  const int tid = threadIdx.x;
+  const PixSetup P = pixel_setup(a, gt, tid);
+  const int W = a.sky_w, H = a.sky_h;
+  const size_t hw = (size_t)W * H;
+  float3 gs = make_float3(0, 0, 0);
+  SkyTaps t;
+  if (P.valid) {
+    const PixGrad g = pixel_grads<NORMALS>(a, P);
+    const uint32_t nck = a.tile_nck[gt];
+    float T;
+    if (nck <= 1) {
+      T = a.fin1[P.pix].w;
+    } else {
+      const size_t s0 = (size_t)a.tile_pbase[gt] * TPB + tid;
+      const float4* part = a.chunk_part + s0 * 4;
+      T = 1.0f;
+      for (uint32_t c = 0; c < nck; ++c) T *= part[(size_t)c * TPB * 4 + 1].w;
+    }
+    gs = make_float3(T * g.GC.x, T * g.GC.y, T * g.GC.z);
+    t = sky_taps(a, P.d);
+  }
+  const bool act = gs.x != 0.0f || gs.y != 0.0f || gs.z != 0.0f;
+  // reference column: the tile's centre pixel direction is not needed; any
+  // fixed column works as long as every tap is counted from it
+  const PixSetup Pc = pixel_setup(a, gt, 0);
+  const int ref = sky_taps(a, Pc.d).o[0] % W;
+  int r0 = 0, r1 = 0, c0 = 0;
+  if (act) {
+    r0 = t.o[0] / W;
+    r1 = t.o[2] / W;
+    int dc = t.o[0] % W - ref;
+    if (dc < 0) dc += W;
+    if (2 * dc > W) dc -= W;
+    c0 = dc;
+  }
+  if (tid == 0) {
+    box[0] = H; box[1] = -1; box[2] = W; box[3] = -W;
+  }
+  __syncthreads();
+  if (act) {
+    atomicMin(&box[0], r0);
+    atomicMax(&box[1], r1);
+    atomicMin(&box[2], c0);
+    atomicMax(&box[3], c0 + 1);
+  }
+  __syncthreads();
+  if (box[1] < 0) return;  // no pixel of the tile adds anything
+  const int rmin = box[0], ncol = box[3] - box[2] + 1, cmin = box[2];
+  const int nrow = box[1] - rmin + 1;
+  if (nrow * ncol > SKY_LDS) {
+    if (act) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (t.w[k] == 0.0f) continue;
+        atomicAdd(a.sky_grad + t.o[k], t.w[k] * gs.x);
+        atomicAdd(a.sky_grad + hw + t.o[k], t.w[k] * gs.y);
+        atomicAdd(a.sky_grad + 2 * hw + t.o[k], t.w[k] * gs.z);
+      }
+    }
+    return;
+  }
+  for (int i = tid; i < 3 * SKY_LDS; i += TPB) (&tab[0][0])[i] = 0.0f;
+  __syncthreads();
+  if (act) {
+    // taps 0/1 on row r0, 2/3 on row r1; columns c0 and c0 + 1
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int row = (k < 2 ? r0 : r1) - rmin;
+      const int col = c0 + (k & 1) - cmin;
+      const int e = row * ncol + col;
+      atomicAdd(&tab[0][e], t.w[k] * gs.x);
+      atomicAdd(&tab[1][e], t.w[k] * gs.y);
+      atomicAdd(&tab[2][e], t.w[k] * gs.z);
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < nrow * ncol; e += TPB) {
+    int col = (ref + cmin + e % ncol) % W;
+    if (col < 0) col += W;
+    const size_t o = (size_t)(rmin + e / ncol) * W + col;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const float val = tab[ch][e];
+      if (val != 0.0f) atomicAdd(a.sky_grad + ch * hw + o, val);
+    }
   }
 }
 
@@ -368,7 +471,8 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
   if (valid) {
     if (nck == 1) {
       const float4 f1 = a.fin1[pix];
-      Saft = (g.GC.x * a.bg[0] + g.GC.y * a.bg[1] + g.GC.z * a.bg[2] + g.GT) * f1.w;
+      const float3 cs = sky_colour(a, P.d);
+      Saft = (g.GC.x * cs.x + g.GC.y * cs.y + g.GC.z * cs.z + g.GT) * f1.w;
       S = gdot(g, a.fin0[pix], f1);
       ST = gdot(g, a.fin2[pix], a.fin3[pix]);
     } else {
@@ -1388,6 +1492,10 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   ca.c = op.explin_c;
   ca.inv_c = 1.0f / op.explin_c;
   for (int i = 0; i < 3; ++i) ca.bg[i] = op.bg[i];
+  ca.sky = op.sky;
+  ca.sky_w = op.sky_w;
+  ca.sky_h = op.sky_h;
+  ca.sky_grad = op.sky ? acc->sky : nullptr;
   ca.mask = op.out_mask;
   ca.counters = (ctx->prof_flags.load() & DV_PROFILE_COUNTERS) ? ctx->counters : nullptr;
   ca.item_tile = st->item_tile.as<uint32_t>();
@@ -1436,6 +1544,10 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
         auto kb = normals ? k_box_bwd<true> : k_box_bwd<false>;
         hipLaunchKernelGGL(kb, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
       }
+    }
+    if (ca.sky_grad) {
+      auto ks = normals ? k_sky_bwd<true> : k_sky_bwd<false>;
+      hipLaunchKernelGGL(ks, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
     }
     DV_TRY_HIP(hipGetLastError());
   }

@@ -78,6 +78,9 @@ struct CompArgs {
   float c;
   float inv_c;
   float bg[3];
+  const float* sky;  // sky map [3][sky_h][sky_w] or null (constant bg)
+  int sky_w, sky_h;
+  float* sky_grad;   // dL/dsky accumulator or null
   uint32_t mask;
   unsigned long long* counters;  // work counters or null
 };
@@ -412,6 +415,50 @@ __device__ inline float piece_tau(float4 geo, float4 ga, float4 gb,
 }
 
 // Pixel of thread tid in tile gt and its unit ray direction.
+// Sky environment map (Sec. 3.1, Eq. 2): the unit world direction d (z up)
+// maps to longitude atan2(d_y, d_x) and colatitude acos(d_z), texel (i, j)
+// is centred at u = i, v = j, and the map is sampled bilinearly with
+// columns wrapping in longitude and rows clamped at the poles.
+struct SkyTaps {
+  int o[4];    // texel offsets j * W + i in one [H][W] plane
+  float w[4];  // bilinear weights
+};
+__device__ inline SkyTaps sky_taps(const CompArgs& a, float3 d) {
+  const float kPi = 3.14159265358979f;
+  const int W = a.sky_w, H = a.sky_h;
+  const float lon = atan2f(d.y, d.x);
+  const float colat = acosf(fminf(fmaxf(d.z, -1.0f), 1.0f));
+  const float u = (lon + kPi) * (0.5f / kPi) * (float)W - 0.5f;
+  const float v = colat * (1.0f / kPi) * (float)H - 0.5f;
+  const float u0 = floorf(u), v0 = floorf(v);
+  const float fu = u - u0, fv = v - v0;
+  int i0 = (int)u0 % W;
+  if (i0 < 0) i0 += W;
+  const int i1 = i0 + 1 == W ? 0 : i0 + 1;
+  const int j0 = min(max((int)v0, 0), H - 1);
+  const int j1 = min(max((int)v0 + 1, 0), H - 1);
+  SkyTaps t;
+  t.o[0] = j0 * W + i0; t.w[0] = (1.0f - fu) * (1.0f - fv);
+  t.o[1] = j0 * W + i1; t.w[1] = fu * (1.0f - fv);
+  t.o[2] = j1 * W + i0; t.w[2] = (1.0f - fu) * fv;
+  t.o[3] = j1 * W + i1; t.w[3] = fu * fv;
+  return t;
+}
+// C_sky of the ray: the map's sample, or the constant colour without one.
+__device__ inline float3 sky_colour(const CompArgs& a, float3 d) {
+  if (!a.sky) return make_float3(a.bg[0], a.bg[1], a.bg[2]);
+  const SkyTaps t = sky_taps(a, d);
+  const size_t hw = (size_t)a.sky_w * a.sky_h;
+  float3 c = make_float3(0, 0, 0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    c.x = fmaf(t.w[k], a.sky[t.o[k]], c.x);
+    c.y = fmaf(t.w[k], a.sky[hw + t.o[k]], c.y);
+    c.z = fmaf(t.w[k], a.sky[2 * hw + t.o[k]], c.z);
+  }
+  return c;
+}
+
 struct PixSetup {
   int v;
   int px, py, bx, by;

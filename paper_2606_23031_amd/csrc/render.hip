@@ -708,16 +708,18 @@ __device__ inline int next_seg_of(const CompArgs& a, uint32_t seg0, int nseg,
   return nseg;
 }
 
-// Final composite with the background colour (Eq. 2) into the outputs.
+// Final composite with the sky behind the voxels (Eq. 2) into the outputs;
+// d is the pixel's unit world ray direction.
 __device__ inline void write_outputs(const CompArgs& a, const ViewConst& V, int v,
                                      int px, int py, float3 C3, float D,
-                                     float3 N3, float T) {
+                                     float3 N3, float T, float3 d) {
   const dv_outputs& O = a.outs[v];
   const size_t hw = (size_t)V.w * V.h, o = (size_t)py * V.w + px;
   if ((a.mask & DV_OUT_RGB) && O.rgb) {
-    O.rgb[o] = fmaf(T, a.bg[0], C3.x);
-    O.rgb[hw + o] = fmaf(T, a.bg[1], C3.y);
-    O.rgb[2 * hw + o] = fmaf(T, a.bg[2], C3.z);
+    const float3 cs = sky_colour(a, d);
+    O.rgb[o] = fmaf(T, cs.x, C3.x);
+    O.rgb[hw + o] = fmaf(T, cs.y, C3.y);
+    O.rgb[2 * hw + o] = fmaf(T, cs.z, C3.z);
   }
   if ((a.mask & DV_OUT_DEPTH) && O.depth) O.depth[o] = D;
   if ((a.mask & DV_OUT_NORMAL) && O.normal) {
@@ -1178,7 +1180,7 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
   a.fin1[pix] = make_float4(N3.x, N3.y, N3.z, T);
   a.fin2[pix] = make_float4(CT.x, CT.y, CT.z, DT);
   a.fin3[pix] = make_float4(NT.x, NT.y, NT.z, 0.0f);
-  write_outputs(a, V, v, px, py, C3, D, N3, T);
+  write_outputs(a, V, v, px, py, C3, D, N3, T, d);
 }
 
 // Forward, part 4 (tiles of several chunks): merge the chunk partials in
@@ -1206,7 +1208,7 @@ __global__ void __launch_bounds__(TPB) k_chunk_merge(CompArgs a) {
   a.fin1[P.pix] = make_float4(N3.x, N3.y, N3.z, T);
   a.fin2[P.pix] = make_float4(0, 0, 0, 0);
   a.fin3[P.pix] = make_float4(0, 0, 0, 0);
-  write_outputs(a, V, P.v, P.px, P.py, C3, D, N3, T);
+  write_outputs(a, V, P.v, P.px, P.py, C3, D, N3, T, P.d);
 }
 
 // ------------------------------------------------------------------ host
@@ -1880,6 +1882,10 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   ca.c = op.explin_c;
   ca.inv_c = 1.0f / op.explin_c;
   for (int i = 0; i < 3; ++i) ca.bg[i] = op.bg[i];
+  ca.sky = op.sky;
+  ca.sky_w = op.sky_w;
+  ca.sky_h = op.sky_h;
+  ca.sky_grad = nullptr;
   ca.mask = op.out_mask;
   ca.counters = (ctx->prof_flags.load() & DV_PROFILE_COUNTERS) ? ctx->counters : nullptr;
   if (nt > 0) {
@@ -1954,6 +1960,11 @@ dv_status check_opts(const dv_render_opts* op) {
       !(op->tau_near >= 0.0f) || !(op->explin_c > 0.0f) ||
       !std::isfinite(op->tau_near)) {
     set_error("invalid render options");
+    return DV_ERR_INVALID;
+  }
+  if (op->sky && (op->sky_w < 1 || op->sky_h < 1 ||
+                  (int64_t)op->sky_w * op->sky_h > ((int64_t)1 << 28))) {
+    set_error("invalid sky map size %d x %d", op->sky_w, op->sky_h);
     return DV_ERR_INVALID;
   }
   return DV_OK;

@@ -72,7 +72,8 @@ class dv_view(C.Structure):
 class dv_render_opts(C.Structure):
     _fields_ = [("K", C.c_int32), ("eps_stop", C.c_float),
                 ("tau_near", C.c_float), ("bg", C.c_float * 3),
-                ("explin_c", C.c_float), ("out_mask", C.c_uint32)]
+                ("explin_c", C.c_float), ("out_mask", C.c_uint32),
+                ("sky", C.c_void_p), ("sky_w", C.c_int32), ("sky_h", C.c_int32)]
 
 
 class dv_outputs(C.Structure):
@@ -91,7 +92,7 @@ class dv_octree_grads(C.Structure):
 
 class dv_param_grads(C.Structure):
     _fields_ = [("octrees", C.POINTER(dv_octree_grads)),
-                ("pose", C.c_void_p)]
+                ("pose", C.c_void_p), ("sky", C.c_void_p)]
 
 
 class dv_state_info(C.Structure):
@@ -215,6 +216,16 @@ def make_opts(o, mask=DV_OUT_RGB | DV_OUT_DEPTH | DV_OUT_T):
     co.bg[:] = [float(x) for x in o.get("bg", (0.0, 0.0, 0.0))]
     co.explin_c = float(o.get("explin_c", 1.1))
     co.out_mask = int(o.get("out_mask", mask))
+    # sky map: a float32 CUDA tensor [3][H][W] kept alive by the caller
+    sky = o.get("sky")
+    if sky is not None:
+        if not (hasattr(sky, "is_cuda") and sky.is_cuda and sky.dim() == 3
+                and sky.shape[0] == 3 and sky.is_contiguous()
+                and str(sky.dtype) == "torch.float32"):
+            raise ValueError("opts['sky'] must be a contiguous float32 CUDA "
+                             "tensor [3][H][W]")
+        co.sky = sky.data_ptr()
+        co.sky_h, co.sky_w = int(sky.shape[1]), int(sky.shape[2])
     return co
 
 
@@ -389,7 +400,7 @@ def dv_render(ctx, scene, views, opts, outs, pose_override=None, keep=False,
 
 
 def dv_render_backward(ctx, scene, state, grads, acc_octrees, pose_grad=None,
-                       stream=None):
+                       stream=None, sky_grad=None):
     """grads: list per view of dicts (rgb/depth/normal/T upstream gradient
     tensors or None); acc_octrees: list per octree of dicts with 'corner'
     and 'sh' accumulator tensors (or None)."""
@@ -403,7 +414,7 @@ def dv_render_backward(ctx, scene, state, grads, acc_octrees, pose_grad=None,
     for k, a in enumerate(acc_octrees):
         a = a or {}
         co[k] = dv_octree_grads(_ptr(a.get("corner")), _ptr(a.get("sh")))
-    pg = dv_param_grads(co, _ptr(pose_grad))
+    pg = dv_param_grads(co, _ptr(pose_grad), _ptr(sky_grad))
     _check(_lib.dv_render_backward(ctx, scene.handle, state, cg, C.byref(pg),
                                    _stream_handle(stream)),
            "dv_render_backward")
