@@ -404,16 +404,35 @@ __global__ void __launch_bounds__(TPB) k_sky_bwd(CompArgs a) {
   }
   for (int i = tid; i < 3 * SKY_LDS; i += TPB) (&tab[0][0])[i] = 0.0f;
   __syncthreads();
-  if (act) {
-    // taps 0/1 on row r0, 2/3 on row r1; columns c0 and c0 + 1
+  // taps 0/1 on row r0, 2/3 on row r1; columns c0 and c0 + 1. The lanes of
+  // a wave mostly share a few texels: per texel, the wave sums its lanes'
+  // values and one lane adds them to the table (the loop is wave-uniform:
+  // keys come from ballots and lane reads).
+  const int lane = tid & 63;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int row = (k < 2 ? r0 : r1) - rmin;
-      const int col = c0 + (k & 1) - cmin;
-      const int e = row * ncol + col;
-      atomicAdd(&tab[0][e], t.w[k] * gs.x);
-      atomicAdd(&tab[1][e], t.w[k] * gs.y);
-      atomicAdd(&tab[2][e], t.w[k] * gs.z);
+  for (int k = 0; k < 4; ++k) {
+    const int e = act ? ((k < 2 ? r0 : r1) - rmin) * ncol + c0 + (k & 1) - cmin : -1;
+    const float vx = act ? t.w[k] * gs.x : 0.0f;
+    const float vy = act ? t.w[k] * gs.y : 0.0f;
+    const float vz = act ? t.w[k] * gs.z : 0.0f;
+    uint64_t pend = __ballot(act);
+    while (pend != 0) {
+      const int leader = __builtin_ctzll(pend);
+      const int key = __shfl(e, leader, 64);
+      const bool mine = e == key;
+      pend &= ~__ballot(mine);
+      float sx = mine ? vx : 0.0f, sy = mine ? vy : 0.0f, sz = mine ? vz : 0.0f;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        sx += __shfl_xor(sx, o, 64);
+        sy += __shfl_xor(sy, o, 64);
+        sz += __shfl_xor(sz, o, 64);
+      }
+      if (lane == leader) {
+        atomicAdd(&tab[0][key], sx);
+        atomicAdd(&tab[1][key], sy);
+        atomicAdd(&tab[2][key], sz);
+      }
     }
   }
   __syncthreads();
