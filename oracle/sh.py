@@ -55,21 +55,72 @@ def basis(dirs, degree):
     return out
 
 
-def basis_grad(dirs, degree, eps=1e-6):
+def basis_grad(dirs, degree):
     """d Y / d w [.., S, 3] at unit w, for the unconstrained function
-    Y(w/|w|) (central differences of the exact basis, step ``eps``).
-    Used only for the camera-position term of pose gradients."""
+    Y(w/|w|) (used for the camera-position term of pose gradients).
+
+    Analytic.  With P_l^m(z) = (-1)^m (1 - z^2)^(m/2) P_l^(m)(z), P_l^(m)
+    the m-th derivative of the Legendre polynomial, and
+    (1 - z^2)^(m/2) e^(i m phi) = (x + i y)^m on the unit sphere, the
+    basis above equals on the sphere
+        F = sqrt2 N Re((x + i y)^m) P_l^(m)(z)      (m > 0)
+        F = N P_l(z)                                (m = 0)
+        F = sqrt2 N Im((x + i y)^|m|) P_l^(|m|)(z)  (m < 0).
+    The derivative of w -> w/|w| at unit w is the projection I - w w^T and
+    F agrees with Y on the sphere, so dY/dw = (I - w w^T) grad F(w)."""
     dirs = np.asarray(dirs, np.float64)
-    g = np.zeros(dirs.shape[:-1] + ((degree + 1) ** 2, 3))
-    for a in range(3):
-        e = np.zeros(3)
-        e[a] = eps
-        p = dirs + e
-        q = dirs - e
-        p = p / np.linalg.norm(p, axis=-1, keepdims=True)
-        q = q / np.linalg.norm(q, axis=-1, keepdims=True)
-        g[..., a] = (basis(p, degree) - basis(q, degree)) / (2 * eps)
-    return g
+    x, y, z = dirs[..., 0], dirs[..., 1], dirs[..., 2]
+    u = x + 1j * y
+    gF = np.zeros(dirs.shape[:-1] + ((degree + 1) ** 2, 3))
+    for l in range(degree + 1):
+        leg = np.polynomial.legendre.Legendre.basis(l)
+        for m in range(-l, l + 1):
+            k = abs(m)
+            norm = math.sqrt((2 * l + 1) / (4 * math.pi)
+                             * math.factorial(l - k) / math.factorial(l + k))
+            q = leg.deriv(k)(z) if k > 0 else leg(z)
+            dq = leg.deriv(k + 1)(z)
+            if m == 0:
+                a, ax, ay = np.ones_like(x), np.zeros_like(x), np.zeros_like(x)
+                c = norm
+            else:
+                uk, duk = u ** k, k * u ** (k - 1)
+                c = math.sqrt(2.0) * norm
+                if m > 0:
+                    a, ax, ay = uk.real, duk.real, -duk.imag
+                else:
+                    a, ax, ay = uk.imag, duk.imag, duk.real
+            i = l * l + l + m
+            gF[..., i, 0] = c * ax * q
+            gF[..., i, 1] = c * ay * q
+            gF[..., i, 2] = c * a * dq
+    # project out the radial part: (I - w w^T) grad F
+    radial = np.einsum("...sa,...a->...s", gF, dirs)
+    return gF - radial[..., None] * dirs[..., None, :]
+
+
+def basis_polynomial_form(dirs, degree):
+    """F of ``basis_grad`` evaluated at ``dirs`` (equals ``basis`` on the
+    unit sphere; kept so the identity behind the gradient can be checked)."""
+    dirs = np.asarray(dirs, np.float64)
+    x, y, z = dirs[..., 0], dirs[..., 1], dirs[..., 2]
+    u = x + 1j * y
+    out = np.zeros(dirs.shape[:-1] + ((degree + 1) ** 2,))
+    for l in range(degree + 1):
+        leg = np.polynomial.legendre.Legendre.basis(l)
+        for m in range(-l, l + 1):
+            k = abs(m)
+            norm = math.sqrt((2 * l + 1) / (4 * math.pi)
+                             * math.factorial(l - k) / math.factorial(l + k))
+            q = leg.deriv(k)(z) if k > 0 else leg(z)
+            if m == 0:
+                v = norm * q
+            elif m > 0:
+                v = math.sqrt(2.0) * norm * (u ** k).real * q
+            else:
+                v = math.sqrt(2.0) * norm * (u ** k).imag * q
+            out[..., l * l + l + m] = v
+    return out
 
 
 def colour(sh, dirs):
