@@ -7,7 +7,8 @@
  * camera ray is split by the actors' box intervals into background and
  * asset segments (Sec. 3.4, App. A, Alg. 1), every segment is integrated
  * with trilinear raw density, exp-linear activation and alpha compositing,
- * and the result is composited over a constant sky colour (Eq. 2).
+ * and the result is composited over the sky (Eq. 2): a constant colour or
+ * a bilinearly sampled environment map (Sec. 3.1, sky modelling).
  *
  * Conventions used by every call:
  *  - "device" pointers are HIP device memory of the context's GPU; "host"
@@ -24,6 +25,7 @@
 #ifndef DV_H
 #define DV_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -179,10 +181,45 @@ typedef struct {
 } dv_state_info;
 
 /* ---------------------------------------------------------------- context */
-/* Create a context on HIP device `hip_device` (memory pool, streams of the
- * caller are used for work).  *out is set on success. */
-dv_status dv_ctx_create(int32_t hip_device, dv_ctx** out);
+/* Device memory provider of a context.  The library keeps a caching pool of
+ * device blocks for its per-call buffers (records, pairs, sort ping-pong,
+ * per-pixel state) and for a scene's packed tables; the pool takes its
+ * backing blocks from alloc and gives them back through free.
+ *  - alloc(user, bytes, device, stream): `bytes` of device memory of
+ *    `device` (the context's), usable in stream order on `stream` (a
+ *    hipStream_t, NULL for the default stream); NULL if none is available
+ *    (the pool then returns idle blocks through free and asks once more).
+ *    Called from the thread of the library call that needs memory (for a
+ *    server, its scheduler threads).
+ *  - free(user, ptr, bytes, device, stream): gives back a block from alloc
+ *    (same bytes); the device is idle when it is called, so the block may
+ *    be reused at once on any stream.
+ * With torch as the provider (torch.cuda.caching_allocator_alloc / _delete)
+ * the library's scratch is torch's memory, counted by torch and shared with
+ * its caching allocator. */
+typedef struct {
+  void* (*alloc)(void* user, size_t bytes, int32_t device, void* stream);
+  void (*free)(void* user, void* ptr, size_t bytes, int32_t device,
+               void* stream);
+  void* user;
+} dv_allocator;
+
+/* Create a context on HIP device `hip_device`.  alloc: the device memory
+ * provider (copied; its callbacks must stay valid until dv_ctx_destroy
+ * returns), or NULL for hipMalloc / hipFree.  Work runs on the caller's
+ * streams.  *out is set on success.  Errors: DV_ERR_INVALID (bad device,
+ * alloc with a NULL callback), DV_ERR_OOM, DV_ERR_DEVICE. */
+dv_status dv_ctx_create(int32_t hip_device, const dv_allocator* alloc,
+                        dv_ctx** out);
+/* Synchronise the device, then free every block (calls alloc's free). */
 void dv_ctx_destroy(dv_ctx* ctx);
+/* Wait for released forward states and hand every idle pool block back to
+ * the provider (synchronises the device).  Blocks held by live scenes and
+ * forward states stay. */
+dv_status dv_ctx_trim(dv_ctx* ctx);
+/* Bytes of pool blocks in use (scenes, forward states, calls in flight)
+ * and cached (idle, kept for reuse); either pointer may be NULL. */
+dv_status dv_ctx_memory(dv_ctx* ctx, int64_t* in_use, int64_t* cached);
 /* Message of the last failing call on this thread ("" if none). */
 const char* dv_last_error(void);
 /* Library version string. */
@@ -252,9 +289,10 @@ int32_t dv_track_pose(const dv_track_desc* track, double t, double R[9],
  * pose_override: NULL (poses from tracks at view.t) or a host array
  * [n_views][n_actors][12] (R row-major, then p; all actors active).
  * keep: NULL, or receives a forward state that dv_render_backward needs;
- * release it with dv_fwd_state_release.  Synchronises the stream twice
- * (to size the record and pair arrays).  Errors: DV_ERR_INVALID,
- * DV_ERR_LIMIT, DV_ERR_OOM, DV_ERR_DEVICE. */
+ * release it with dv_fwd_state_release.  Synchronises the stream once, to
+ * read the record and pair counts that size the record, pair and sort
+ * arrays.  Errors: DV_ERR_INVALID, DV_ERR_LIMIT, DV_ERR_OOM,
+ * DV_ERR_DEVICE. */
 dv_status dv_render(dv_ctx* ctx, const dv_scene* scene, const dv_view* views,
                     int32_t n_views, const double* pose_override,
                     const dv_render_opts* opts, const dv_outputs* outs,
@@ -278,6 +316,30 @@ dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
                              const dv_out_grads* g, const dv_param_grads* acc,
                              void* stream);
 
+/* dv_render without any allocation, for callers that cannot allocate
+ * device memory inside the call (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments and
+ * results as dv_render with keep = NULL (no backward).  Every per-call
+ * buffer (records, pairs, sort ping-pong, scan partials, per-pixel state)
+ * is carved from one static device workspace of dv_noalloc_capacity()
+ * bytes (128 MiB) per GPU, held from the library's first use on that GPU
+ * until the process ends; host staging comes from a pinned block made by
+ * dv_ctx_create.  The call allocates no device or pinned memory (host-side
+ * bookkeeping uses the C++ heap).  A render whose buffers exceed the
+ * workspace fails with DV_ERR_LIMIT and a message naming the need; kernels
+ * enqueued before the failure may have written into the workspace, and the
+ * outputs are then unspecified.  Calls on the same GPU share the one
+ * workspace: calls on one stream are ordered, calls that overlap on
+ * different streams race (serialise them).  Synchronises the stream once,
+ * as dv_render does; profiling timers are not recorded for it. */
+dv_status dv_render_noalloc(dv_ctx* ctx, const dv_scene* scene,
+                            const dv_view* views, int32_t n_views,
+                            const double* pose_override,
+                            const dv_render_opts* opts, const dv_outputs* outs,
+                            void* stream);
+/* Size in bytes of the static workspace of dv_render_noalloc. */
+int64_t dv_noalloc_capacity(void);
+
 void dv_fwd_state_release(dv_fwd_state* state);
 dv_status dv_fwd_state_info(const dv_fwd_state* state, dv_state_info* info);
 /* Copy the sorted tile lists of one view to the host (synchronises):
@@ -291,6 +353,10 @@ dv_status dv_fwd_state_export_lists(const dv_fwd_state* state, int32_t view,
                                     int64_t actor_capacity);
 
 /* ---------------------------------------------------------------- serving */
+/* Sensor simulation (Sec. 1: the reconstructed scene is rendered for new
+ * cameras, timestamps and actor configurations): the scene and actor tracks
+ * stay resident in HBM while render requests arrive; each request is one
+ * view of the render above (camera, timestamp, resolution). */
 typedef struct {
   int32_t max_inflight;         /* requests admitted at once (slots)       */
   int64_t mem_budget;           /* device bytes for in-flight requests     */

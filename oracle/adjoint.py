@@ -27,7 +27,9 @@ _GW_CENTRE = F.trilinear_weight_grads(np.full(3, 0.5))       # [8,3]
 def new_accumulators(ctx):
     # corner_abs: sum of |per-piece contribution| per corner, the scale of
     # the summands behind each corner gradient (bookkeeping for error bars)
-    acc = dict(corner=[], corner_abs=[], dcol=[], dcol_abs=[], dnw=[], dR=[], dp=[])
+    # dR_abs / dp_abs: the same for the pose entries
+    acc = dict(corner=[], corner_abs=[], dcol=[], dcol_abs=[], dnw=[], dR=[],
+               dp=[], dR_abs=[], dp_abs=[])
     for k, o in enumerate(ctx.scene["octrees"]):
         acc["corner"].append(np.zeros(o["corner_density"].shape[0]))
         acc["corner_abs"].append(np.zeros(o["corner_density"].shape[0]))
@@ -37,6 +39,8 @@ def new_accumulators(ctx):
         acc["dnw"].append(np.zeros((n, 3)))
         acc["dR"].append(np.zeros((3, 3)))
         acc["dp"].append(np.zeros(3))
+        acc["dR_abs"].append(np.zeros((3, 3)))
+        acc["dp_abs"].append(np.zeros(3))
     # sky texture gradient (the map is sampled per ray, Eq. 2)
     acc["sky"] = None if ctx.sky is None else np.zeros_like(ctx.sky)
     return acc
@@ -69,6 +73,8 @@ def ray_adjoint(ctx, o, d, gC, gD, gN, gT, acc):
     frames = pc["frames"]
     go = [np.zeros(3) for _ in ctx.oct]
     gd = [np.zeros(3) for _ in ctx.oct]
+    go_abs = [np.zeros(3) for _ in ctx.oct]
+    gd_abs = [np.zeros(3) for _ in ctx.oct]
     for i in range(n):
         k, vv = int(ks[i]), int(vs[i])
         ent = ctx.oct[k]
@@ -93,6 +99,8 @@ def ray_adjoint(ctx, o, d, gC, gD, gN, gT, acc):
         if k >= 1:
             go[k] += dtau[i] * dtdx.sum(0)
             gd[k] += dtau[i] * (smp["tq"][i][:, None] * dtdx).sum(0)
+            go_abs[k] += np.abs(dtau[i] * dtdx).sum(0)
+            gd_abs[k] += np.abs(dtau[i] * smp["tq"][i][:, None] * dtdx).sum(0)
         for (src, t, gg) in ((pc["sa"][i], pc["a"][i], ga),
                              (pc["sb"][i], pc["b"][i], gb)):
             j, ax = int(src[0]), int(src[1])
@@ -100,12 +108,17 @@ def ray_adjoint(ctx, o, d, gC, gD, gN, gT, acc):
                 dj = frames[j][1]
                 go[j][ax] += gg * (-1.0 / dj[ax])
                 gd[j][ax] += gg * (-t / dj[ax])
+                go_abs[j][ax] += abs(gg / dj[ax])
+                gd_abs[j][ax] += abs(gg * t / dj[ax])
     for k in range(1, len(ctx.oct)):
         if not go[k].any() and not gd[k].any():
             continue
         R, p = ctx.oct[k]["R"], ctx.oct[k]["p"]
         acc["dR"][k] += np.outer(o - p, go[k]) + np.outer(d, gd[k])
         acc["dp"][k] += -R @ go[k]
+        acc["dR_abs"][k] += (np.outer(np.abs(o - p), go_abs[k])
+                             + np.outer(np.abs(d), gd_abs[k]))
+        acc["dp_abs"][k] += np.abs(R) @ go_abs[k]
     return res
 
 
@@ -113,7 +126,7 @@ def finalize(ctx, acc):
     """Per-leaf colour and normal gradients -> SH coefficients, corners
     (through normals) and poses (SH direction, normal rotation)."""
     out = dict(corner=[], corner_abs=[], sh=[], sh_abs=[], dR=[], dp=[],
-               sky=acc.get("sky"))
+               dR_abs=[], dp_abs=[], sky=acc.get("sky"))
     for k, o in enumerate(ctx.scene["octrees"]):
         ent = ctx.oct[k]
         dcol = acc["dcol"][k] * (ent["raw"] > 0)
@@ -125,6 +138,7 @@ def finalize(ctx, acc):
         corner = acc["corner"][k].copy()
         corner_abs = acc["corner_abs"][k].copy()
         dR, dp = acc["dR"][k].copy(), acc["dp"][k].copy()
+        dR_abs, dp_abs = acc["dR_abs"][k].copy(), acc["dp_abs"][k].copy()
         R, p = ent["R"], ent["p"]
         # normals: n_w = R n_loc, n_loc = -v/|v|, v = grad of trilinear
         dnw = acc["dnw"][k]
@@ -133,6 +147,7 @@ def finalize(ctx, acc):
             nl = ent["n_loc"][nz]
             if k >= 1:
                 dR += np.einsum("na,nb->ab", dnw[nz], nl)
+                dR_abs += np.einsum("na,nb->ab", np.abs(dnw[nz]), np.abs(nl))
             dnl = dnw[nz] @ R                           # R^T dnw
             vv = F.centre_gradient(ent["g8"][nz])
             nrm = np.linalg.norm(vv, axis=1)
@@ -152,10 +167,15 @@ def finalize(ctx, acc):
                 dP = -(dw / ent["r"][cz][:, None]).sum(0)
                 dR += np.outer(ctx.cam - p, dP)
                 dp += -R @ dP
+                dP_abs = np.abs(dw / ent["r"][cz][:, None]).sum(0)
+                dR_abs += np.outer(np.abs(ctx.cam - p), dP_abs)
+                dp_abs += np.abs(R) @ dP_abs
         out["corner"].append(corner)
         out["corner_abs"].append(corner_abs)
         out["dR"].append(dR)
         out["dp"].append(dp)
+        out["dR_abs"].append(dR_abs)
+        out["dp_abs"].append(dp_abs)
     return out
 
 

@@ -5,7 +5,9 @@ pointers of the Scene's own tensors, so those tensors are the leaves of the
 graph: mark them ``requires_grad_(True)`` and update them in place (under
 ``torch.no_grad()``) after each step.  Actor poses (R row-major, then p per
 view and actor) are an optional FP64 CPU tensor; the pose gradient comes back
-in the same layout (dL/dR, dL/dp).
+in the same layout (dL/dR, dL/dp).  A sky environment map passed as
+``opts['sky']`` (float32 CUDA tensor [3][H][W]) is a graph input too: when it
+requires grad, its gradient dL/dsky is returned.
 
 Nothing here computes: forward runs dv_render with a kept state, backward
 runs dv_render_backward into fresh accumulators and releases the state."""
@@ -38,8 +40,9 @@ class _State:
 
 class _Render(torch.autograd.Function):
     @staticmethod
-    def forward(fctx, spec, poses, *params):
+    def forward(fctx, spec, poses, sky, *params):
         ctx, scene, views, opts, mask = spec
+        opts = dict(opts, sky=sky)
         outs = dv.alloc_outputs(views, mask)
         po = None if poses is None else poses.detach().cpu().numpy()
         st = dv.dv_render(ctx, scene, views, dv.make_opts(opts, mask), outs,
@@ -47,6 +50,7 @@ class _Render(torch.autograd.Function):
                           stream=torch.cuda.current_stream())
         fctx.state = _State(st)
         fctx.spec = spec
+        fctx.sky_shape = None if sky is None else tuple(sky.shape)
         fctx.pose_meta = None if poses is None else (poses.dtype, poses.device,
                                                      poses.shape)
         flat = [o[k] for o in outs for k in _KEYS if o[k] is not None]
@@ -73,13 +77,16 @@ class _Render(torch.autograd.Function):
         acc = []
         for k, o in enumerate(scene.octs):
             acc.append(dict(
-                corner=torch.zeros_like(o["corner_density"]) if need[2 + 2 * k] else None,
-                sh=torch.zeros_like(o["sh"]) if need[3 + 2 * k] else None))
+                corner=torch.zeros_like(o["corner_density"]) if need[3 + 2 * k] else None,
+                sh=torch.zeros_like(o["sh"]) if need[4 + 2 * k] else None))
         pg = None
         if fctx.pose_meta is not None and need[1] and scene.n_actors > 0:
             pg = torch.zeros(len(views), scene.n_actors, 12, device="cuda")
+        sg = None
+        if fctx.sky_shape is not None and need[2]:
+            sg = torch.zeros(fctx.sky_shape, device="cuda")
         dv.dv_render_backward(ctx, scene, fctx.state.handle, grads, acc, pg,
-                              stream=torch.cuda.current_stream())
+                              stream=torch.cuda.current_stream(), sky_grad=sg)
         fctx.state.release()
         g_params = []
         for a in acc:
@@ -88,7 +95,7 @@ class _Render(torch.autograd.Function):
         if pg is not None:
             dt, dev, shape = fctx.pose_meta
             g_pose = pg.to(device=dev, dtype=dt).reshape(shape)
-        return (None, g_pose, *g_params)
+        return (None, g_pose, sg, *g_params)
 
 
 def track_poses(scene, views):
@@ -112,12 +119,15 @@ def render(ctx, scene, views, opts, mask=dv.DV_OUT_RGB | dv.DV_OUT_DEPTH | dv.DV
            poses=None):
     """Differentiable render of ``views``: returns one dict per view with the
     requested outputs.  Gradients flow to the Scene's corner-density and SH
-    tensors that require grad, and to ``poses`` if given and requiring grad."""
+    tensors that require grad, to ``poses`` if given and requiring grad, and
+    to the sky map ``opts['sky']`` if it requires grad."""
     params = []
     for o in scene.octs:
         params += [o["corner_density"], o["sh"]]
-    flat = _Render.apply((ctx, scene, list(views), dict(opts), int(mask)), poses,
-                         *params)
+    opts = dict(opts)
+    sky = opts.pop("sky", None)
+    flat = _Render.apply((ctx, scene, list(views), opts, int(mask)), poses,
+                         sky, *params)
     res, i = [], 0
     for _ in views:
         d = {}

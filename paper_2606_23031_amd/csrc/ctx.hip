@@ -22,21 +22,49 @@ const char* get_error() { return g_err.c_str(); }
 
 static thread_local bool t_release_idle = false;
 
+static thread_local Arena* t_arena = nullptr;
+Arena* thread_arena() { return t_arena; }
+ArenaScope::ArenaScope(Arena* a) { t_arena = a; }
+ArenaScope::~ArenaScope() { t_arena = nullptr; }
+
 IdleRelease::IdleRelease() { t_release_idle = true; }
 IdleRelease::~IdleRelease() { t_release_idle = false; }
 
+void* Pool::raw_alloc(size_t bytes, hipStream_t s) {
+  if (has_user_alloc_)
+    return user_alloc_.alloc(user_alloc_.user, bytes, device_, (void*)s);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void Pool::raw_free(void* p, size_t bytes, hipStream_t s) {
+  if (has_user_alloc_) {
+    user_alloc_.free(user_alloc_.user, p, bytes, device_, (void*)s);
+    return;
+  }
+  (void)hipFree(p);
+}
+
 Pool::~Pool() {
   hipSetDevice(device_);
-  for (auto& kv : free_) hipFree(kv.second.p);
-  for (auto& kv : live_) hipFree(kv.first);
+  // the owner synchronised the device: nothing is in flight
+  for (auto& kv : free_) raw_free(kv.second.p, kv.second.size, kv.second.stream);
+  for (auto& kv : live_) raw_free(kv.first, kv.second, nullptr);
   for (auto& kv : ev_refs_) hipEventDestroy(kv.first);
   for (auto e : spare_events_) hipEventDestroy(e);
 }
 
+// Block sizes: powers of two from 512 B, multiples of 2 MiB from 1 MiB
+// (all multiples of 512 B, the granule of torch's caching allocator, so a
+// provider backed by it counts exactly the pool's bytes).
 static size_t round_size(size_t b) {
-  if (b < 256) return 256;
+  if (b < 512) return 512;
   if (b < (1u << 20)) {
-    size_t r = 256;
+    size_t r = 512;
     while (r < b) r <<= 1;
     return r;
   }
@@ -74,14 +102,11 @@ void* Pool::alloc(size_t bytes, hipStream_t s) {
       ++it;
     }
   }
-  void* p = nullptr;
-  if (hipMalloc(&p, want) != hipSuccess) {
-    (void)hipGetLastError();
+  void* p = raw_alloc(want, s);
+  if (!p) {
     trim();
-    if (hipMalloc(&p, want) != hipSuccess) {
-      (void)hipGetLastError();
-      return nullptr;
-    }
+    p = raw_alloc(want, s);
+    if (!p) return nullptr;
   }
   std::lock_guard<std::mutex> lk(mu_);
   live_[p] = want;
@@ -151,20 +176,40 @@ void Pool::trim() {
   }
   if (hipDeviceSynchronize() != hipSuccess) (void)hipGetLastError();
   std::sort(snap.begin(), snap.end());
-  std::lock_guard<std::mutex> lk(mu_);
-  for (auto it = free_.begin(); it != free_.end();) {
-    if (std::binary_search(snap.begin(), snap.end(), it->second.p)) {
-      hipFree(it->second.p);
-      drop_event(it->second.ev);
-      it = free_.erase(it);
-    } else {
-      ++it;
+  std::vector<Block> gone;
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto it = free_.begin(); it != free_.end();) {
+      if (std::binary_search(snap.begin(), snap.end(), it->second.p)) {
+        gone.push_back(it->second);
+        drop_event(it->second.ev);
+        it = free_.erase(it);
+      } else {
+        ++it;
+      }
     }
   }
+  // outside the lock: a user callback may take locks of its own
+  for (const Block& b : gone) raw_free(b.p, b.size, b.stream);
 }
 
 dv_status alloc(dv_ctx* ctx, DBuf& b, size_t bytes, hipStream_t s) {
   b.reset();
+  if (Arena* ar = t_arena) {
+    const size_t want = (bytes + 255) & ~(size_t)255;
+    if (want > ar->cap - ar->used) {
+      set_error("scratch need of the call exceeds the %zu-byte static "
+                "workspace (%zu bytes in use, %zu more asked)", ar->cap,
+                ar->used, bytes);
+      return DV_ERR_LIMIT;
+    }
+    b.pool = nullptr;               // carved, never returned one by one
+    b.p = ar->base + ar->used;
+    b.bytes = bytes;
+    b.stream = s;
+    ar->used += want;
+    return DV_OK;
+  }
   void* p = ctx->pool->alloc(bytes, s);
   if (!p) {
     set_error("device allocation of %zu bytes failed", bytes);
@@ -234,7 +279,8 @@ const char* dv_last_error(void) { return get_error(); }
 
 const char* dv_version(void) { return "dvox 0.1 (gfx950)"; }
 
-dv_status dv_ctx_create(int32_t hip_device, dv_ctx** out) {
+dv_status dv_ctx_create(int32_t hip_device, const dv_allocator* alloc,
+                        dv_ctx** out) {
   if (!out) {
     set_error("dv_ctx_create: out is NULL");
     return DV_ERR_INVALID;
@@ -251,7 +297,12 @@ dv_status dv_ctx_create(int32_t hip_device, dv_ctx** out) {
   auto* c = new (std::nothrow) dv_ctx();
   if (!c) return DV_ERR_OOM;
   c->device = hip_device;
-  c->pool.reset(new Pool(hip_device));
+  if (alloc && (!alloc->alloc || !alloc->free)) {
+    delete c;
+    set_error("dv_ctx_create: allocator needs both alloc and free");
+    return DV_ERR_INVALID;
+  }
+  c->pool.reset(new Pool(hip_device, alloc));
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess)
     c->n_cu = prop.multiProcessorCount;
@@ -261,6 +312,13 @@ dv_status dv_ctx_create(int32_t hip_device, dv_ctx** out) {
     set_error("dv_ctx_create: pinned allocation failed");
     return DV_ERR_OOM;
   }
+  {
+    const dv_status rs = noalloc_setup(c);
+    if (rs != DV_OK) {
+      dv_ctx_destroy(c);
+      return rs;
+    }
+  }
   *out = c;
   return DV_OK;
 }
@@ -269,8 +327,10 @@ dv_status dv_ctx_set_profiling(dv_ctx* ctx, int32_t flags) {
   if (!ctx) return DV_ERR_INVALID;
   DV_TRY_HIP(hipSetDevice(ctx->device));
   if ((flags & DV_PROFILE_COUNTERS) && !ctx->counters) {
-    DV_TRY_HIP(hipMalloc((void**)&ctx->counters, 8 * sizeof(unsigned long long)));
+    DV_TRY(alloc_n<unsigned long long>(ctx, ctx->counters_buf, 8, nullptr));
+    ctx->counters = ctx->counters_buf.as<unsigned long long>();
     DV_TRY_HIP(hipMemset(ctx->counters, 0, 8 * sizeof(unsigned long long)));
+    DV_TRY_HIP(hipDeviceSynchronize());
   }
   ctx->prof_flags = flags;
   return DV_OK;
@@ -318,6 +378,21 @@ dv_status dv_ctx_stage_times(dv_ctx* ctx, dv_stage_times* out, int32_t reset) {
   return DV_OK;
 }
 
+dv_status dv_ctx_trim(dv_ctx* ctx) {
+  if (!ctx) return DV_ERR_INVALID;
+  DV_TRY_HIP(hipSetDevice(ctx->device));
+  reap_states(ctx, true);
+  ctx->pool->trim();
+  return DV_OK;
+}
+
+dv_status dv_ctx_memory(dv_ctx* ctx, int64_t* in_use, int64_t* cached) {
+  if (!ctx) return DV_ERR_INVALID;
+  if (in_use) *in_use = (int64_t)ctx->pool->bytes_in_use();
+  if (cached) *cached = (int64_t)ctx->pool->bytes_cached();
+  return DV_OK;
+}
+
 const char* dv_stage_name(int32_t i) {
   if (i < 0 || i >= DV_NUM_STAGES) return "";
   return kStageNames[i];
@@ -336,9 +411,14 @@ void dv_ctx_destroy(dv_ctx* ctx) {
     }
     ctx->prof_pending.clear();
   }
-  if (ctx->counters) hipFree(ctx->counters);
+  ctx->counters = nullptr;
+  {
+    IdleRelease idle;
+    ctx->counters_buf.reset();
+  }
   ctx->pool.reset();
   if (ctx->pinned) hipHostFree(ctx->pinned);
+  if (ctx->noalloc_pinned) hipHostFree(ctx->noalloc_pinned);
   delete ctx;
 }
 

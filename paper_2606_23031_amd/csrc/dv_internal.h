@@ -46,9 +46,17 @@ const char* get_error();
 // event recorded per free would put a marker between kernels in the queue
 // for every buffer; one per call does not.) Blocks freed after their last
 // use is known to be complete (IdleRelease) are reusable by any stream.
+// Backing memory comes from the caller's allocator callbacks when the
+// context was created with one (torch's caching allocator, say), else from
+// hipMalloc; trim() hands every idle block back.
 class Pool {
  public:
-  explicit Pool(int device) : device_(device) {}
+  Pool(int device, const dv_allocator* a) : device_(device) {
+    if (a && a->alloc && a->free) {
+      user_alloc_ = *a;
+      has_user_alloc_ = true;
+    }
+  }
   ~Pool();
   void* alloc(size_t bytes, hipStream_t s);
   void release(void* p, hipStream_t s);
@@ -66,6 +74,10 @@ class Pool {
     bool idle;      // no use pending on any stream
   };
   void drop_event(hipEvent_t ev);
+  void* raw_alloc(size_t bytes, hipStream_t s);
+  void raw_free(void* p, size_t bytes, hipStream_t s);
+  dv_allocator user_alloc_{};
+  bool has_user_alloc_ = false;
   std::mutex mu_;
   std::multimap<size_t, Block> free_;
   std::map<void*, size_t> live_;
@@ -73,7 +85,34 @@ class Pool {
   std::unordered_map<hipEvent_t, int> ev_refs_;  // blocks per stamp event
   std::vector<hipEvent_t> spare_events_;
   size_t in_use_ = 0;
+ public:
+  size_t bytes_cached() {
+    std::lock_guard<std::mutex> lk(mu_);
+    size_t b = 0;
+    for (auto& kv : free_) b += kv.first;
+    return b;
+  }
+ private:
   int device_;
+};
+
+// Bump arena over caller-independent static device memory (the
+// allocation-free entry point): while one is installed on a thread, every
+// buffer that thread's library call asks for is carved from it (never
+// freed individually), and host staging comes from its pinned block.
+struct Arena {
+  uint8_t* base = nullptr;      // device
+  size_t cap = 0;
+  size_t used = 0;
+  uint8_t* pinned = nullptr;    // host, pinned: [0, cap/2) tables, rest words
+  size_t pinned_cap = 0;
+};
+Arena* thread_arena();
+struct ArenaScope {
+  explicit ArenaScope(Arena* a);
+  ~ArenaScope();
+  ArenaScope(const ArenaScope&) = delete;
+  ArenaScope& operator=(const ArenaScope&) = delete;
 };
 
 // While alive on a thread, blocks freed by that thread are marked idle: for
@@ -145,12 +184,23 @@ struct dv_ctx {
   std::vector<Interval> prof_pending;
   double prof_ms[DV_NUM_STAGES] = {0};
   int64_t prof_calls[DV_NUM_STAGES] = {0};
-  unsigned long long* counters = nullptr;  // device [8]
+  unsigned long long* counters = nullptr;  // device [8], from the pool
+  dv::DBuf counters_buf;
+  // allocation-free entry point: this device's static scratch array (its
+  // device address, from hipGetSymbolAddress at context creation) and a
+  // pinned host block for its staging, both set up by dv_ctx_create
+  uint8_t* noalloc_scratch = nullptr;
+  size_t noalloc_bytes = 0;
+  uint8_t* noalloc_pinned = nullptr;
+  size_t noalloc_pinned_bytes = 0;
 };
 
 namespace dv {
 
 dv_status alloc(dv_ctx* ctx, DBuf& b, size_t bytes, hipStream_t s);
+// Locate this device's static scratch array of the allocation-free entry
+// point and allocate its pinned staging (at context creation).
+dv_status noalloc_setup(dv_ctx* ctx);
 // Declared first in a library call: on return, after the call's own buffers
 // are freed, stamps the blocks freed during the call.
 struct PoolStamp {

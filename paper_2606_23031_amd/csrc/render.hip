@@ -206,6 +206,7 @@ struct PreArgs {
   int64_t n_items;
   int32_t rank_bits;
   uint32_t* block_count;
+  unsigned long long* pair_total;  // pass 0: (leaf, tile) pairs, summed
   const uint32_t* block_off;
   uint64_t* keys;
   uint32_t* vals;
@@ -272,16 +273,29 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
   }
   if (PASS == 0) {
     __shared__ uint32_t wtot[TPB / 64];
+    __shared__ uint32_t wpairs[TPB / 64];
     m = __ballot(vis);
+    // tiles covered by the rectangle: the pairs this leaf emits
+    uint32_t np = vis ? (uint32_t)(((r.xh >> 4) - (r.xl >> 4) + 1) *
+                                   ((r.yh >> 4) - (r.yl >> 4) + 1))
+                      : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o, 64);
     if (lane == 0) {
       p.wave_mask[wave] = m;
       wtot[w] = (uint32_t)__popcll(m);
+      wpairs[w] = np;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       uint32_t tot = 0;
-      for (int i = 0; i < TPB / 64; ++i) tot += wtot[i];
+      unsigned long long pt = 0;
+      for (int i = 0; i < TPB / 64; ++i) {
+        tot += wtot[i];
+        pt += wpairs[i];
+      }
       p.block_count[blockIdx.x] = tot;
+      if (pt) atomicAdd(p.pair_total, pt);
     }
     return;
   }
@@ -1432,6 +1446,13 @@ dv_status setup_state(dv_fwd_state* st, const dv_scene* sc,
 // One pinned host word per calling thread for device->host counts, so
 // concurrent renders on different streams never wait for each other.
 static uint64_t* pinned_words(size_t n) {
+  if (Arena* ar = thread_arena()) {
+    if (n * sizeof(uint64_t) > ar->pinned_cap / 2) {
+      set_error("%zu count words exceed the static staging", n);
+      return nullptr;
+    }
+    return reinterpret_cast<uint64_t*>(ar->pinned + ar->pinned_cap / 2);
+  }
   static thread_local uint64_t* w = nullptr;
   static thread_local size_t cap = 0;
   if (n > cap) {
@@ -1450,7 +1471,6 @@ static uint64_t* pinned_words(size_t n) {
   }
   return w;
 }
-static uint64_t* pinned_word() { return pinned_words(1); }
 
 // Pinned staging for the per-call host tables (one per host thread).  An
 // event after each upload guards reuse: the next call waits for it (a call
@@ -1466,6 +1486,15 @@ static HostStage& host_stage() {
   return h;
 }
 uint8_t* stage_acquire(size_t bytes) {
+  if (Arena* ar = thread_arena()) {
+    // the call synchronises its stream after this upload, before it
+    // returns, so the next call may reuse the block
+    if (bytes > ar->pinned_cap / 2) {
+      set_error("%zu bytes of host tables exceed the static staging", bytes);
+      return nullptr;
+    }
+    return ar->pinned;
+  }
   HostStage& h = host_stage();
   if (h.pending) {
     (void)hipEventSynchronize(h.ev);
@@ -1493,6 +1522,7 @@ uint8_t* stage_acquire(size_t bytes) {
   return h.p;
 }
 dv_status stage_release(hipStream_t s) {
+  if (thread_arena()) return DV_OK;
   HostStage& h = host_stage();
   DV_TRY_HIP(hipEventRecord(h.ev, s));
   h.pending = true;
@@ -1518,8 +1548,9 @@ __global__ void k_view_slots(int n_views, int n_oct, const int64_t* pstart,
   out[v] = sl;
 }
 
-// Enqueue the whole forward pass on stream s.  Two host synchronisations
-// read the record and pair counts.
+// Enqueue the whole forward pass on stream s.  One host synchronisation
+// reads the record count (per view) and the pair count, both known after
+// the first preprocess pass.
 dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
                       const dv_outputs* outs, hipStream_t s) {
   const std::vector<int64_t>& seg_start = st->seg_start_h;
@@ -1587,6 +1618,9 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   DV_TRY(alloc_n<uint32_t>(ctx, bcount, nblk, s));
   DV_TRY(alloc_n<uint32_t>(ctx, boff, nblk, s));
   DV_TRY(alloc_n<uint64_t>(ctx, total, 2, s));
+  // first record slot per view, the record total, then the pair total
+  DV_TRY(alloc_n<uint64_t>(ctx, vslot, (size_t)n_views + 2, s));
+  DV_TRY(fill_u32(vslot.as<uint32_t>() + 2 * (n_views + 1), 0u, 2, s));
   PreArgs pa;
   std::memset(&pa, 0, sizeof(pa));
   pa.views = st->views_d.as<ViewConst>();
@@ -1600,6 +1634,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   pa.n_items = n_items;
   pa.rank_bits = st->rank_bits;
   pa.block_count = bcount.as<uint32_t>();
+  pa.pair_total = reinterpret_cast<unsigned long long*>(vslot.as<uint64_t>() + n_views + 1);
   pa.block_off = boff.as<uint32_t>();
   {
     StageTimer tm(ctx, ST_PREPROCESS, s);
@@ -1610,22 +1645,22 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
     DV_TRY_HIP(hipGetLastError());
     DV_TRY(exclusive_scan_u32(ctx, bcount.as<uint32_t>(), boff.as<uint32_t>(),
                               total.as<uint64_t>(), nblk, s));
-    DV_TRY(alloc_n<uint64_t>(ctx, vslot, (size_t)n_views + 1, s));
     hipLaunchKernelGGL(k_view_slots, dim3(grid_for(n_views + 1, TPB)), dim3(TPB),
                        0, s, n_views, n_oct, segs_d.as<int64_t>(), n_items,
                        boff.as<uint32_t>(), wmask.as<uint64_t>(),
                        total.as<uint64_t>(), vslot.as<uint64_t>());
     DV_TRY_HIP(hipGetLastError());
   }
-  uint64_t n_vis = 0;
+  uint64_t n_vis = 0, n_pairs = 0;
   {
-    uint64_t* pin = pinned_words((size_t)n_views + 1);
+    uint64_t* pin = pinned_words((size_t)n_views + 2);
     if (!pin) return DV_ERR_OOM;
     StageTimer tm(ctx, ST_HOST_SYNC, s);
-    DV_TRY_HIP(hipMemcpyAsync(pin, vslot.p, sizeof(uint64_t) * (n_views + 1),
+    DV_TRY_HIP(hipMemcpyAsync(pin, vslot.p, sizeof(uint64_t) * (n_views + 2),
                               hipMemcpyDeviceToHost, s));
     DV_TRY_HIP(hipStreamSynchronize(s));
     n_vis = pin[n_views];
+    n_pairs = pin[n_views + 1];
     st->view_slot_h.assign(pin, pin + n_views + 1);
   }
   st->n_vis = (int64_t)n_vis;
@@ -1688,14 +1723,6 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   DV_TRY(exclusive_scan_u32(ctx, r_count.as<uint32_t>(), r_off.as<uint32_t>(),
                             total.as<uint64_t>(), nv, s));
   tm_gather.stop();
-  uint64_t n_pairs = 0;
-  {
-    uint64_t* pin = pinned_word();
-    if (!pin) return DV_ERR_OOM;
-    DV_TRY_HIP(hipMemcpyAsync(pin, total.p, 8, hipMemcpyDeviceToHost, s));
-    DV_TRY_HIP(hipStreamSynchronize(s));
-    n_pairs = *pin;
-  }
   if (n_pairs >= 0xFFFFFFFFull) {
     set_error("%llu (leaf, tile) pairs exceed the 32-bit range",
               (unsigned long long)n_pairs);

@@ -131,9 +131,23 @@ class dv_result(C.Structure):
                 ("t_admit", C.c_double), ("t_done", C.c_double)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32,
+                        C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32,
+                       C.c_void_p)
+
+
+class dv_allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
 _P = C.c_void_p
 _sig = {
-    "dv_ctx_create": (C.c_int32, [C.c_int32, C.POINTER(_P)]),
+    "dv_ctx_create": (C.c_int32, [C.c_int32, C.POINTER(dv_allocator),
+                                  C.POINTER(_P)]),
+    "dv_ctx_trim": (C.c_int32, [_P]),
+    "dv_ctx_memory": (C.c_int32, [_P, C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int64)]),
     "dv_ctx_destroy": (None, [_P]),
     "dv_last_error": (C.c_char_p, []),
     "dv_version": (C.c_char_p, []),
@@ -150,6 +164,10 @@ _sig = {
                               C.POINTER(dv_outputs), C.POINTER(_P), _P]),
     "dv_render_backward": (C.c_int32, [_P, _P, _P, C.POINTER(dv_out_grads),
                                        C.POINTER(dv_param_grads), _P]),
+    "dv_render_noalloc": (C.c_int32, [_P, _P, C.POINTER(dv_view), C.c_int32, _P,
+                                      C.POINTER(dv_render_opts),
+                                      C.POINTER(dv_outputs), _P]),
+    "dv_noalloc_capacity": (C.c_int64, []),
     "dv_fwd_state_release": (None, [_P]),
     "dv_fwd_state_info": (C.c_int32, [_P, C.POINTER(dv_state_info)]),
     "dv_fwd_state_export_lists": (C.c_int32, [_P, C.c_int32, _P, _P, _P,
@@ -230,14 +248,47 @@ def make_opts(o, mask=DV_OUT_RGB | DV_OUT_DEPTH | DV_OUT_T):
 
 
 # ------------------------------------------------------------------ context
-def dv_ctx_create(device=0):
+def _torch_alloc(user, nbytes, device, stream):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), int(device),
+                                                  int(stream or 0))
+    except Exception:          # out of memory: the pool trims and retries
+        return None
+
+
+def _torch_free(user, ptr, nbytes, device, stream):
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+# the C callbacks must outlive every context created with them
+_TORCH_ALLOCATOR = dv_allocator(_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free),
+                                None)
+
+
+def dv_ctx_create(device=0, torch_memory=True):
+    """Context on HIP device ``device``.  With ``torch_memory`` the library's
+    device pool takes its blocks from torch's caching allocator (the memory
+    shows in torch.cuda.memory_allocated), else from hipMalloc."""
     h = C.c_void_p()
-    _check(_lib.dv_ctx_create(device, C.byref(h)), "dv_ctx_create")
+    alloc = C.byref(_TORCH_ALLOCATOR) if torch_memory else None
+    _check(_lib.dv_ctx_create(device, alloc, C.byref(h)), "dv_ctx_create")
     return h
 
 
 def dv_ctx_destroy(ctx):
     _lib.dv_ctx_destroy(ctx)
+
+
+def dv_ctx_trim(ctx):
+    """Hand the pool's idle blocks back to the provider (synchronises)."""
+    _check(_lib.dv_ctx_trim(ctx), "dv_ctx_trim")
+
+
+def dv_ctx_memory(ctx):
+    """(bytes in use, bytes cached) of the context's device pool."""
+    a, b = C.c_int64(), C.c_int64()
+    _check(_lib.dv_ctx_memory(ctx, C.byref(a), C.byref(b)), "dv_ctx_memory")
+    return a.value, b.value
 
 
 PROFILE_EVENTS, PROFILE_COUNTERS = 1, 2
@@ -377,6 +428,13 @@ def alloc_outputs(views, mask=DV_OUT_RGB | DV_OUT_DEPTH | DV_OUT_T,
     return outs
 
 
+class FwdState(C.c_void_p):
+    """Forward-state handle of dv_render; remembers the shape [3, H, W] of
+    the sky map its render used (None without a map), which a sky gradient
+    buffer of dv_render_backward must match."""
+    sky_shape = None
+
+
 def dv_render(ctx, scene, views, opts, outs, pose_override=None, keep=False,
               stream=None):
     """Render ``views`` (list of view dicts) into ``outs`` (list of dicts of
@@ -391,7 +449,9 @@ def dv_render(ctx, scene, views, opts, outs, pose_override=None, keep=False,
     if pose_override is not None:
         pov = np.ascontiguousarray(pose_override, np.float64)
         po = pov.ctypes.data_as(C.c_void_p)
-    st = C.c_void_p()
+    st = FwdState()
+    if opts.sky:
+        st.sky_shape = (3, int(opts.sky_h), int(opts.sky_w))
     rc = _lib.dv_render(ctx, scene.handle, cviews, nv, po, C.byref(opts),
                         couts, C.byref(st) if keep else None,
                         _stream_handle(stream))
@@ -399,11 +459,46 @@ def dv_render(ctx, scene, views, opts, outs, pose_override=None, keep=False,
     return st if keep else None
 
 
+def dv_render_noalloc(ctx, scene, views, opts, outs, pose_override=None,
+                      stream=None):
+    """dv_render without allocations: scratch from the library's static
+    workspace (dv_noalloc_capacity() bytes); no forward state."""
+    nv = len(views)
+    cviews = (dv_view * nv)(*[make_view(v) for v in views])
+    couts = (dv_outputs * nv)()
+    for i, o in enumerate(outs):
+        couts[i] = dv_outputs(_ptr(o.get("rgb")), _ptr(o.get("depth")),
+                              _ptr(o.get("normal")), _ptr(o.get("T")))
+    po = None
+    if pose_override is not None:
+        pov = np.ascontiguousarray(pose_override, np.float64)
+        po = pov.ctypes.data_as(C.c_void_p)
+    _check(_lib.dv_render_noalloc(ctx, scene.handle, cviews, nv, po, C.byref(opts),
+                                  couts, _stream_handle(stream)),
+           "dv_render_noalloc")
+
+
+def dv_noalloc_capacity():
+    return int(_lib.dv_noalloc_capacity())
+
+
 def dv_render_backward(ctx, scene, state, grads, acc_octrees, pose_grad=None,
                        stream=None, sky_grad=None):
     """grads: list per view of dicts (rgb/depth/normal/T upstream gradient
     tensors or None); acc_octrees: list per octree of dicts with 'corner'
-    and 'sh' accumulator tensors (or None)."""
+    and 'sh' accumulator tensors (or None).  sky_grad: float32 CUDA tensor
+    of the forward's sky map shape (checked here: the kernels scatter into
+    it by texel index), or None."""
+    if sky_grad is not None:
+        shape = getattr(state, "sky_shape", None)
+        if shape is None:
+            raise ValueError("sky_grad given but the forward state has no sky "
+                             "map (or was not made by dv_render)")
+        if not (hasattr(sky_grad, "is_cuda") and sky_grad.is_cuda
+                and tuple(sky_grad.shape) == shape and sky_grad.is_contiguous()
+                and str(sky_grad.dtype) == "torch.float32"):
+            raise ValueError(f"sky_grad must be a contiguous float32 CUDA tensor "
+                             f"of shape {shape}")
     nv = len(grads)
     cg = (dv_out_grads * nv)()
     for i, g in enumerate(grads):

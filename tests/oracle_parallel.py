@@ -28,8 +28,8 @@ def _grad_chunk(args):
             nz = np.nonzero(arr.reshape(arr.shape[0], -1).any(1))[0]
             lst.append((nz, arr[nz]))
         out[key] = lst
-    out["dR"] = acc["dR"]
-    out["dp"] = acc["dp"]
+    for key in ("dR", "dp", "dR_abs", "dp_abs"):
+        out[key] = acc[key]
     out["sky"] = acc["sky"]
     return out
 
@@ -48,9 +48,9 @@ def render_and_grad_parallel(scene, view, opts, grads, pixels, procs):
         for key in ("corner", "corner_abs", "dcol", "dcol_abs", "dnw"):
             for k, (nz, vals) in enumerate(part[key]):
                 acc[key][k][nz] += vals
-        for k in range(len(acc["dR"])):
-            acc["dR"][k] += part["dR"][k]
-            acc["dp"][k] += part["dp"][k]
+        for key in ("dR", "dp", "dR_abs", "dp_abs"):
+            for k in range(len(acc[key])):
+                acc[key][k] += part[key][k]
         if acc["sky"] is not None:
             acc["sky"] += part["sky"]
     _CTX = None

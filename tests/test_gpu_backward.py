@@ -23,7 +23,15 @@ def ctx():
     return gpu_ctx()
 
 
-def _close(name, g, ref, rel=1e-3, floor=1e-2):
+# An FP32 summand carries a relative rounding error of a few ulps; a
+# gradient element that is a signed sum of many summands inherits their
+# errors in absolute terms, so where the oracle reports the element's
+# summand magnitude (sum of |contribution|) the bar adds 2^-20 of it
+# (16 ulps per summand) to the relative bar.
+SUMMAND_ULPS = 2.0 ** -20
+
+
+def _close(name, g, ref, rel=1e-3, floor=1e-2, summed=None):
     g = np.asarray(g, np.float64)
     ref = np.asarray(ref, np.float64)
     scale = np.abs(ref).max()
@@ -31,6 +39,8 @@ def _close(name, g, ref, rel=1e-3, floor=1e-2):
         assert np.abs(g).max() == 0.0, name
         return
     bound = rel * np.maximum(np.abs(ref), floor * scale)
+    if summed is not None:
+        bound = bound + SUMMAND_ULPS * np.asarray(summed, np.float64)
     err = np.abs(g - ref)
     worst = float((err / bound).max())
     print(f"  {name}: max|ref| {scale:.3e} worst err/bound {worst:.3f}")

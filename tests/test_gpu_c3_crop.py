@@ -52,6 +52,28 @@ def _subscene(scene, view):
     return dict(octrees=octs, tracks=scene["tracks"])
 
 
+def pick_car_crop(scene, v0, min_depth=6.0):
+    """The car nearest to the camera of view v0 inside its field of view,
+    and the crop origin (car plus the road below it)."""
+    best = None
+    for k in range(1, len(scene["octrees"])):
+        act, R, p = G.pose_at(scene["tracks"][k], v0["t"])
+        if not act:
+            continue
+        X = v0["c2w"][:, :3].T @ (p - v0["c2w"][:, 3])
+        if X[2] > min_depth:
+            u = v0["cx"] + v0["fx"] * X[0] / X[2]
+            w_ = v0["cy"] + v0["fy"] * X[1] / X[2]
+            if 40 <= u < v0["w"] - 40 and 30 <= w_ < v0["h"] - 30:
+                if best is None or X[2] < best[0]:
+                    best = (X[2], k, int(u), int(w_))
+    assert best is not None
+    _, kcar, u, w_ = best
+    x0 = int(np.clip(u - CW // 2, 0, v0["w"] - CW))
+    y0 = int(np.clip(w_ + 20 - CH // 2, 0, v0["h"] - CH))   # car + road
+    return kcar, x0, y0
+
+
 def test_c3_crop_gradients(tmp_path):
     import torch
     from paper_2606_23031_amd import dv
@@ -64,21 +86,7 @@ def test_c3_crop_gradients(tmp_path):
     # the ray's transmittance where translucent background precedes a car
     opts = dict(cfg["opts"], eps_stop=0.0)
     v0 = views[0]
-    # the car nearest to camera 0 inside its field of view
-    best = None
-    for k in range(1, len(scene["octrees"])):
-        act, R, p = G.pose_at(scene["tracks"][k], v0["t"])
-        X = v0["c2w"][:, :3].T @ (p - v0["c2w"][:, 3])
-        if X[2] > 6.0:
-            u = v0["cx"] + v0["fx"] * X[0] / X[2]
-            w_ = v0["cy"] + v0["fy"] * X[1] / X[2]
-            if 40 <= u < v0["w"] - 40 and 30 <= w_ < v0["h"] - 30:
-                if best is None or X[2] < best[0]:
-                    best = (X[2], k, int(u), int(w_))
-    assert best is not None
-    _, kcar, u, w_ = best
-    x0 = int(np.clip(u - CW // 2, 0, v0["w"] - CW))
-    y0 = int(np.clip(w_ + 20 - CH // 2, 0, v0["h"] - CH))   # car + road
+    kcar, x0, y0 = pick_car_crop(scene, v0)
     ctx = dv.dv_ctx_create(0)
     sc = dv.Scene(ctx, scene)
     mask = dv.DV_OUT_RGB | dv.DV_OUT_DEPTH | dv.DV_OUT_T

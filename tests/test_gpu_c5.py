@@ -117,3 +117,97 @@ def test_c5_backward_all_views(c5):
     assert float(a0[0]["corner"].norm()) > 0.0 and seen >= 20
     assert bool(p0.isfinite().all())
     assert float((p0 - p1).norm()) <= 1e-5 * float(p0.norm())
+
+
+def test_c5_crop_gradients_leaf_major(c5):
+    """Backward parity at full size on the leaf-major path.  The GPU
+    backward runs over all 24 views in the launch configuration of the
+    benchmark, with an upstream gradient (RGB, depth, normal, T) that is
+    non-zero only on a 64x48 crop of one view at t = 0.1 s centred on a car;
+    the launch holds more than 1.5 records per leaf, so SH and corner
+    gradients are summed per leaf over the views before they are written.
+    The reference is the oracle's adjoint over the crop's pixels on the
+    sub-scene of leaves binned to the crop (bar of the full-size crops)."""
+    import torch
+    from oracle_parallel import render_and_grad_parallel
+    from test_gpu_c3_crop import CW, CH, _crop_view, _subscene, pick_car_crop
+    from test_gpu_fullsize import _close
+    dv, ctx, cfg, sc = c5
+    scene, views = cfg["scene"], cfg["views"]
+    opts = dict(cfg["opts"], eps_stop=0.0)
+    iv = 6                                   # camera 0 at t = 0.1 s
+    v0 = views[iv]
+    assert v0["t"] == 0.1
+    kcar, x0, y0 = pick_car_crop(scene, v0)
+    outs, st = _render(dv, ctx, sc, views, opts, keep=True)
+    info = dv.dv_fwd_state_info(st)
+    padded = sum((len(o["level"]) + 63) // 64 * 64 for o in scene["octrees"])
+    print(f"  {info['n_visible']} records for {padded} leaf threads")
+    assert info["n_visible"] >= 1.5 * padded        # the leaf-major pass runs
+    rng = np.random.default_rng(55)
+    h, w = v0["h"], v0["w"]
+    G = dict(rgb=np.zeros((3, h, w), np.float32), depth=np.zeros((h, w), np.float32),
+             normal=np.zeros((3, h, w), np.float32), T=np.zeros((h, w), np.float32))
+    ys, xs = slice(y0, y0 + CH), slice(x0, x0 + CW)
+    G["rgb"][:, ys, xs] = rng.normal(size=(3, CH, CW))
+    G["depth"][ys, xs] = 0.02 * rng.normal(size=(CH, CW))
+    G["normal"][:, ys, xs] = rng.normal(size=(3, CH, CW))
+    G["T"][ys, xs] = rng.normal(size=(CH, CW))
+    grads = []
+    for i, v in enumerate(views):
+        if i == iv:
+            grads.append({k: torch.tensor(a, device="cuda") for k, a in G.items()})
+        else:
+            grads.append(dict(rgb=torch.zeros(3, v["h"], v["w"], device="cuda")))
+    acc = [dict(corner=torch.zeros(len(o["corner_density"]), device="cuda"),
+                sh=torch.zeros(o["sh"].shape, device="cuda"))
+           for o in scene["octrees"]]
+    na = len(scene["octrees"]) - 1
+    pg = torch.zeros(len(views), na, 12, device="cuda")
+    dv.dv_render_backward(ctx, sc, st, grads, acc, pg)
+    torch.cuda.synchronize()
+    dv.dv_fwd_state_release(st)
+    crop = _crop_view(v0, x0, y0)
+    sub = _subscene(scene, crop)
+    pix = RD.window_pixels(crop)
+    gpix = np.zeros((len(pix), 8))
+    gpix[:, 0:3] = G["rgb"][:, pix[:, 1], pix[:, 0]].T
+    gpix[:, 3] = G["depth"][pix[:, 1], pix[:, 0]]
+    gpix[:, 4:7] = G["normal"][:, pix[:, 1], pix[:, 0]].T
+    gpix[:, 7] = G["T"][pix[:, 1], pix[:, 0]]
+    ref = render_and_grad_parallel(sub, v0, opts, gpix, pix, RD.default_procs())
+    nsub = [len(o["level"]) for o in sub["octrees"] if len(o["level"])]
+    print(f"  car {kcar}, crop ({x0},{y0}) of view {iv}, sub-scene "
+          f"{sum(nsub)} leaves in {len(nsub)} octrees")
+    gc, rc, mc, gs, rs, ms = [], [], [], [], [], []
+    for k, o in enumerate(sub["octrees"]):
+        keep = o["_keep"]
+        if len(keep) == 0:
+            continue
+        gc.append(acc[k]["corner"].cpu().numpy())
+        rc.append(ref["corner"][k])
+        mc.append(ref["corner_abs"][k])
+        gs.append(acc[k]["sh"].cpu().numpy()[:, :, keep].ravel())
+        rs.append(np.asarray(ref["sh"][k]).ravel())
+        ms.append(np.asarray(ref["sh_abs"][k]).ravel())
+    # leaves outside the sub-scene receive nothing from the crop
+    for k, o in enumerate(sub["octrees"]):
+        out = np.ones(len(scene["octrees"][k]["level"]), bool)
+        out[o["_keep"]] = False
+        if out.any():
+            assert float(acc[k]["sh"][:, :, torch.from_numpy(out).cuda()].abs().max()) == 0.0
+    worst = {"corner": _close("corner (all octrees)", np.concatenate(gc),
+                              np.concatenate(rc), mag=np.concatenate(mc)),
+             "sh": _close("sh (all octrees)", np.concatenate(gs), np.concatenate(rs),
+                          mag=np.concatenate(ms))}
+    p0 = pg.cpu().numpy()[iv]
+    refR = np.stack([ref["dR"][i + 1] for i in range(na)])
+    refp = np.stack([ref["dp"][i + 1] for i in range(na)])
+    worst["dR"] = _close("dR (all actors)", p0[:, :9], refR.reshape(na, 9))
+    worst["dp"] = _close("dp (all actors)", p0[:, 9:], refp)
+    worst[f"corner[{kcar}]"] = _close(f"corner[{kcar}]", acc[kcar]["corner"].cpu().numpy(),
+                                      ref["corner"][kcar], mag=ref["corner_abs"][kcar])
+    others = torch.cat([pg[:iv], pg[iv + 1:]])
+    assert float(others.abs().max()) == 0.0
+    bad = {k: wv for k, wv in worst.items() if wv > 1.0}
+    assert not bad, bad

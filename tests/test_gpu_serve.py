@@ -130,3 +130,71 @@ def test_concurrent_submitters(env):
     res = [dv.dv_serve_poll(srv, t, -1) for t in tickets]
     assert all(r[0] == 0 for r in res)
     dv.dv_serve_destroy(srv)
+
+
+def test_serving_workload_scene_staggered_mix():
+    """The serving workload: the 1M-leaf + 8-car driving scene resident,
+    requests of mixed resolution (640x360, 960x540, 1920x1080), random
+    timestamps and headings on the ego lane, submitted with Poisson
+    arrivals so that requests join while others are on the GPU.  Every
+    served frame equals the same view rendered alone by dv_render, bit for
+    bit (the benchmark's launch options); sampled pixels of each resolution
+    are within 1e-4 of the oracle (exact walk, eps_stop = 0)."""
+    import torch
+    from paper_2606_23031_amd import dv
+    from synth import make_config
+    import bench
+    cfg = make_config(4)
+    ctx = dv.dv_ctx_create(0)
+    sc = dv.Scene(ctx, cfg["scene"])
+    views = bench.serve_views(36, seed=14)
+    sizes = {(v["w"], v["h"]) for v in views}
+    assert len(sizes) == 3
+    mask = dv.DV_OUT_RGB | dv.DV_OUT_DEPTH
+    rng = np.random.default_rng(15)
+    gaps = rng.exponential(1.0 / 400.0, len(views))   # ~2.5 ms apart
+    for eps in (cfg["opts"]["eps_stop"], 0.0):
+        opts = dict(cfg["opts"], eps_stop=eps)
+        srv = dv.dv_serve_create(ctx, sc, dv.make_opts(opts, mask), max_inflight=8,
+                                 mem_budget=16 << 30, batched=True, max_batch=4)
+        outs = [_alloc(dv, v, mask) for v in views]
+        torch.cuda.synchronize()
+        tickets = []
+        for v, o, g in zip(views, outs, gaps):
+            time.sleep(g)
+            tickets.append(dv.dv_serve_submit(srv, v, o))
+        res = [dv.dv_serve_poll(srv, t, -1) for t in tickets]
+        dv.dv_serve_destroy(srv)
+        assert all(r[0] == 0 for r in res)
+        # requests overlapped: some were admitted before an earlier one was done
+        admits = [r[2] for r in res]
+        dones = [r[3] for r in res]
+        overlap = sum(1 for i in range(1, len(res)) if admits[i] < dones[i - 1])
+        print(f"  eps {eps}: {overlap} of {len(res) - 1} requests admitted while "
+              f"the previous one was in flight")
+        assert overlap > 0
+        copts = dv.make_opts(opts, mask)
+        for v, o in zip(views, outs):
+            alone = dv.alloc_outputs([v], mask)
+            dv.dv_render(ctx, sc, [v], copts, alone)
+            torch.cuda.synchronize()
+            for k in ("rgb", "depth"):
+                assert torch.equal(alone[0][k], o[k]), (v["w"], k)
+    # oracle on sampled pixels of one request per resolution (eps = 0 run)
+    done = set()
+    for v, o in zip(views, outs):
+        key = (v["w"], v["h"])
+        if key in done:
+            continue
+        done.add(key)
+        pix = np.stack([rng.integers(0, v["w"], 6), rng.integers(0, v["h"], 6)], 1)
+        ref = RD.render_pixels(cfg["scene"], v, dict(cfg["opts"], eps_stop=0.0), pix,
+                               procs=RD.default_procs())
+        gx, gy = pix[:, 0], pix[:, 1]
+        rgb = o["rgb"].cpu().numpy().astype(np.float64)[:, gy, gx].T
+        dep = o["depth"].cpu().numpy().astype(np.float64)[gy, gx]
+        e_rgb = np.abs(rgb - ref[:, 0:3]).max()
+        e_d = np.abs(dep - ref[:, 3])
+        print(f"  {key}: rgb {e_rgb:.2e} depth {e_d.max():.2e}")
+        assert e_rgb <= 1e-4
+        assert np.all(e_d <= 1e-4 * (1.0 + np.abs(ref[:, 3])))
