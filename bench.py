@@ -1,15 +1,19 @@
 """Benchmark: one training step of the compositional renderer on one MI355X.
 
-A step is the whole hot path over one batch: forward render of the
-driving workload (1M-leaf static octree + 8 car octrees of ~20k leaves,
-one 1920x1080 camera; preprocessing, binning, sorts, directories and the
+A step is the whole hot path over one batch: forward render of the stress
+workload (8M-leaf static octree to level 14 + 100 car octrees of ~50k
+leaves; 6 cameras x 4 timestamps = 24 views of 1920x1080 in one launch,
+RGB, depth and normal; preprocessing, binning, sorts, directories and the
 multi-octree compositing walk), an L1 loss against a random target, and the
 hand-written backward to corner densities, SH coefficients and actor poses.
-Inputs are synthetic and resident in HBM before timing starts.
+Inputs are synthetic and resident in HBM before timing starts.  The 1080p
+single-view and six-camera training workloads are timed after it as extra
+entries, and the serving workload (1M-leaf scene, Poisson requests) after
+those.
 
 Prints one JSON line (metric, value, roofline of the dominant kernel,
-CPU-oracle baseline).  ``--gpus`` above 1 is not supported: this build
-runs on one GPU.
+per-stage HBM fractions, CPU-oracle baseline).  ``--gpus`` above 1 is not
+supported: this build runs on one GPU.
 """
 import argparse
 import json
@@ -25,7 +29,12 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (published)
 
-# Algorithmic FLOPs (FMA = 2) of the compositing walks, K = 1:
+# Algorithmic operations of the compositing walks (FMA = 2), K = 1.
+# Per processed (pixel, list entry): forward 50 + 40 K, backward 2.5 x the
+# forward (the per-entry counts the roofline fraction is quoted with).
+OPS_ENTRY_FWD = 50 + 40 * 1
+OPS_ENTRY_BWD = 2.5 * OPS_ENTRY_FWD
+# Finer count of what the walks evaluate, reported beside it:
 #   per (pixel, list entry) slab test           21
 #   per piece, forward (optical depth 49,
 #     compositing 22)                            71
@@ -45,7 +54,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=5)
+    ap.add_argument("--extra-configs", default="2,3",
+                    help="training workloads timed after the headline "
+                         "(comma list, empty: none)")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="end with a 256 MiB device copy (reference for "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--v-close", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -63,11 +78,14 @@ def parse():
 class Step:
     """Forward + L1 loss gradient + backward for one batch of views."""
 
-    def __init__(self, ctx, dv, scene_dict, views, opts, sky=None, sc=None):
+    def __init__(self, ctx, dv, scene_dict, views, opts, sky=None, sc=None,
+                 normals=False):
         import torch
         self.torch, self.dv, self.ctx = torch, dv, ctx
         self.views = views
         self.mask = dv.DV_OUT_RGB | dv.DV_OUT_DEPTH | dv.DV_OUT_T
+        if normals:
+            self.mask |= dv.DV_OUT_NORMAL
         # optional sky environment map [3][H][W] and its gradient
         self.sky = sky
         self.sky_grad = None if sky is None else torch.zeros_like(sky)
@@ -137,11 +155,18 @@ def cpu_baseline(cfg, budget_s):
     with mp.get_context("fork").Pool(procs) as pool:
         pool.map(_pool_work, [(pix[c], grads[c]) for c in chunks])
     dt = time.time() - t0
+    host = os.cpu_count()
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = host
     return dict(value=len(pix) / dt / 1e6, unit="Mpix/s", cores=procs,
-                kind="oracle",
-                sample=f"{len(pix)} rays (every {stride}th row/column of the "
-                       f"1920x1080 view), FP64 forward+adjoint, "
-                       f"{dt:.1f}s wall; per-view setup {t_ctx:.1f}s excluded")
+                kind="oracle", host_cores=host, host_cores_available=avail,
+                sample=f"{len(pix)} rays (every {stride}th row/column of view 0, "
+                       f"1920x1080, of the {cfg['name']} workload), FP64 "
+                       f"forward+adjoint over every leaf of every octree, "
+                       f"{procs} worker processes, {dt:.1f}s wall; per-view "
+                       f"setup {t_ctx:.1f}s excluded")
 
 
 _CTX = None
@@ -256,10 +281,10 @@ KERNEL_OF_STAGE = {"composite_fwd": "dv::k_composite_fwd", "composite_bwd": "dv:
 
 def stored_traffic(stage, workload):
     """HBM bytes (read + write) per launch of the stage's kernel from the
-    committed rocprofv3 counter summary, or None when the kernels have
-    changed since those counters were taken."""
+    committed rocprofv3 counter summary of that workload, or None when the
+    kernels have changed since those counters were taken."""
     from paper_2606_23031_amd.srchash import csrc_hash
-    path = os.path.join(ROOT, "profiles", "traffic_driving-1M-8x20k-1080p.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path) or stage not in KERNEL_OF_STAGE:
         return None
     with open(path) as f:
@@ -268,76 +293,90 @@ def stored_traffic(stage, workload):
         return None
     for name, v in d["kernels"].items():
         if name.startswith(KERNEL_OF_STAGE[stage]):
-            return round(v["fetch_bytes"] + v["write_bytes"])
+            return round((v["fetch_bytes"] + v["write_bytes"]) / max(v.get("launches_per_step", 1), 1))
     return None
 
 
-def roofline(stage, ms, calls, info, counters, scene_stats):
-    """Roofline entry for the dominant stage (per launch)."""
-    per = ms / max(calls, 1) / 1e3   # seconds per launch
-    if stage in ("composite_fwd", "composite_bwd", "actor_fwd", "actor_bwd"):
-        suf = {"composite_fwd": "fwd", "composite_bwd": "bwd",
-               "actor_fwd": "actor_fwd", "actor_bwd": "actor_bwd"}[stage]
-        per_piece = FLOP_PIECE_FWD if suf.endswith("fwd") else FLOP_PIECE_BWD
-        flops = FLOP_TEST * counters["entries_" + suf] + per_piece * counters["pieces_" + suf]
-        ach = flops / per / 1e12
-        return dict(bound="alu", achieved=ach, peak=PEAK_FP32_TFLOPS,
-                    unit="TFLOP/s", frac=ach / PEAK_FP32_TFLOPS, traffic=None,
-                    kernel=stage, flops_per_launch=flops)
+def alu_roofline(stage, ms, calls, launches_per_step, counters):
+    """Roofline entry of a compositing walk (per launch): operations per
+    processed (pixel, entry) times the entries one launch processes, over
+    the launch's average device time (ms over calls launches), against the
+    FP32 vector peak; the finer per-test / per-piece count is reported
+    beside it.  counters: work counted over one step."""
+    per = ms / max(calls, 1) / 1e3
+    suf = {"composite_fwd": "fwd", "composite_bwd": "bwd",
+           "actor_fwd": "actor_fwd", "actor_bwd": "actor_bwd"}[stage]
+    fwd = suf.endswith("fwd")
+    entries = counters["entries_" + suf] / max(launches_per_step, 1)
+    pieces = counters["pieces_" + suf] / max(launches_per_step, 1)
+    ops = (OPS_ENTRY_FWD if fwd else OPS_ENTRY_BWD) * entries
+    fine = FLOP_TEST * entries + (FLOP_PIECE_FWD if fwd else FLOP_PIECE_BWD) * pieces
+    ach = ops / per / 1e12
+    return dict(bound="alu", achieved=ach, peak=PEAK_FP32_TFLOPS,
+                unit="TFLOP/s", frac=ach / PEAK_FP32_TFLOPS, traffic=None,
+                kernel=stage, ops_per_launch=ops,
+                ops_per_entry=OPS_ENTRY_FWD if fwd else OPS_ENTRY_BWD,
+                entries_per_launch=entries, launch_ms=per * 1e3,
+                fine_count=dict(flops_per_launch=fine,
+                                achieved=fine / per / 1e12,
+                                frac=fine / per / 1e12 / PEAK_FP32_TFLOPS))
+
+
+def hbm_stages(stages, info, scene_stats):
+    """Algorithmic HBM bytes of the streaming stages per step (the method's
+    own reads and writes: preprocess V 8 + V_vis (12 S + 64) + V_vis 48,
+    sorts V_vis 16 p_v + P 24 p_p with p the radix passes, SH / record
+    backward V_vis (12 + 24 S)) over the stage's device time per step."""
     nv, npairs = info["n_visible"], info["n_pairs"]
-    if stage == "sort_pairs":
-        passes = (info["tile_bits"] + 7) // 8
-        byts = npairs * 16 * passes
-    elif stage == "sort_records":
-        passes = (info["key_bits"] + 7) // 8
-        byts = nv * 24 * passes
-    elif stage == "preprocess":
-        byts = scene_stats["items"] * 8 * 2 + nv * (64 + 12 * scene_stats["S"] + 112)
-    elif stage == "emit_pairs":
-        byts = npairs * 8 + nv * 12
-    else:
-        byts = nv * 16
-    ach = byts / per / 1e9
-    return dict(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s",
-                frac=ach / PEAK_HBM_GBS, traffic=None, kernel=stage,
-                bytes_per_launch=byts)
+    S, V = scene_stats["S"], scene_stats["items"]
+    p_v = (info["key_bits"] + 7) // 8
+    p_p = (info["tile_bits"] + 7) // 8
+    algo = {
+        "preprocess": V * 8 + nv * (12 * S + 64) + nv * 48,
+        "sort_records": nv * 16 * p_v,
+        "sort_pairs": npairs * 24 * p_p,
+        "record_bwd": nv * (12 + 24 * S),
+    }
+    out = {}
+    for k, b in algo.items():
+        if k not in stages or stages[k][1] == 0:
+            continue
+        ms = stages[k][0] / scene_stats["steps"]
+        gbs = b / (ms / 1e3) / 1e9
+        out[k] = dict(bytes=int(b), ms=round(ms, 4), achieved_GBs=round(gbs, 1),
+                      frac=round(gbs / PEAK_HBM_GBS, 4))
+    out["_passes"] = dict(records=p_v, pairs=p_p)
+    return out
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this renderer "
-              "runs on one GPU (see the sharding design notes)", file=sys.stderr)
-        sys.exit(2)
+def run_workload(dv, ctx, cfg, args, headline):
+    """Time one training workload: warmup, args.steps timed steps (wall
+    clock around the whole batch), then per-stage HIP-event times over
+    profiled steps and the walks' work counters on one more step."""
     import torch
-    from paper_2606_23031_amd import dv
-    from synth import make_config
-    t0 = time.time()
-    cfg = make_config(args.config, v_close=args.v_close)
     views = cfg["views"]
-    log(f"[bench] generated {cfg['name']} in {time.time() - t0:.1f}s: "
-        f"{cfg['info']['n_total']} leaves, {len(views)} view(s)")
-    ctx = dv.dv_ctx_create(0)
-    step = Step(ctx, dv, cfg["scene"], views, cfg["opts"])
+    normals = cfg["name"].startswith("driving-8M")
+    step = Step(ctx, dv, cfg["scene"], views, cfg["opts"], normals=normals)
     torch.cuda.synchronize()
     for i in range(args.warmup):
         step(info=(i == 0))
     torch.cuda.synchronize()
-    log(f"[bench] warmup done; info {step.last_info}")
+    log(f"[bench] {cfg['name']}: warmup done; info {step.last_info}")
+    steps = args.steps if headline else max(5, args.steps // 2)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms = dt / args.steps * 1e3
-    value = step.npix / (dt / args.steps) / 1e6
-    log(f"[bench] timed {args.steps} steps: {ms:.3f} ms/step, {value:.1f} Mpix/s")
-    # per-stage device times (HIP events on the stream of each kernel)
+    ms = dt / steps * 1e3
+    value = step.npix / (dt / steps) / 1e6
+    log(f"[bench] {cfg['name']}: timed {steps} steps: {ms:.3f} ms/step, "
+        f"{value:.1f} Mpix/s")
     dv.dv_ctx_set_profiling(ctx, dv.PROFILE_EVENTS)
     dv.dv_ctx_stage_times(ctx, reset=True)
-    per_step = []
-    stages = {}
-    for _ in range(args.profile_steps):
+    per_step, stages = [], {}
+    nprof = args.profile_steps if headline else max(3, args.profile_steps // 4)
+    for _ in range(nprof):
         step()
         torch.cuda.synchronize()
         st = dv.dv_ctx_stage_times(ctx, reset=True)
@@ -353,89 +392,161 @@ def main():
             continue
         xs = np.array([d.get(k, 0.0) for d in per_step])
         spread[k] = [round(float(np.percentile(xs, q)), 4) for q in (50, 10, 90)]
-    # work counters in a separate, untimed step
     dv.dv_ctx_set_profiling(ctx, dv.PROFILE_COUNTERS)
     step()
     torch.cuda.synchronize()
     counters = dv.dv_ctx_stage_times(ctx, reset=True)["_counters"]
     dv.dv_ctx_set_profiling(ctx, 0)
-    stage_avg = {k: (v[0] / max(v[1], 1)) for k, v in stages.items() if v[1] > 0}
-    dom = max((k for k in stage_avg if k not in ("host_sync", "other")),
+    dom = max((k for k in stages if stages[k][1] > 0
+               and k not in ("host_sync", "other", "bwd_clear")),
               key=lambda k: stages[k][0])
     S = max((o["sh_degree"] + 1) ** 2 for o in cfg["scene"]["octrees"])
     items = sum(len(o["level"]) for o in cfg["scene"]["octrees"]) * len(views)
-    rl = roofline(dom, stages[dom][0], stages[dom][1], step.last_info, counters,
-                  dict(items=items, S=S))
+    res = dict(workload=cfg["name"], views=len(views), pixels_per_step=step.npix,
+               leaves=int(cfg["info"]["n_total"]),
+               actors=len(cfg["scene"]["octrees"]) - 1,
+               outputs="rgb,depth,normal,T" if normals else "rgb,depth,T",
+               ms_per_step=round(ms, 4), mpix_per_s=round(value, 3), steps=steps,
+               n_visible=step.last_info["n_visible"],
+               n_pairs=step.last_info["n_pairs"], work=counters,
+               stages_ms_per_step={k: round(v[0] / nprof, 4)
+                                   for k, v in stages.items() if v[1] > 0},
+               stages_ms_p50_p10_p90=spread,
+               stages_hbm=hbm_stages(stages, step.last_info,
+                                     dict(items=items, S=S, steps=nprof)))
+    if dom in ("composite_fwd", "composite_bwd", "actor_fwd", "actor_bwd"):
+        rl = alu_roofline(dom, stages[dom][0], stages[dom][1],
+                          stages[dom][1] / nprof, counters)
+    else:
+        h = res["stages_hbm"].get(dom, {})
+        rl = dict(bound="hbm", achieved=h.get("achieved_GBs"), peak=PEAK_HBM_GBS,
+                  unit="GB/s", frac=h.get("frac"), traffic=None, kernel=dom)
     rl["traffic"] = stored_traffic(dom, cfg["name"])
+    res["roofline"] = rl
+    res["_step"] = step
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this renderer "
+              "runs on one GPU (see the sharding design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2606_23031_amd import dv
+    from synth import make_config
+    ctx = dv.dv_ctx_create(0)
+    t0 = time.time()
+    cfg = make_config(args.config, v_close=args.v_close)
+    log(f"[bench] generated {cfg['name']} in {time.time() - t0:.1f}s: "
+        f"{cfg['info']['n_total']} leaves, {len(cfg['views'])} view(s)")
+    head = run_workload(dv, ctx, cfg, args, headline=True)
+    head_step = head.pop("_step")
     out = {
         "metric": "fwd+bwd Mpix/s per train step",
-        "value": round(value, 3),
+        "value": head["mpix_per_s"],
         "unit": "Mpix/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": cfg["name"], "pixels_per_step": step.npix,
-                   "leaves": int(cfg["info"]["n_total"]),
-                   "actors": len(cfg["scene"]["octrees"]) - 1,
+        "config": {"workload": cfg["name"], "pixels_per_step": head["pixels_per_step"],
+                   "views": head["views"], "leaves": head["leaves"],
+                   "actors": head["actors"], "outputs": head["outputs"],
                    "v_close": args.v_close, "K": cfg["opts"]["K"],
                    "eps_stop": cfg["opts"]["eps_stop"],
-                   "n_visible": step.last_info["n_visible"],
-                   "n_pairs": step.last_info["n_pairs"],
-                   "work": counters},
-        "roofline": rl,
-        "stages_ms_per_step": {k: round(v[0] / args.profile_steps, 4)
-                               for k, v in stages.items() if v[1] > 0},
-        "stages_ms_p50_p10_p90": spread,
+                   "n_visible": head["n_visible"], "n_pairs": head["n_pairs"],
+                   "work": head["work"]},
+        "roofline": head["roofline"],
+        "stages_ms_per_step": head["stages_ms_per_step"],
+        "stages_ms_p50_p10_p90": head["stages_ms_p50_p10_p90"],
+        "stages_hbm": head["stages_hbm"],
     }
-    if args.sky_map != "0":
-        # the same step with a sky environment map: bilinear C_sky per pixel
-        # in the composite, T_final G_C scattered into the map's gradient
-        H, W = (int(x) for x in args.sky_map.lower().split("x"))
-        g = torch.Generator(device="cpu").manual_seed(99)
-        sky = torch.rand(3, H, W, generator=g).cuda()
-        sstep = Step(ctx, dv, cfg["scene"], views, cfg["opts"], sky=sky, sc=step.sc)
-        for _ in range(args.warmup):
-            sstep()
+    # the CPU oracle on the headline workload while its scene is in memory
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle baseline ...")
+        cpu = cpu_baseline(cfg, args.cpu_seconds)
+    head_step.sc.close()
+    del head_step, cfg
+    torch.cuda.synchronize()
+    dv.dv_ctx_trim(ctx)
+    extra = {}
+    c2 = None
+    for k in [int(x) for x in args.extra_configs.split(",") if x.strip()]:
+        if k == args.config:
+            continue
+        c = make_config(k, v_close=args.v_close)
+        r = run_workload(dv, ctx, c, args, headline=False)
+        st = r.pop("_step")
+        if k == 2 and args.sky_map != "0":
+            # the same step with a sky environment map: bilinear C_sky per
+            # pixel in the composite, T_final G_C scattered into its gradient
+            H, W = (int(x) for x in args.sky_map.lower().split("x"))
+            g = torch.Generator(device="cpu").manual_seed(99)
+            sky = torch.rand(3, H, W, generator=g).cuda()
+            sstep = Step(ctx, dv, c["scene"], c["views"], c["opts"], sky=sky, sc=st.sc)
+            for _ in range(args.warmup):
+                sstep()
+            torch.cuda.synchronize()
+            n = max(5, args.steps // 2)
+            t0 = time.perf_counter()
+            for _ in range(n):
+                sstep()
+            torch.cuda.synchronize()
+            sms = (time.perf_counter() - t0) / n * 1e3
+            log(f"[bench] with a {H}x{W} sky map: {sms:.3f} ms/step")
+            r["sky"] = {"map": [3, H, W], "ms_per_step": round(sms, 4),
+                        "ms_per_step_constant_bg": r["ms_per_step"]}
+            del sstep
+        if k == 2:
+            c2 = (c, st.sc)
+        else:
+            st.sc.close()
+        del st
+        extra[c["name"]] = r
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            sstep()
-        torch.cuda.synchronize()
-        sms = (time.perf_counter() - t0) / args.steps * 1e3
-        log(f"[bench] with a {H}x{W} sky map: {sms:.3f} ms/step")
-        out["sky"] = {"map": [3, H, W], "ms_per_step": round(sms, 4),
-                      "ms_per_step_constant_bg": round(ms, 4)}
-        del sstep
-    if args.serve_requests > 0 and args.config == 2:
+        dv.dv_ctx_trim(ctx)
+    if extra:
+        out["other_workloads"] = extra
+    if args.serve_requests > 0:
+        if c2 is None:
+            c = make_config(4, v_close=args.v_close)
+            c2 = (c, dv.Scene(ctx, c["scene"]))
+        c, sc2 = c2
         sv = serve_views(args.serve_requests, seed=4)
         log(f"[bench] serving {len(sv)} requests at {args.serve_rate}/s ...")
         out["serving"] = dict(
             workload="driving-1M+8x20k-serving, Poisson arrivals, mixed "
                      "640x360/960x540/1920x1080, RGB+depth",
-            batched=serve_run(dv, ctx, step.sc, cfg["opts"], sv,
-                              args.serve_rate, True, seed=5),
-            per_request=serve_run(dv, ctx, step.sc, cfg["opts"], sv,
-                                  args.serve_rate, False, seed=5))
+            batched=serve_run(dv, ctx, sc2, c["opts"], sv, args.serve_rate, True,
+                              seed=5),
+            per_request=serve_run(dv, ctx, sc2, c["opts"], sv, args.serve_rate,
+                                  False, seed=5))
         if args.serve_saturate > 0:
             sat = sv[:args.serve_saturate]
             log(f"[bench] serving capacity: {len(sat)} requests queued at once ...")
             out["serving"]["capacity"] = dict(
-                batched=serve_run(dv, ctx, step.sc, cfg["opts"], sat,
-                                  float("inf"), True, seed=6),
-                per_request=serve_run(dv, ctx, step.sc, cfg["opts"], sat,
-                                      float("inf"), False, seed=6))
+                batched=serve_run(dv, ctx, sc2, c["opts"], sat, float("inf"), True,
+                                  seed=6),
+                per_request=serve_run(dv, ctx, sc2, c["opts"], sat, float("inf"),
+                                      False, seed=6))
         log(f"[bench] serving: {out['serving']}")
-    if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle baseline ...")
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
-    else:
-        out["cpu_baseline"] = None
+    out["cpu_baseline"] = cpu
+    if args.calibration_copy:
+        x = torch.empty(64 << 20, device="cuda")
+        y = torch.empty(64 << 20, device="cuda")
+        x.fill_(1.0)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy of 256 MiB done")
     print(json.dumps(out), flush=True)
 
 

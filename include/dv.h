@@ -129,6 +129,23 @@ typedef struct {
    * when sky is set (DV_ERR_INVALID otherwise). */
   const float* sky;
   int32_t sky_w, sky_h;
+  /* Feature accumulation (Sec. 4.3, 3D semantic segmentation: the colour
+   * step of the volume rendering replaced by a high-dimensional per-voxel
+   * feature).  feat: NULL for the colour render, else a host array
+   * [n_octrees] of device pointers, octree k's features [feat_dim][N_k]
+   * (caller-owned, f32).  A feature render composites, in place of each
+   * leaf's SH colour, its channels 3 feat_group .. 3 feat_group + 2
+   * (channels >= feat_dim count as 0; no clamp, no view dependence) with
+   * the same weights as the colour render, over a zero background (bg and
+   * sky are ignored): out.rgb receives sum_i w_i f_i for those 3 channels.
+   * Depth, normal and T are as in the colour render.  Its backward adds
+   * dL/dfeature into dv_octree_grads.feat (and corner and pose gradients as
+   * usual; features carry no SH term).  feat_dim >= 1 and
+   * 0 <= 3 feat_group < feat_dim when feat is set (DV_ERR_INVALID
+   * otherwise). */
+  const float* const* feat;
+  int32_t feat_dim;
+  int32_t feat_group;
 } dv_render_opts;
 
 /* Per-view device output planes (window-sized, float).  Entries not in
@@ -152,7 +169,9 @@ typedef struct {
 /* Gradient accumulators of one octree (device; results are ADDED). */
 typedef struct {
   float* corner;                /* [Nc] or NULL                            */
-  float* sh;                    /* [S][3][N] or NULL                       */
+  float* sh;                    /* [S][3][N] or NULL (colour renders)      */
+  float* feat;                  /* [feat_dim][N] or NULL (feature renders:
+                                   the render's 3 channels are added)     */
 } dv_octree_grads;
 
 typedef struct {

@@ -21,7 +21,7 @@ design notes; each function names the reading it implements.
 
 It shares no code with the HIP path and imports nothing from it.
 """
-from . import geometry, sh, field, render, adjoint, binning, prior
+from . import geometry, sh, field, render, adjoint, binning, prior, features
 
 __all__ = ["geometry", "sh", "field", "render", "adjoint", "binning",
-           "prior"]
+           "prior", "features"]

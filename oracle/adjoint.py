@@ -158,7 +158,10 @@ def finalize(ctx, acc):
             np.add.at(corner, o["corner_idx"][:, nz].T.ravel(), dg8.ravel())
             np.add.at(corner_abs, o["corner_idx"][:, nz].T.ravel(),
                       np.abs(dg8).ravel())
-        if k >= 1:
+        # the SH colour depends on the viewing direction (camera position in
+        # the actor frame); a view-independent per-leaf value (the feature
+        # render's) does not
+        if k >= 1 and not getattr(ctx, "view_independent", False):
             cz = np.nonzero(np.abs(dcol).sum(1) > 0)[0]
             if cz.size:
                 gY = SH.basis_grad(ent["wdir"][cz], deg)   # [n,S,3]

@@ -1248,6 +1248,63 @@ __device__ inline void sh_leaf(const ShArgs& p, int k, int64_t x0, int lane,
   }
 }
 
+// Feature renders, leaf-major: the leaf's colour-slot gradients summed
+// over its records are its feature gradient (no basis, no clamp).
+__device__ inline void feat_leaf(const ShArgs& p, int k, int64_t x0, int lane,
+                                 int N, float* gf, int nc, float* gcor,
+                                 const int32_t* cidx) {
+  const int64_t x = x0 + lane;
+  const bool in = x < N;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  float acc[3] = {0.0f, 0.0f, 0.0f};
+  float dgs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  bool any = false, anyc = false;
+  for (int v = 0; v < p.n_views; ++v) {
+    const int sg = v * p.n_oct + k;
+    if (p.seg_len[sg] == 0) continue;
+    const int64_t item0 = p.pstart[sg] + x0;
+    const uint64_t m = p.wmask[item0 >> 6];
+    if (m == 0) continue;
+    const int64_t blk = item0 / TPB;
+    const int wib = (int)((item0 >> 6) % (TPB / 64));
+    uint32_t base = p.boff[blk];
+    for (int i = 0; i < wib; ++i)
+      base += (uint32_t)__popcll(p.wmask[blk * (TPB / 64) + i]);
+    if (!in || !((m >> lane) & 1ull)) continue;
+    const uint32_t slot = base + (uint32_t)__popcll(m & lt);
+    if (gcor) {
+      const float4 a8 = p.gg8a[slot], b8 = p.gg8b[slot];
+      float dg[8] = {a8.x, a8.y, a8.z, a8.w, b8.x, b8.y, b8.z, b8.w};
+      float nl[3];
+      if (p.normals)
+        normal_to_corners(p.gnrm[slot], p.rg8a[slot], p.rg8b[slot],
+                          p.vo[sg].R, dg, nl);
+#pragma unroll
+      for (int c8 = 0; c8 < 8; ++c8) {
+        dgs[c8] += dg[c8];
+        anyc = anyc || dg[c8] != 0.0f;
+      }
+    }
+    if (!gf) continue;
+    const float4 dc = p.gcol[slot];
+    acc[0] += dc.x;
+    acc[1] += dc.y;
+    acc[2] += dc.z;
+    any = any || dc.x != 0.0f || dc.y != 0.0f || dc.z != 0.0f;
+  }
+  if (anyc) {
+    int32_t ci[8];
+#pragma unroll
+    for (int c8 = 0; c8 < 8; ++c8) ci[c8] = cidx[(int64_t)c8 * N + x];
+#pragma unroll
+    for (int c8 = 0; c8 < 8; ++c8) atomicAdd(gcor + ci[c8], dgs[c8]);
+  }
+  if (!any) return;
+  float old[3];
+  for (int ch = 0; ch < nc; ++ch) old[ch] = gf[(int64_t)ch * N + x];
+  for (int ch = 0; ch < nc; ++ch) gf[(int64_t)ch * N + x] = old[ch] + acc[ch];
+}
+
 __global__ void __launch_bounds__(TPB) k_leaf_bwd(ShArgs p) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1262,11 +1319,17 @@ __global__ void __launch_bounds__(TPB) k_leaf_bwd(ShArgs p) {
   const OctDev& O = p.oct[k];
   float* const gsh = p.og[k].sh;
   float* const gcor = p.og[k].corner;
-  if (!gsh && !gcor) return;
+  float* const gf = p.og[k].feat;
+  const int fnc = p.og[k].feat_nc;
+  if (!gsh && !gcor && !gf) return;
   const int64_t x0 = t0 - p.lstart[k];
   const int N = O.n_vox;
   if (x0 >= N) return;
   const int32_t* const cidx = O.corner_idx;
+  if (fnc > 0) {
+    feat_leaf(p, k, x0, lane, N, gf, fnc, gcor, cidx);
+    return;
+  }
   switch (O.sh_degree) {
     case 0: sh_leaf<1>(p, k, x0, lane, N, 0, gsh, gcor, cidx); break;
     case 1: sh_leaf<4>(p, k, x0, lane, N, 1, gsh, gcor, cidx); break;
@@ -1305,13 +1368,23 @@ k_record_bwd(int64_t off, int64_t n, const uint32_t* rseg, const uint32_t* rvox,
     const float rn = sqrtf(cx * cx + cy * cy + cz * cz);
     const float ir = rn > 0.0f ? 1.0f / rn : 0.0f;
     const float wx = cx * ir, wy = cy * ir, wz = cz * ir;
-    const float mc[3] = {cn.x > 0.0f ? dc.x : 0.0f, cn.y > 0.0f ? dc.y : 0.0f,
-                         cn.z > 0.0f ? dc.z : 0.0f};
+    const bool featm = G.feat_nc > 0;
+    // colour clamped at 0 (subgradient 0 there); features are not clamped
+    const float mc[3] = {featm || cn.x > 0.0f ? dc.x : 0.0f,
+                         featm || cn.y > 0.0f ? dc.y : 0.0f,
+                         featm || cn.z > 0.0f ? dc.z : 0.0f};
     const int S = (O.sh_degree + 1) * (O.sh_degree + 1);
     float* const gsh = leafmajor ? nullptr : G.sh;
     float* const gcor = leafmajor ? nullptr : G.corner;
     const int32_t* const cidx = O.corner_idx;
-    if (gsh && (mc[0] != 0.0f || mc[1] != 0.0f || mc[2] != 0.0f)) {
+    if (featm && G.feat && !leafmajor) {
+      // one record per leaf in this launch: plain read-modify-write
+      float old[3];
+      for (int ch = 0; ch < G.feat_nc; ++ch) old[ch] = G.feat[(int64_t)ch * N + vox];
+      for (int ch = 0; ch < G.feat_nc; ++ch)
+        if (mc[ch] != 0.0f) G.feat[(int64_t)ch * N + vox] = old[ch] + mc[ch];
+    }
+    if (!featm && gsh && (mc[0] != 0.0f || mc[1] != 0.0f || mc[2] != 0.0f)) {
       float Y[16];
       sh_basis(O.sh_degree, wx, wy, wz, Y);
       // one launch covers the records of one view, where a leaf has at most
@@ -1323,7 +1396,8 @@ k_record_bwd(int64_t off, int64_t n, const uint32_t* rseg, const uint32_t* rvox,
         default: sh_grad_rmw<16>(gsh, N, vox, Y, mc); break;
       }
     }
-    if (POSE && k > 0 && (mc[0] != 0.0f || mc[1] != 0.0f || mc[2] != 0.0f)) {
+    if (POSE && k > 0 && !featm &&
+        (mc[0] != 0.0f || mc[1] != 0.0f || mc[2] != 0.0f)) {
       float gx[16], gy[16], gz[16];
       sh_basis_grad(O.sh_degree, wx, wy, wz, gx, gy, gz);
       float dw[3] = {0, 0, 0};
@@ -1422,6 +1496,18 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   for (int k = 0; k < n_oct; ++k) {
     og[k].corner = acc->octrees ? acc->octrees[k].corner : nullptr;
     og[k].sh = acc->octrees ? acc->octrees[k].sh : nullptr;
+    og[k].feat = nullptr;
+    og[k].feat_nc = 0;
+    og[k].pad = 0;
+    if (st->opts.feat) {
+      // feature render: the colour gradient is the feature gradient of the
+      // render's channel group; no SH term
+      const int c0 = 3 * st->opts.feat_group;
+      og[k].feat_nc = std::min(3, st->opts.feat_dim - c0);
+      float* f = acc->octrees ? acc->octrees[k].feat : nullptr;
+      og[k].feat = f ? f + (size_t)c0 * scene->desc[k].n_voxels : nullptr;
+      og[k].sh = nullptr;
+    }
   }
   // leaf-major thread space of the SH backward: octree k from lstart[k]
   st->lstart_keep.emplace_back((size_t)n_oct + 1, 0);

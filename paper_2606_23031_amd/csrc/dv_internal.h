@@ -294,7 +294,9 @@ struct VOConst {
   int32_t active;
   int32_t octree;
   int32_t view;
-  int32_t pad;
+  int32_t feat_nc;          // feature render: channels of this group (1..3)
+  const float* feat;        // feature render: the group's first channel
+                            // [feat_nc][N] (stride N), else null
 };
 
 }  // namespace dv

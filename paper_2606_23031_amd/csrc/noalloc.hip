@@ -12,6 +12,8 @@ dv_status setup_state(dv_fwd_state* st, const dv_scene* sc, const dv_view* views
 dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
                       const dv_outputs* outs, hipStream_t s);
 dv_status check_opts(const dv_render_opts* op);
+dv_render_opts effective_opts(const dv_render_opts& op);
+dv_status check_feat_ptrs(const dv_render_opts& op, const dv_scene* sc);
 
 // The workspace: 128 MiB per GPU, held from the library's first use on that
 // GPU until the process ends.  Host code must not pass this name to a
@@ -84,7 +86,8 @@ dv_status dv_render_noalloc(dv_ctx* ctx, const dv_scene* scene,
   st.ctx = ctx;
   st.scene = scene;
   st.stream = s;
-  st.opts = *opts;
+  DV_TRY(check_feat_ptrs(*opts, scene));
+  st.opts = effective_opts(*opts);
   dv_status rs = setup_state(&st, scene, views, n_views, pose_override);
   if (rs == DV_OK) rs = run_forward(ctx, scene, &st, outs, s);
   ctx->prof_flags = prof;

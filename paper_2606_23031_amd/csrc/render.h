@@ -577,6 +577,9 @@ __device__ inline void sh_basis_grad(int deg, float x, float y, float z,
 struct OctGrad {
   float* corner;
   float* sh;
+  float* feat;       // feature renders: dL/df of the group's first channel
+  int32_t feat_nc;   // channels of the group (0: colour render)
+  int32_t pad;
 };
 
 // Per-pixel segment scratch: slot s of tile gt, pixel tid.

@@ -321,11 +321,18 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
   sh_basis(O.sh_degree, (float)(cx * inv_r), (float)(cy * inv_r),
            (float)(cz * inv_r), Y);
   float col[3];
-  switch (O.sh_degree) {
-    case 0: sh_colour<1>(O.sh, N, vox, Y, col); break;
-    case 1: sh_colour<4>(O.sh, N, vox, Y, col); break;
-    case 2: sh_colour<9>(O.sh, N, vox, Y, col); break;
-    default: sh_colour<16>(O.sh, N, vox, Y, col); break;
+  if (C.feat) {
+    // feature render: the leaf's channels of this group in place of colour
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+      col[ch] = ch < C.feat_nc ? C.feat[(int64_t)ch * N + vox] : 0.0f;
+  } else {
+    switch (O.sh_degree) {
+      case 0: sh_colour<1>(O.sh, N, vox, Y, col); break;
+      case 1: sh_colour<4>(O.sh, N, vox, Y, col); break;
+      case 2: sh_colour<9>(O.sh, N, vox, Y, col); break;
+      default: sh_colour<16>(O.sh, N, vox, Y, col); break;
+    }
   }
   float g[8];
 #pragma unroll
@@ -1358,6 +1365,11 @@ dv_status setup_state(dv_fwd_state* st, const dv_scene* sc,
       VOConst& C = st->vo_h[(size_t)v * n_oct + k];
       std::memset(&C, 0, sizeof(C));
       C.active = active;
+      if (st->opts.feat) {
+        const int c0 = 3 * st->opts.feat_group;
+        C.feat_nc = std::min(3, st->opts.feat_dim - c0);
+        C.feat = st->opts.feat[k] + (size_t)c0 * sc->desc[k].n_voxels;
+      }
       C.octree = k;
       C.view = v;
       mat_t_mul(Rc, R, C.A);
@@ -1994,6 +2006,34 @@ dv_status check_opts(const dv_render_opts* op) {
     set_error("invalid sky map size %d x %d", op->sky_w, op->sky_h);
     return DV_ERR_INVALID;
   }
+  if (op->feat && (op->feat_dim < 1 || op->feat_group < 0 ||
+                   3 * (int64_t)op->feat_group >= op->feat_dim)) {
+    set_error("invalid feature render: dim %d, group %d", op->feat_dim,
+              op->feat_group);
+    return DV_ERR_INVALID;
+  }
+  return DV_OK;
+}
+
+// The options a render runs with: a feature render composites over a zero
+// background.
+dv_render_opts effective_opts(const dv_render_opts& op) {
+  dv_render_opts o = op;
+  if (o.feat) {
+    o.bg[0] = o.bg[1] = o.bg[2] = 0.0f;
+    o.sky = nullptr;
+    o.sky_w = o.sky_h = 0;
+  }
+  return o;
+}
+
+dv_status check_feat_ptrs(const dv_render_opts& op, const dv_scene* sc) {
+  if (!op.feat) return DV_OK;
+  for (int k = 0; k < sc->n_oct; ++k)
+    if (!op.feat[k] && sc->desc[k].n_voxels > 0) {
+      set_error("feature render: octree %d has no feature array", k);
+      return DV_ERR_INVALID;
+    }
   return DV_OK;
 }
 
@@ -2022,7 +2062,8 @@ dv_status dv_render(dv_ctx* ctx, const dv_scene* scene, const dv_view* views,
   st->ctx = ctx;
   st->scene = scene;
   st->stream = s;
-  st->opts = *opts;
+  DV_TRY(check_feat_ptrs(*opts, scene));
+  st->opts = effective_opts(*opts);
   reap_states(ctx, false);
   DV_TRY(setup_state(st.get(), scene, views, n_views, pose_override));
   dv_status rs = run_forward(ctx, scene, st.get(), outs, s);

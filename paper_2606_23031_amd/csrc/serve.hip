@@ -163,6 +163,10 @@ dv_status dv_serve_create(dv_ctx* ctx, const dv_scene* scene,
     return DV_ERR_INVALID;
   }
   DV_TRY(check_opts(&opts->opts));
+  if (opts->opts.feat) {
+    set_error("dv_serve_create: feature renders are not served");
+    return DV_ERR_INVALID;
+  }
   DV_TRY_HIP(hipSetDevice(ctx->device));
   std::unique_ptr<dv_server> srv(new dv_server());
   srv->ctx = ctx;

@@ -73,7 +73,9 @@ class dv_render_opts(C.Structure):
     _fields_ = [("K", C.c_int32), ("eps_stop", C.c_float),
                 ("tau_near", C.c_float), ("bg", C.c_float * 3),
                 ("explin_c", C.c_float), ("out_mask", C.c_uint32),
-                ("sky", C.c_void_p), ("sky_w", C.c_int32), ("sky_h", C.c_int32)]
+                ("sky", C.c_void_p), ("sky_w", C.c_int32), ("sky_h", C.c_int32),
+                ("feat", C.POINTER(C.c_void_p)), ("feat_dim", C.c_int32),
+                ("feat_group", C.c_int32)]
 
 
 class dv_outputs(C.Structure):
@@ -87,7 +89,7 @@ class dv_out_grads(C.Structure):
 
 
 class dv_octree_grads(C.Structure):
-    _fields_ = [("corner", C.c_void_p), ("sh", C.c_void_p)]
+    _fields_ = [("corner", C.c_void_p), ("sh", C.c_void_p), ("feat", C.c_void_p)]
 
 
 class dv_param_grads(C.Structure):
@@ -244,6 +246,22 @@ def make_opts(o, mask=DV_OUT_RGB | DV_OUT_DEPTH | DV_OUT_T):
                              "tensor [3][H][W]")
         co.sky = sky.data_ptr()
         co.sky_h, co.sky_w = int(sky.shape[1]), int(sky.shape[2])
+    # feature render: per octree a float32 CUDA tensor [F][N], and the
+    # group of three channels this render composites
+    feat = o.get("feat")
+    if feat is not None:
+        F = int(feat[0].shape[0])
+        arr = (C.c_void_p * len(feat))()
+        for k, t in enumerate(feat):
+            if not (t.is_cuda and t.dim() == 2 and t.shape[0] == F
+                    and t.is_contiguous() and str(t.dtype) == "torch.float32"):
+                raise ValueError("opts['feat'] entries must be contiguous float32 "
+                                 "CUDA tensors [F][N] with one F")
+            arr[k] = t.data_ptr()
+        co.feat = C.cast(arr, C.POINTER(C.c_void_p))
+        co._feat_arr = arr           # kept alive with the struct
+        co.feat_dim = F
+        co.feat_group = int(o.get("feat_group", 0))
     return co
 
 
@@ -478,6 +496,30 @@ def dv_render_noalloc(ctx, scene, views, opts, outs, pose_override=None,
            "dv_render_noalloc")
 
 
+def feature_groups(F):
+    return (int(F) + 2) // 3
+
+
+def render_features(ctx, scene, views, opts, feats, out_feat, mask=DV_OUT_T,
+                    keep=False, stream=None):
+    """F-channel feature render (colour step replaced by per-leaf features):
+    one dv_render per group of three channels, each into a scratch [3][h][w]
+    plane whose valid channels are copied into ``out_feat`` (list per view
+    of [F][h][w] tensors).  Returns the forward states per group if keep."""
+    import torch
+    F = int(feats[0].shape[0])
+    states = []
+    for g in range(feature_groups(F)):
+        tmp = alloc_outputs(views, DV_OUT_RGB | mask)
+        copts = make_opts(dict(opts, feat=feats, feat_group=g), DV_OUT_RGB | mask)
+        st = dv_render(ctx, scene, views, copts, tmp, keep=keep, stream=stream)
+        nc = min(3, F - 3 * g)
+        for o, t in zip(out_feat, tmp):
+            o[3 * g:3 * g + nc].copy_(t["rgb"][:nc])
+        states.append((st, tmp))
+    return states if keep else None
+
+
 def dv_noalloc_capacity():
     return int(_lib.dv_noalloc_capacity())
 
@@ -508,7 +550,8 @@ def dv_render_backward(ctx, scene, state, grads, acc_octrees, pose_grad=None,
     co = (dv_octree_grads * no)()
     for k, a in enumerate(acc_octrees):
         a = a or {}
-        co[k] = dv_octree_grads(_ptr(a.get("corner")), _ptr(a.get("sh")))
+        co[k] = dv_octree_grads(_ptr(a.get("corner")), _ptr(a.get("sh")),
+                                _ptr(a.get("feat")))
     pg = dv_param_grads(co, _ptr(pose_grad), _ptr(sky_grad))
     _check(_lib.dv_render_backward(ctx, scene.handle, state, cg, C.byref(pg),
                                    _stream_handle(stream)),
