@@ -371,6 +371,68 @@ dv_status dv_fwd_state_export_lists(const dv_fwd_state* state, int32_t view,
                                     int64_t* actor_start, int32_t* actor_oct,
                                     int64_t actor_capacity);
 
+/* ---------------------------------------------------------------- training */
+/* Training losses (Supp. 'Optimization Details', Training Losses), per
+ * view, with the gradient planes of the rendered outputs written for
+ * dv_render_backward:
+ *   L = color ((1 - ssim) mean|C - C_gt| + ssim (1 - SSIM(C, C_gt)))
+ *     + depth mean_{D_lidar > 0} |D - D_lidar|
+ *     + normal mean_{|N_pseudo| > 0} (1 - cos(N, N_pseudo))
+ *     + sky mean_{sky_mask > 0} (T_final - 1)^2.
+ * Readings: the printed colour term is garbled; an L1 pixel loss and an
+ * SSIM term are combined with weight `ssim` on SSIM.  SSIM uses an 11 x 11
+ * Gaussian window (sigma 1.5), C1 = 0.01^2, C2 = 0.03^2, zero padding at
+ * the border, the mean over pixels and channels.  cos = N.Np /
+ * (max(|N|, 1e-8) |Np|).  Means over empty pixel sets are 0. */
+typedef struct {
+  int32_t h, w;                 /* image size (the render's window)        */
+  const float* rgb;             /* rendered [3][h][w] (device), or NULL    */
+  const float* depth;           /* [h][w] or NULL                          */
+  const float* normal;          /* [3][h][w] or NULL                       */
+  const float* T;               /* [h][w] or NULL                          */
+  const float* rgb_gt;          /* target [3][h][w]; NULL: no colour term  */
+  const float* depth_lidar;     /* sparse depth [h][w], 0 = no return      */
+  const float* normal_pseudo;   /* [3][h][w], 0 vector = no normal         */
+  const float* sky_mask;        /* [h][w], > 0 = sky                       */
+  float* g_rgb;                 /* gradient planes, written (overwritten); */
+  float* g_depth;               /* a term's plane is required when the term */
+  float* g_normal;              /* has both its inputs (g_rgb), else may    */
+  float* g_T;                   /* be NULL (the term's gradient is skipped) */
+} dv_loss_view;
+
+typedef struct {
+  float color, ssim, depth, normal, sky;   /* the loss weights             */
+} dv_loss_weights;
+
+/* Losses of n_views views.  terms: device double [n_views][8], written:
+ * total, colour term, L1, SSIM, depth, normal, sky, 0.  Enqueued on the
+ * stream; allocates scratch from the context's pool.  Errors:
+ * DV_ERR_INVALID (empty image, a colour term without g_rgb). */
+dv_status dv_loss(dv_ctx* ctx, const dv_loss_view* views, int32_t n_views,
+                  const dv_loss_weights* w, double* terms, void* stream);
+
+/* One Adam step over structure-of-arrays parameters (corner densities, SH
+ * coefficients, sky map, poses): for each element
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps),
+ * all tensors of the call in one launch.  All pointers device f32 of n
+ * elements; p, m, v updated in place. */
+typedef struct {
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t n;
+} dv_adam_param;
+
+typedef struct {
+  float lr, beta1, beta2, eps;
+  int32_t step;                 /* >= 1 (bias correction)                  */
+} dv_adam_opts;
+
+dv_status dv_adam(dv_ctx* ctx, const dv_adam_param* params, int32_t n_params,
+                  const dv_adam_opts* opts, void* stream);
+
 /* ---------------------------------------------------------------- serving */
 /* Sensor simulation (Sec. 1: the reconstructed scene is rendered for new
  * cameras, timestamps and actor configurations): the scene and actor tracks

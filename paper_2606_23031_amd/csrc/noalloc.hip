@@ -10,7 +10,7 @@ namespace dv {
 dv_status setup_state(dv_fwd_state* st, const dv_scene* sc, const dv_view* views,
                       int32_t n_views, const double* pose_override);
 dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
-                      const dv_outputs* outs, hipStream_t s);
+                      const dv_outputs* outs, hipStream_t s, bool composite);
 dv_status check_opts(const dv_render_opts* op);
 dv_render_opts effective_opts(const dv_render_opts& op);
 dv_status check_feat_ptrs(const dv_render_opts& op, const dv_scene* sc);
@@ -89,7 +89,7 @@ dv_status dv_render_noalloc(dv_ctx* ctx, const dv_scene* scene,
   DV_TRY(check_feat_ptrs(*opts, scene));
   st.opts = effective_opts(*opts);
   dv_status rs = setup_state(&st, scene, views, n_views, pose_override);
-  if (rs == DV_OK) rs = run_forward(ctx, scene, &st, outs, s);
+  if (rs == DV_OK) rs = run_forward(ctx, scene, &st, outs, s, true);
   ctx->prof_flags = prof;
   if (rs == DV_ERR_DEVICE) ctx->poisoned = true;
   // the state's buffers are views into the workspace: nothing to free

@@ -183,6 +183,7 @@ dv_status stage_release(hipStream_t s);
 dv_status launch_order_by_weight(int64_t n, const uint32_t* w0, const uint32_t* w,
                                  uint32_t* order, hipStream_t s);
 
+
 // Background entries per chunk: a tile whose list is longer than 1.5
 // chunks is split into ceil(len / CHUNK) equal chunks, each composited by
 // its own block into per-pixel partial states that are merged in order.
@@ -423,7 +424,8 @@ struct SkyTaps {
   int o[4];    // texel offsets j * W + i in one [H][W] plane
   float w[4];  // bilinear weights
 };
-__device__ inline SkyTaps sky_taps(const CompArgs& a, float3 d) {
+template <class A>
+__device__ inline SkyTaps sky_taps(const A& a, float3 d) {
   const float kPi = 3.14159265358979f;
   const int W = a.sky_w, H = a.sky_h;
   const float lon = atan2f(d.y, d.x);
@@ -445,7 +447,8 @@ __device__ inline SkyTaps sky_taps(const CompArgs& a, float3 d) {
   return t;
 }
 // C_sky of the ray: the map's sample, or the constant colour without one.
-__device__ inline float3 sky_colour(const CompArgs& a, float3 d) {
+template <class A>
+__device__ inline float3 sky_colour(const A& a, float3 d) {
   if (!a.sky) return make_float3(a.bg[0], a.bg[1], a.bg[2]);
   const SkyTaps t = sky_taps(a, d);
   const size_t hw = (size_t)a.sky_w * a.sky_h;
@@ -466,7 +469,8 @@ struct PixSetup {
   float3 d;
   size_t pix;
 };
-__device__ inline PixSetup pixel_setup(const CompArgs& a, uint32_t gt, int tid) {
+template <class A>
+__device__ inline PixSetup pixel_setup(const A& a, uint32_t gt, int tid) {
   PixSetup P;
   P.v = view_of_tile(a.views, a.n_views, gt);
   const ViewConst& V = a.views[P.v];
@@ -495,14 +499,16 @@ __device__ inline PixSetup pixel_setup(const CompArgs& a, uint32_t gt, int tid) 
 // B_c is searched by CB_SPLIT blocks over consecutive parts of the chunk;
 // the first part (in list order) with a chord gives it.
 constexpr int CB_SPLIT = 4;
-__device__ inline float chunk_first(const CompArgs& a, size_t slot, int tid) {
+template <class A>
+__device__ inline float chunk_first(const A& a, size_t slot, int tid) {
   const float* p = a.chunk_b + slot * CB_SPLIT * TPB + tid;
   float b = p[0];
   for (int q = 1; q < CB_SPLIT; ++q)
     if (b == F_INF) b = p[(size_t)q * TPB];
   return b;
 }
-__device__ inline void chunk_bounds(const CompArgs& a, uint32_t gt, uint32_t nck,
+template <class A>
+__device__ inline void chunk_bounds(const A& a, uint32_t gt, uint32_t nck,
                                     uint32_t c, int tid, float& Bc, float& Bn) {
   Bc = -F_INF;
   Bn = F_INF;
@@ -582,6 +588,44 @@ struct OctGrad {
   int32_t pad;
 };
 
+// ------------------------------------------------------------------ serving
+// Device side of the serving loop (render.hip): renders whose background
+// walks were left out (groups) are published into a ring; one persistent
+// kernel drains their work items, merges chunked tiles, counts finished
+// tiles per view and raises a request's completion flag in host memory
+// when its last tile is written.
+constexpr int SV_RING = 1024;    // ring entries (groups published)
+constexpr int SV_GROUPS = 16;    // group slots (forward states in flight)
+constexpr int SV_FLAGS = 1024;   // request completion flags
+
+struct ServeGroup {
+  CompArgs a;                    // walk arguments of the group's forward
+  uint32_t* tile_ck;             // [n_tiles] chunks finished per tile
+  uint32_t* view_done;           // [n_views] tiles finished per view
+  const uint32_t* view_ntiles;   // [n_views]
+  const uint32_t* view_flag;     // [n_views] completion flag of the request
+  const unsigned long long* view_seq;  // [n_views] value the flag receives
+  unsigned long long* flags;     // host-mapped [SV_FLAGS]
+};
+
+struct ServeQueue {
+  unsigned long long tail;            // groups published so far
+  unsigned long long head;            // first group not known to be drained
+  unsigned long long claim[SV_RING];  // (group number << 32) | items taken
+  uint32_t slot[SV_RING];
+  uint32_t n_items[SV_RING];
+};
+
+// Publish group number g (group slot `slot`, item count plan_counts[0]) on
+// stream s, after the group's forward work and its ServeGroup upload.
+dv_status launch_serve_publish(ServeQueue* q, uint64_t g, uint32_t slot,
+                               const uint32_t* plan_counts, hipStream_t s);
+// The persistent drain kernel: `blocks` blocks; each exits after idle_limit
+// consecutive empty polls (about 3.5 us each).
+dv_status launch_serve_drain(ServeQueue* q, const ServeGroup* groups,
+                             bool normals, bool k1, int blocks, int idle_limit,
+                             hipStream_t s);
+
 // Per-pixel segment scratch: slot s of tile gt, pixel tid.
 __device__ inline size_t seg_index(uint32_t slot, int tid) {
   return (size_t)slot * TPB + tid;
@@ -630,4 +674,6 @@ struct dv_fwd_state {
       aplan_counts, apart;
   int64_t max_aitems = 0, max_aslots = 0;
   int64_t max_items = 0, max_slots = 0;
+  // walk arguments of a forward enqueued without its background walks
+  dv::CompArgs ca_fwd{};
 };

@@ -623,8 +623,8 @@ struct Batch {
 
 // NORMALS = false: the normal slot carries the leaf's far corner instead
 // (see batch_slab).
-template <bool NORMALS>
-__device__ inline void load_batch(Batch& B, const CompArgs& a, uint32_t base,
+template <bool NORMALS, class A>
+__device__ inline void load_batch(Batch& B, const A& a, uint32_t base,
                                   uint32_t n) {
   const int tid = threadIdx.x;
   if ((uint32_t)tid < n) {
@@ -731,7 +731,8 @@ __device__ inline int next_seg_of(const CompArgs& a, uint32_t seg0, int nseg,
 
 // Final composite with the sky behind the voxels (Eq. 2) into the outputs;
 // d is the pixel's unit world ray direction.
-__device__ inline void write_outputs(const CompArgs& a, const ViewConst& V, int v,
+template <class A>
+__device__ inline void write_outputs(const A& a, const ViewConst& V, int v,
                                      int px, int py, float3 C3, float D,
                                      float3 N3, float T, float3 d) {
   const dv_outputs& O = a.outs[v];
@@ -1041,12 +1042,12 @@ __global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a) {
 // chunk writes the outputs; a chunk writes its partial state (T starts at
 // 1 in every chunk, and so does the stop test) for k_chunk_merge.
 // KC = 1 fixes one sample per piece at compile time.
-template <bool NORMALS, int KC>
-__global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs a) {
-  __shared__ Batch B;
-  __shared__ uint32_t blk_work;
-  if (blockIdx.x >= a.plan_counts[0]) return;
-  const uint32_t item = a.order[blockIdx.x];
+// The walk of one item (also run by the persistent serving kernel, which
+// drains items of several renders); B and blk_work: the block's LDS.
+template <bool NORMALS, int KC, class A>
+__device__ __forceinline__ void composite_item(const A& a, uint32_t idx,
+                                               Batch& B, uint32_t& blk_work) {
+  const uint32_t item = a.order[idx];
   const uint32_t gt = a.item_tile[item], chunk = a.item_chunk[item];
   const uint32_t nck = a.tile_nck[gt];
   const int tid = threadIdx.x;
@@ -1204,10 +1205,18 @@ __global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs
   write_outputs(a, V, v, px, py, C3, D, N3, T, d);
 }
 
+template <bool NORMALS, int KC>
+__global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs a) {
+  __shared__ Batch B;
+  __shared__ uint32_t blk_work;
+  if (blockIdx.x >= a.plan_counts[0]) return;
+  composite_item<NORMALS, KC>(a, blockIdx.x, B, blk_work);
+}
+
 // Forward, part 4 (tiles of several chunks): merge the chunk partials in
 // order, C = sum_c T_<c C_c, T = prod_c T_c, and write the outputs.
-__global__ void __launch_bounds__(TPB) k_chunk_merge(CompArgs a) {
-  const uint32_t gt = blockIdx.x;
+template <class A>
+__device__ __forceinline__ void chunk_merge_tile(const A& a, uint32_t gt) {
   const uint32_t nck = a.tile_nck[gt];
   if (nck <= 1) return;
   const int tid = threadIdx.x;
@@ -1230,6 +1239,153 @@ __global__ void __launch_bounds__(TPB) k_chunk_merge(CompArgs a) {
   a.fin2[P.pix] = make_float4(0, 0, 0, 0);
   a.fin3[P.pix] = make_float4(0, 0, 0, 0);
   write_outputs(a, V, P.v, P.px, P.py, C3, D, N3, T, P.d);
+}
+
+__global__ void __launch_bounds__(TPB) k_chunk_merge(CompArgs a) {
+  chunk_merge_tile(a, blockIdx.x);
+}
+
+// ------------------------------------------------------------------ serving
+__global__ void k_serve_publish(ServeQueue* q, unsigned long long g,
+                                uint32_t slot, const uint32_t* plan_counts) {
+  const uint32_t e = (uint32_t)(g % SV_RING);
+  q->slot[e] = slot;
+  q->n_items[e] = plan_counts ? plan_counts[0] : 0u;
+  __hip_atomic_store(&q->claim[e], g << 32, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  // the entry (and, earlier in stream order, the group's buffers) before
+  // the tail that makes it visible
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __hip_atomic_store(&q->tail, g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Persistent drain.  Thread 0 of a block takes the next item of the oldest
+// published group that has items left (compare-and-swap on the group's
+// claim word, which carries the group number so an entry reused by a later
+// group is never taken for an earlier one); the block walks it; after the
+// last chunk of a tile the block that finished it merges the chunks, and
+// the block that finishes a view's last tile raises the request's flag.
+// A block with nothing to take sleeps and polls again; after idle_limit
+// empty polls in a row it exits, so every block ends (the host launches
+// the kernel again when new groups arrive).
+template <bool NORMALS, int KC>
+__global__ void __launch_bounds__(TPB, 4)
+k_serve_drain(ServeQueue* q, const ServeGroup* __restrict__ groups,
+              int idle_limit) {
+  __shared__ Batch B;
+  __shared__ uint32_t blk_work;
+  __shared__ uint32_t s_cmd, s_slot, s_idx, s_last;
+  int idle = 0;
+  while (true) {
+    if (threadIdx.x == 0) {
+      uint32_t cmd = 0;
+      for (int tries = 0; tries < 16 && cmd == 0; ++tries) {
+        const unsigned long long h =
+            __hip_atomic_load(&q->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long t =
+            __hip_atomic_load(&q->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (h >= t) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const uint32_t e = (uint32_t)(h % SV_RING);
+        const unsigned long long w =
+            __hip_atomic_load(&q->claim[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((w >> 32) != (h & 0xFFFFFFFFull)) {
+          // h was drained and its entry reused: move on
+          atomicCAS(&q->head, h, h + 1);
+          continue;
+        }
+        const uint32_t n = __hip_atomic_load(&q->n_items[e], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t c = (uint32_t)w;
+        if (c >= n) {
+          atomicCAS(&q->head, h, h + 1);
+          continue;
+        }
+        if (atomicCAS(&q->claim[e], w, w + 1) == w) {
+          s_slot = __hip_atomic_load(&q->slot[e], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+          s_idx = c;
+          cmd = 1;
+        }
+      }
+      if (cmd == 0 && ++idle > idle_limit) cmd = 2;
+      if (cmd == 1) idle = 0;
+      s_cmd = cmd;
+    }
+    __syncthreads();
+    const uint32_t cmd = s_cmd;
+    if (cmd == 2) return;
+    if (cmd == 0) {
+      __builtin_amdgcn_s_sleep(127);
+      __syncthreads();
+      continue;
+    }
+    // the group's tables and records were written before it was published
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // wave-uniform: the group's arguments come through scalar loads
+    const uint32_t slot = __builtin_amdgcn_readfirstlane(s_slot);
+    // through the constant address space: the arguments are read-only for
+    // the kernel's lifetime, so their loads can be repeated instead of kept
+    typedef __attribute__((address_space(4))) const ServeGroup CGroup;
+    CGroup& G = ((CGroup*)groups)[slot];
+    const auto& a = G.a;
+    const uint32_t idx = __builtin_amdgcn_readfirstlane(s_idx);
+    composite_item<NORMALS, KC>(a, idx, B, blk_work);
+    const uint32_t item = a.order[idx];
+    const uint32_t gt = a.item_tile[item];
+    const uint32_t nck = a.tile_nck[gt];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      s_last = nck > 1 ? (atomicAdd(G.tile_ck + gt, 1u) == nck - 1) : 1u;
+    }
+    __syncthreads();
+    if (s_last) {
+      if (nck > 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        chunk_merge_tile(a, gt);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        // everything this block reads of the group is read before its count
+        // goes in: once a view's last tile is counted, the host may free the
+        // group's buffers
+        const int v = view_of_tile(a.views, a.n_views, gt);
+        const uint32_t ntv = G.view_ntiles[v];
+        const uint32_t fslot = G.view_flag[v];
+        const unsigned long long fval = G.view_seq[v];
+        unsigned long long* const flags = G.flags;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (atomicAdd(G.view_done + v, 1u) == ntv - 1) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // system scope
+          __hip_atomic_store(flags + fslot, fval, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+dv_status launch_serve_publish(ServeQueue* q, uint64_t g, uint32_t slot,
+                               const uint32_t* plan_counts, hipStream_t s) {
+  hipLaunchKernelGGL(k_serve_publish, dim3(1), dim3(1), 0, s, q,
+                     (unsigned long long)g, slot, plan_counts);
+  DV_TRY_HIP(hipGetLastError());
+  return DV_OK;
+}
+
+dv_status launch_serve_drain(ServeQueue* q, const ServeGroup* groups,
+                             bool normals, bool k1, int blocks, int idle_limit,
+                             hipStream_t s) {
+  auto kern = normals ? (k1 ? k_serve_drain<true, 1> : k_serve_drain<true, 0>)
+                      : (k1 ? k_serve_drain<false, 1> : k_serve_drain<false, 0>);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(TPB), 0, s, q, groups,
+                     idle_limit);
+  DV_TRY_HIP(hipGetLastError());
+  return DV_OK;
 }
 
 // ------------------------------------------------------------------ host
@@ -1564,7 +1720,7 @@ __global__ void k_view_slots(int n_views, int n_oct, const int64_t* pstart,
 // reads the record count (per view) and the pair count, both known after
 // the first preprocess pass.
 dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
-                      const dv_outputs* outs, hipStream_t s) {
+                      const dv_outputs* outs, hipStream_t s, bool composite) {
   const std::vector<int64_t>& seg_start = st->seg_start_h;
   const std::vector<uint32_t>& act_tile = st->act_tile_h;
   const int n_views = st->n_views, n_oct = st->n_oct;
@@ -1943,6 +2099,12 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
       StageTimer tm_ch(ctx, ST_OTHER, s);
       hipLaunchKernelGGL(k_chunk_bounds, dim3(ni * CB_SPLIT), dim3(TPB), 0, s, ca);
     }
+    if (!composite) {
+      // the background walks are run by the caller (the serving kernel)
+      st->ca_fwd = ca;
+      DV_TRY_HIP(hipGetLastError());
+      return DV_OK;
+    }
     {
       StageTimer tm_comp(ctx, ST_COMPOSITE_FWD, s);
       auto kern = nrm ? (k1 ? k_composite_fwd<true, 1> : k_composite_fwd<true, 0>)
@@ -2066,7 +2228,7 @@ dv_status dv_render(dv_ctx* ctx, const dv_scene* scene, const dv_view* views,
   st->opts = effective_opts(*opts);
   reap_states(ctx, false);
   DV_TRY(setup_state(st.get(), scene, views, n_views, pose_override));
-  dv_status rs = run_forward(ctx, scene, st.get(), outs, s);
+  dv_status rs = run_forward(ctx, scene, st.get(), outs, s, true);
   if (rs == DV_ERR_DEVICE) ctx->poisoned = true;
   if (rs != DV_OK) {
     if (rs == DV_ERR_DEVICE) return rs;

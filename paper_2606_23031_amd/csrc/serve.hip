@@ -1,15 +1,31 @@
 // Serving loop: sensor-simulation requests (camera, timestamp, resolution)
-// against a resident scene.
+// against a resident scene (Sec. 1: the reconstruction serves novel views
+// of the scene at new times and viewpoints).
 //
-// Continuous batching: worker threads, each with its own HIP stream, take
-// the queued requests that fit the free slots and the memory budget and
-// render them together in one multi-view launch; requests arriving while
-// batches are on the GPU wait in the queue and are admitted by the next
-// free worker, so preprocessing and sorting of one batch overlap the
-// compositing of another on the device.  In per-request mode a single
-// worker renders one request per launch in FIFO order.  Memory admission
-// uses a running bytes-per-pixel estimate taken from the sizes of finished
-// launches; a request is always admitted when nothing else is in flight.
+// Continuous batching (batched = 1).  A scheduler thread admits queued
+// requests while request slots, group slots and the memory budget allow,
+// takes up to max_batch of them as one group, and enqueues on its prep
+// stream the group's front half in one multi-view launch sequence:
+// preprocess, sorts, tile directories, ownership segments and asset walks.
+// It then uploads the group's walk arguments and publishes the group's work
+// items into a device ring.  One persistent kernel on a second stream
+// drains (group, item) work, the background walks of every published
+// group, so requests admitted while others are on the GPU have their front
+// half overlap the walks of earlier ones, and their items join the same
+// kernel.  The block that writes a request's last tile raises the
+// request's flag in host-mapped memory; a completion thread watches the
+// flags, finishes requests, frees groups, and launches the drain kernel
+// again whenever work is pending and the previous one has run out of work
+// and exited.
+//
+// One launch per request (batched = 0), the baseline: two worker threads,
+// each with its own stream (the same number of streams), render one
+// request per dv_render call in arrival order.
+//
+// Memory admission uses a running bytes-per-pixel estimate taken from the
+// sizes of finished renders; a request is always admitted when nothing else
+// is in flight.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -22,6 +38,11 @@
 
 namespace dv {
 dv_status check_opts(const dv_render_opts* op);
+dv_render_opts effective_opts(const dv_render_opts& op);
+dv_status setup_state(dv_fwd_state* st, const dv_scene* sc, const dv_view* views,
+                      int32_t n_views, const double* pose_override);
+dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
+                      const dv_outputs* outs, hipStream_t s, bool composite);
 }
 
 using namespace dv;
@@ -40,7 +61,28 @@ struct Request {
   dv_status status = DV_PENDING;
   int64_t est_bytes = 0;
   bool done = false;
+  int flag = -1;           // completion flag slot (batched mode)
 };
+
+// Host record of a published group.
+struct Group {
+  bool used = false;
+  uint64_t number = 0;
+  std::vector<uint64_t> tickets;
+  int remaining = 0;
+  dv_fwd_state* st = nullptr;
+  DBuf counters;           // tile_ck [n_tiles] + view_done [n_views]
+  DBuf vtab;               // view_ntiles, view_flag, view_seq
+  int64_t used_bytes = 0, pixels = 0;
+};
+
+// Idle polls (about 3.5 us each) after which a drain block exits.
+constexpr int DRAIN_IDLE_POLLS = 600;
+// Requests per group (one view each) and the pinned staging per group slot:
+// its ServeGroup, then per view the tile count, flag slot and flag value.
+constexpr int MAX_GROUP_VIEWS = 256;
+constexpr size_t STAGE_TABLE = (size_t)MAX_GROUP_VIEWS * 16 + 64;
+constexpr size_t STAGE_STRIDE = ((sizeof(ServeGroup) + 255) & ~(size_t)255) + STAGE_TABLE;
 
 }  // namespace
 
@@ -59,61 +101,84 @@ struct dv_server {
   double bytes_per_pixel = 512.0;   // running estimate
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
+  // batched mode
+  hipStream_t prep = nullptr, comp = nullptr;
+  DBuf qbuf;                        // ServeQueue
+  DBuf gbuf;                        // ServeGroup[SV_GROUPS]
+  uint8_t* gstage = nullptr;        // pinned staging, STAGE_STRIDE per slot
+  unsigned long long* flags = nullptr;      // host-mapped [SV_FLAGS]
+  unsigned long long* flags_dev = nullptr;  // their device address
+  std::vector<int> free_flags;
+  Group groups[SV_GROUPS];
+  std::vector<int> free_groups;
+  uint64_t next_group = 0;
+  int groups_live = 0;
+  bool drain_running = false;
+  hipEvent_t drain_ev = nullptr;
+  std::thread completer;
 
   void worker(int wid);
+  void scheduler();
+  void completion();
   bool admissible(const Request& r) const {
     if (inflight >= opts.max_inflight) return false;
     if (inflight == 0) return true;
     return mem_inflight + r.est_bytes <= opts.mem_budget;
   }
+  void finish(uint64_t tk, dv_status rc, double t) {
+    Request& r = reqs[tk];
+    r.status = rc;
+    r.t_done = t;
+    r.done = true;
+    inflight -= 1;
+    mem_inflight -= r.est_bytes;
+    if (r.flag >= 0) free_flags.push_back(r.flag);
+    r.flag = -1;
+  }
+  void fail_queued(dv_status rc, double t) {
+    for (uint64_t tk : queue) {
+      Request& r = reqs[tk];
+      r.status = rc;
+      r.done = true;
+      r.t_done = t;
+    }
+    queue.clear();
+  }
 };
 
+// ---------------------------------------------------------------- baseline
 void dv_server::worker(int wid) {
   hipSetDevice(ctx->device);
   hipStream_t s = streams[wid];
-  const int max_batch = opts.batched ? std::max(1, opts.max_batch) : 1;
-  std::vector<uint64_t> batch;
-  std::vector<dv_view> views;
-  std::vector<dv_outputs> outs;
   while (true) {
-    batch.clear();
+    uint64_t tk = 0;
+    dv_view view;
+    dv_outputs out;
     {
       std::unique_lock<std::mutex> lk(mu);
       cv_work.wait(lk, [&] {
-        return stop || (!queue.empty() && admissible(reqs[queue.front()]));
+        return (stop && queue.empty()) ||
+               (!queue.empty() && admissible(reqs[queue.front()]));
       });
-      if (stop && queue.empty()) return;
-      if (queue.empty()) continue;
-      if (!admissible(reqs[queue.front()])) {
-        // only reachable while stopping: wait for in-flight work to drain
-        cv_done.wait_for(lk, std::chrono::milliseconds(1));
+      if (queue.empty()) {
+        if (stop) return;
         continue;
       }
-      const double t = now_s();
-      while (!queue.empty() && (int)batch.size() < max_batch) {
-        Request& r = reqs[queue.front()];
-        if (!batch.empty() && !admissible(r)) break;
-        if (batch.empty() && !admissible(r)) break;
-        r.t_admit = t;
-        inflight += 1;
-        mem_inflight += r.est_bytes;
-        batch.push_back(queue.front());
-        queue.pop_front();
-      }
-      views.clear();
-      outs.clear();
-      for (uint64_t tk : batch) {
-        views.push_back(reqs[tk].view);
-        outs.push_back(reqs[tk].out);
-      }
+      if (!admissible(reqs[queue.front()])) continue;
+      tk = queue.front();
+      queue.pop_front();
+      Request& r = reqs[tk];
+      r.t_admit = now_s();
+      inflight += 1;
+      mem_inflight += r.est_bytes;
+      view = r.view;
+      out = r.out;
     }
-    if (batch.empty()) continue;
     dv_fwd_state* st = nullptr;
     dv_status rc = ctx->poisoned ? DV_ERR_DEVICE
-                                 : dv_render(ctx, scene, views.data(),
-                                             (int32_t)views.size(), nullptr,
-                                             &opts.opts, outs.data(), &st, s);
-    int64_t used = 0, pixels = 0;
+                                 : dv_render(ctx, scene, &view, 1, nullptr,
+                                             &opts.opts, &out, &st, s);
+    int64_t used = 0;
     if (rc == DV_OK && st) {
       used = 24 * st->n_pairs + 150 * st->n_vis + 40 * st->n_tiles * TPB;
       dv_fwd_state_release(st);
@@ -123,34 +188,247 @@ void dv_server::worker(int wid) {
       rc = DV_ERR_DEVICE;
       ctx->poisoned = true;
     }
-    for (auto& v : views) pixels += (int64_t)v.w * v.h;
     {
       std::lock_guard<std::mutex> lk(mu);
       const double t = now_s();
-      for (uint64_t tk : batch) {
-        Request& r = reqs[tk];
-        r.status = rc;
-        r.t_done = t;
-        r.done = true;
-        inflight -= 1;
-        mem_inflight -= r.est_bytes;
+      finish(tk, rc, t);
+      if (rc == DV_OK)
+        bytes_per_pixel = 0.8 * bytes_per_pixel +
+                          0.2 * ((double)used / ((double)view.w * view.h));
+      if (rc == DV_ERR_DEVICE) fail_queued(DV_ERR_DEVICE, t);
+    }
+    cv_done.notify_all();
+    cv_work.notify_all();
+  }
+}
+
+// ---------------------------------------------------------------- batched
+void dv_server::scheduler() {
+  hipSetDevice(ctx->device);
+  const int max_batch = std::max(1, opts.max_batch);
+  std::vector<uint64_t> batch;
+  std::vector<dv_view> views;
+  std::vector<dv_outputs> outs;
+  while (true) {
+    int gslot = -1;
+    batch.clear();
+    views.clear();
+    outs.clear();
+    std::vector<int> bflags;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_work.wait(lk, [&] {
+        return (stop && queue.empty()) ||
+               (!queue.empty() && admissible(reqs[queue.front()]) &&
+                !free_groups.empty() && !free_flags.empty());
+      });
+      if (queue.empty()) {
+        if (stop) return;
+        continue;
       }
-      if (rc == DV_OK && pixels > 0)
-        bytes_per_pixel = 0.8 * bytes_per_pixel + 0.2 * ((double)used / pixels);
-      if (rc == DV_ERR_DEVICE) {
-        // a device fault poisons the context: fail everything still queued
-        for (uint64_t tk : queue) {
-          Request& r = reqs[tk];
-          r.status = DV_ERR_DEVICE;
-          r.done = true;
-          r.t_done = t;
+      if (!admissible(reqs[queue.front()]) || free_groups.empty() ||
+          free_flags.empty())
+        continue;
+      gslot = free_groups.back();
+      free_groups.pop_back();
+      const double t = now_s();
+      while (!queue.empty() && (int)batch.size() < max_batch &&
+             !free_flags.empty() && admissible(reqs[queue.front()])) {
+        const uint64_t tk = queue.front();
+        Request& r = reqs[tk];
+        r.t_admit = t;
+        r.flag = free_flags.back();
+        free_flags.pop_back();
+        inflight += 1;
+        mem_inflight += r.est_bytes;
+        batch.push_back(tk);
+        views.push_back(r.view);
+        outs.push_back(r.out);
+        bflags.push_back(r.flag);
+      }
+      groups_live += 1;
+    }
+    Group& G = groups[gslot];
+    const uint64_t gnum = next_group++;
+    int64_t pixels = 0;
+    for (auto& v : views) pixels += (int64_t)v.w * v.h;
+    int64_t used_bytes = 0;
+    dv_status rc = ctx->poisoned ? DV_ERR_DEVICE : DV_OK;
+    // front half of the group's render on the prep stream
+    dv_fwd_state* st = nullptr;
+    if (rc == DV_OK) {
+      std::unique_ptr<dv_fwd_state> ps(new dv_fwd_state());
+      ps->ctx = ctx;
+      ps->scene = scene;
+      ps->stream = prep;
+      ps->opts = effective_opts(opts.opts);
+      PoolStamp stamp_on_return(ctx);
+      rc = setup_state(ps.get(), scene, views.data(), (int32_t)views.size(), nullptr);
+      if (rc == DV_OK) rc = run_forward(ctx, scene, ps.get(), outs.data(), prep, false);
+      const int nv = (int)views.size();
+      const int64_t nt = ps->n_tiles;
+      if (rc == DV_OK) rc = alloc_n<uint32_t>(ctx, G.counters, (size_t)nt + nv, prep);
+      if (rc == DV_OK)
+        rc = alloc_n<uint8_t>(ctx, G.vtab, (size_t)nv * 16 + 64, prep);
+      if (rc == DV_OK) rc = fill_u32(G.counters.as<uint32_t>(), 0u, nt + nv, prep);
+      if (rc == DV_OK) {
+        // per view: tile count, flag slot, flag value (the ticket)
+        uint8_t* slot_stage = gstage + (size_t)gslot * STAGE_STRIDE;
+        ServeGroup& sg = *reinterpret_cast<ServeGroup*>(slot_stage);
+        uint8_t* tab = slot_stage + ((sizeof(ServeGroup) + 255) & ~(size_t)255);
+        uint32_t* ntl = reinterpret_cast<uint32_t*>(tab);
+        uint32_t* fl = ntl + nv;
+        unsigned long long* sq = reinterpret_cast<unsigned long long*>(
+            tab + (((size_t)nv * 8 + 7) & ~(size_t)7));
+        for (int v = 0; v < nv; ++v) {
+          ntl[v] = (uint32_t)ps->views_h[v].ntx * ps->views_h[v].nty;
+          fl[v] = (uint32_t)bflags[v];
+          sq[v] = batch[v];
         }
-        queue.clear();
+        const size_t tab_bytes = (size_t)(reinterpret_cast<uint8_t*>(sq + nv) - tab);
+        uint8_t* vt = G.vtab.as<uint8_t>();
+        sg.a = ps->ca_fwd;
+        sg.tile_ck = G.counters.as<uint32_t>();
+        sg.view_done = G.counters.as<uint32_t>() + nt;
+        sg.view_ntiles = reinterpret_cast<const uint32_t*>(vt);
+        sg.view_flag = reinterpret_cast<const uint32_t*>(vt) + nv;
+        sg.view_seq = reinterpret_cast<const unsigned long long*>(
+            vt + (((size_t)nv * 8 + 7) & ~(size_t)7));
+        sg.flags = flags_dev;
+        ServeGroup* gd = gbuf.as<ServeGroup>() + gslot;
+        hipError_t e = hipMemcpyAsync(vt, tab, tab_bytes, hipMemcpyHostToDevice, prep);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(gd, &sg, sizeof(ServeGroup), hipMemcpyHostToDevice, prep);
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          rc = DV_ERR_DEVICE;
+        }
+      }
+      if (rc == DV_OK)
+        rc = launch_serve_publish(qbuf.as<ServeQueue>(), gnum, (uint32_t)gslot,
+                                  ps->plan_counts.as<uint32_t>(), prep);
+      if (rc == DV_OK) {
+        used_bytes = 24 * ps->n_pairs + 150 * ps->n_vis + 40 * ps->n_tiles * TPB;
+        st = ps.release();
+      } else {
+        // the group's buffers may still be read by queued prep work
+        hipStreamSynchronize(prep);
+        IdleRelease idle;
+        ps.reset();
+        G.counters.reset();
+        G.vtab.reset();
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (rc != DV_OK) {
+        if (rc == DV_ERR_DEVICE) ctx->poisoned = true;
+        const double t = now_s();
+        for (uint64_t tk : batch) finish(tk, rc, t);
+        free_groups.push_back(gslot);
+        groups_live -= 1;
+        if (rc == DV_ERR_DEVICE) fail_queued(DV_ERR_DEVICE, t);
+      } else {
+        G.used = true;
+        G.number = gnum;
+        G.tickets = batch;
+        G.remaining = (int)batch.size();
+        G.pixels = pixels;
+        G.used_bytes = used_bytes;
+        G.st = st;
       }
     }
     cv_done.notify_all();
     cv_work.notify_all();
   }
+}
+
+void dv_server::completion() {
+  hipSetDevice(ctx->device);
+  while (true) {
+    bool busy;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      busy = groups_live > 0;
+      if (!busy && stop && queue.empty()) break;
+    }
+    // keep one drain kernel running while groups are in flight
+    if (drain_running) {
+      const hipError_t q = hipEventQuery(drain_ev);
+      if (q == hipSuccess) {
+        drain_running = false;
+      } else if (q != hipErrorNotReady) {
+        (void)hipGetLastError();
+        ctx->poisoned = true;
+        drain_running = false;
+      }
+    }
+    if (busy && !drain_running && !ctx->poisoned) {
+      const bool nrm = (opts.opts.out_mask & DV_OUT_NORMAL) != 0;
+      if (launch_serve_drain(qbuf.as<ServeQueue>(), gbuf.as<ServeGroup>(), nrm,
+                             opts.opts.K == 1, 3 * std::max(ctx->n_cu, 1),
+                             DRAIN_IDLE_POLLS, comp) == DV_OK &&
+          hipEventRecord(drain_ev, comp) == hipSuccess) {
+        drain_running = true;
+      } else {
+        (void)hipGetLastError();
+        ctx->poisoned = true;
+      }
+    }
+    bool changed = false;
+    std::vector<dv_fwd_state*> retire;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      const double t = now_s();
+      for (int gs = 0; gs < SV_GROUPS; ++gs) {
+        Group& G = groups[gs];
+        if (!G.used || !G.st) continue;
+        for (uint64_t tk : G.tickets) {
+          Request& r = reqs[tk];
+          if (r.done || r.flag < 0) continue;
+          const unsigned long long f = __atomic_load_n(flags + r.flag, __ATOMIC_ACQUIRE);
+          if (f == tk) {
+            finish(tk, DV_OK, t);
+            G.remaining -= 1;
+            changed = true;
+          } else if (ctx->poisoned) {
+            finish(tk, DV_ERR_DEVICE, t);
+            G.remaining -= 1;
+            changed = true;
+          }
+        }
+        if (G.remaining == 0) {
+          if (G.pixels > 0 && !ctx->poisoned)
+            bytes_per_pixel = 0.8 * bytes_per_pixel +
+                              0.2 * ((double)G.used_bytes / (double)G.pixels);
+          retire.push_back(G.st);
+          G.st = nullptr;
+          {
+            IdleRelease idle;
+            G.counters.reset();
+            G.vtab.reset();
+          }
+          G.used = false;
+          free_groups.push_back(gs);
+          groups_live -= 1;
+        }
+      }
+      if (ctx->poisoned) fail_queued(DV_ERR_DEVICE, t);
+    }
+    if (!retire.empty()) {
+      // every tile of these groups was written: no kernel reads their
+      // buffers any more
+      IdleRelease idle;
+      for (dv_fwd_state* st : retire) delete st;
+    }
+    if (changed) {
+      cv_done.notify_all();
+      cv_work.notify_all();
+    } else {
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+  }
+  if (drain_running) hipEventSynchronize(drain_ev);
 }
 
 extern "C" {
@@ -172,14 +450,40 @@ dv_status dv_serve_create(dv_ctx* ctx, const dv_scene* scene,
   srv->ctx = ctx;
   srv->scene = scene;
   srv->opts = *opts;
-  const int nw = opts->batched ? 2 : 1;
-  for (int i = 0; i < nw; ++i) {
-    hipStream_t s;
-    DV_TRY_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    srv->streams.push_back(s);
+  srv->opts.max_inflight = std::min(opts->max_inflight, SV_FLAGS);
+  if (!opts->batched) {
+    for (int i = 0; i < 2; ++i) {
+      hipStream_t s;
+      DV_TRY_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      srv->streams.push_back(s);
+    }
+    for (int i = 0; i < 2; ++i)
+      srv->workers.emplace_back(&dv_server::worker, srv.get(), i);
+    *out = srv.release();
+    return DV_OK;
   }
-  for (int i = 0; i < nw; ++i)
-    srv->workers.emplace_back(&dv_server::worker, srv.get(), i);
+  DV_TRY_HIP(hipStreamCreateWithFlags(&srv->prep, hipStreamNonBlocking));
+  srv->streams.push_back(srv->prep);
+  DV_TRY_HIP(hipStreamCreateWithFlags(&srv->comp, hipStreamNonBlocking));
+  srv->streams.push_back(srv->comp);
+  DV_TRY_HIP(hipEventCreateWithFlags(&srv->drain_ev, hipEventDisableTiming));
+  DV_TRY(alloc_n<uint8_t>(ctx, srv->qbuf, sizeof(ServeQueue), srv->prep));
+  DV_TRY(alloc_n<ServeGroup>(ctx, srv->gbuf, SV_GROUPS, srv->prep));
+  DV_TRY(fill_u32(srv->qbuf.as<uint32_t>(), 0u, (int64_t)(sizeof(ServeQueue) / 4),
+                  srv->prep));
+  DV_TRY_HIP(hipStreamSynchronize(srv->prep));
+  // pinned staging: per group slot its ServeGroup and per-view table
+  DV_TRY_HIP(hipHostMalloc((void**)&srv->gstage, SV_GROUPS * STAGE_STRIDE,
+                           hipHostMallocDefault));
+  DV_TRY_HIP(hipHostMalloc((void**)&srv->flags, SV_FLAGS * sizeof(unsigned long long),
+                           hipHostMallocCoherent | hipHostMallocMapped));
+  std::memset(srv->flags, 0, SV_FLAGS * sizeof(unsigned long long));
+  DV_TRY_HIP(hipHostGetDevicePointer((void**)&srv->flags_dev, srv->flags, 0));
+  for (int i = SV_FLAGS - 1; i >= 0; --i) srv->free_flags.push_back(i);
+  for (int i = SV_GROUPS - 1; i >= 0; --i) srv->free_groups.push_back(i);
+  srv->opts.max_batch = std::min(opts->max_batch, MAX_GROUP_VIEWS);
+  srv->workers.emplace_back(&dv_server::scheduler, srv.get());
+  srv->completer = std::thread(&dv_server::completion, srv.get());
   *out = srv.release();
   return DV_OK;
 }
@@ -221,7 +525,7 @@ dv_status dv_serve_submit(dv_server* srv, const dv_request* req,
   r.est_bytes = (int64_t)(srv->bytes_per_pixel * (double)v.w * v.h);
   srv->reqs.emplace(*ticket, r);
   srv->queue.push_back(*ticket);
-  srv->cv_work.notify_one();
+  srv->cv_work.notify_all();
   return DV_OK;
 }
 
@@ -262,13 +566,28 @@ dv_status dv_serve_destroy(dv_server* srv) {
   }
   srv->cv_work.notify_all();
   for (auto& t : srv->workers) t.join();
+  if (srv->completer.joinable()) srv->completer.join();
   hipSetDevice(srv->ctx->device);
   for (auto s : srv->streams) hipStreamSynchronize(s);
   // retired forward states release their buffers with events on the
   // worker streams: free them while those streams still exist
   reap_states(srv->ctx, true);
+  {
+    IdleRelease idle;
+    for (auto& G : srv->groups) {
+      if (G.st) delete G.st;
+      G.st = nullptr;
+      G.counters.reset();
+      G.vtab.reset();
+    }
+    srv->qbuf.reset();
+    srv->gbuf.reset();
+  }
   srv->ctx->pool->stamp();
   for (auto s : srv->streams) hipStreamDestroy(s);
+  if (srv->drain_ev) hipEventDestroy(srv->drain_ev);
+  if (srv->gstage) hipHostFree(srv->gstage);
+  if (srv->flags) hipHostFree(srv->flags);
   delete srv;
   return DV_OK;
 }

@@ -143,8 +143,33 @@ class dv_allocator(C.Structure):
     _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
 
 
+class dv_loss_view(C.Structure):
+    _fields_ = [("h", C.c_int32), ("w", C.c_int32)] + [
+        (k, C.c_void_p) for k in ("rgb", "depth", "normal", "T", "rgb_gt",
+                                  "depth_lidar", "normal_pseudo", "sky_mask",
+                                  "g_rgb", "g_depth", "g_normal", "g_T")]
+
+
+class dv_loss_weights(C.Structure):
+    _fields_ = [(k, C.c_float) for k in ("color", "ssim", "depth", "normal", "sky")]
+
+
+class dv_adam_param(C.Structure):
+    _fields_ = [("p", C.c_void_p), ("g", C.c_void_p), ("m", C.c_void_p),
+                ("v", C.c_void_p), ("n", C.c_int64)]
+
+
+class dv_adam_opts(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("step", C.c_int32)]
+
+
 _P = C.c_void_p
 _sig = {
+    "dv_loss": (C.c_int32, [_P, C.POINTER(dv_loss_view), C.c_int32,
+                            C.POINTER(dv_loss_weights), _P, _P]),
+    "dv_adam": (C.c_int32, [_P, C.POINTER(dv_adam_param), C.c_int32,
+                            C.POINTER(dv_adam_opts), _P]),
     "dv_ctx_create": (C.c_int32, [C.c_int32, C.POINTER(dv_allocator),
                                   C.POINTER(_P)]),
     "dv_ctx_trim": (C.c_int32, [_P]),
@@ -518,6 +543,43 @@ def render_features(ctx, scene, views, opts, feats, out_feat, mask=DV_OUT_T,
             o[3 * g:3 * g + nc].copy_(t["rgb"][:nc])
         states.append((st, tmp))
     return states if keep else None
+
+
+LOSS_TERMS = ("total", "color", "l1", "ssim", "depth", "normal", "sky", "_")
+
+
+def dv_loss(ctx, views, weights, stream=None):
+    """Training losses of several views.  views: list of dicts with the
+    rendered planes (rgb, depth, normal, T), the targets (rgb_gt,
+    depth_lidar, normal_pseudo, sky_mask) and the gradient planes to write
+    (g_rgb, g_depth, g_normal, g_T); weights: dict color, ssim, depth,
+    normal, sky.  Returns a CUDA float64 tensor [n_views, 8] of the terms
+    (total, color, l1, ssim, depth, normal, sky, 0)."""
+    import torch
+    nv = len(views)
+    cv = (dv_loss_view * nv)()
+    for i, v in enumerate(views):
+        ref = next(v[k] for k in ("rgb", "depth", "T", "rgb_gt") if v.get(k) is not None)
+        h, w = int(ref.shape[-2]), int(ref.shape[-1])
+        cv[i] = dv_loss_view(h, w, *[_ptr(v.get(k)) for k, _ in dv_loss_view._fields_[2:]])
+    lw = dv_loss_weights(*[float(weights[k]) for k in ("color", "ssim", "depth",
+                                                       "normal", "sky")])
+    terms = torch.zeros(nv, 8, dtype=torch.float64, device="cuda")
+    _check(_lib.dv_loss(ctx, cv, nv, C.byref(lw), _ptr(terms), _stream_handle(stream)),
+           "dv_loss")
+    return terms
+
+
+def dv_adam(ctx, params, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """One Adam step over params: list of dicts p, g, m, v (float32 CUDA
+    tensors of one size each), updated in place."""
+    n = len(params)
+    cp = (dv_adam_param * n)()
+    for i, q in enumerate(params):
+        cp[i] = dv_adam_param(_ptr(q["p"]), _ptr(q["g"]), _ptr(q["m"]), _ptr(q["v"]),
+                              int(q["p"].numel()))
+    o = dv_adam_opts(float(lr), float(beta1), float(beta2), float(eps), int(step))
+    _check(_lib.dv_adam(ctx, cp, n, C.byref(o), _stream_handle(stream)), "dv_adam")
 
 
 def dv_noalloc_capacity():
