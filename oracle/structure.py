@@ -21,6 +21,15 @@ path.
   leaf is unchanged wherever no finer neighbour already holds a corner at a
   child's corner position (always, on a uniform grid).
 * Prune: leaves are removed; corners no longer used are dropped.
+* Refinement (initialisation step 2, all rounds): while the finest leaf is
+  not yet below the minimum size, the leaves near a point (proximity rule
+  above) that are above the maximum level are split; it stops early when a
+  round flags none.
+* Bookkeeping for the optimiser state: every new leaf names its source
+  leaf (itself when kept, its parent when a child) and every new corner
+  the old corner at its position (-1 for a new position).  A child takes
+  its parent's SH coefficients (the colour does not change under a split,
+  reading).
 
 Canonical order, so lists can be compared exactly: leaves that stay, in
 their order, then the children of the split leaves, parent by parent,
@@ -91,6 +100,7 @@ def subdivide(o, split):
     par = np.nonzero(split)[0]
     new_lv = [lv[keep]]
     new_ijk = [ijk[:, keep]]
+    src = [keep]
     ch_lv, ch_ijk, ch_par, ch_m = [], [], [], []
     for p in par:
         for m in range(8):
@@ -102,6 +112,8 @@ def subdivide(o, split):
     if par.size:
         new_lv.append(np.array(ch_lv, np.int64))
         new_ijk.append(np.array(ch_ijk, np.int64).T)
+        src.append(np.array(ch_par, np.int64))
+    leaf_src = np.concatenate(src)
     level = np.concatenate(new_lv)
     cells = np.concatenate(new_ijk, axis=1)
     # corner table: old positions keep their value; new ones come from the
@@ -109,10 +121,11 @@ def subdivide(o, split):
     old_pos = _corner_keys(lv, ijk, L)
     old_val = np.asarray(o["corner_density"], np.float64)
     cidx = np.asarray(o["corner_idx"], np.int64)
-    value = {}
+    value, origin = {}, {}
     for m in range(8):
         for v in range(len(lv)):
             value[tuple(old_pos[m, v])] = old_val[cidx[m, v]]
+            origin[tuple(old_pos[m, v])] = cidx[m, v]
     pos = _corner_keys(level, cells, L)
     for j in range(par.size * 8):
         v = len(keep) + j
@@ -125,7 +138,7 @@ def subdivide(o, split):
             # local coordinates of the child's corner m in the parent
             u = np.array([((mc >> a) & 1) + ((m >> a) & 1) for a in range(3)]) / 2.0
             value[key] = _trilinear(g8, u)
-    return _finish(o, level, cells, pos, value)
+    return _finish(o, level, cells, pos, value, origin, leaf_src)
 
 
 def prune(o, keep_mask):
@@ -136,16 +149,46 @@ def prune(o, keep_mask):
     old_pos = _corner_keys(lv, ijk, L)
     old_val = np.asarray(o["corner_density"], np.float64)
     cidx = np.asarray(o["corner_idx"], np.int64)
-    value = {}
+    value, origin = {}, {}
     for m in range(8):
         for v in keep:
             value[tuple(old_pos[m, v])] = old_val[cidx[m, v]]
+            origin[tuple(old_pos[m, v])] = cidx[m, v]
     level, cells = lv[keep], ijk[:, keep]
     return _finish(o, level, cells, _corner_keys(level, cells, L), value,
-                   sh_keep=keep)
+                   origin, keep)
 
 
-def _finish(o, level, cells, pos, value, sh_keep=None):
+def refine(o, points, ratio, min_size, max_rounds=32):
+    """Proximity subdivision rounds until the finest leaf is smaller than
+    min_size (or no leaf is flagged, or max_rounds).  leaf_src and
+    corner_src of the result refer to the input octree."""
+    cur = dict(o)
+    leaf_src = np.arange(len(o["level"]), dtype=np.int64)
+    corner_src = np.arange(len(o["corner_density"]), dtype=np.int64)
+    rounds = 0
+    L = int(o["max_level"])
+    while rounds < max_rounds:
+        lv = np.asarray(cur["level"], np.int64)
+        if lv.size == 0 or cur["root_size"] / 2.0 ** lv.max() < min_size:
+            break
+        flags = proximity_flags(cur, points, ratio) & (lv < L)
+        if not flags.any():
+            break
+        nxt = subdivide(cur, flags)
+        leaf_src = leaf_src[nxt["leaf_src"]]
+        cs = nxt["corner_src"]
+        corner_src = np.where(cs >= 0, corner_src[np.maximum(cs, 0)], -1)
+        cur = nxt
+        rounds += 1
+    out = dict(cur)
+    out["leaf_src"] = leaf_src
+    out["corner_src"] = corner_src
+    out["rounds"] = rounds
+    return out
+
+
+def _finish(o, level, cells, pos, value, origin, leaf_src):
     n = len(level)
     keys = sorted({tuple(pos[m, v]) for m in range(8) for v in range(n)})
     index = {k: i for i, k in enumerate(keys)}
@@ -157,8 +200,10 @@ def _finish(o, level, cells, pos, value, sh_keep=None):
     out["corner_idx"] = cidx
     out["corner_density"] = np.array([value[k] for k in keys], np.float64)
     out["corner_pos"] = np.array(keys, np.int64).reshape(-1, 3)
-    if sh_keep is not None and "sh" in o:
-        out["sh"] = np.asarray(o["sh"])[:, :, sh_keep]
+    out["corner_src"] = np.array([origin.get(k, -1) for k in keys], np.int64)
+    out["leaf_src"] = np.asarray(leaf_src, np.int64)
+    if "sh" in o:
+        out["sh"] = np.asarray(o["sh"])[:, :, np.asarray(leaf_src, np.int64)]
     return out
 
 

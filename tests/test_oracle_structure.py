@@ -135,3 +135,70 @@ def test_corner_prior_is_eq1_of_the_nearest_point():
     cw = ST.corner_world_positions(o)
     d = np.array([np.sqrt(((pts - c) ** 2).sum(1)).min() for c in cw])
     assert np.allclose(v, -10.0 + 8.0 * np.exp(-2.0 * d * d / (s * s)), atol=1e-13)
+
+
+def test_sources_name_the_parent_and_the_old_corner_at_the_same_place():
+    # leaf_src: kept leaves name themselves, children a leaf whose box holds
+    # theirs; corner_src: an old corner at the same world position with the
+    # same value, -1 exactly where no old corner sits; children carry their
+    # parent's SH
+    o = _octree(9)
+    rng = np.random.default_rng(10)
+    split = (rng.uniform(size=len(o["level"])) < 0.25) & (o["level"] < o["max_level"])
+    o2 = ST.subdivide(o, split)
+    lo, hi, _ = ST.leaf_boxes(o)
+    lo2, hi2, _ = ST.leaf_boxes(o2)
+    src = o2["leaf_src"]
+    n_keep = int((~split).sum())
+    assert np.array_equal(src[:n_keep], np.nonzero(~split)[0])
+    assert np.all(split[src[n_keep:]])
+    assert np.all(lo2 >= lo[src] - 1e-15) and np.all(hi2 <= hi[src] + 1e-15)
+    assert np.array_equal(o2["sh"], o["sh"][:, :, src])
+    old_w = ST.corner_world_positions(o)
+    new_w = ST.corner_world_positions(o2)
+    old_set = {tuple(p) for p in old_w.round(12)}
+    cs = o2["corner_src"]
+    for c in range(len(cs)):
+        if cs[c] >= 0:
+            assert np.array_equal(new_w[c], old_w[cs[c]])
+            assert o2["corner_density"][c] == o["corner_density"][cs[c]]
+        else:
+            assert tuple(new_w[c].round(12)) not in old_set
+    assert (cs < 0).any() and (cs >= 0).any()
+    # prune: sources are the kept leaves, corners all old
+    keep = rng.uniform(size=len(o["level"])) < 0.5
+    o3 = ST.prune(o, keep)
+    assert np.array_equal(o3["leaf_src"], np.nonzero(keep)[0])
+    assert np.all(o3["corner_src"] >= 0)
+    assert np.array_equal(ST.corner_world_positions(o3),
+                          old_w[o3["corner_src"]])
+
+
+def test_refine_rounds_reach_the_minimum_size_near_points():
+    # uniform level-2 grid over [-1, 1]^3 (leaf 0.5), points on a plane:
+    # after refinement every leaf within ratio * h of a point is below the
+    # minimum size (or at the maximum level), the leaves still tile the
+    # cube, and the field of the uniform start grid is unchanged
+    rng = np.random.default_rng(11)
+    o = random_octree(rng, (-1.0, -1.0, -1.0), 2.0, 2, 0, 6, 0)
+    o = dict(o, corner_density=o["corner_density"].astype(np.float64))
+    pts = np.column_stack([rng.uniform(-1, 1, 60), rng.uniform(-1, 1, 60),
+                           np.full(60, 0.1)])
+    r = ST.refine(o, pts, ratio=0.5, min_size=0.1)
+    lo, hi, h = ST.leaf_boxes(r)
+    assert r["rounds"] == 3                      # 0.5 -> 0.25 -> 0.125 -> 0.0625
+    assert abs((h ** 3).sum() - 8.0) < 1e-12
+    near = ST.proximity_flags(r, pts, 0.5)
+    assert np.all((h[near] < 0.1) | (r["level"][near] == r["max_level"]))
+    assert h.min() < 0.1 and h.max() == 0.5
+    lo0, hi0, _ = ST.leaf_boxes(o)
+    src = r["leaf_src"]
+    assert np.all(lo >= lo0[src] - 1e-15) and np.all(hi <= hi0[src] + 1e-15)
+    for _ in range(40):
+        x = rng.uniform(-0.98, 0.98, 3)
+        assert abs(ST.field_at(r, x) - ST.field_at(o, x)) < 1e-12
+    # corner sources refer to the input table
+    old_w = ST.corner_world_positions(o)
+    new_w = ST.corner_world_positions(r)
+    cs = r["corner_src"]
+    assert np.array_equal(new_w[cs >= 0], old_w[cs[cs >= 0]])
