@@ -594,7 +594,8 @@ struct OctGrad {
 // kernel drains their work items, merges chunked tiles, counts finished
 // tiles per view and raises a request's completion flag in host memory
 // when its last tile is written.
-constexpr int SV_RING = 1024;    // ring entries (groups published)
+constexpr int SV_RING = 1024;    // ring entries (groups published), and the
+                                 // argument blocks, one per entry
 constexpr int SV_GROUPS = 16;    // group slots (forward states in flight)
 constexpr int SV_FLAGS = 1024;   // request completion flags
 
@@ -612,19 +613,21 @@ struct ServeQueue {
   unsigned long long tail;            // groups published so far
   unsigned long long head;            // first group not known to be drained
   unsigned long long claim[SV_RING];  // (group number << 32) | items taken
-  uint32_t slot[SV_RING];
   uint32_t n_items[SV_RING];
 };
 
-// Publish group number g (group slot `slot`, item count plan_counts[0]) on
-// stream s, after the group's forward work and its ServeGroup upload.
-dv_status launch_serve_publish(ServeQueue* q, uint64_t g, uint32_t slot,
+// Publish group number g (item count plan_counts[0]) on stream s, after the
+// group's forward work and the upload of its ServeGroup into entry
+// g % SV_RING of the argument ring.
+dv_status launch_serve_publish(ServeQueue* q, uint64_t g,
                                const uint32_t* plan_counts, hipStream_t s);
 // The persistent drain kernel: `blocks` blocks; each exits after idle_limit
-// consecutive empty polls (about 3.5 us each).
+// consecutive empty polls (about 3.5 us each), or when the oldest group
+// with items left is numbered g_hi or above (the host keeps g_hi at most
+// SV_RING / 2 above the oldest unfinished group).
 dv_status launch_serve_drain(ServeQueue* q, const ServeGroup* groups,
                              bool normals, bool k1, int blocks, int idle_limit,
-                             hipStream_t s);
+                             uint64_t g_hi, hipStream_t s);
 
 // Per-pixel segment scratch: slot s of tile gt, pixel tid.
 __device__ inline size_t seg_index(uint32_t slot, int tid) {

@@ -1247,14 +1247,13 @@ __global__ void __launch_bounds__(TPB) k_chunk_merge(CompArgs a) {
 
 // ------------------------------------------------------------------ serving
 __global__ void k_serve_publish(ServeQueue* q, unsigned long long g,
-                                uint32_t slot, const uint32_t* plan_counts) {
+                                const uint32_t* plan_counts) {
   const uint32_t e = (uint32_t)(g % SV_RING);
-  q->slot[e] = slot;
   q->n_items[e] = plan_counts ? plan_counts[0] : 0u;
   __hip_atomic_store(&q->claim[e], g << 32, __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
-  // the entry (and, earlier in stream order, the group's buffers) before
-  // the tail that makes it visible
+  // the entry (and, earlier in stream order, the group's buffers and its
+  // argument block) before the tail that makes it visible
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __hip_atomic_store(&q->tail, g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -1268,10 +1267,16 @@ __global__ void k_serve_publish(ServeQueue* q, unsigned long long g,
 // A block with nothing to take sleeps and polls again; after idle_limit
 // empty polls in a row it exits, so every block ends (the host launches
 // the kernel again when new groups arrive).
+// Group g's arguments sit in entry g % SV_RING of `groups` and are read
+// through scalar loads, which one launch may keep cached.  A launch
+// therefore serves only groups below g_hi, which the host sets at most
+// SV_RING / 2 above the oldest unfinished group: within one launch no
+// entry is read for two different groups, and a block that reaches g_hi
+// exits so that a fresh launch (fresh caches) takes the later groups.
 template <bool NORMALS, int KC>
 __global__ void __launch_bounds__(TPB, 4)
 k_serve_drain(ServeQueue* q, const ServeGroup* __restrict__ groups,
-              int idle_limit) {
+              int idle_limit, unsigned long long g_hi) {
   __shared__ Batch B;
   __shared__ uint32_t blk_work;
   __shared__ uint32_t s_cmd, s_slot, s_idx, s_last;
@@ -1285,6 +1290,10 @@ k_serve_drain(ServeQueue* q, const ServeGroup* __restrict__ groups,
         const unsigned long long t =
             __hip_atomic_load(&q->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (h >= t) break;
+        if (h >= g_hi) {
+          cmd = 2;
+          break;
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const uint32_t e = (uint32_t)(h % SV_RING);
         const unsigned long long w =
@@ -1302,8 +1311,7 @@ k_serve_drain(ServeQueue* q, const ServeGroup* __restrict__ groups,
           continue;
         }
         if (atomicCAS(&q->claim[e], w, w + 1) == w) {
-          s_slot = __hip_atomic_load(&q->slot[e], __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
+          s_slot = e;
           s_idx = c;
           cmd = 1;
         }
@@ -1324,8 +1332,9 @@ k_serve_drain(ServeQueue* q, const ServeGroup* __restrict__ groups,
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     // wave-uniform: the group's arguments come through scalar loads
     const uint32_t slot = __builtin_amdgcn_readfirstlane(s_slot);
-    // through the constant address space: the arguments are read-only for
-    // the kernel's lifetime, so their loads can be repeated instead of kept
+    // through the constant address space: within this launch the entry holds
+    // one group's arguments only (see g_hi), so their loads can be repeated
+    // instead of kept
     typedef __attribute__((address_space(4))) const ServeGroup CGroup;
     CGroup& G = ((CGroup*)groups)[slot];
     const auto& a = G.a;
@@ -1369,21 +1378,21 @@ k_serve_drain(ServeQueue* q, const ServeGroup* __restrict__ groups,
   }
 }
 
-dv_status launch_serve_publish(ServeQueue* q, uint64_t g, uint32_t slot,
+dv_status launch_serve_publish(ServeQueue* q, uint64_t g,
                                const uint32_t* plan_counts, hipStream_t s) {
   hipLaunchKernelGGL(k_serve_publish, dim3(1), dim3(1), 0, s, q,
-                     (unsigned long long)g, slot, plan_counts);
+                     (unsigned long long)g, plan_counts);
   DV_TRY_HIP(hipGetLastError());
   return DV_OK;
 }
 
 dv_status launch_serve_drain(ServeQueue* q, const ServeGroup* groups,
                              bool normals, bool k1, int blocks, int idle_limit,
-                             hipStream_t s) {
+                             uint64_t g_hi, hipStream_t s) {
   auto kern = normals ? (k1 ? k_serve_drain<true, 1> : k_serve_drain<true, 0>)
                       : (k1 ? k_serve_drain<false, 1> : k_serve_drain<false, 0>);
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(TPB), 0, s, q, groups,
-                     idle_limit);
+                     idle_limit, (unsigned long long)g_hi);
   DV_TRY_HIP(hipGetLastError());
   return DV_OK;
 }

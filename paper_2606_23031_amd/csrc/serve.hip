@@ -31,6 +31,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <set>
 #include <thread>
 #include <unordered_map>
 
@@ -104,7 +105,7 @@ struct dv_server {
   // batched mode
   hipStream_t prep = nullptr, comp = nullptr;
   DBuf qbuf;                        // ServeQueue
-  DBuf gbuf;                        // ServeGroup[SV_GROUPS]
+  DBuf gbuf;                        // ServeGroup[SV_RING]: group g in entry g % SV_RING
   uint8_t* gstage = nullptr;        // pinned staging, STAGE_STRIDE per slot
   unsigned long long* flags = nullptr;      // host-mapped [SV_FLAGS]
   unsigned long long* flags_dev = nullptr;  // their device address
@@ -112,6 +113,7 @@ struct dv_server {
   Group groups[SV_GROUPS];
   std::vector<int> free_groups;
   uint64_t next_group = 0;
+  std::set<uint64_t> live_nums;     // numbers of groups taken and not yet finished
   int groups_live = 0;
   bool drain_running = false;
   hipEvent_t drain_ev = nullptr;
@@ -120,6 +122,13 @@ struct dv_server {
   void worker(int wid);
   void scheduler();
   void completion();
+  // the oldest unfinished group (every older one has raised all its flags)
+  uint64_t oldest_live() const {
+    return live_nums.empty() ? next_group : *live_nums.begin();
+  }
+  // group next_group may take its argument entry: the group that used it
+  // SV_RING numbers earlier has finished
+  bool ring_entry_free() const { return oldest_live() + SV_RING > next_group; }
   bool admissible(const Request& r) const {
     if (inflight >= opts.max_inflight) return false;
     if (inflight == 0) return true;
@@ -211,6 +220,7 @@ void dv_server::scheduler() {
   std::vector<dv_outputs> outs;
   while (true) {
     int gslot = -1;
+    uint64_t gnum = 0;
     batch.clear();
     views.clear();
     outs.clear();
@@ -220,17 +230,19 @@ void dv_server::scheduler() {
       cv_work.wait(lk, [&] {
         return (stop && queue.empty()) ||
                (!queue.empty() && admissible(reqs[queue.front()]) &&
-                !free_groups.empty() && !free_flags.empty());
+                !free_groups.empty() && !free_flags.empty() && ring_entry_free());
       });
       if (queue.empty()) {
         if (stop) return;
         continue;
       }
       if (!admissible(reqs[queue.front()]) || free_groups.empty() ||
-          free_flags.empty())
+          free_flags.empty() || !ring_entry_free())
         continue;
       gslot = free_groups.back();
       free_groups.pop_back();
+      gnum = next_group++;
+      live_nums.insert(gnum);
       const double t = now_s();
       while (!queue.empty() && (int)batch.size() < max_batch &&
              !free_flags.empty() && admissible(reqs[queue.front()])) {
@@ -249,7 +261,6 @@ void dv_server::scheduler() {
       groups_live += 1;
     }
     Group& G = groups[gslot];
-    const uint64_t gnum = next_group++;
     int64_t pixels = 0;
     for (auto& v : views) pixels += (int64_t)v.w * v.h;
     int64_t used_bytes = 0;
@@ -295,7 +306,7 @@ void dv_server::scheduler() {
         sg.view_seq = reinterpret_cast<const unsigned long long*>(
             vt + (((size_t)nv * 8 + 7) & ~(size_t)7));
         sg.flags = flags_dev;
-        ServeGroup* gd = gbuf.as<ServeGroup>() + gslot;
+        ServeGroup* gd = gbuf.as<ServeGroup>() + (size_t)(gnum % SV_RING);
         hipError_t e = hipMemcpyAsync(vt, tab, tab_bytes, hipMemcpyHostToDevice, prep);
         if (e == hipSuccess)
           e = hipMemcpyAsync(gd, &sg, sizeof(ServeGroup), hipMemcpyHostToDevice, prep);
@@ -305,7 +316,7 @@ void dv_server::scheduler() {
         }
       }
       if (rc == DV_OK)
-        rc = launch_serve_publish(qbuf.as<ServeQueue>(), gnum, (uint32_t)gslot,
+        rc = launch_serve_publish(qbuf.as<ServeQueue>(), gnum,
                                   ps->plan_counts.as<uint32_t>(), prep);
       if (rc == DV_OK) {
         used_bytes = 24 * ps->n_pairs + 150 * ps->n_vis + 40 * ps->n_tiles * TPB;
@@ -326,6 +337,7 @@ void dv_server::scheduler() {
         const double t = now_s();
         for (uint64_t tk : batch) finish(tk, rc, t);
         free_groups.push_back(gslot);
+        live_nums.erase(gnum);
         groups_live -= 1;
         if (rc == DV_ERR_DEVICE) fail_queued(DV_ERR_DEVICE, t);
       } else {
@@ -347,10 +359,12 @@ void dv_server::completion() {
   hipSetDevice(ctx->device);
   while (true) {
     bool busy;
+    uint64_t g_hi = 0;
     {
       std::lock_guard<std::mutex> lk(mu);
       busy = groups_live > 0;
       if (!busy && stop && queue.empty()) break;
+      g_hi = oldest_live() + SV_RING / 2;
     }
     // keep one drain kernel running while groups are in flight
     if (drain_running) {
@@ -367,7 +381,7 @@ void dv_server::completion() {
       const bool nrm = (opts.opts.out_mask & DV_OUT_NORMAL) != 0;
       if (launch_serve_drain(qbuf.as<ServeQueue>(), gbuf.as<ServeGroup>(), nrm,
                              opts.opts.K == 1, 3 * std::max(ctx->n_cu, 1),
-                             DRAIN_IDLE_POLLS, comp) == DV_OK &&
+                             DRAIN_IDLE_POLLS, g_hi, comp) == DV_OK &&
           hipEventRecord(drain_ev, comp) == hipSuccess) {
         drain_running = true;
       } else {
@@ -410,6 +424,7 @@ void dv_server::completion() {
           }
           G.used = false;
           free_groups.push_back(gs);
+          live_nums.erase(G.number);
           groups_live -= 1;
         }
       }
@@ -468,7 +483,7 @@ dv_status dv_serve_create(dv_ctx* ctx, const dv_scene* scene,
   srv->streams.push_back(srv->comp);
   DV_TRY_HIP(hipEventCreateWithFlags(&srv->drain_ev, hipEventDisableTiming));
   DV_TRY(alloc_n<uint8_t>(ctx, srv->qbuf, sizeof(ServeQueue), srv->prep));
-  DV_TRY(alloc_n<ServeGroup>(ctx, srv->gbuf, SV_GROUPS, srv->prep));
+  DV_TRY(alloc_n<ServeGroup>(ctx, srv->gbuf, SV_RING, srv->prep));
   DV_TRY(fill_u32(srv->qbuf.as<uint32_t>(), 0u, (int64_t)(sizeof(ServeQueue) / 4),
                   srv->prep));
   DV_TRY_HIP(hipStreamSynchronize(srv->prep));
