@@ -433,6 +433,106 @@ typedef struct {
 dv_status dv_adam(dv_ctx* ctx, const dv_adam_param* params, int32_t n_params,
                   const dv_adam_opts* opts, void* stream);
 
+/* ---------------------------------------------------------------- structure */
+/* LiDAR-guided initialisation of the background octree (Sec. 3.3,
+ * 'Initialization': proximity-based voxel subdivision and the soft density
+ * prior, Eq. 1) and the structure edits of training (Sec. 3.1: adaptive
+ * pruning and progressive subdivision; Supp. 'Adaptive Optimization
+ * Schedule').  Points are device FP64 [3][n] (x row, y row, z row); every
+ * call enqueues on the stream and synchronises it to read a few counts. */
+typedef struct dv_edit dv_edit;
+
+#define DV_EDIT_SUBDIVIDE 0
+#define DV_EDIT_PRUNE 1
+
+/* Exact Euclidean distance from each query ([3][n_queries] FP64) to its
+ * nearest point, written to dist [n_queries] (FP64, device) when it is
+ * below r_max, +inf otherwise (also for non-finite queries and when there
+ * are no points).  Points hashed into a grid of r_max / 2 cells.  Errors:
+ * DV_ERR_INVALID (r_max <= 0, non-finite points), DV_ERR_LIMIT (point
+ * extent above 2^21 cells, 2^32 points). */
+dv_status dv_nearest_distance(dv_ctx* ctx, const double* points, int64_t n_points,
+                              const double* queries, int64_t n_queries,
+                              double r_max, double* dist, void* stream);
+
+/* Soft density prior (Eq. 1): every corner of the octree (leaf geometry
+ * and corner_idx of `octree`; its densities and SH are not read) gets
+ *   v = v_far + (v_close - v_far) exp(-2 d^2 / s^2),
+ * d the distance from the corner's world position (root_min + finest-grid
+ * position * root_size / 2^max_level) to the nearest point, written as
+ * float to density [n_corners] (device).  Corners farther than r_cut from
+ * every point, and corners no leaf uses, get v_far: with r_cut = 3 s the
+ * omitted term is below |v_close - v_far| e^-18 (1.2e-7 for the paper's
+ * v_close = -2, v_far = -10, under the float spacing at 10).  The paper
+ * takes s as the minimum voxel size.  Errors: DV_ERR_INVALID, DV_ERR_RANGE
+ * (a level, cell or corner index out of range), those of
+ * dv_nearest_distance. */
+dv_status dv_corner_prior(dv_ctx* ctx, const dv_octree_desc* octree,
+                          const double* points, int64_t n_points, double s,
+                          double v_close, double v_far, double r_cut,
+                          float* density, void* stream);
+
+/* Proximity rule of the initialisation's subdivision rounds: flags[v]
+ * (device uint8 [n_voxels]) = 1 iff some point lies within ratio * h_v of
+ * leaf v's closed box (Euclidean point-to-box distance, FP64; the paper
+ * names a distance threshold without a value, reading: proportional to
+ * the leaf side).  Errors: DV_ERR_INVALID, DV_ERR_RANGE. */
+dv_status dv_proximity_flags(dv_ctx* ctx, const dv_octree_desc* octree,
+                             const double* points, int64_t n_points, double ratio,
+                             uint8_t* flags, void* stream);
+
+/* Structure edit, planned on the device: op DV_EDIT_SUBDIVIDE splits the
+ * leaves with flags[v] != 0 into their 8 children (DV_ERR_RANGE if one is
+ * at max_level), DV_EDIT_PRUNE keeps only the leaves with flags[v] != 0.
+ * New leaf order: the leaves that stay, in order, then the children of the
+ * split leaves, parent by parent, child m = mx + 2 my + 4 mz.  New corner
+ * table: one corner per distinct finest-grid position of the new leaves'
+ * corners, in (i, j, k) lexicographic order.  A position held by an old
+ * corner keeps its density; a new position (inside a split leaf) takes the
+ * parent's trilinear field there (FP64, rounded to float), so the field
+ * inside a split leaf is unchanged unless a finer neighbour already holds
+ * a corner at a child corner position.  Positions are assumed to name one
+ * old corner each (which survives is unspecified otherwise).  Children
+ * take their parent's SH.  *n_leaves and *n_corners receive the new sizes;
+ * *out the plan, which keeps device copies of the new tables until
+ * dv_edit_release.  `octree`'s arrays (and its SH, read by dv_edit_apply)
+ * must stay valid until dv_edit_apply's work has run.  Synchronises the
+ * stream twice. */
+dv_status dv_edit_plan(dv_ctx* ctx, const dv_octree_desc* octree,
+                       const uint8_t* flags, int32_t op, dv_edit** out,
+                       int64_t* n_leaves, int64_t* n_corners, void* stream);
+
+/* Proximity-based subdivision rounds (initialisation step 2): while the
+ * finest leaf is not below min_size, split the leaves (below max_level)
+ * within ratio * h of a point; stop early when a round splits none or
+ * after max_rounds.  The corner table is canonical (as dv_edit_plan's) even
+ * after zero rounds.  Sources and densities as dv_edit_plan's, relative to
+ * the input.  *rounds receives the rounds done. */
+dv_status dv_refine_plan(dv_ctx* ctx, const dv_octree_desc* octree,
+                         const double* points, int64_t n_points, double ratio,
+                         double min_size, int32_t max_rounds, dv_edit** out,
+                         int64_t* n_leaves, int64_t* n_corners, int32_t* rounds,
+                         void* stream);
+
+/* Caller-allocated device outputs of a plan (sizes from the plan). */
+typedef struct {
+  uint8_t* level;               /* [n_leaves]                              */
+  int32_t* ijk;                 /* [3][n_leaves]                           */
+  int32_t* corner_idx;          /* [8][n_leaves]                           */
+  float* corner_density;        /* [n_corners]                             */
+  float* sh;                    /* [S][3][n_leaves] or NULL: gathered from
+                                   the input's SH by leaf_src              */
+  int32_t* leaf_src;            /* [n_leaves] or NULL: the input leaf each
+                                   new leaf comes from (itself or parent)  */
+  int32_t* corner_src;          /* [n_corners] or NULL: the input corner at
+                                   the same position, -1 for a new one     */
+} dv_edit_out;
+
+/* Write a plan's tables into caller buffers (enqueued copies and one SH
+ * gather).  May be called more than once. */
+dv_status dv_edit_apply(dv_edit* edit, const dv_edit_out* out, void* stream);
+void dv_edit_release(dv_edit* edit);
+
 /* ---------------------------------------------------------------- serving */
 /* Sensor simulation (Sec. 1: the reconstructed scene is rendered for new
  * cameras, timestamps and actor configurations): the scene and actor tracks

@@ -161,11 +161,13 @@ def prune(o, keep_mask):
 
 def refine(o, points, ratio, min_size, max_rounds=32):
     """Proximity subdivision rounds until the finest leaf is smaller than
-    min_size (or no leaf is flagged, or max_rounds).  leaf_src and
-    corner_src of the result refer to the input octree."""
-    cur = dict(o)
-    leaf_src = np.arange(len(o["level"]), dtype=np.int64)
-    corner_src = np.arange(len(o["corner_density"]), dtype=np.int64)
+    min_size (or no leaf is flagged, or max_rounds).  The result is in
+    canonical order even after no round; leaf_src and corner_src refer to
+    the input octree."""
+    # the input in canonical corner order (an all-keep prune)
+    cur = prune(o, np.ones(len(o["level"]), bool))
+    leaf_src = cur["leaf_src"]
+    corner_src = cur["corner_src"]
     rounds = 0
     L = int(o["max_level"])
     while rounds < max_rounds:

@@ -159,6 +159,13 @@ class dv_adam_param(C.Structure):
                 ("v", C.c_void_p), ("n", C.c_int64)]
 
 
+class dv_edit_out(C.Structure):
+    _fields_ = [("level", C.c_void_p), ("ijk", C.c_void_p),
+                ("corner_idx", C.c_void_p), ("corner_density", C.c_void_p),
+                ("sh", C.c_void_p), ("leaf_src", C.c_void_p),
+                ("corner_src", C.c_void_p)]
+
+
 class dv_adam_opts(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
                 ("eps", C.c_float), ("step", C.c_int32)]
@@ -202,6 +209,22 @@ _sig = {
     "dv_ctx_set_profiling": (C.c_int32, [_P, C.c_int32]),
     "dv_ctx_stage_times": (C.c_int32, [_P, C.POINTER(dv_stage_times), C.c_int32]),
     "dv_stage_name": (C.c_char_p, [C.c_int32]),
+    "dv_nearest_distance": (C.c_int32, [_P, _P, C.c_int64, _P, C.c_int64,
+                                        C.c_double, _P, _P]),
+    "dv_corner_prior": (C.c_int32, [_P, C.POINTER(dv_octree_desc), _P, C.c_int64,
+                                    C.c_double, C.c_double, C.c_double,
+                                    C.c_double, _P, _P]),
+    "dv_proximity_flags": (C.c_int32, [_P, C.POINTER(dv_octree_desc), _P,
+                                       C.c_int64, C.c_double, _P, _P]),
+    "dv_edit_plan": (C.c_int32, [_P, C.POINTER(dv_octree_desc), _P, C.c_int32,
+                                 C.POINTER(_P), C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_int64), _P]),
+    "dv_refine_plan": (C.c_int32, [_P, C.POINTER(dv_octree_desc), _P, C.c_int64,
+                                   C.c_double, C.c_double, C.c_int32,
+                                   C.POINTER(_P), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_int32), _P]),
+    "dv_edit_apply": (C.c_int32, [_P, C.POINTER(dv_edit_out), _P]),
+    "dv_edit_release": (None, [_P]),
     "dv_serve_create": (C.c_int32, [_P, _P, C.POINTER(dv_serve_opts),
                                     C.POINTER(_P)]),
     "dv_serve_submit": (C.c_int32, [_P, C.POINTER(dv_request),
@@ -673,3 +696,130 @@ def dv_serve_poll(srv, ticket, wait_us=0):
 
 def dv_serve_destroy(srv):
     _check(_lib.dv_serve_destroy(srv), "dv_serve_destroy")
+
+
+# ------------------------------------------------------------------ structure
+DV_EDIT_SUBDIVIDE, DV_EDIT_PRUNE = 0, 1
+
+
+def octree_tensors(o, device="cuda"):
+    """Device tensors of one octree dict (level, ijk, corner_idx,
+    corner_density, sh) and its dv_octree_desc (the tensors must outlive
+    the desc's use)."""
+    t = dict(
+        level=torch.from_numpy(np.ascontiguousarray(o["level"], np.uint8)).to(device),
+        ijk=torch.from_numpy(np.ascontiguousarray(o["ijk"], np.int32)).to(device),
+        corner_idx=torch.from_numpy(np.ascontiguousarray(o["corner_idx"], np.int32)).to(device),
+        corner_density=torch.from_numpy(
+            np.ascontiguousarray(o["corner_density"], np.float32)).to(device))
+    if o.get("sh") is not None:
+        t["sh"] = torch.from_numpy(np.ascontiguousarray(o["sh"], np.float32)).to(device)
+    return t, octree_desc(o, t)
+
+
+def octree_desc(o, t):
+    """dv_octree_desc of the device tensors t (level, ijk, corner_idx,
+    corner_density, optional sh) with o's root, max_level and sh_degree."""
+    d = dv_octree_desc()
+    d.root_min[:] = [float(x) for x in o["root_min"]]
+    d.root_size = float(o["root_size"])
+    d.n_voxels = int(t["level"].shape[0])
+    d.max_level = int(o["max_level"])
+    d.n_corners = int(t["corner_density"].shape[0])
+    d.sh_degree = int(o.get("sh_degree", 0)) if t.get("sh") is not None else 0
+    d.level = t["level"].data_ptr()
+    d.ijk = t["ijk"].data_ptr()
+    d.corner_idx = t["corner_idx"].data_ptr()
+    d.corner_density = t["corner_density"].data_ptr()
+    d.sh = t["sh"].data_ptr() if t.get("sh") is not None else None
+    return d
+
+
+def _points(points):
+    if not (points.is_cuda and points.dim() == 2 and points.shape[0] == 3
+            and points.is_contiguous() and points.dtype == torch.float64):
+        raise ValueError("points must be a contiguous float64 CUDA tensor [3][n]")
+    return _ptr(points), int(points.shape[1])
+
+
+def dv_nearest_distance(ctx, points, queries, r_max, stream=None):
+    """Exact nearest-point distance of each query (float64 CUDA [3][m]);
+    +inf where none is within r_max."""
+    pp, n = _points(points)
+    qp, m = _points(queries)
+    dist = torch.empty(m, dtype=torch.float64, device="cuda")
+    _check(_lib.dv_nearest_distance(ctx, pp, n, qp, m, float(r_max), _ptr(dist),
+                                    _stream_handle(stream)), "dv_nearest_distance")
+    return dist
+
+
+def dv_corner_prior(ctx, desc, points, s, v_close=-2.0, v_far=-10.0, r_cut=None,
+                    stream=None):
+    """Eq. 1 for every corner of the octree desc: float32 CUDA [n_corners]."""
+    pp, n = _points(points)
+    out = torch.empty(max(desc.n_corners, 0), dtype=torch.float32, device="cuda")
+    r = 3.0 * s if r_cut is None else r_cut
+    _check(_lib.dv_corner_prior(ctx, C.byref(desc), pp, n, float(s), float(v_close),
+                                float(v_far), float(r), _ptr(out),
+                                _stream_handle(stream)), "dv_corner_prior")
+    return out
+
+
+def dv_proximity_flags(ctx, desc, points, ratio, stream=None):
+    pp, n = _points(points)
+    flags = torch.empty(max(desc.n_voxels, 0), dtype=torch.uint8, device="cuda")
+    _check(_lib.dv_proximity_flags(ctx, C.byref(desc), pp, n, float(ratio),
+                                   _ptr(flags), _stream_handle(stream)),
+           "dv_proximity_flags")
+    return flags
+
+
+def _apply(edit, n, nc, sh_rows, stream):
+    out = dict(level=torch.empty(n, dtype=torch.uint8, device="cuda"),
+               ijk=torch.empty(3, n, dtype=torch.int32, device="cuda"),
+               corner_idx=torch.empty(8, n, dtype=torch.int32, device="cuda"),
+               corner_density=torch.empty(nc, dtype=torch.float32, device="cuda"),
+               leaf_src=torch.empty(n, dtype=torch.int32, device="cuda"),
+               corner_src=torch.empty(nc, dtype=torch.int32, device="cuda"))
+    if sh_rows:
+        out["sh"] = torch.empty(sh_rows // 3, 3, n, dtype=torch.float32, device="cuda")
+    eo = dv_edit_out(*[_ptr(out.get(k)) for k, _ in dv_edit_out._fields_])
+    _check(_lib.dv_edit_apply(edit, C.byref(eo), _stream_handle(stream)),
+           "dv_edit_apply")
+    return out
+
+
+def _sh_rows(desc):
+    return 3 * (desc.sh_degree + 1) ** 2 if desc.sh else 0
+
+
+def dv_edit(ctx, desc, flags, op, stream=None):
+    """Subdivide (op 0) or prune (op 1) by flags (uint8 CUDA [N]): dict of
+    the new tables (level, ijk, corner_idx, corner_density, leaf_src,
+    corner_src, and sh when the desc has SH)."""
+    h = C.c_void_p()
+    n, nc = C.c_int64(), C.c_int64()
+    _check(_lib.dv_edit_plan(ctx, C.byref(desc), _ptr(flags), int(op), C.byref(h),
+                             C.byref(n), C.byref(nc), _stream_handle(stream)),
+           "dv_edit_plan")
+    try:
+        return _apply(h, n.value, nc.value, _sh_rows(desc), stream)
+    finally:
+        torch.cuda.current_stream().synchronize()
+        _lib.dv_edit_release(h)
+
+
+def dv_refine(ctx, desc, points, ratio, min_size, max_rounds=32, stream=None):
+    """Proximity subdivision rounds: (tables dict as dv_edit's, rounds)."""
+    pp, np_ = _points(points)
+    h = C.c_void_p()
+    n, nc, r = C.c_int64(), C.c_int64(), C.c_int32()
+    _check(_lib.dv_refine_plan(ctx, C.byref(desc), pp, np_, float(ratio),
+                               float(min_size), int(max_rounds), C.byref(h),
+                               C.byref(n), C.byref(nc), C.byref(r),
+                               _stream_handle(stream)), "dv_refine_plan")
+    try:
+        return _apply(h, n.value, nc.value, _sh_rows(desc), stream), r.value
+    finally:
+        torch.cuda.current_stream().synchronize()
+        _lib.dv_edit_release(h)
