@@ -68,6 +68,12 @@ def parse():
     ap.add_argument("--sky-map", default="512x1024",
                     help="HxW of the sky environment map timed after the "
                          "headline step (0: skip)")
+    ap.add_argument("--structure", type=int, default=1,
+                    help="time the background initialisation and structure "
+                         "edits on the workload-2 world (0: skip)")
+    ap.add_argument("--train-extras", type=int, default=1,
+                    help="time the fused losses and the Adam step on the "
+                         "workload-2 parameters (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-saturate", type=int, default=400,
@@ -271,6 +277,117 @@ def serve_run(dv, ctx, sc, opts, views, rate, batched, seed):
                 p99_ms=round(float(np.percentile(lat, 99)), 3),
                 requests=len(views),
                 offered_req_per_s=None if np.isinf(rate) else rate)
+
+
+def _timed(torch, fn, reps):
+    """Median wall time (ms) of fn over reps runs, each synchronised."""
+    ts, r = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return r, round(float(np.median(ts)) * 1e3, 3)
+
+
+def structure_bench(dv, ctx, reps=3):
+    """Background initialisation (Sec. 3.3) on the workload-2 world: the
+    LiDAR-like cloud, the 1.6 m inner grid plus far shell, proximity rounds
+    (ratio 0.5) until the finest leaf is below 0.3 m, the Eq. 1 prior
+    (s = 0.2 m, v_close = -2) on the result; then a prune (keep 90 %) and a
+    subdivision (5 % of the leaves) of the refined octree.  Each call is
+    timed whole (including its count readbacks and the copies into fresh
+    tensors); the oracle's proximity test is timed on a sample of leaves."""
+    import torch
+    from oracle import structure as ST
+    from synth.driving import init_workload
+    t0 = time.time()
+    o, pts = init_workload()
+    log(f"[bench] init workload: {len(o['level'])} leaves, {len(pts)} points "
+        f"({time.time() - t0:.1f}s)")
+    t, desc = dv.octree_tensors(o)
+    P = torch.from_numpy(np.ascontiguousarray(pts.T)).cuda()
+    dv.dv_refine(ctx, desc, P, 0.5, 0.3)                       # warm
+    (res, rounds), ms_refine = _timed(torch, lambda: dv.dv_refine(ctx, desc, P, 0.5, 0.3),
+                                      reps)
+    desc2 = dv.octree_desc(o, res)
+    n = int(res["level"].numel())
+    nc = int(res["corner_density"].numel())
+    _, ms_prior = _timed(torch, lambda: dv.dv_corner_prior(ctx, desc2, P, 0.2,
+                                                           v_close=-2.0), reps)
+    _, ms_prox = _timed(torch, lambda: dv.dv_proximity_flags(ctx, desc2, P, 0.5), reps)
+    rng = np.random.default_rng(0)
+    keep = torch.from_numpy((rng.uniform(size=n) < 0.9).astype(np.uint8)).cuda()
+    lv = res["level"].cpu().numpy()
+    split = torch.from_numpy(((rng.uniform(size=n) < 0.05) &
+                              (lv < o["max_level"])).astype(np.uint8)).cuda()
+    _, ms_prune = _timed(torch, lambda: dv.dv_edit(ctx, desc2, keep, dv.DV_EDIT_PRUNE),
+                         reps)
+    _, ms_sub = _timed(torch, lambda: dv.dv_edit(ctx, desc2, split,
+                                                 dv.DV_EDIT_SUBDIVIDE), reps)
+    # oracle: the proximity test of a leaf sample against every point
+    sample = rng.choice(len(o["level"]), 40, replace=False)
+    sub = dict(o, level=o["level"][sample], ijk=o["ijk"][:, sample])
+    t0 = time.time()
+    ST.proximity_flags(sub, pts, 0.5)
+    cpu_dt = time.time() - t0
+    del res, t, P
+    torch.cuda.synchronize()
+    return dict(
+        workload="driving-1M world: 3.46M LiDAR points, 1.6 m inner grid + far "
+                 "shell -> proximity rounds (ratio 0.5, until < 0.3 m), Eq. 1 "
+                 "prior (s 0.2 m)",
+        points=int(len(pts)), leaves_in=int(len(o["level"])), leaves_out=n,
+        corners_out=nc, rounds=int(rounds),
+        ms=dict(refine=ms_refine, corner_prior=ms_prior, proximity_flags=ms_prox,
+                prune=ms_prune, subdivide=ms_sub),
+        corner_prior_mqueries_per_s=round(nc / ms_prior / 1e3, 2),
+        cpu_oracle=dict(kind="oracle", proximity_leaves_per_s=round(40 / cpu_dt, 2),
+                        sample="40 leaves of the start grid against every point, "
+                               "1 process"))
+
+
+def train_extras(dv, ctx, step, reps=5):
+    """Fused losses (colour L1 + SSIM, sparse depth L1, sky transmittance;
+    Supp. training losses) on the step's 1080p outputs and one Adam step
+    over every corner density, SH coefficient and pose of the workload,
+    with the bytes each must move at least: the loss reads the rendered and
+    target planes and writes the gradient planes (56 B per pixel), Adam
+    reads p, g, m, v and writes p, m, v (28 B per element)."""
+    import torch
+    out, h, w = step.outs[0], step.views[0]["h"], step.views[0]["w"]
+    g = torch.Generator(device="cpu").manual_seed(7)
+    lidar = torch.rand(h, w, generator=g) * 60.0
+    lidar[torch.rand(h, w, generator=g) > 0.05] = 0.0
+    sky = (torch.rand(h, w, generator=g) < 0.1).float()
+    view = dict(rgb=out["rgb"], depth=out["depth"], T=out["T"],
+                rgb_gt=step.targets[0], depth_lidar=lidar.cuda(), sky_mask=sky.cuda(),
+                g_rgb=torch.empty(3, h, w, device="cuda"),
+                g_depth=torch.empty(h, w, device="cuda"),
+                g_T=torch.empty(h, w, device="cuda"))
+    wts = dict(color=1.0, ssim=0.2, depth=0.1, normal=0.0, sky=0.01)
+    dv.dv_loss(ctx, [view], wts)
+    _, ms_loss = _timed(torch, lambda: dv.dv_loss(ctx, [view], wts), reps)
+    params = []
+    for k, o in enumerate(step.sc.octs):
+        for name, gname in (("corner_density", "corner"), ("sh", "sh")):
+            p = o[name]
+            params.append(dict(p=p.view(-1), g=step.acc[k][gname].view(-1),
+                               m=torch.zeros(p.numel(), device="cuda"),
+                               v=torch.zeros(p.numel(), device="cuda")))
+    n_el = sum(q["p"].numel() for q in params)
+    dv.dv_adam(ctx, params, lr=0.0, step=1)
+    _, ms_adam = _timed(torch, lambda: dv.dv_adam(ctx, params, lr=0.0, step=1), reps)
+    return dict(loss=dict(pixels=h * w, ms=ms_loss,
+                          min_bytes=56 * h * w,
+                          achieved_GBs=round(56 * h * w / ms_loss / 1e6, 1)),
+                adam=dict(elements=int(n_el), tensors=len(params), ms=ms_adam,
+                          min_bytes=28 * n_el,
+                          achieved_GBs=round(28 * n_el / ms_adam / 1e6, 1),
+                          frac_hbm=round(28 * n_el / ms_adam / 1e6 / PEAK_HBM_GBS, 4)),
+                note="lr = 0 so the parameters stay as rendered; the wall time "
+                     "includes the launch and its synchronisation")
 
 
 KERNEL_OF_STAGE = {"composite_fwd": "dv::k_composite_fwd", "composite_bwd": "dv::k_composite_bwd",
@@ -505,6 +622,9 @@ def main():
             r["sky"] = {"map": [3, H, W], "ms_per_step": round(sms, 4),
                         "ms_per_step_constant_bg": r["ms_per_step"]}
             del sstep
+        if k == 2 and args.train_extras:
+            r["train_extras"] = train_extras(dv, ctx, st)
+            log(f"[bench] losses / Adam: {r['train_extras']}")
         if k == 2:
             c2 = (c, st.sc)
         else:
@@ -515,6 +635,11 @@ def main():
         dv.dv_ctx_trim(ctx)
     if extra:
         out["other_workloads"] = extra
+    if args.structure:
+        out["structure"] = structure_bench(dv, ctx)
+        log(f"[bench] structure: {out['structure']}")
+        torch.cuda.synchronize()
+        dv.dv_ctx_trim(ctx)
     if args.serve_requests > 0:
         if c2 is None:
             c = make_config(4, v_close=args.v_close)

@@ -339,8 +339,9 @@ def make_driving_config(k, seed, v_close=10.0, scale=1.0, n_cars=None,
     """Workload k in {2, 3, 4, 5}.  ``scale`` shrinks leaf budgets (tests)."""
     spec = SPECS[k]
     rng = np.random.default_rng(seed)
-    bg, info, _ = background_octree(rng, int(spec["bg"] * scale), v_close,
-                                    top=spec["top"])
+    bg, info, pts = background_octree(rng, int(spec["bg"] * scale), v_close,
+                                      top=spec["top"])
+    info = dict(info, points=pts)
     nc = spec["cars"] if n_cars is None else n_cars
     cv = int((spec["car_vox"] if car_vox is None else car_vox) * min(1.0, scale * 4))
     octs = [bg]
@@ -367,3 +368,21 @@ def make_driving_config(k, seed, v_close=10.0, scale=1.0, n_cars=None,
     return dict(name=names[k], scene=dict(octrees=octs, tracks=tracks),
                 views=views, opts=opts, info=dict(info, n_total=n_total,
                                                   v_close=v_close))
+
+
+def init_workload(seed=2, top=12, sweep_step=4.0, n_buildings=40, deg=3):
+    """Inputs of the background initialisation (Sec. 3.3): the LiDAR-like
+    point cloud of the workload-2 world and the starting grid before the
+    proximity rounds, i.e. uniform 1.6 m cells over the inner region plus
+    the coarse far shell, every corner at v_far, random SH.  Returns
+    (octree dict, points [n, 3] FP64)."""
+    rng = np.random.default_rng(seed)
+    blds = make_buildings(rng, n_buildings)
+    pts = lidar_points(rng, blds, step=sweep_step)
+    parts = [(9, _cells_box(INNER_LO, INNER_HI, 9))] + far_shell()
+    lv = np.concatenate([np.full(len(c), l, np.uint8) for l, c in parts])
+    ijk = np.concatenate([c for _, c in parts], 0).T.astype(np.int32)
+    cidx, upos = dedup_corners(lv, ijk, top)
+    dens = np.full(upos.shape[0], V_FAR, np.float32)
+    sh = _sh_random(rng, lv.shape[0], deg)
+    return make_octree(ROOT_MIN, ROOT_SIZE, top, lv, ijk, cidx, dens, sh), pts
