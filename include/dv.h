@@ -426,7 +426,9 @@ typedef struct {
 } dv_adam_param;
 
 typedef struct {
-  float lr, beta1, beta2, eps;
+  double lr, beta1, beta2, eps; /* b1, 1 - b1, b2, 1 - b2 and the bias     */
+                                /* corrections are formed in double, then  */
+                                /* rounded to FP32 for the update          */
   int32_t step;                 /* >= 1 (bias correction)                  */
 } dv_adam_opts;
 
@@ -541,8 +543,12 @@ void dv_edit_release(dv_edit* edit);
 typedef struct {
   int32_t max_inflight;         /* requests admitted at once (slots)       */
   int64_t mem_budget;           /* device bytes for in-flight requests     */
-  int32_t batched;              /* 1: continuous batching, 0: one launch
-                                   per request in FIFO order               */
+  int32_t batched;              /* 1: continuous batching (up to max_batch
+                                   queued requests per multi-view launch,
+                                   two launches in flight), 0: one launch
+                                   per request in FIFO order (same two
+                                   streams), 2: persistent drain kernel,
+                                   refused (DV_ERR_INVALID) in this build  */
   int32_t max_batch;            /* requests per batched launch             */
   dv_render_opts opts;
 } dv_serve_opts;
@@ -561,9 +567,9 @@ typedef struct {
 } dv_result;
 
 /* Start a serving loop on `scene` (kept resident; the scene must outlive
- * the server).  A scheduler thread admits queued requests while slots and
- * memory allow, renders them in batched launches that overlap on the
- * device, and marks them done.  Errors: DV_ERR_INVALID, DV_ERR_OOM. */
+ * the server).  Two worker threads admit queued requests while slots and
+ * memory allow, render them in batched launches that overlap on the
+ * device, and mark them done.  Errors: DV_ERR_INVALID, DV_ERR_OOM. */
 dv_status dv_serve_create(dv_ctx* ctx, const dv_scene* scene,
                           const dv_serve_opts* opts, dv_server** out);
 /* Queue a request (thread-safe); *ticket identifies it.  A malformed

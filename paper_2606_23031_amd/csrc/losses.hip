@@ -332,8 +332,8 @@ struct AdamTensor {
 };
 
 __global__ void __launch_bounds__(TPB)
-k_adam(const AdamTensor* __restrict__ ts, int nt, float lr, float b1, float b2,
-       float eps, float c1, float c2) {
+k_adam(const AdamTensor* __restrict__ ts, int nt, float lr, float b1, float omb1,
+       float b2, float omb2, float eps, float c1, float c2) {
   int lo = 0, hi = nt - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -346,8 +346,8 @@ k_adam(const AdamTensor* __restrict__ ts, int nt, float lr, float b1, float b2,
     const int64_t i = base + (int64_t)j * TPB + threadIdx.x;
     if (i >= T.n) break;
     const float g = T.g[i];
-    const float m = fmaf(b1, T.m[i], (1.0f - b1) * g);
-    const float v = fmaf(b2, T.v[i], (1.0f - b2) * g * g);
+    const float m = fmaf(b1, T.m[i], omb1 * g);
+    const float v = fmaf(b2, T.v[i], omb2 * g * g);
     T.m[i] = m;
     T.v[i] = v;
     T.p[i] -= lr * (m * c1) / (sqrtf(v * c2) + eps);
@@ -432,8 +432,8 @@ dv_status dv_loss(dv_ctx* ctx, const dv_loss_view* views, int32_t n_views,
 dv_status dv_adam(dv_ctx* ctx, const dv_adam_param* params, int32_t n_params,
                   const dv_adam_opts* opts, void* stream) {
   if (!ctx || !params || n_params < 1 || !opts || opts->step < 1 ||
-      !(opts->lr >= 0.0f) || !(opts->beta1 >= 0.0f && opts->beta1 < 1.0f) ||
-      !(opts->beta2 >= 0.0f && opts->beta2 < 1.0f) || !(opts->eps > 0.0f)) {
+      !(opts->lr >= 0.0) || !(opts->beta1 >= 0.0 && opts->beta1 < 1.0) ||
+      !(opts->beta2 >= 0.0 && opts->beta2 < 1.0) || !(opts->eps > 0.0)) {
     set_error("dv_adam: invalid arguments");
     return DV_ERR_INVALID;
   }
@@ -465,11 +465,15 @@ dv_status dv_adam(dv_ctx* ctx, const dv_adam_param* params, int32_t n_params,
   std::memcpy(stage, ts.data(), bytes);
   DV_TRY_HIP(hipMemcpyAsync(tab.p, stage, bytes, hipMemcpyHostToDevice, s));
   DV_TRY(stage_release(s));
-  const double c1 = 1.0 / (1.0 - std::pow((double)opts->beta1, opts->step));
-  const double c2 = 1.0 / (1.0 - std::pow((double)opts->beta2, opts->step));
+  // the constants are formed in double and rounded once: 1 - b in FP32
+  // from a rounded b (0.999f) would be off by 5e-5 relative
+  const double c1 = 1.0 / (1.0 - std::pow(opts->beta1, opts->step));
+  const double c2 = 1.0 / (1.0 - std::pow(opts->beta2, opts->step));
   hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(TPB), 0, s,
-                     tab.as<AdamTensor>(), (int)ts.size(), opts->lr, opts->beta1,
-                     opts->beta2, opts->eps, (float)c1, (float)c2);
+                     tab.as<AdamTensor>(), (int)ts.size(), (float)opts->lr,
+                     (float)opts->beta1, (float)(1.0 - opts->beta1),
+                     (float)opts->beta2, (float)(1.0 - opts->beta2),
+                     (float)opts->eps, (float)c1, (float)c2);
   DV_TRY_HIP(hipGetLastError());
   return DV_OK;
 }

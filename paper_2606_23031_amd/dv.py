@@ -167,8 +167,8 @@ class dv_edit_out(C.Structure):
 
 
 class dv_adam_opts(C.Structure):
-    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
-                ("eps", C.c_float), ("step", C.c_int32)]
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("step", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -669,8 +669,10 @@ def dv_fwd_state_export_lists(state, view, n_tiles, capacity, actor_capacity=0):
 # ------------------------------------------------------------------ serving
 def dv_serve_create(ctx, scene, opts, max_inflight=8, mem_budget=8 << 30,
                     batched=True, max_batch=8):
-    so = dv_serve_opts(max_inflight, mem_budget, 1 if batched else 0,
-                       max_batch, opts)
+    """batched: True / 1 continuous batching, False / 0 one launch per
+    request, 2 the persistent drain (refused by this build)."""
+    mode = (1 if batched else 0) if isinstance(batched, bool) else int(batched)
+    so = dv_serve_opts(max_inflight, mem_budget, mode, max_batch, opts)
     h = C.c_void_p()
     _check(_lib.dv_serve_create(ctx, scene.handle, C.byref(so), C.byref(h)),
            "dv_serve_create")
