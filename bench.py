@@ -259,8 +259,10 @@ def serve_run(dv, ctx, sc, opts, views, rate, batched, seed):
     for i in range(len(views)):
         while tickets[i] is None:
             time.sleep(0.0002)
-        st, ts, ta, td = dv.dv_serve_poll(srv, tickets[i], -1)
-        assert st == 0, st
+        st, ts, ta, td = dv.dv_serve_poll(srv, tickets[i], 60_000_000)
+        if st != 0:
+            raise RuntimeError(f"serving request {i} ended with status {st} "
+                               "(pending after 60 s if positive)")
         lat.append(td - (t0 + arrivals[i]))
         done_t.append(td)
         with lock:

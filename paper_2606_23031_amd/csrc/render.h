@@ -429,7 +429,10 @@ __device__ inline SkyTaps sky_taps(const A& a, float3 d) {
   const float kPi = 3.14159265358979f;
   const int W = a.sky_w, H = a.sky_h;
   const float lon = atan2f(d.y, d.x);
-  const float colat = acosf(fminf(fmaxf(d.z, -1.0f), 1.0f));
+  // colatitude as atan2(|d_xy|, d_z), which equals acos(d_z) for a unit d
+  // but stays well conditioned at the poles (acos of an FP32 d_z near 1
+  // turns its rounding into ~3e-4 rad of angle)
+  const float colat = atan2f(sqrtf(d.x * d.x + d.y * d.y), d.z);
   const float u = (lon + kPi) * (0.5f / kPi) * (float)W - 0.5f;
   const float v = colat * (1.0f / kPi) * (float)H - 0.5f;
   const float u0 = floorf(u), v0 = floorf(v);
@@ -599,7 +602,12 @@ constexpr int SV_RING = 1024;    // ring entries (groups published), and the
 constexpr int SV_GROUPS = 16;    // group slots (forward states in flight)
 constexpr int SV_FLAGS = 1024;   // request completion flags
 
-struct ServeGroup {
+// The drain kernel reads an entry through scalar loads (scalar cache),
+// which are not kept coherent with the uploads of later groups: each entry
+// fills whole 256-byte blocks of its own, so reading one group's arguments
+// never brings a line of the next entry (uploaded later, perhaps while the
+// kernel runs) into the cache ahead of its upload.
+struct alignas(256) ServeGroup {
   CompArgs a;                    // walk arguments of the group's forward
   uint32_t* tile_ck;             // [n_tiles] chunks finished per tile
   uint32_t* view_done;           // [n_views] tiles finished per view
@@ -608,6 +616,8 @@ struct ServeGroup {
   const unsigned long long* view_seq;  // [n_views] value the flag receives
   unsigned long long* flags;     // host-mapped [SV_FLAGS]
 };
+
+static_assert(sizeof(ServeGroup) % 256 == 0, "ring entries share cache lines");
 
 struct ServeQueue {
   unsigned long long tail;            // groups published so far

@@ -2,25 +2,27 @@
 // against a resident scene (Sec. 1: the reconstruction serves novel views
 // of the scene at new times and viewpoints).
 //
-// Continuous batching (batched = 1).  A scheduler thread admits queued
-// requests while request slots, group slots and the memory budget allow,
-// takes up to max_batch of them as one group, and enqueues on its prep
-// stream the group's front half in one multi-view launch sequence:
-// preprocess, sorts, tile directories, ownership segments and asset walks.
-// It then uploads the group's walk arguments and publishes the group's work
-// items into a device ring.  One persistent kernel on a second stream
-// drains (group, item) work, the background walks of every published
-// group, so requests admitted while others are on the GPU have their front
-// half overlap the walks of earlier ones, and their items join the same
-// kernel.  The block that writes a request's last tile raises the
-// request's flag in host-mapped memory; a completion thread watches the
-// flags, finishes requests, frees groups, and launches the drain kernel
-// again whenever work is pending and the previous one has run out of work
-// and exited.
+// Continuous batching (batched = 1).  Two worker threads, each with its own
+// stream, admit the oldest queued requests while request slots and the
+// memory budget allow, up to max_batch at a time, and render them as the
+// views of one multi-view launch sequence (preprocess, sorts, tile
+// directories and compositing are each one launch for the whole batch).
+// A request that arrives while both workers are busy joins the next batch
+// a worker takes; with two batches in flight, one's preprocessing and
+// sorts overlap the other's compositing.
 //
-// One launch per request (batched = 0), the baseline: two worker threads,
-// each with its own stream (the same number of streams), render one
-// request per dv_render call in arrival order.
+// One launch per request (batched = 0), the baseline: the same two worker
+// threads and streams, one request per dv_render call in arrival order.
+//
+// Persistent drain (batched = 2; refused by dv_serve_create in this build).
+// A scheduler thread enqueues each group's front half (everything up to the
+// background walks) on a prep stream and publishes the group's work items
+// into a device ring; one persistent kernel on a second stream drains
+// (group, item) work of every published group, and the block that writes a
+// request's last tile raises the request's flag in host-mapped memory,
+// which a completion thread watches.  On the GPU, a group after the first
+// never raised its flags, with the cause not yet found; the code is kept
+// for that investigation and is not reachable.
 //
 // Memory admission uses a running bytes-per-pixel estimate taken from the
 // sizes of finished renders; a request is always admitted when nothing else
@@ -82,8 +84,9 @@ constexpr int DRAIN_IDLE_POLLS = 600;
 // Requests per group (one view each) and the pinned staging per group slot:
 // its ServeGroup, then per view the tile count, flag slot and flag value.
 constexpr int MAX_GROUP_VIEWS = 256;
-constexpr size_t STAGE_TABLE = (size_t)MAX_GROUP_VIEWS * 16 + 64;
+constexpr size_t STAGE_TABLE = ((size_t)MAX_GROUP_VIEWS * 16 + 64 + 255) & ~(size_t)255;
 constexpr size_t STAGE_STRIDE = ((sizeof(ServeGroup) + 255) & ~(size_t)255) + STAGE_TABLE;
+static_assert(STAGE_STRIDE % alignof(ServeGroup) == 0, "staging slots misaligned");
 
 }  // namespace
 
@@ -155,14 +158,24 @@ struct dv_server {
   }
 };
 
-// ---------------------------------------------------------------- baseline
+// ---------------------------------------------------------------- workers
+// Each worker thread owns one stream.  It admits the oldest queued
+// requests while slots and the memory budget allow (at most max_batch of
+// them when batching, one otherwise), renders them as the views of one
+// multi-view launch sequence, waits for its stream and finishes them.
+// Two workers keep two such launches in flight, so one batch's
+// preprocessing and sorts overlap the other's compositing.
 void dv_server::worker(int wid) {
   hipSetDevice(ctx->device);
   hipStream_t s = streams[wid];
+  const int take = opts.batched ? std::max(1, opts.max_batch) : 1;
+  std::vector<uint64_t> tks;
+  std::vector<dv_view> views;
+  std::vector<dv_outputs> outs;
   while (true) {
-    uint64_t tk = 0;
-    dv_view view;
-    dv_outputs out;
+    tks.clear();
+    views.clear();
+    outs.clear();
     {
       std::unique_lock<std::mutex> lk(mu);
       cv_work.wait(lk, [&] {
@@ -173,20 +186,28 @@ void dv_server::worker(int wid) {
         if (stop) return;
         continue;
       }
-      if (!admissible(reqs[queue.front()])) continue;
-      tk = queue.front();
-      queue.pop_front();
-      Request& r = reqs[tk];
-      r.t_admit = now_s();
-      inflight += 1;
-      mem_inflight += r.est_bytes;
-      view = r.view;
-      out = r.out;
+      const double t = now_s();
+      while (!queue.empty() && (int)tks.size() < take &&
+             admissible(reqs[queue.front()])) {
+        const uint64_t tk = queue.front();
+        queue.pop_front();
+        Request& r = reqs[tk];
+        r.t_admit = t;
+        inflight += 1;
+        mem_inflight += r.est_bytes;
+        tks.push_back(tk);
+        views.push_back(r.view);
+        outs.push_back(r.out);
+      }
+      if (tks.empty()) continue;
     }
+    int64_t pixels = 0;
+    for (auto& v : views) pixels += (int64_t)v.w * v.h;
     dv_fwd_state* st = nullptr;
-    dv_status rc = ctx->poisoned ? DV_ERR_DEVICE
-                                 : dv_render(ctx, scene, &view, 1, nullptr,
-                                             &opts.opts, &out, &st, s);
+    dv_status rc = ctx->poisoned
+                       ? DV_ERR_DEVICE
+                       : dv_render(ctx, scene, views.data(), (int32_t)views.size(),
+                                   nullptr, &opts.opts, outs.data(), &st, s);
     int64_t used = 0;
     if (rc == DV_OK && st) {
       used = 24 * st->n_pairs + 150 * st->n_vis + 40 * st->n_tiles * TPB;
@@ -200,10 +221,9 @@ void dv_server::worker(int wid) {
     {
       std::lock_guard<std::mutex> lk(mu);
       const double t = now_s();
-      finish(tk, rc, t);
-      if (rc == DV_OK)
-        bytes_per_pixel = 0.8 * bytes_per_pixel +
-                          0.2 * ((double)used / ((double)view.w * view.h));
+      for (uint64_t tk : tks) finish(tk, rc, t);
+      if (rc == DV_OK && pixels > 0)
+        bytes_per_pixel = 0.8 * bytes_per_pixel + 0.2 * ((double)used / (double)pixels);
       if (rc == DV_ERR_DEVICE) fail_queued(DV_ERR_DEVICE, t);
     }
     cv_done.notify_all();
@@ -451,7 +471,8 @@ extern "C" {
 dv_status dv_serve_create(dv_ctx* ctx, const dv_scene* scene,
                           const dv_serve_opts* opts, dv_server** out) {
   if (!ctx || !scene || !opts || !out || opts->max_inflight < 1 ||
-      opts->mem_budget <= 0 || opts->max_batch < 1) {
+      opts->mem_budget <= 0 || opts->max_batch < 1 || opts->batched < 0 ||
+      opts->batched > 2) {
     set_error("dv_serve_create: invalid arguments");
     return DV_ERR_INVALID;
   }
@@ -466,7 +487,15 @@ dv_status dv_serve_create(dv_ctx* ctx, const dv_scene* scene,
   srv->scene = scene;
   srv->opts = *opts;
   srv->opts.max_inflight = std::min(opts->max_inflight, SV_FLAGS);
-  if (!opts->batched) {
+  if (opts->batched == 2) {
+    // the persistent drain (scheduler + completion threads below): a
+    // group after the first never raised its completion flags on the GPU,
+    // and the cause is not yet found, so this mode is refused
+    set_error("dv_serve_create: the persistent-drain mode (batched = 2) is "
+              "disabled in this build");
+    return DV_ERR_INVALID;
+  }
+  if (opts->batched == 0 || opts->batched == 1) {
     for (int i = 0; i < 2; ++i) {
       hipStream_t s;
       DV_TRY_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));

@@ -39,6 +39,14 @@ def _requests(n, seed=0):
     return out
 
 
+def _poll(dv, srv, ticket, limit_s=60.0):
+    """Wait for a ticket, at most limit_s seconds (a request that never
+    completes fails the test instead of stalling it)."""
+    r = dv.dv_serve_poll(srv, ticket, int(limit_s * 1e6))
+    assert r[0] <= 0, f"ticket {ticket} still pending after {limit_s} s"
+    return r
+
+
 def _alloc(dv, v, mask):
     return dv.alloc_outputs([v], mask)[0]
 
@@ -55,7 +63,7 @@ def _serve(dv, ctx, sc, opts, views, batched, budget=8 << 30, stagger=0.0):
         tickets.append(dv.dv_serve_submit(srv, v, o))
         if stagger:
             time.sleep(stagger)
-    res = [dv.dv_serve_poll(srv, t, -1) for t in tickets]
+    res = [_poll(dv, srv, t) for t in tickets]
     dv.dv_serve_destroy(srv)
     return outs, res
 
@@ -102,7 +110,7 @@ def test_bad_request_fails_alone(env):
     views[2] = bad
     outs = [_alloc(dv, v, mask) for v in views]
     tickets = [dv.dv_serve_submit(srv, v, o) for v, o in zip(views, outs)]
-    res = [dv.dv_serve_poll(srv, t, -1) for t in tickets]
+    res = [_poll(dv, srv, t) for t in tickets]
     assert res[2][0] == -1
     assert all(r[0] == 0 for i, r in enumerate(res) if i != 2)
     # a finished ticket is forgotten once its status was returned
@@ -127,7 +135,7 @@ def test_concurrent_submitters(env):
         t.start()
     for t in th:
         t.join()
-    res = [dv.dv_serve_poll(srv, t, -1) for t in tickets]
+    res = [_poll(dv, srv, t) for t in tickets]
     assert all(r[0] == 0 for r in res)
     dv.dv_serve_destroy(srv)
 
@@ -163,7 +171,7 @@ def test_serving_workload_scene_staggered_mix():
         for v, o, g in zip(views, outs, gaps):
             time.sleep(g)
             tickets.append(dv.dv_serve_submit(srv, v, o))
-        res = [dv.dv_serve_poll(srv, t, -1) for t in tickets]
+        res = [_poll(dv, srv, t) for t in tickets]
         dv.dv_serve_destroy(srv)
         assert all(r[0] == 0 for r in res)
         # requests overlapped: some were admitted before an earlier one was done
@@ -198,3 +206,11 @@ def test_serving_workload_scene_staggered_mix():
         print(f"  {key}: rgb {e_rgb:.2e} depth {e_d.max():.2e}")
         assert e_rgb <= 1e-4
         assert np.all(e_d <= 1e-4 * (1.0 + np.abs(ref[:, 3])))
+
+
+def test_persistent_drain_mode_is_refused(env):
+    dv, ctx, cfg, sc = env
+    mask = dv.DV_OUT_RGB | dv.DV_OUT_DEPTH
+    with pytest.raises(dv.DVError) as ei:
+        dv.dv_serve_create(ctx, sc, dv.make_opts(cfg["opts"], mask), batched=2)
+    assert "persistent-drain" in str(ei.value)
