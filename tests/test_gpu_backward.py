@@ -31,7 +31,7 @@ def ctx():
 SUMMAND_ULPS = 2.0 ** -20
 
 
-def _close(name, g, ref, rel=1e-3, floor=1e-2, summed=None):
+def _close(name, g, ref, rel=1e-3, floor=1e-2, summed=None, extra=None):
     g = np.asarray(g, np.float64)
     ref = np.asarray(ref, np.float64)
     scale = np.abs(ref).max()
@@ -41,6 +41,8 @@ def _close(name, g, ref, rel=1e-3, floor=1e-2, summed=None):
     bound = rel * np.maximum(np.abs(ref), floor * scale)
     if summed is not None:
         bound = bound + SUMMAND_ULPS * np.asarray(summed, np.float64)
+    if extra is not None:
+        bound = bound + np.asarray(extra, np.float64)
     err = np.abs(g - ref)
     worst = float((err / bound).max())
     print(f"  {name}: max|ref| {scale:.3e} worst err/bound {worst:.3f}")
