@@ -163,7 +163,10 @@ def refine(o, points, ratio, min_size, max_rounds=32):
     """Proximity subdivision rounds until the finest leaf is smaller than
     min_size (or no leaf is flagged, or max_rounds).  The result is in
     canonical order even after no round; leaf_src and corner_src refer to
-    the input octree."""
+    the input octree.  Each round is one subdivision edit of the stored
+    octree, whose corner densities are FP32 parameters: a round
+    interpolates (in FP64) from the previous round's values as stored,
+    i.e. rounded to float32."""
     # the input in canonical corner order (an all-keep prune)
     cur = prune(o, np.ones(len(o["level"]), bool))
     leaf_src = cur["leaf_src"]
@@ -178,6 +181,8 @@ def refine(o, points, ratio, min_size, max_rounds=32):
         if not flags.any():
             break
         nxt = subdivide(cur, flags)
+        nxt["corner_density"] = np.asarray(nxt["corner_density"],
+                                           np.float32).astype(np.float64)
         leaf_src = leaf_src[nxt["leaf_src"]]
         cs = nxt["corner_src"]
         corner_src = np.where(cs >= 0, corner_src[np.maximum(cs, 0)], -1)

@@ -194,9 +194,13 @@ def test_refine_rounds_reach_the_minimum_size_near_points():
     lo0, hi0, _ = ST.leaf_boxes(o)
     src = r["leaf_src"]
     assert np.all(lo >= lo0[src] - 1e-15) and np.all(hi <= hi0[src] + 1e-15)
+    # each round stores its densities as float32 (half an ulp each) and the
+    # next interpolates them with convex weights, so the field moves by at
+    # most rounds * 2^-24 * max|g|
+    tol = r["rounds"] * 2.0 ** -24 * np.abs(o["corner_density"]).max()
     for _ in range(40):
         x = rng.uniform(-0.98, 0.98, 3)
-        assert abs(ST.field_at(r, x) - ST.field_at(o, x)) < 1e-12
+        assert abs(ST.field_at(r, x) - ST.field_at(o, x)) <= tol
     # corner sources refer to the input table
     old_w = ST.corner_world_positions(o)
     new_w = ST.corner_world_positions(r)
