@@ -254,7 +254,24 @@ def _box_distance(p, half):
     return np.linalg.norm(np.maximum(q, 0.0), axis=-1)
 
 
+_CAR_CACHE = {}
+
+
 def car_octree(rng, target, v_close, base=4, top=6):
+    """A car octree: structure and corner densities depend only on the leaf
+    budget and v_close (built once per pair and copied), the SH coefficients
+    are drawn from rng per car."""
+    key = (int(target), float(v_close), base, top)
+    if key not in _CAR_CACHE:
+        _CAR_CACHE.clear()
+        _CAR_CACHE[key] = _car_structure(target, v_close, base, top)
+    rmin, side, lv, ijk, cidx, dens = _CAR_CACHE[key]
+    sh = _sh_random(rng, lv.shape[0], 3)
+    return make_octree(rmin, side, top, lv.copy(), ijk.copy(), cidx.copy(),
+                       dens.copy(), sh)
+
+
+def _car_structure(target, v_close, base, top):
     side = 1.2 * CAR.max()
     rmin = -side / 2 * np.ones(3)
     half = CAR / 2
@@ -298,8 +315,8 @@ def car_octree(rng, target, v_close, base=4, top=6):
     d = _box_distance(cpos, half)
     s_min = side / (1 << top)
     dens = soft_prior(d, s_min, v_close).astype(np.float32)
-    sh = _sh_random(rng, lv.shape[0], 3)
-    return make_octree(rmin, side, top, lv, ijk, cidx, dens, sh)
+    return (rmin, side, np.ascontiguousarray(lv), np.ascontiguousarray(ijk),
+            np.ascontiguousarray(cidx), np.ascontiguousarray(dens))
 
 
 def car_tracks(rng, n, t_end=10.0, lane_ys=(-4.0, 4.0), x_start=-30.0,

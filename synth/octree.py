@@ -69,12 +69,22 @@ def corner_positions(level, ijk, max_level):
 def dedup_corners(level, ijk, max_level):
     """Shared-corner table: corner_idx i32[8,N] and the unique integer
     positions int64[Nc,3] (finest grid) in first-appearance-sorted order."""
-    pos = corner_positions(level, ijk, max_level)  # [8,3,N]
-    n = pos.shape[2]
-    flat = pos.transpose(0, 2, 1).reshape(-1, 3)  # [8N,3], m-major
+    lv = np.asarray(level, np.int64)
+    c = np.asarray(ijk, np.int64)
+    n = lv.shape[0]
+    sh = max_level - lv
     side = (1 << max_level) + 1
-    key = (flat[:, 0] * side + flat[:, 1]) * side + flat[:, 2]
-    uniq, inv = np.unique(key, return_inverse=True)
+    # corner m of a leaf sits at ((ijk + (mx, my, mz)) << (max_level - l));
+    # key = (x * side + y) * side + z, built per axis without the [8,3,N]
+    # position array
+    ax = [[(c[a] + o) << sh for o in (0, 1)] for a in range(3)]
+    key = np.empty((8, n), np.int64)
+    for m in range(8):
+        np.multiply(ax[0][m & 1], side, out=key[m])
+        key[m] += ax[1][(m >> 1) & 1]
+        key[m] *= side
+        key[m] += ax[2][(m >> 2) & 1]
+    uniq, inv = np.unique(key.reshape(-1), return_inverse=True)
     cidx = inv.reshape(8, n).astype(np.int32)
     upos = np.stack([uniq // (side * side), (uniq // side) % side,
                      uniq % side], -1)
