@@ -509,7 +509,9 @@ dv_status dv_edit_plan(dv_ctx* ctx, const dv_octree_desc* octree,
  * within ratio * h of a point; stop early when a round splits none or
  * after max_rounds.  The corner table is canonical (as dv_edit_plan's) even
  * after zero rounds.  Sources and densities as dv_edit_plan's, relative to
- * the input.  *rounds receives the rounds done. */
+ * the input; each round interpolates the previous round's densities as
+ * stored (float), as a sequence of dv_edit_plan calls would.  *rounds
+ * receives the rounds done. */
 dv_status dv_refine_plan(dv_ctx* ctx, const dv_octree_desc* octree,
                          const double* points, int64_t n_points, double ratio,
                          double min_size, int32_t max_rounds, dv_edit** out,
