@@ -266,7 +266,14 @@ typedef struct {
   int64_t pieces_actor_fwd;
   int64_t entries_actor_bwd;
   int64_t pieces_actor_bwd;
+  int64_t wave_entries_fwd;     /* list entries walked by a wave in the
+                                   background walk's straight-line
+                                   iteration, forward                      */
+  int64_t wave_hits_fwd;        /* those where some lane had a chord       */
+  int64_t wave_entries_bwd;     /* same, backward re-walk                  */
+  int64_t wave_hits_bwd;
 } dv_stage_times;
+#define DV_NUM_COUNTERS 12
 dv_status dv_ctx_set_profiling(dv_ctx* ctx, int32_t flags);
 dv_status dv_ctx_stage_times(dv_ctx* ctx, dv_stage_times* out, int32_t reset);
 /* Name of stage i (0 <= i < DV_NUM_STAGES), e.g. "composite_fwd". */

@@ -479,6 +479,7 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
   const float invK = 1.0f / (float)K;
   uint32_t n_test = 0, n_piece = 0;
   uint32_t w_test = 0, w_piece = 0;  // wave-level counts (plain walk)
+  uint32_t w_iter = 0, w_hit = 0;
   // upstream gradients scaled by the transmittance T_pre in front of the
   // chunk (1 for a tile of one chunk), so that
   //   dL/dtau_i = T_pre (T_{i+1} v_i - S_{i+1}) - S_after
@@ -583,7 +584,7 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
     load_bwd_batch<NORMALS>(B, a, base, nb);
     __syncthreads();
     uint64_t wm[4];
-    wave_entry_masks(B.rect, nb, bx, by, wm);
+    wave_live_masks(B.rect, nb, bx, by, __ballot(live()), wm);
     for (int c = 0; c < 4; ++c) {
       uint64_t m = wm[c];
       if (!wseg) {
@@ -596,6 +597,7 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
           const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
           m &= m - 1;
           w_test += (uint32_t)__popcll(lm);
+          ++w_iter;
           const float4 geo = B.geo[r];
           float t0, t1;
           batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
@@ -603,6 +605,7 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
           const bool hit = live() && t1 > t0;
           const uint64_t hm = __ballot(hit);
           if (hm == 0) continue;
+          ++w_hit;
           w_piece += (uint32_t)__popcll(hm);
           const float pa = hit ? t0 : 0.0f, pb = hit ? t1 : 0.0f;
           PieceDer pd;
@@ -632,8 +635,10 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
         const bool plain = !chord || (excl <= t0 && ns >= t1);
         if (__ballot(!plain) == 0) {
           w_test += (uint32_t)__popcll(lm);
+          ++w_iter;
           const uint64_t hm = __ballot(chord);
           if (hm == 0) continue;
+          ++w_hit;
           w_piece += (uint32_t)__popcll(hm);
           const float pa = chord ? t0 : 0.0f, pb = chord ? t1 : 0.0f;
           PieceDer pd;
@@ -706,6 +711,7 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
     n_piece += w_piece;
   }
   count_work(a.counters, 2, n_test, n_piece);
+  count_waves(a.counters, 10, w_iter, w_hit);
 }
 
 // Segments of actor j on the ray of this lane: count, first and last.
@@ -937,7 +943,7 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
       load_bwd_batch<NORMALS>(B, a, base, nb);
       __syncthreads();
       uint64_t wm[4];
-      wave_entry_masks(B.rect, nb, bx, by, wm);
+      wave_live_masks(B.rect, nb, bx, by, __ballot(live()), wm);
       for (int wc = 0; wc < 4; ++wc) {
       uint64_t m = wm[wc];
       if (single) {

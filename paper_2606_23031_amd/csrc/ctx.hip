@@ -327,9 +327,9 @@ dv_status dv_ctx_set_profiling(dv_ctx* ctx, int32_t flags) {
   if (!ctx) return DV_ERR_INVALID;
   DV_TRY_HIP(hipSetDevice(ctx->device));
   if ((flags & DV_PROFILE_COUNTERS) && !ctx->counters) {
-    DV_TRY(alloc_n<unsigned long long>(ctx, ctx->counters_buf, 8, nullptr));
+    DV_TRY(alloc_n<unsigned long long>(ctx, ctx->counters_buf, DV_NUM_COUNTERS, nullptr));
     ctx->counters = ctx->counters_buf.as<unsigned long long>();
-    DV_TRY_HIP(hipMemset(ctx->counters, 0, 8 * sizeof(unsigned long long)));
+    DV_TRY_HIP(hipMemset(ctx->counters, 0, DV_NUM_COUNTERS * sizeof(unsigned long long)));
     DV_TRY_HIP(hipDeviceSynchronize());
   }
   ctx->prof_flags = flags;
@@ -356,7 +356,7 @@ dv_status dv_ctx_stage_times(dv_ctx* ctx, dv_stage_times* out, int32_t reset) {
     out->calls[i] = ctx->prof_calls[i];
   }
   if (ctx->counters) {
-    unsigned long long c[8];
+    unsigned long long c[DV_NUM_COUNTERS];
     DV_TRY_HIP(hipDeviceSynchronize());
     DV_TRY_HIP(hipMemcpy(c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost));
     out->entries_fwd = (int64_t)c[0];
@@ -367,6 +367,10 @@ dv_status dv_ctx_stage_times(dv_ctx* ctx, dv_stage_times* out, int32_t reset) {
     out->pieces_actor_fwd = (int64_t)c[5];
     out->entries_actor_bwd = (int64_t)c[6];
     out->pieces_actor_bwd = (int64_t)c[7];
+    out->wave_entries_fwd = (int64_t)c[8];
+    out->wave_hits_fwd = (int64_t)c[9];
+    out->wave_entries_bwd = (int64_t)c[10];
+    out->wave_hits_bwd = (int64_t)c[11];
     if (reset) DV_TRY_HIP(hipMemset(ctx->counters, 0, sizeof(c)));
   }
   if (reset) {

@@ -184,7 +184,7 @@ struct dv_ctx {
   std::vector<Interval> prof_pending;
   double prof_ms[DV_NUM_STAGES] = {0};
   int64_t prof_calls[DV_NUM_STAGES] = {0};
-  unsigned long long* counters = nullptr;  // device [8], from the pool
+  unsigned long long* counters = nullptr;  // device [DV_NUM_COUNTERS], from the pool
   dv::DBuf counters_buf;
   // allocation-free entry point: this device's static scratch array (its
   // device address, from hipGetSymbolAddress at context creation) and a

@@ -102,6 +102,18 @@ __device__ inline void count_work(unsigned long long* counters, int i,
   }
 }
 
+// Wave-level counts (wave-uniform values, added once per wave by lane 0):
+// list entries a wave walked in the straight-line iteration, and those of
+// them where at least one lane had a chord.
+__device__ inline void count_waves(unsigned long long* counters, int i,
+                                   uint32_t iters, uint32_t hits) {
+  if (!counters) return;
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(counters + i, (unsigned long long)iters);
+    atomicAdd(counters + i + 1, (unsigned long long)hits);
+  }
+}
+
 // Pixel of thread tid inside a 16x16 tile: each wave64 covers an 8x8
 // quadrant, so a wave can skip list entries whose pixel rectangle misses
 // its quadrant.
@@ -112,24 +124,40 @@ __device__ inline int tile_py(int tid) {
   return (((tid >> 6) >> 1) << 3) | ((tid >> 3) & 7);
 }
 
-// Does the entry's covered pixel rectangle meet the 8x8 block at (bx, by)?
-// Evaluated identically by every lane of a wave (wave-uniform branch).
-__device__ inline bool rect_hits_block(uint2 rc, int bx, int by) {
-  const int xl = (int)(rc.x & 0xFFFF), xh = (int)(rc.x >> 16);
-  const int yl = (int)(rc.y & 0xFFFF), yh = (int)(rc.y >> 16);
-  return xl <= bx + 7 && xh >= bx && yl <= by + 7 && yh >= by;
-}
-
 // Entries of a staged batch (nb <= 256) whose pixel rectangle meets the
-// calling wave's 8x8 block, as four wave-uniform 64-bit masks (bit i of
-// m[c] is entry 64 c + i).  Called by every lane of the wave.
-__device__ inline void wave_entry_masks(const uint2* rect, uint32_t nb, int bx,
-                                        int by, uint64_t m[4]) {
+// pixel box of the wave's lanes in `lanes` (a wave ballot, e.g. of the
+// lanes still compositing), as four wave-uniform 64-bit masks (bit i of
+// m[c] is entry 64 c + i).  Lane l of the wave is pixel (bx + l % 8,
+// by + l / 8) of the 8x8 block at (bx, by), so the box comes from scalar
+// bit operations on the ballot.  Called by every lane of the wave.  An
+// entry whose rectangle misses the box has no chord for any of those lanes
+// (the rectangle covers every pixel the leaf's chord can reach), so
+// skipping it changes nothing for them.  No lane: no entries.
+__device__ inline void wave_live_masks(const uint2* rect, uint32_t nb, int bx,
+                                       int by, uint64_t lanes, uint64_t m[4]) {
+  if (lanes == 0) {
+    m[0] = m[1] = m[2] = m[3] = 0;
+    return;
+  }
+  uint64_t cols = lanes | (lanes >> 32);
+  cols |= cols >> 16;
+  cols |= cols >> 8;
+  cols &= 0xFFull;
+  const int x0 = bx + __builtin_ctzll(cols);
+  const int x1 = bx + 63 - __builtin_clzll(cols);
+  const int y0 = by + (__builtin_ctzll(lanes) >> 3);
+  const int y1 = by + ((63 - __builtin_clzll(lanes)) >> 3);
   const uint32_t lane = threadIdx.x & 63;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const uint32_t r = (uint32_t)c * 64 + lane;
-    const bool hit = r < nb && rect_hits_block(rect[r], bx, by);
+    bool hit = false;
+    if (r < nb) {
+      const uint2 rc = rect[r];
+      const int xl = (int)(rc.x & 0xFFFF), xh = (int)(rc.x >> 16);
+      const int yl = (int)(rc.y & 0xFFFF), yh = (int)(rc.y >> 16);
+      hit = xl <= x1 && xh >= x0 && yl <= y1 && yh >= y0;
+    }
     m[c] = __ballot(hit);
   }
 }
@@ -679,7 +707,7 @@ struct dv_fwd_state {
   dv::DBuf host_tables;   // one upload: views, constants, segments, actor CSR
   // preprocess ballots and block offsets: record slot of any (view,
   // octree, leaf) item, kept for the leaf-major SH backward
-  dv::DBuf pre_wmask, pre_boff;
+  dv::DBuf pre_wmask, pre_boff, pre_wseg;
   dv::DBuf seg_pstart_d, seg_len_d;   // views into host_tables
   std::vector<std::vector<int64_t>> lstart_keep;
   dv::DBuf chunk_b, chunk_part, act_tile;

@@ -194,11 +194,15 @@ __device__ inline void sh_colour(const float* sh, int N, int vox, const float* Y
   }
 }
 
+constexpr int PAIR_PARTS = 256;
+constexpr int PAIR_STRIDE = 16;   // 128 bytes between counters
+
 struct PreArgs {
   const ViewConst* views;
   const VOConst* vo;
   const OctDev* oct;
   const int64_t* seg_start;   // padded: segments start on multiples of 64
+  const uint32_t* wave_seg;   // segment of every wave of 64 items
   const int32_t* seg_len;     // leaves per segment
   uint64_t* wave_mask;        // visibility ballot per wave (pass 0 -> 1)
   int32_t n_seg;
@@ -206,7 +210,10 @@ struct PreArgs {
   int64_t n_items;
   int32_t rank_bits;
   uint32_t* block_count;
-  unsigned long long* pair_total;  // pass 0: (leaf, tile) pairs, summed
+  // pass 0: (leaf, tile) pairs, summed into PAIR_PARTS counters (block b
+  // adds to counter b % PAIR_PARTS, PAIR_STRIDE words apart) instead of one
+  // word: a million blocks adding to one address serialised on it
+  unsigned long long* pair_parts;
   const uint32_t* block_off;
   uint64_t* keys;
   uint32_t* vals;
@@ -218,6 +225,15 @@ struct PreArgs {
   uint32_t* s_vox;
   uint64_t* s_rect;
 };
+
+// Segment s fills the entries of its waves in the per-wave segment table
+// (one block per segment; segments are padded to whole waves).
+__global__ void k_wave_segments(const int64_t* __restrict__ pstart,
+                                uint32_t* __restrict__ wave_seg) {
+  const int s = blockIdx.x;
+  const int64_t w0 = pstart[s] / 64, w1 = pstart[s + 1] / 64;
+  for (int64_t w = w0 + threadIdx.x; w < w1; w += TPB) wave_seg[w] = (uint32_t)s;
+}
 
 // Segments (view, octree) start on multiples of 64 items, so each wave
 // holds leaves of one segment: the segment search and the per-segment
@@ -238,15 +254,8 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
     m = bm[w];
     if (!((m >> lane) & 1ull)) return;
   }
-  int s = 0;
-  if (t0 < p.n_items) {
-    int lo = 0, hi = p.n_seg - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (p.seg_start[mid] <= t0) lo = mid; else hi = mid - 1;
-    }
-    s = lo;
-  }
+  // the wave's (view, octree) segment, from the per-wave table
+  const int s = t0 < p.n_items ? (int)p.wave_seg[wave] : 0;
   const int vox = (int)(t0 - p.seg_start[s]) + lane;
   const int v = s / p.n_oct, k = s % p.n_oct;
   const ViewConst& V = p.views[v];
@@ -295,7 +304,7 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
         pt += wpairs[i];
       }
       p.block_count[blockIdx.x] = tot;
-      if (pt) atomicAdd(p.pair_total, pt);
+      if (pt) atomicAdd(p.pair_parts + (blockIdx.x % PAIR_PARTS) * PAIR_STRIDE, pt);
     }
     return;
   }
@@ -382,29 +391,52 @@ __global__ void k_gather(int64_t n, const uint64_t* __restrict__ keys,
   r_count[i] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
 }
 
+// Block b of the pair emission covers pairs [256 b, 256 b + 256); brec[b]
+// is the record holding pair 256 b (each record marks the blocks whose
+// first pair it holds, so every block gets exactly one).
+__global__ void k_pair_block_rec(int64_t n_rec, int64_t n_pairs,
+                                 const uint32_t* __restrict__ off,
+                                 uint32_t* __restrict__ brec) {
+  const int64_t r = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (r >= n_rec) return;
+  const int64_t lo = off[r];
+  const int64_t hi = r + 1 < n_rec ? (int64_t)off[r + 1] : n_pairs;
+  for (int64_t b = (lo + TPB - 1) / TPB; b * TPB < hi; ++b) brec[b] = (uint32_t)r;
+}
+
 // Pair p of the depth-sorted record list: key = global tile, value = the
-// record's slot (pairs come out in depth order within every tile).
-__global__ void k_emit(int64_t n_pairs, int64_t n_rec,
-                       const uint32_t* __restrict__ off,
-                       const uint32_t* __restrict__ order,
-                       const uint64_t* __restrict__ rect,
-                       const uint32_t* __restrict__ seg, int n_oct,
-                       const ViewConst* __restrict__ views,
-                       uint32_t* __restrict__ pkey,
-                       uint32_t* __restrict__ pval) {
-  const int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (p >= n_pairs) return;
-  int64_t lo = 0, hi = n_rec - 1;
-  while (lo < hi) {
-    int64_t mid = (lo + hi + 1) >> 1;
-    if ((int64_t)off[mid] <= p) lo = mid; else hi = mid - 1;
+// record's slot (pairs come out in depth order within every tile).  Every
+// record holds at least one pair (a visible leaf covers a tile), so the
+// block's 256 pairs lie in records brec[b] .. brec[b] + 255: their offsets
+// are staged in LDS and each thread finds its record there, instead of a
+// search over all records.
+__global__ void __launch_bounds__(TPB)
+k_emit(int64_t n_pairs, int64_t n_rec, const uint32_t* __restrict__ off,
+       const uint32_t* __restrict__ brec, const uint32_t* __restrict__ order,
+       const uint64_t* __restrict__ rect, const uint32_t* __restrict__ seg,
+       int n_oct, const ViewConst* __restrict__ views,
+       uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval) {
+  __shared__ uint32_t soff[TPB];
+  const int64_t p0 = (int64_t)blockIdx.x * TPB;
+  const uint32_t r0 = brec[blockIdx.x];
+  {
+    const int64_t r = (int64_t)r0 + threadIdx.x;
+    soff[threadIdx.x] = r < n_rec ? off[r] : (uint32_t)n_pairs;
   }
-  const uint32_t sl = order[lo];
+  __syncthreads();
+  const int64_t p = p0 + threadIdx.x;
+  if (p >= n_pairs) return;
+  int lo = 0, hi = TPB - 1;  // the last record starting at or before p
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)soff[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  const uint32_t sl = order[(int64_t)r0 + lo];
   const uint64_t rc = rect[sl];
   const uint32_t tx0 = (rc & 0xFFFF) >> 4, tx1 = ((rc >> 16) & 0xFFFF) >> 4;
   const uint32_t ty0 = ((rc >> 32) & 0xFFFF) >> 4;
   const uint32_t wdt = tx1 - tx0 + 1;
-  const uint32_t i = (uint32_t)(p - off[lo]);
+  const uint32_t i = (uint32_t)(p - soff[lo]);
   const ViewConst& V = views[seg[sl] / n_oct];
   pkey[p] = V.tile_base + (ty0 + i / wdt) * V.ntx + (tx0 + i % wdt);
   pval[p] = sl;
@@ -645,6 +677,22 @@ __device__ inline void load_batch(Batch& B, const A& a, uint32_t base,
   }
 }
 
+// Only what a slab test needs: leaf corner, far corner (in the normal
+// slot, as load_batch<false> forms it) and the pixel rectangle.
+template <class A>
+__device__ inline void load_batch_geo(Batch& B, const A& a, uint32_t base,
+                                      uint32_t n) {
+  const int tid = threadIdx.x;
+  if ((uint32_t)tid < n) {
+    const uint32_t r = a.pair_val[base + tid];
+    const float4 geo = a.rec_geo[r];
+    B.geo[tid] = geo;
+    const float3 hi = leaf_hi(geo);
+    B.nrm[tid] = make_float4(hi.x, hi.y, hi.z, 0.0f);
+    const uint64_t rc = a.rec_rect[r];
+    B.rect[tid] = make_uint2((uint32_t)rc, (uint32_t)(rc >> 32));
+  }
+}
 
 __device__ inline uint32_t src_code(int slot, int axis) {
   return ((uint32_t)slot << 2) | (uint32_t)axis;
@@ -888,7 +936,7 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
     load_batch<NORMALS>(B, a, base, nb);
     __syncthreads();
     uint64_t wm[4];
-    wave_entry_masks(B.rect, nb, bx, by, wm);
+    wave_live_masks(B.rect, nb, bx, by, __ballot(live()), wm);
     for (int c = 0; c < 4; ++c) {
       uint64_t m = wm[c];
       if (single) {
@@ -1012,10 +1060,10 @@ __global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a) {
   bool found = !P.valid;
   for (uint32_t base = cb; base < ce; base += TPB) {
     const uint32_t nb = min((uint32_t)TPB, ce - base);
-    load_batch<false>(B, a, base, nb);
+    load_batch_geo(B, a, base, nb);
     __syncthreads();
     uint64_t wm[4];
-    wave_entry_masks(B.rect, nb, P.bx, P.by, wm);
+    wave_live_masks(B.rect, nb, P.bx, P.by, __ballot(!found), wm);
     for (int q = 0; q < 4; ++q) {
       uint64_t m = wm[q];
       while (m != 0 && __ballot(!found) != 0) {
@@ -1061,6 +1109,7 @@ __device__ __forceinline__ void composite_item(const A& a, uint32_t idx,
   const float invK = 1.0f / (float)K;
   uint32_t n_test = 0, n_piece = 0;
   uint32_t w_test = 0, w_piece = 0;  // wave-level counts (straight-line)
+  uint32_t w_iter = 0, w_hit = 0;
   const uint32_t a_beg = a.act_beg[gt];
   const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
   const uint32_t seg0 = 3 * a_beg + n_at;
@@ -1125,7 +1174,7 @@ __device__ __forceinline__ void composite_item(const A& a, uint32_t idx,
     load_batch<NORMALS>(B, a, base, nb);
     __syncthreads();
     uint64_t wm[4];
-    wave_entry_masks(B.rect, nb, bx, by, wm);
+    wave_live_masks(B.rect, nb, bx, by, __ballot(live()), wm);
     for (int c = 0; c < 4; ++c) {
       uint64_t m = wm[c];
       while (m != 0) {
@@ -1141,8 +1190,11 @@ __device__ __forceinline__ void composite_item(const A& a, uint32_t idx,
         // no lane's chord meets a segment: one piece [t0, t1) per chord
         const bool plain = !chord || (excl <= t0 && ns >= t1);
         if (__ballot(!plain) == 0) {
+          const uint64_t hm = __ballot(chord);
           w_test += (uint32_t)__popcll(lm);
-          w_piece += (uint32_t)__popcll(__ballot(chord));
+          w_piece += (uint32_t)__popcll(hm);
+          ++w_iter;
+          w_hit += hm != 0 ? 1u : 0u;
           if (chord) add_piece(r, geo, t0, t1);
           continue;
         }
@@ -1177,6 +1229,7 @@ __device__ __forceinline__ void composite_item(const A& a, uint32_t idx,
     n_piece += w_piece;
   }
   count_work(a.counters, 0, n_test, n_piece);
+  count_waves(a.counters, 8, w_iter, w_hit);
   // measured work (slab tests + 4 per piece, at least 1), the backward's
   // schedule key
   {
@@ -1707,15 +1760,21 @@ dv_status stage_release(hipStream_t s) {
 }
 
 // First record slot of every view (records are in slot order: view,
-// octree, leaf), and the record total at index n_views.  A view's first
-// item starts a wave, so its slot is the block offset plus the ballots of
-// the block's earlier waves.
+// octree, leaf), the record total at index n_views and the pair total (the
+// sum of the preprocess's partial pair counters) at index n_views + 1.  A
+// view's first item starts a wave, so its slot is the block offset plus
+// the ballots of the block's earlier waves.
 __global__ void k_view_slots(int n_views, int n_oct, const int64_t* pstart,
                              int64_t n_items, const uint32_t* block_off,
                              const uint64_t* wave_mask, const uint64_t* total,
-                             uint64_t* out) {
+                             const unsigned long long* pair_parts, uint64_t* out) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v > n_views) return;
+  if (v == n_views) {
+    uint64_t np = 0;
+    for (int i = 0; i < PAIR_PARTS; ++i) np += pair_parts[i * PAIR_STRIDE];
+    out[n_views + 1] = np;
+  }
   const int64_t it = v < n_views ? pstart[(size_t)v * n_oct] : n_items;
   if (it >= n_items) { out[v] = total[0]; return; }
   const int64_t b = it / TPB;
@@ -1797,13 +1856,23 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   DV_TRY(alloc_n<uint64_t>(ctx, total, 2, s));
   // first record slot per view, the record total, then the pair total
   DV_TRY(alloc_n<uint64_t>(ctx, vslot, (size_t)n_views + 2, s));
-  DV_TRY(fill_u32(vslot.as<uint32_t>() + 2 * (n_views + 1), 0u, 2, s));
+  DBuf pparts;
+  DV_TRY(alloc_n<uint64_t>(ctx, pparts, (size_t)PAIR_PARTS * PAIR_STRIDE, s));
+  DV_TRY(fill_u32(pparts.as<uint32_t>(), 0u, 2 * PAIR_PARTS * PAIR_STRIDE, s));
   PreArgs pa;
   std::memset(&pa, 0, sizeof(pa));
   pa.views = st->views_d.as<ViewConst>();
   pa.vo = st->vo_d.as<VOConst>();
   pa.oct = sc->oct_dev.as<OctDev>();
   pa.seg_start = segs_d.as<int64_t>();
+  DBuf& wseg = st->pre_wseg;
+  DV_TRY(alloc_n<uint32_t>(ctx, wseg, (size_t)std::max<int64_t>(n_items / 64, 1), s));
+  if (n_items > 0) {
+    hipLaunchKernelGGL(k_wave_segments, dim3((unsigned)n_seg), dim3(TPB), 0, s,
+                       segs_d.as<int64_t>(), wseg.as<uint32_t>());
+    DV_TRY_HIP(hipGetLastError());
+  }
+  pa.wave_seg = wseg.as<uint32_t>();
   pa.seg_len = slen_d.as<int32_t>();
   pa.wave_mask = wmask.as<uint64_t>();
   pa.n_seg = n_seg;
@@ -1811,7 +1880,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   pa.n_items = n_items;
   pa.rank_bits = st->rank_bits;
   pa.block_count = bcount.as<uint32_t>();
-  pa.pair_total = reinterpret_cast<unsigned long long*>(vslot.as<uint64_t>() + n_views + 1);
+  pa.pair_parts = reinterpret_cast<unsigned long long*>(pparts.as<uint64_t>());
   pa.block_off = boff.as<uint32_t>();
   {
     StageTimer tm(ctx, ST_PREPROCESS, s);
@@ -1825,7 +1894,9 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
     hipLaunchKernelGGL(k_view_slots, dim3(grid_for(n_views + 1, TPB)), dim3(TPB),
                        0, s, n_views, n_oct, segs_d.as<int64_t>(), n_items,
                        boff.as<uint32_t>(), wmask.as<uint64_t>(),
-                       total.as<uint64_t>(), vslot.as<uint64_t>());
+                       total.as<uint64_t>(),
+                       reinterpret_cast<const unsigned long long*>(pparts.as<uint64_t>()),
+                       vslot.as<uint64_t>());
     DV_TRY_HIP(hipGetLastError());
   }
   uint64_t n_vis = 0, n_pairs = 0;
@@ -1915,12 +1986,18 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   DV_TRY(alloc_n<uint32_t>(ctx, pkey2, np, s));
   DV_TRY(alloc_n<uint32_t>(ctx, pval2, np, s));
   StageTimer tm_emit(ctx, ST_EMIT, s);
-  if (np > 0)
-    hipLaunchKernelGGL(k_emit, dim3(grid_for(np, TPB)), dim3(TPB), 0, s, np, nv,
-                       r_off.as<uint32_t>(), vs, st->rec_rect.as<uint64_t>(),
-                       st->rec_seg.as<uint32_t>(), n_oct,
-                       st->views_d.as<ViewConst>(), pkey.as<uint32_t>(),
+  if (np > 0) {
+    const unsigned eb = grid_for(np, TPB);
+    DBuf brec;
+    DV_TRY(alloc_n<uint32_t>(ctx, brec, eb, s));
+    hipLaunchKernelGGL(k_pair_block_rec, dim3(grid_for(nv, TPB)), dim3(TPB), 0, s,
+                       nv, np, r_off.as<uint32_t>(), brec.as<uint32_t>());
+    hipLaunchKernelGGL(k_emit, dim3(eb), dim3(TPB), 0, s, np, nv,
+                       r_off.as<uint32_t>(), brec.as<uint32_t>(), vs,
+                       st->rec_rect.as<uint64_t>(), st->rec_seg.as<uint32_t>(),
+                       n_oct, st->views_d.as<ViewConst>(), pkey.as<uint32_t>(),
                        st->pair_val.as<uint32_t>());
+  }
   DV_TRY_HIP(hipGetLastError());
   tm_emit.stop();
   {

@@ -115,7 +115,9 @@ class dv_stage_times(C.Structure):
                 ("entries_fwd", C.c_int64), ("pieces_fwd", C.c_int64),
                 ("entries_bwd", C.c_int64), ("pieces_bwd", C.c_int64),
                 ("entries_actor_fwd", C.c_int64), ("pieces_actor_fwd", C.c_int64),
-                ("entries_actor_bwd", C.c_int64), ("pieces_actor_bwd", C.c_int64)]
+                ("entries_actor_bwd", C.c_int64), ("pieces_actor_bwd", C.c_int64),
+                ("wave_entries_fwd", C.c_int64), ("wave_hits_fwd", C.c_int64),
+                ("wave_entries_bwd", C.c_int64), ("wave_hits_bwd", C.c_int64)]
 
 
 class dv_serve_opts(C.Structure):
@@ -376,7 +378,11 @@ def dv_ctx_stage_times(ctx, reset=True):
                             entries_actor_fwd=t.entries_actor_fwd,
                             pieces_actor_fwd=t.pieces_actor_fwd,
                             entries_actor_bwd=t.entries_actor_bwd,
-                            pieces_actor_bwd=t.pieces_actor_bwd)
+                            pieces_actor_bwd=t.pieces_actor_bwd,
+                            wave_entries_fwd=t.wave_entries_fwd,
+                            wave_hits_fwd=t.wave_hits_fwd,
+                            wave_entries_bwd=t.wave_entries_bwd,
+                            wave_hits_bwd=t.wave_hits_bwd)
     return out
 
 
