@@ -223,6 +223,7 @@ struct PreArgs {
   float4* s_cn;
   float4* s_nrm;
   uint32_t* s_vox;
+  uint32_t* s_seg;              // (view, octree) segment of the record
   uint64_t* s_rect;
 };
 
@@ -360,6 +361,7 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
   p.keys[slot] = ((uint64_t)s << p.rank_bits) | rank;
   p.vals[slot] = slot;
   p.s_vox[slot] = (uint32_t)vox;
+  p.s_seg[slot] = (uint32_t)s;
   // window-relative covered pixel bounds (inclusive), 16 bits each
   p.s_rect[slot] = (uint64_t)(uint32_t)r.xl | ((uint64_t)(uint32_t)r.xh << 16) |
                    ((uint64_t)(uint32_t)r.yl << 32) |
@@ -374,17 +376,14 @@ __global__ void __launch_bounds__(TPB) k_preprocess(PreArgs p) {
 }
 
 // Records stay where the preprocess put them (slot order: view, octree,
-// leaf).  For the depth-sorted order i -> slot order[i], record each slot's
-// (view, octree) id and the tile count of sorted record i.
-__global__ void k_gather(int64_t n, const uint64_t* __restrict__ keys,
-                         const uint32_t* __restrict__ order, int rank_bits,
+// leaf; the preprocess also stores each slot's (view, octree) id).  For the
+// depth-sorted order i -> slot order[i], the tile count of sorted record i.
+__global__ void k_gather(int64_t n, const uint32_t* __restrict__ order,
                          const uint64_t* __restrict__ rect,
-                         uint32_t* __restrict__ rseg,
                          uint32_t* __restrict__ r_count) {
   const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (i >= n) return;
   const uint32_t sl = order[i];
-  rseg[sl] = (uint32_t)(keys[i] >> rank_bits);
   const uint64_t rc = rect[sl];
   const uint32_t tx0 = (rc & 0xFFFF) >> 4, tx1 = ((rc >> 16) & 0xFFFF) >> 4;
   const uint32_t ty0 = ((rc >> 32) & 0xFFFF) >> 4, ty1 = (rc >> 48) >> 4;
@@ -1941,6 +1940,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   pa.s_cn = st->rec_cn.as<float4>();
   pa.s_nrm = st->rec_nrm.as<float4>();
   pa.s_vox = st->rec_vox.as<uint32_t>();
+  pa.s_seg = st->rec_seg.as<uint32_t>();
   pa.s_rect = st->rec_rect.as<uint64_t>();
   {
     StageTimer tm(ctx, ST_PREPROCESS, s);
@@ -1956,17 +1956,15 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
                           keys2.as<uint64_t>(), vals2.as<uint32_t>(), nv,
                           st->key_bits, s, &alt));
   }
-  uint64_t* ks = alt ? keys2.as<uint64_t>() : keys.as<uint64_t>();
   uint32_t* vs = alt ? vals2.as<uint32_t>() : vals.as<uint32_t>();
-  // per sorted record: slot's (view, octree) id, tile count and offset
+  // per sorted record: tile count and offset
   DBuf r_count, r_off;
   DV_TRY(alloc_n<uint32_t>(ctx, r_count, nv, s));
   DV_TRY(alloc_n<uint32_t>(ctx, r_off, nv, s));
   StageTimer tm_gather(ctx, ST_GATHER, s);
   if (nv > 0)
     hipLaunchKernelGGL(k_gather, dim3(grid_for(nv, TPB)), dim3(TPB), 0, s, nv,
-                       ks, vs, st->rank_bits, st->rec_rect.as<uint64_t>(),
-                       st->rec_seg.as<uint32_t>(), r_count.as<uint32_t>());
+                       vs, st->rec_rect.as<uint64_t>(), r_count.as<uint32_t>());
   DV_TRY_HIP(hipGetLastError());
   DV_TRY(exclusive_scan_u32(ctx, r_count.as<uint32_t>(), r_off.as<uint32_t>(),
                             total.as<uint64_t>(), nv, s));
