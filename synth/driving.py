@@ -19,7 +19,8 @@ least 8 m apart.
 import numpy as np
 from scipy.spatial import cKDTree
 
-from .octree import children, dedup_corners, make_octree, corner_positions
+from .octree import (children, dedup_corners, make_octree, corner_positions,
+                     morton_order_leaves, morton_order_corners)
 from .configs import make_view, look_at_c2w, _sh_random
 
 ROOT_SIZE = 819.2
@@ -235,7 +236,9 @@ def background_octree(rng, target_leaves, v_close, n_buildings=40,
     parts = inner + far
     lv = np.concatenate([np.full(len(c), l, np.uint8) for l, c in parts])
     ijk = np.concatenate([c for _, c in parts], 0).T.astype(np.int32)
-    cidx, upos = dedup_corners(lv, ijk, top)
+    # leaves and corners stored in Morton order (spatially compact runs)
+    lv, ijk = morton_order_leaves(lv, ijk, top)
+    cidx, upos = morton_order_corners(*dedup_corners(lv, ijk, top))
     cpos = ROOT_MIN + upos * (ROOT_SIZE / (1 << top))
     # beyond 1 m the prior equals v_far to double precision (s <= 0.2 m)
     d, _ = tree.query(cpos, k=1, distance_upper_bound=1.0, workers=-1)
@@ -310,7 +313,8 @@ def _car_structure(target, v_close, base, top):
     parts = build(lo)
     lv = np.concatenate([np.full(len(c), l, np.uint8) for l, c in parts])
     ijk = np.concatenate([c for _, c in parts], 0).T.astype(np.int32)
-    cidx, upos = dedup_corners(lv, ijk, top)
+    lv, ijk = morton_order_leaves(lv, ijk, top)
+    cidx, upos = morton_order_corners(*dedup_corners(lv, ijk, top))
     cpos = rmin + upos * (side / (1 << top))
     d = _box_distance(cpos, half)
     s_min = side / (1 << top)

@@ -91,6 +91,45 @@ def dedup_corners(level, ijk, max_level):
     return np.ascontiguousarray(cidx), upos
 
 
+def _spread3(x):
+    """Spread the low 21 bits of x (uint64 array) to every third bit."""
+    x = np.asarray(x, np.uint64) & np.uint64(0x1FFFFF)
+    for sh, m in ((32, 0x1F00000000FFFF), (16, 0x1F0000FF0000FF),
+                  (8, 0x100F00F00F00F00F), (4, 0x10C30C30C30C30C3),
+                  (2, 0x1249249249249249)):
+        x = (x | (x << np.uint64(sh))) & np.uint64(m)
+    return x
+
+
+def morton_codes(pos):
+    """Morton (Z-order) codes of integer positions int64[n, 3]."""
+    pos = np.asarray(pos, np.int64).reshape(-1, 3)
+    return (_spread3(pos[:, 0]) | (_spread3(pos[:, 1]) << np.uint64(1)) |
+            (_spread3(pos[:, 2]) << np.uint64(2)))
+
+
+def morton_order_leaves(level, ijk, max_level):
+    """Leaves sorted by the Morton code of their cell's low corner on the
+    finest grid (leaves never overlap, so the codes are distinct): each run
+    of consecutive leaves is a compact piece of space."""
+    lv = np.asarray(level, np.int64)
+    c = np.asarray(ijk, np.int64)
+    pos = (c << (max_level - lv)[None, :]).T
+    order = np.argsort(morton_codes(pos), kind="stable")
+    return (np.ascontiguousarray(np.asarray(level)[order]),
+            np.ascontiguousarray(np.asarray(ijk)[:, order]))
+
+
+def morton_order_corners(cidx, upos):
+    """Renumber a shared-corner table so corners are in Morton order of
+    their finest-grid position: returns (corner_idx, positions)."""
+    order = np.argsort(morton_codes(upos), kind="stable")
+    rank = np.empty(len(order), np.int64)
+    rank[order] = np.arange(len(order))
+    return (np.ascontiguousarray(rank[cidx].astype(np.int32)),
+            np.ascontiguousarray(np.asarray(upos)[order]))
+
+
 def make_octree(root_min, root_size, max_level, level, ijk, corner_idx,
                 corner_density, sh, box_min=None, box_max=None):
     level = np.ascontiguousarray(level, dtype=np.uint8)
