@@ -1357,8 +1357,9 @@ k_record_bwd(int64_t off, int64_t n, const uint32_t* rseg, const uint32_t* rvox,
 #pragma unroll
   for (int c = 0; c < 12; ++c) p12[c] = 0.0f;
   uint32_t seg = 0xFFFFFFFFu;
-  if (i < n) {
-    seg = rseg[i];
+  if (i < n) seg = rseg[i];
+  // leaf-major launches add pose terms only: background records have none
+  if (i < n && !(leafmajor && seg % n_oct == 0)) {
     const int k = (int)(seg % n_oct);
     const OctDev& O = oct[k];
     const OctGrad& G = og[k];
@@ -1494,7 +1495,14 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   hipStream_t s = (hipStream_t)stream;
   const int64_t nv = st->n_vis, nt = st->n_tiles;
   const int n_oct = st->n_oct;
-  const bool normals = (st->opts.out_mask & DV_OUT_NORMAL) != 0;
+  // the normal terms of the backward (normal gradients per record, the
+  // normals in the per-entry sums) run only when some view passes a normal
+  // gradient; without one they are exactly zero, and the walks take the
+  // kernels without normals (same forward arithmetic: the far corner the
+  // slab test uses is formed from the leaf corner either way)
+  bool normals = false;
+  if (st->opts.out_mask & DV_OUT_NORMAL)
+    for (int v = 0; v < st->n_views; ++v) normals = normals || g[v].normal != nullptr;
   // per-view upstream gradients and per-octree accumulators
   st->grads_keep.emplace_back(g, g + st->n_views);
   st->og_keep.emplace_back(n_oct);

@@ -703,7 +703,7 @@ struct dv_fwd_state {
   dv::DBuf seg_se, seg_meta, seg_p0, seg_p1, seg_bw, pix_nseg;
   dv::DBuf fin0, fin1, fin2, fin3, seg_t0, seg_t1;
   dv::DBuf order_fwd, order_bwd, item_tile, item_chunk, item_work;
-  dv::DBuf tile_nck, tile_ibase, tile_pbase, plan_counts;
+  dv::DBuf tile_nck, tile_ibase, tile_pbase, plan_counts, slot_tile;
   dv::DBuf host_tables;   // one upload: views, constants, segments, actor CSR
   // preprocess ballots and block offsets: record slot of any (view,
   // octree, leaf) item, kept for the leaf-major SH backward

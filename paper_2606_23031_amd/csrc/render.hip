@@ -567,6 +567,7 @@ struct PlanArgs {
   uint32_t* item_chunk;
   uint32_t* order;
   uint32_t* counts;
+  uint32_t* slot_tile;         // chunk slot -> its list (or null)
 };
 
 // Block b plans list set b (the background lists and the (tile, actor)
@@ -611,6 +612,8 @@ __global__ void __launch_bounds__(1024) k_plan_items(PlanArgs p0, PlanArgs p1) {
       tile_nck[t] = k;
       tile_ibase[t] = ib;
       tile_pbase[t] = pb;
+      if (P.slot_tile && k > 1)
+        for (uint32_t c = 0; c < k; ++c) P.slot_tile[pb + c] = (uint32_t)t;
       for (uint32_t c = 0; c < k; ++c) {
         uint32_t cb, ce;
         chunk_range(0, len, k, c, cb, ce);
@@ -1034,51 +1037,60 @@ __global__ void __launch_bounds__(TPB) k_actor_merge(CompArgs a) {
 }
 
 // Forward, part 2 (chunked tiles, chunks c > 0): B_c of every pixel, the
-// entry depth of its first non-empty chord among the chunk's entries.
-__global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a) {
+// entry depth of its first non-empty chord among the chunk's entries.  The
+// grid walks the chunk slots (slot -> list from the plan; each chunk in
+// CB_SPLIT parts, one per block), so no block is spent on unchunked tiles;
+// every block leaves once the slots run out.
+__global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a,
+                                                      const uint32_t* slot_tile) {
   __shared__ Batch B;
   const uint32_t part = blockIdx.x % CB_SPLIT;
-  if (blockIdx.x / CB_SPLIT >= a.plan_counts[0]) return;
-  const uint32_t k = a.order[blockIdx.x / CB_SPLIT];
-  const uint32_t gt = a.item_tile[k], c = a.item_chunk[k];
-  const uint32_t nck = a.tile_nck[gt];
-  if (nck <= 1 || c == 0) return;
+  const uint32_t n_slots = a.plan_counts[1];
   const int tid = threadIdx.x;
-  const PixSetup P = pixel_setup(a, gt, tid);
-  const float3 inv = safe_inv(P.d);
-  uint32_t cb, ce;
-  chunk_range(a.tile_start[gt], a.tile_bgend[gt], nck, c, cb, ce);
-  {
-    // this block's part of the chunk
-    const uint32_t len = ce - cb;
-    const uint32_t pb = cb + (uint32_t)((uint64_t)len * part / CB_SPLIT);
-    ce = cb + (uint32_t)((uint64_t)len * (part + 1) / CB_SPLIT);
-    cb = pb;
-  }
-  float Bc = F_INF;
-  bool found = !P.valid;
-  for (uint32_t base = cb; base < ce; base += TPB) {
-    const uint32_t nb = min((uint32_t)TPB, ce - base);
-    load_batch_geo(B, a, base, nb);
-    __syncthreads();
-    uint64_t wm[4];
-    wave_live_masks(B.rect, nb, P.bx, P.by, __ballot(!found), wm);
-    for (int q = 0; q < 4; ++q) {
-      uint64_t m = wm[q];
-      while (m != 0 && __ballot(!found) != 0) {
-        const uint32_t r = (uint32_t)q * 64 + (uint32_t)__builtin_ctzll(m);
-        m &= m - 1;
-        if (found) continue;
-        const float4 geo = B.geo[r];
-        float t0, t1;
-        batch_slab<false>(B, r, geo, inv, t0, t1);
-        t0 = fmaxf(t0, a.tau_near);
-        if (t1 > t0) { Bc = t0; found = true; }
-      }
+  for (uint32_t sl = blockIdx.x / CB_SPLIT; sl < n_slots;
+       sl += gridDim.x / CB_SPLIT) {
+    const uint32_t gt = slot_tile[sl];
+    if (gt == 0xFFFFFFFFu) continue;           // slot of no granted list
+    const uint32_t c = sl - a.tile_pbase[gt];
+    if (c == 0) continue;                      // chunk 0 starts at the camera
+    const uint32_t nck = a.tile_nck[gt];
+    const PixSetup P = pixel_setup(a, gt, tid);
+    const float3 inv = safe_inv(P.d);
+    uint32_t cb, ce;
+    chunk_range(a.tile_start[gt], a.tile_bgend[gt], nck, c, cb, ce);
+    {
+      // this block's part of the chunk
+      const uint32_t len = ce - cb;
+      const uint32_t pb = cb + (uint32_t)((uint64_t)len * part / CB_SPLIT);
+      ce = cb + (uint32_t)((uint64_t)len * (part + 1) / CB_SPLIT);
+      cb = pb;
     }
-    if (__syncthreads_and(found)) break;
+    float Bc = F_INF;
+    bool found = !P.valid;
+    for (uint32_t base = cb; base < ce; base += TPB) {
+      const uint32_t nb = min((uint32_t)TPB, ce - base);
+      load_batch_geo(B, a, base, nb);
+      __syncthreads();
+      uint64_t wm[4];
+      wave_live_masks(B.rect, nb, P.bx, P.by, __ballot(!found), wm);
+      for (int q = 0; q < 4; ++q) {
+        uint64_t m = wm[q];
+        while (m != 0 && __ballot(!found) != 0) {
+          const uint32_t r = (uint32_t)q * 64 + (uint32_t)__builtin_ctzll(m);
+          m &= m - 1;
+          if (found) continue;
+          const float4 geo = B.geo[r];
+          float t0, t1;
+          batch_slab<false>(B, r, geo, inv, t0, t1);
+          t0 = fmaxf(t0, a.tau_near);
+          if (t1 > t0) { Bc = t0; found = true; }
+        }
+      }
+      if (__syncthreads_and(found)) break;
+    }
+    a.chunk_b[((size_t)sl * CB_SPLIT + part) * TPB + tid] = Bc;
+    __syncthreads();
   }
-  a.chunk_b[(((size_t)a.tile_pbase[gt] + c) * CB_SPLIT + part) * TPB + tid] = Bc;
 }
 
 // Forward, part 3: the background walk of one work item (a tile, or one
@@ -2047,6 +2059,8 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
   DV_TRY(alloc_n<uint32_t>(ctx, st->tile_nck, nt, s));
   DV_TRY(alloc_n<uint32_t>(ctx, st->tile_ibase, nt, s));
   DV_TRY(alloc_n<uint32_t>(ctx, st->tile_pbase, nt, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, st->slot_tile, st->max_slots, s));
+  DV_TRY(fill_u32(st->slot_tile.as<uint32_t>(), 0xFFFFFFFFu, st->max_slots, s));
   DV_TRY(alloc_n<uint32_t>(ctx, st->plan_counts, 2, s));
   DV_TRY(alloc_n<float>(ctx, st->chunk_b, st->max_slots * CB_SPLIT * TPB, s));
   DV_TRY(alloc_n<float4>(ctx, st->chunk_part, st->max_slots * TPB * 4, s));
@@ -2073,7 +2087,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
                                 st->aitem_pair.as<uint32_t>(),
                                 st->aitem_chunk.as<uint32_t>(),
                                 st->aorder.as<uint32_t>(),
-                                st->aplan_counts.as<uint32_t>()};
+                                st->aplan_counts.as<uint32_t>(), nullptr};
   }
   if (nt > 0)
     plans[n_plans++] = PlanArgs{nt, st->tile_start.as<uint32_t>(),
@@ -2084,7 +2098,8 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
                                 st->item_tile.as<uint32_t>(),
                                 st->item_chunk.as<uint32_t>(),
                                 st->order_fwd.as<uint32_t>(),
-                                st->plan_counts.as<uint32_t>()};
+                                st->plan_counts.as<uint32_t>(),
+                                st->slot_tile.as<uint32_t>()};
   if (n_plans > 0) {
     hipLaunchKernelGGL(k_plan_items, dim3(n_plans), dim3(1024), 0, s, plans[0],
                        plans[n_plans - 1]);
@@ -2181,7 +2196,9 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
     const unsigned ni = (unsigned)st->max_items;
     {
       StageTimer tm_ch(ctx, ST_OTHER, s);
-      hipLaunchKernelGGL(k_chunk_bounds, dim3(ni * CB_SPLIT), dim3(TPB), 0, s, ca);
+      const unsigned gb = (unsigned)std::min<int64_t>(st->max_slots, 2048) * CB_SPLIT;
+      hipLaunchKernelGGL(k_chunk_bounds, dim3(gb), dim3(TPB), 0, s, ca,
+                         (const uint32_t*)st->slot_tile.as<uint32_t>());
     }
     if (!composite) {
       // the background walks are run by the caller (the serving kernel)

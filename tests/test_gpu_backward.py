@@ -49,7 +49,7 @@ def _close(name, g, ref, rel=1e-3, floor=1e-2, summed=None, extra=None):
     assert np.all(err <= bound), (name, worst)
 
 
-def _run(ctx, cfg, mask_normals=True, seed=0, pose=True):
+def _run(ctx, cfg, mask_normals=True, seed=0, pose=True, normal_grad=True):
     import torch
     from paper_2606_23031_amd import dv
     scene, view, opts = cfg["scene"], cfg["views"][0], cfg["opts"]
@@ -62,10 +62,11 @@ def _run(ctx, cfg, mask_normals=True, seed=0, pose=True):
     rng = np.random.default_rng(seed)
     h, w = view["h"], view["w"]
     G = dict(rgb=rng.normal(size=(3, h, w)), depth=rng.normal(size=(h, w)) * 0.3,
-             normal=rng.normal(size=(3, h, w)) if mask_normals else np.zeros((3, h, w)),
+             normal=(rng.normal(size=(3, h, w)) if mask_normals and normal_grad
+                     else np.zeros((3, h, w))),
              T=rng.normal(size=(h, w)))
     gt = {k: torch.tensor(v, dtype=torch.float32, device="cuda") for k, v in G.items()}
-    if not mask_normals:
+    if not (mask_normals and normal_grad):
         gt["normal"] = None
     acc = [dict(corner=torch.zeros(len(o["corner_density"]), device="cuda"),
                 sh=torch.zeros(o["sh"].shape, device="cuda"))
@@ -95,6 +96,21 @@ def test_backward_matches_oracle_adjoint(ctx, seed, K, overlap, normals):
     cfg = actor_scene(seed=seed, n_actors=3 if overlap else 2, deg=2,
                       overlap=overlap, K=K)
     acc, pg, ref, _ = _run(ctx, cfg, mask_normals=normals, seed=seed)
+    for k in range(len(acc)):
+        _close(f"corner[{k}]", acc[k]["corner"].cpu().numpy(), ref["corner"][k])
+        _close(f"sh[{k}]", acc[k]["sh"].cpu().numpy(), ref["sh"][k])
+    p = pg.cpu().numpy()[0]
+    for i in range(len(acc) - 1):
+        _close(f"dR[{i}]", p[i, :9].reshape(3, 3), ref["dR"][i + 1])
+        _close(f"dp[{i}]", p[i, 9:], ref["dp"][i + 1])
+
+
+def test_backward_normals_rendered_without_normal_gradient(ctx):
+    """Normals are rendered but no view passes a normal gradient: the
+    backward runs without normal terms (they are exactly zero), and the
+    gradients equal the oracle's adjoint with a zero normal gradient."""
+    cfg = actor_scene(seed=5, n_actors=2, deg=2)
+    acc, pg, ref, _ = _run(ctx, cfg, mask_normals=True, seed=5, normal_grad=False)
     for k in range(len(acc)):
         _close(f"corner[{k}]", acc[k]["corner"].cpu().numpy(), ref["corner"][k])
         _close(f"sh[{k}]", acc[k]["sh"].cpu().numpy(), ref["sh"][k])
