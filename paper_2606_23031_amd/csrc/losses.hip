@@ -46,14 +46,33 @@ struct LossView {
   float* g_T;
 };
 
+// Per-block sums go to LS_SLOTS accumulators per quantity (block b adds to
+// slot b % LS_SLOTS, LS_STRIDE doubles apart), summed by k_loss_finish:
+// thousands of blocks adding to one word serialise on it.
+constexpr int LS_SLOTS = 64;
+constexpr int LS_STRIDE = 8;
+// quantities: pixel counts of depth, normal, sky; sums of L1, SSIM, depth,
+// normal, sky
+enum { LQ_CD, LQ_CN, LQ_CS, LQ_L1, LQ_SSIM, LQ_DEP, LQ_NOR, LQ_SKY, LQ_N };
+
 struct LossArgs {
   LossView v;
   dv_loss_weights lam;
   float win[2 * LR + 1];
   double* terms;            // [8] of this view
-  unsigned int* counts;     // [3] of this view: depth, normal, sky pixels
+  double* acc;              // [LQ_N][LS_SLOTS][LS_STRIDE] of this view
   float* part;              // [3 channels][3 partials][h][w] (SSIM pass)
 };
+
+__device__ inline void acc_add(const LossArgs& a, int q, double x) {
+  if (x != 0.0)
+    atomicAdd(a.acc + ((size_t)q * LS_SLOTS + blockIdx.x % LS_SLOTS) * LS_STRIDE, x);
+}
+__device__ inline double acc_total(const double* acc, int q) {
+  double s = 0.0;
+  for (int i = 0; i < LS_SLOTS; ++i) s += acc[((size_t)q * LS_SLOTS + i) * LS_STRIDE];
+  return s;
+}
 
 __device__ inline double block_sum(double x, double* lds) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -86,9 +105,9 @@ __global__ void __launch_bounds__(TPB) k_loss_count(LossArgs a) {
   cn = block_sum(cn, lds);
   cs = block_sum(cs, lds);
   if (threadIdx.x == 0) {
-    if (cd > 0) atomicAdd(a.counts + 0, (unsigned int)cd);
-    if (cn > 0) atomicAdd(a.counts + 1, (unsigned int)cn);
-    if (cs > 0) atomicAdd(a.counts + 2, (unsigned int)cs);
+    acc_add(a, LQ_CD, cd);
+    acc_add(a, LQ_CN, cn);
+    acc_add(a, LQ_CS, cs);
   }
 }
 
@@ -98,8 +117,10 @@ __global__ void __launch_bounds__(TPB) k_loss_count(LossArgs a) {
 __global__ void __launch_bounds__(TPB) k_loss_point(LossArgs a) {
   __shared__ double lds[TPB / 64];
   const int64_t n = (int64_t)a.v.h * a.v.w;
-  const float nd = (float)max(a.counts[0], 1u), nn = (float)max(a.counts[1], 1u),
-              ns = (float)max(a.counts[2], 1u);
+  __shared__ float cnt[3];
+  if (threadIdx.x < 3) cnt[threadIdx.x] = (float)fmax(acc_total(a.acc, threadIdx.x), 1.0);
+  __syncthreads();
+  const float nd = cnt[0], nn = cnt[1], ns = cnt[2];
   const dv_loss_weights& L = a.lam;
   const float k1 = L.color * (1.0f - L.ssim) / (3.0f * (float)n);
   double s1 = 0, sd = 0, sn = 0, ss = 0;
@@ -179,10 +200,10 @@ __global__ void __launch_bounds__(TPB) k_loss_point(LossArgs a) {
   sn = block_sum(sn, lds);
   ss = block_sum(ss, lds);
   if (threadIdx.x == 0) {
-    atomicAdd(a.terms + 2, s1);
-    atomicAdd(a.terms + 4, sd);
-    atomicAdd(a.terms + 5, sn);
-    atomicAdd(a.terms + 6, ss);
+    acc_add(a, LQ_L1, s1);
+    acc_add(a, LQ_DEP, sd);
+    acc_add(a, LQ_NOR, sn);
+    acc_add(a, LQ_SKY, ss);
   }
 }
 
@@ -254,7 +275,7 @@ __global__ void __launch_bounds__(TPB) k_ssim_a(LossArgs a) {
     a.part[(c * 3 + 2) * n + o] = dxy;
   }
   ssum = block_sum(ssum, lds);
-  if (threadIdx.x == 0) atomicAdd(a.terms + 3, ssum);
+  if (threadIdx.x == 0) acc_add(a, LQ_SSIM, ssum);
 }
 
 // SSIM pass 2: dSSIM/dx = w * dm + 2 x (w * dxx) + y (w * dxy), scaled by
@@ -301,13 +322,13 @@ __global__ void __launch_bounds__(TPB) k_ssim_b(LossArgs a) {
 
 // Per view: the sums into terms [total, color, l1, ssim, depth, normal,
 // sky, 0] (means and the weighted total).
-__global__ void k_loss_finish(double* terms, const unsigned int* counts,
-                              int64_t n, dv_loss_weights L, int has_rgb) {
-  const double l1 = terms[2] / (3.0 * (double)n);
-  const double ss = has_rgb ? terms[3] / (3.0 * (double)n) : 1.0;
-  const double dep = terms[4] / (double)max(counts[0], 1u);
-  const double nor = terms[5] / (double)max(counts[1], 1u);
-  const double sky = terms[6] / (double)max(counts[2], 1u);
+__global__ void k_loss_finish(double* terms, const double* acc, int64_t n,
+                              dv_loss_weights L, int has_rgb) {
+  const double l1 = acc_total(acc, LQ_L1) / (3.0 * (double)n);
+  const double ss = has_rgb ? acc_total(acc, LQ_SSIM) / (3.0 * (double)n) : 1.0;
+  const double dep = acc_total(acc, LQ_DEP) / fmax(acc_total(acc, LQ_CD), 1.0);
+  const double nor = acc_total(acc, LQ_NOR) / fmax(acc_total(acc, LQ_CN), 1.0);
+  const double sky = acc_total(acc, LQ_SKY) / fmax(acc_total(acc, LQ_CS), 1.0);
   const double col = (1.0 - L.ssim) * l1 + L.ssim * (1.0 - ss);
   terms[0] = L.color * col + L.depth * dep + L.normal * nor + L.sky * sky;
   terms[1] = col;
@@ -380,10 +401,10 @@ dv_status dv_loss(dv_ctx* ctx, const dv_loss_view* views, int32_t n_views,
     }
     for (int k = 0; k < 2 * LR + 1; ++k) win[k] = (float)(g[k] / sum);
   }
-  DBuf counts;
-  DV_TRY(alloc_n<unsigned int>(ctx, counts, (size_t)3 * n_views, s));
-  DV_TRY(fill_u32(counts.as<uint32_t>(), 0u, 3 * n_views, s));
-  DV_TRY(fill_u32(reinterpret_cast<uint32_t*>(terms), 0u, 16 * (int64_t)n_views, s));
+  DBuf accs;
+  const size_t per_view = (size_t)LQ_N * LS_SLOTS * LS_STRIDE;
+  DV_TRY(alloc_n<double>(ctx, accs, per_view * n_views, s));
+  DV_TRY(fill_u32(accs.as<uint32_t>(), 0u, 2 * (int64_t)(per_view * n_views), s));
   for (int i = 0; i < n_views; ++i) {
     const dv_loss_view& V = views[i];
     if (V.h < 1 || V.w < 1) {
@@ -406,7 +427,7 @@ dv_status dv_loss(dv_ctx* ctx, const dv_loss_view* views, int32_t n_views,
     a.lam = *lam;
     std::memcpy(a.win, win, sizeof(win));
     a.terms = terms + 8 * (size_t)i;
-    a.counts = counts.as<unsigned int>() + 3 * i;
+    a.acc = accs.as<double>() + per_view * i;
     const int64_t n = (int64_t)V.h * V.w;
     const unsigned g = std::min<int64_t>(grid_for(n, TPB), 4096);
     hipLaunchKernelGGL(k_loss_count, dim3(g), dim3(TPB), 0, s, a);
@@ -422,8 +443,8 @@ dv_status dv_loss(dv_ctx* ctx, const dv_loss_view* views, int32_t n_views,
       if (lam->ssim != 0.0f && lam->color != 0.0f)
         hipLaunchKernelGGL(k_ssim_b, dim3((unsigned)(ntx * nty), 3), dim3(TPB), 0, s, a);
     }
-    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(1), 0, s, a.terms, a.counts, n,
-                       *lam, has_rgb ? 1 : 0);
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(1), 0, s, a.terms,
+                       (const double*)a.acc, n, *lam, has_rgb ? 1 : 0);
     DV_TRY_HIP(hipGetLastError());
   }
   return DV_OK;

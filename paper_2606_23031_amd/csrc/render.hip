@@ -2196,7 +2196,7 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
     const unsigned ni = (unsigned)st->max_items;
     {
       StageTimer tm_ch(ctx, ST_OTHER, s);
-      const unsigned gb = (unsigned)std::min<int64_t>(st->max_slots, 2048) * CB_SPLIT;
+      const unsigned gb = (unsigned)std::min<int64_t>(st->max_slots, 16384) * CB_SPLIT;
       hipLaunchKernelGGL(k_chunk_bounds, dim3(gb), dim3(TPB), 0, s, ca,
                          (const uint32_t*)st->slot_tile.as<uint32_t>());
     }
