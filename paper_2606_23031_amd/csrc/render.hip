@@ -772,6 +772,88 @@ __device__ inline int build_segments(const CompArgs& a, uint32_t sbase,
   return nseg;
 }
 
+// The same sweep with the box intervals in registers, for tiles of at most
+// BS_REG actor boxes: no box slot is written and read back, and the open
+// segment is stored once it is complete.  Same comparisons in the same
+// order, so the segments are those of build_segments.
+constexpr int BS_REG = 8;
+__device__ inline void store_segment(const CompArgs& a, uint32_t q, int tid,
+                                     float s, float e, uint32_t meta) {
+  const size_t qi = seg_index(q, tid);
+  a.seg_se[qi] = make_float2(s, e);
+  a.seg_meta[qi] = meta;
+  a.seg_p0[qi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  a.seg_p1[qi] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+  a.seg_t0[qi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  a.seg_t1[qi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+__device__ inline int build_segments_reg(const CompArgs& a, uint32_t seg0,
+                                         int n_at, uint32_t a_beg, int v,
+                                         float3 d, int tid) {
+  float bs[BS_REG], be[BS_REG];
+  uint32_t bm[BS_REG];
+#pragma unroll
+  for (int j = 0; j < BS_REG; ++j) {
+    bs[j] = F_INF;
+    be[j] = F_INF;
+    bm[j] = 0u;  // no box: never a breakpoint, never an owner
+    if (j < n_at) {
+      const VOConst& C = a.vo[v * a.n_oct + a.act_oct[a_beg + j]];
+      const float3 dj = mat3_mul(C.Rt, d);
+      const float3 inv = safe_inv(dj);
+      float t0, t1;
+      int a0, a1;
+      slab_axes(make_float3(C.boxlo[0], C.boxlo[1], C.boxlo[2]),
+                make_float3(C.boxhi[0], C.boxhi[1], C.boxhi[2]), inv, t0, t1,
+                a0, a1);
+      uint32_t s0 = src_code(j, a0);
+      if (t0 < a.tau_near) { t0 = a.tau_near; s0 = SRC_NONE; }
+      bs[j] = t0;
+      be[j] = t1;
+      bm[j] = s0 | (src_code(j, a1) << 10) | ((t1 > t0) ? (1u << 20) : 0u);
+    }
+  }
+  int nseg = 0;
+  float cur = -F_INF;
+  uint32_t cur_src = SRC_NONE;
+  float ls = 0.0f, le = 0.0f;  // the last segment, stored when complete
+  uint32_t lm = 0u;
+  for (int guard = 0; guard < 2 * n_at + 1; ++guard) {
+    float nb = F_INF;
+    uint32_t nb_src = SRC_NONE;
+#pragma unroll
+    for (int j = 0; j < BS_REG; ++j) {
+      if (!(bm[j] & (1u << 20))) continue;
+      if (bs[j] > cur && bs[j] < nb) { nb = bs[j]; nb_src = bm[j] & 0x3FF; }
+      if (be[j] > cur && be[j] < nb) { nb = be[j]; nb_src = (bm[j] >> 10) & 0x3FF; }
+    }
+    if (nb == F_INF) break;
+    int owner = -1;
+    if (cur > -F_INF) {
+      // the lowest index containing cur
+#pragma unroll
+      for (int j = BS_REG - 1; j >= 0; --j)
+        if ((bm[j] & (1u << 20)) && bs[j] <= cur && cur < be[j]) owner = j;
+    }
+    if (owner >= 0) {
+      if (nseg > 0 && (int)(lm & 0xFF) == owner && le == cur) {
+        le = nb;
+        lm = (lm & ~(0x3FFu << 18)) | (nb_src << 18);
+      } else {
+        if (nseg > 0) store_segment(a, seg0 + nseg - 1, tid, ls, le, lm);
+        ls = cur;
+        le = nb;
+        lm = (uint32_t)owner | (cur_src << 8) | (nb_src << 18);
+        ++nseg;
+      }
+    }
+    cur = nb;
+    cur_src = nb_src;
+  }
+  if (nseg > 0) store_segment(a, seg0 + nseg - 1, tid, ls, le, lm);
+  return nseg;
+}
+
 __device__ inline int next_seg_of(const CompArgs& a, uint32_t seg0, int nseg,
                                   int from, int j, int tid) {
   for (int q = from; q < nseg; ++q)
@@ -804,15 +886,21 @@ __device__ inline void write_outputs(const A& a, const ViewConst& V, int v,
 
 // Forward, part 1a (tiles with actor boxes): per pixel, the ownership
 // segments of the actor boxes its ray meets.
+// One block per (tile, actor) pair; the block of the tile's first pair
+// builds the tile's segments, the others exit (no block is spent on tiles
+// without actor boxes).
 __global__ void __launch_bounds__(TPB) k_build_segments(CompArgs a) {
-  const uint32_t gt = blockIdx.x;
+  const uint32_t gt = a.act_tile[blockIdx.x];
   const uint32_t a_beg = a.act_beg[gt];
+  if (blockIdx.x != a_beg) return;
   const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
-  if (n_at == 0) return;
   const int tid = threadIdx.x;
   const PixSetup P = pixel_setup(a, gt, tid);
   int nseg = 0;
-  if (P.valid) nseg = build_segments(a, 3 * a_beg, n_at, a_beg, P.v, P.d, tid);
+  if (P.valid)
+    nseg = n_at <= BS_REG
+               ? build_segments_reg(a, 3 * a_beg + n_at, n_at, a_beg, P.v, P.d, tid)
+               : build_segments(a, 3 * a_beg, n_at, a_beg, P.v, P.d, tid);
   a.pix_nseg[P.pix] = (uint32_t)nseg;
 }
 
@@ -1075,15 +1163,33 @@ __global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a,
       wave_live_masks(B.rect, nb, P.bx, P.by, __ballot(!found), wm);
       for (int q = 0; q < 4; ++q) {
         uint64_t m = wm[q];
+        // four entries per step: independent slab tests, and the first
+        // chord among them in list order
         while (m != 0 && __ballot(!found) != 0) {
-          const uint32_t r = (uint32_t)q * 64 + (uint32_t)__builtin_ctzll(m);
-          m &= m - 1;
-          if (found) continue;
-          const float4 geo = B.geo[r];
-          float t0, t1;
-          batch_slab<false>(B, r, geo, inv, t0, t1);
-          t0 = fmaxf(t0, a.tau_near);
-          if (t1 > t0) { Bc = t0; found = true; }
+          uint32_t r[4];
+          int nr = 0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            r[k] = (uint32_t)q * 64 + (uint32_t)__builtin_ctzll(m | (1ull << 63));
+            if (m != 0) { m &= m - 1; ++nr; }
+          }
+          float h0[4];
+          bool hk[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const float4 geo = B.geo[r[k]];
+            float t0, t1;
+            batch_slab<false>(B, r[k], geo, inv, t0, t1);
+            t0 = fmaxf(t0, a.tau_near);
+            h0[k] = t0;
+            hk[k] = k < nr && t1 > t0;
+          }
+          if (!found) {
+#pragma unroll
+            for (int k = 3; k >= 0; --k)
+              if (hk[k]) Bc = h0[k];
+            found = hk[0] || hk[1] || hk[2] || hk[3];
+          }
         }
       }
       if (__syncthreads_and(found)) break;
@@ -1206,6 +1312,8 @@ __device__ __forceinline__ void composite_item(const A& a, uint32_t idx,
           w_piece += (uint32_t)__popcll(hm);
           ++w_iter;
           w_hit += hm != 0 ? 1u : 0u;
+          // (a straight-line form with the empty piece for lanes without a
+          // chord, as in the backward, is slower here)
           if (chord) add_piece(r, geo, t0, t1);
           continue;
         }
@@ -2187,7 +2295,8 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
     const bool k1 = op.K == 1;
     if (st->n_apairs > 0) {
       StageTimer tm_act(ctx, ST_ACTOR_FWD, s);
-      hipLaunchKernelGGL(k_build_segments, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
+      hipLaunchKernelGGL(k_build_segments, dim3((unsigned)st->n_apairs), dim3(TPB), 0, s,
+                         ca);
       auto ka = nrm ? (k1 ? k_actor_fwd<true, 1> : k_actor_fwd<true, 0>)
                     : (k1 ? k_actor_fwd<false, 1> : k_actor_fwd<false, 0>);
       hipLaunchKernelGGL(ka, dim3((unsigned)st->max_aitems), dim3(TPB), 0, s, ca);
