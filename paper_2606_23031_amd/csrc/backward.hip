@@ -219,6 +219,21 @@ __device__ inline void flush_batch(BwdBatch& B, const CompArgs& a,
   }
 }
 
+// One lane's gradients of entry r added to the batch slot (LDS atomics),
+// for walks in which the lanes of a wave hold different entries.
+template <bool NORMALS>
+__device__ inline void lane_record(BwdBatch& B, uint32_t r, float3 dcol,
+                                   float3 dnrm, const float* dg) {
+  float v[NACC];
+  v[0] = dcol.x; v[1] = dcol.y; v[2] = dcol.z;
+  v[3] = dnrm.x; v[4] = dnrm.y; v[5] = dnrm.z;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) v[6 + m] = dg[m];
+#pragma unroll
+  for (int c = 0; c < NACC; ++c)
+    if ((NORMALS || c < 3 || c >= 6) && v[c] != 0.0f) atomicAdd(&B.acc[c][r], v[c]);
+}
+
 // Block-reduce 12 floats per thread and add them to dst (one atomic each).
 // Called by the whole block.
 __device__ inline void block_add12(float* red, const float* v12, float* dst) {
@@ -943,7 +958,48 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
       load_bwd_batch<NORMALS>(B, a, base, nb);
       __syncthreads();
       uint64_t wm[4];
-      wave_live_masks(B.rect, nb, bx, by, __ballot(live()), wm);
+      const uint64_t lv = __ballot(live());
+      wave_live_masks(B.rect, nb, bx, by, lv, wm);
+      if (single && sparse_cover(B.rect, nb, bx, by, lv, wm)) {
+        // entries cover few of the wave's pixels (far actors): every lane
+        // walks its own entries, those whose rectangle holds its pixel, and
+        // adds its gradients to the entry's slot itself
+        uint64_t pm[4];
+        lane_masks(B.rect, wm, P.px, P.py, pm);
+        for (int wc = 0; wc < 4; ++wc) {
+          uint64_t m = pm[wc];
+          while (__ballot(m != 0 && live()) != 0) {
+            // a lane without an entry reads slot 0 (loaded) and takes the
+            // empty piece
+            const uint32_t r =
+                m != 0 ? (uint32_t)wc * 64 + (uint32_t)__builtin_ctzll(m) : 0u;
+            const bool own = m != 0;
+            m &= m - 1;
+            const bool act = own && live() && base + r >= wlo && base + r < whi;
+            const float4 geo = B.geo[r];
+            float t0, t1;
+            int ax0, ax1;
+            float3 hi;
+            if (NORMALS) {
+              hi = leaf_hi(geo);
+            } else {
+              const float4 h4 = B.nrm[r];
+              hi = make_float3(h4.x, h4.y, h4.z);
+            }
+            slab_axes(make_float3(geo.x, geo.y, geo.z), hi, inv, t0, t1, ax0, ax1);
+            n_test += act ? 1u : 0u;
+            const float pa0 = fmaxf(t0, qs), pb0 = fminf(t1, qe);
+            const bool hit = act && pb0 > pa0;
+            if (act && t1 > t0 && t1 > qs && (qe <= t0 || t1 > qe)) fin = true;
+            if (__ballot(hit) == 0) continue;
+            const float pa = hit ? pa0 : 0.0f, pb = hit ? pb0 : 0.0f;
+            float3 dcol, dnrm = make_float3(0, 0, 0);
+            float dg[8];
+            piece(r, geo, t0, t1, ax0, ax1, pa, pb, dcol, dnrm, dg, true, hit);
+            if (hit) lane_record<NORMALS>(B, r, dcol, dnrm, dg);
+          }
+        }
+      } else {
       for (int wc = 0; wc < 4; ++wc) {
       uint64_t m = wm[wc];
       if (single) {
@@ -1015,6 +1071,7 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
           }
         }
         accum_record<NORMALS>(B, r, hit, dcol, dnrm, dg);
+      }
       }
       }
       flush_batch(B, a, nb);

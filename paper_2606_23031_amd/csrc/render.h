@@ -162,6 +162,62 @@ __device__ inline void wave_live_masks(const uint2* rect, uint32_t nb, int bx,
   }
 }
 
+// Whether the wave's selected entries (masks wm from wave_live_masks over
+// the live lanes `lanes`) cover, on average, less than a quarter of the
+// live-lane box: then a walk in which every lane takes only the entries
+// whose rectangle holds its own pixel (lane_masks) does fewer iterations
+// than the walk over the wave's union of entries.  Wave-uniform.
+__device__ inline bool sparse_cover(const uint2* rect, uint32_t nb, int bx,
+                                    int by, uint64_t lanes, const uint64_t m[4]) {
+  if (lanes == 0) return false;
+  uint64_t cols = lanes | (lanes >> 32);
+  cols |= cols >> 16;
+  cols |= cols >> 8;
+  cols &= 0xFFull;
+  const int x0 = bx + __builtin_ctzll(cols);
+  const int x1 = bx + 63 - __builtin_clzll(cols);
+  const int y0 = by + (__builtin_ctzll(lanes) >> 3);
+  const int y1 = by + ((63 - __builtin_clzll(lanes)) >> 3);
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t cov = 0, n = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    n += (uint32_t)__popcll(m[c]);
+    if ((m[c] >> lane) & 1ull) {
+      const uint2 rc = rect[c * 64 + lane];
+      const int xl = max((int)(rc.x & 0xFFFF), x0), xh = min((int)(rc.x >> 16), x1);
+      const int yl = max((int)(rc.y & 0xFFFF), y0), yh = min((int)(rc.y >> 16), y1);
+      cov += (uint32_t)((xh - xl + 1) * (yh - yl + 1));
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cov += __shfl_xor(cov, o, 64);
+  const uint32_t box = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+  return 4u * cov < n * box;
+}
+
+// Per-lane masks: of the wave's selected entries (wm), those whose
+// rectangle holds the lane's own pixel (px, py).  An entry whose rectangle
+// misses the pixel has no chord on the pixel's ray (the rectangle covers
+// every pixel the leaf's chord can reach), so a lane that skips it walks
+// the same pieces in the same order.
+__device__ inline void lane_masks(const uint2* rect, const uint64_t wm[4],
+                                  int px, int py, uint64_t pm[4]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    uint64_t m = wm[c], out = 0;
+    while (m != 0) {
+      const int b = __builtin_ctzll(m);
+      m &= m - 1;
+      const uint2 rc = rect[c * 64 + b];
+      const bool in = (int)(rc.x & 0xFFFF) <= px && px <= (int)(rc.x >> 16) &&
+                      (int)(rc.y & 0xFFFF) <= py && py <= (int)(rc.y >> 16);
+      out |= in ? (1ull << b) : 0ull;
+    }
+    pm[c] = out;
+  }
+}
+
 __device__ inline int view_of_tile(const ViewConst* views, int n_views,
                                    uint32_t gt) {
   int lo = 0, hi = n_views - 1;

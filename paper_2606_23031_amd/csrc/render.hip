@@ -927,7 +927,7 @@ __device__ inline int segs_of_actor(const CompArgs& a, uint32_t seg0, int nseg,
 // chunk, merged by k_actor_merge), while rays with several segments of it
 // (overlapping boxes) walk the whole list in chunk 0.
 template <bool NORMALS, int KC>
-__global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
+__global__ void __launch_bounds__(TPB, NORMALS ? 4 : 5) k_actor_fwd(CompArgs a) {
   __shared__ Batch B;
   if (blockIdx.x >= a.aplan_counts[0]) return;
   const uint32_t item = a.aorder[blockIdx.x];
@@ -1021,30 +1021,52 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
   // piece is the chord clipped to [qs, qe), and a chord reaching past qe
   // ends the lane (later entries lie farther along the ray)
   const bool single = __ballot(nj > 1) == 0;
+  // one entry of the single-segment walk
+  auto single_entry = [&](uint32_t r, uint32_t base) {
+    if (live() && base + r >= wlo && base + r < whi) {
+      const float4 geo = B.geo[r];
+      float t0, t1;
+      batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
+      ++n_test;
+      const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
+      if (pb > pa) {
+        piece(r, geo, pa, pb);
+        ++n_piece;
+      }
+      if (t1 > t0 && t1 > qs && (qe <= t0 || t1 > qe)) fin = true;
+    }
+  };
   for (uint32_t base = lo; base < hi; base += TPB) {
     const uint32_t nb = min((uint32_t)TPB, hi - base);
     load_batch<NORMALS>(B, a, base, nb);
     __syncthreads();
     uint64_t wm[4];
-    wave_live_masks(B.rect, nb, bx, by, __ballot(live()), wm);
+    const uint64_t lv = __ballot(live());
+    wave_live_masks(B.rect, nb, bx, by, lv, wm);
+    if (single && sparse_cover(B.rect, nb, bx, by, lv, wm)) {
+      // entries cover few of the wave's pixels (far actors): every lane
+      // walks its own entries, those whose rectangle holds its pixel
+      uint64_t pm[4];
+      lane_masks(B.rect, wm, P.px, P.py, pm);
+      for (int c = 0; c < 4; ++c) {
+        uint64_t m = pm[c];
+        while (__ballot(m != 0 && live()) != 0) {
+          const uint32_t r =
+              m != 0 ? (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m) : 0u;
+          if (m != 0) {
+            m &= m - 1;
+            single_entry(r, base);
+          }
+        }
+      }
+    } else {
     for (int c = 0; c < 4; ++c) {
       uint64_t m = wm[c];
       if (single) {
         while (m != 0 && __ballot(live()) != 0) {
           const uint32_t r = (uint32_t)c * 64 + (uint32_t)__builtin_ctzll(m);
           m &= m - 1;
-          if (live() && base + r >= wlo && base + r < whi) {
-            const float4 geo = B.geo[r];
-            float t0, t1;
-            batch_slab<NORMALS>(B, r, geo, inv, t0, t1);
-            ++n_test;
-            const float pa = fmaxf(t0, qs), pb = fminf(t1, qe);
-            if (pb > pa) {
-              piece(r, geo, pa, pb);
-              ++n_piece;
-            }
-            if (t1 > t0 && t1 > qs && (qe <= t0 || t1 > qe)) fin = true;
-          }
+          single_entry(r, base);
         }
         continue;
       }
@@ -1082,6 +1104,7 @@ __global__ void __launch_bounds__(TPB) k_actor_fwd(CompArgs a) {
           break;
         }
       }
+    }
     }
     if (!__syncthreads_or(live())) break;
   }

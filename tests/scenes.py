@@ -67,9 +67,12 @@ def moving_track(yaw0, yaw1, p0, p1, t0=0.0, t1=10.0):
                 trans=np.array([p0, p1], np.float64))
 
 
-def actor_scene(seed=0, n_actors=2, deg=1, overlap=False, K=1, bg_levels=(2, 24, 4)):
+def actor_scene(seed=0, n_actors=2, deg=1, overlap=False, K=1, bg_levels=(2, 24, 4),
+                fov=60.0, target=(0.0, 0.0, 0.0)):
     """Small background cube [-2,2]^3 with two or three actor cubes of side
-    1 inside the view; useful for parity and gradient pins."""
+    1 inside the view; useful for parity and gradient pins.  The default
+    view shows actor leaves of about one pixel; a narrow ``fov`` aimed at an
+    actor (``target``) shows them several pixels wide."""
     rng = np.random.default_rng(seed)
     b0, nsub, lmax = bg_levels
     bg = random_octree(rng, (-2.0, -2.0, -2.0), 4.0, b0, nsub, lmax, deg,
@@ -87,7 +90,7 @@ def actor_scene(seed=0, n_actors=2, deg=1, overlap=False, K=1, bg_levels=(2, 24,
         c = np.array(centres[i])
         tracks.append(moving_track(0.2 + 0.3 * i, 0.5 + 0.3 * i, c, c + (0.3, 0.1, 0.0)))
     eye = np.array([3.0, 1.5, 1.2])
-    view = make_view(64, 48, 60.0, look_at_c2w(eye, (0.0, 0.0, 0.0)), t=2.5)
+    view = make_view(64, 48, fov, look_at_c2w(eye, target), t=2.5)
     opts = dict(K=K, eps_stop=0.0, tau_near=0.0, bg=(0.1, 0.2, 0.3),
                 explin_c=1.1)
     return dict(scene=dict(octrees=octs, tracks=tracks), views=[view],

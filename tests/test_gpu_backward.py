@@ -105,6 +105,23 @@ def test_backward_matches_oracle_adjoint(ctx, seed, K, overlap, normals):
         _close(f"dp[{i}]", p[i, 9:], ref["dp"][i + 1])
 
 
+@pytest.mark.parametrize("fov", [30.0, 14.0])
+def test_backward_actor_close_up(ctx, fov):
+    """Actor leaves several pixels wide: the actor backward walks over the
+    wave's entries with the butterfly reduction (all steps at 14 degrees,
+    about half at 30, the rest per lane with per-lane slot adds)."""
+    cfg = actor_scene(seed=13, n_actors=2, deg=2, fov=fov,
+                      target=(-0.55, 0.33, 0.11))
+    acc, pg, ref, _ = _run(ctx, cfg, mask_normals=True, seed=13)
+    for k in range(len(acc)):
+        _close(f"corner[{k}]", acc[k]["corner"].cpu().numpy(), ref["corner"][k])
+        _close(f"sh[{k}]", acc[k]["sh"].cpu().numpy(), ref["sh"][k])
+    p = pg.cpu().numpy()[0]
+    for i in range(len(acc) - 1):
+        _close(f"dR[{i}]", p[i, :9].reshape(3, 3), ref["dR"][i + 1])
+        _close(f"dp[{i}]", p[i, 9:], ref["dp"][i + 1])
+
+
 def test_backward_normals_rendered_without_normal_gradient(ctx):
     """Normals are rendered but no view passes a normal gradient: the
     backward runs without normal terms (they are exactly zero), and the

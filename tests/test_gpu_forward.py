@@ -92,6 +92,23 @@ def test_actor_scene_parity(ctx, seed, overlap, K):
     _lists_equal(ctx, st, cfg["scene"], v)
 
 
+@pytest.mark.parametrize("fov", [30.0, 14.0])
+def test_actor_close_up_parity(ctx, fov):
+    # the default actor views show leaves of about a pixel, so the actor
+    # walks take every lane's own entries; close up (leaves several pixels
+    # wide) the walk over the wave's entries runs too: at 30 degrees about
+    # half of the (quadrant, batch) steps take each walk, at 14 all take
+    # the wave's
+    from gpu_helpers import render_gpu
+    cfg = actor_scene(seed=12, n_actors=2, deg=2, fov=fov,
+                      target=(-0.55, 0.33, 0.11))
+    v = cfg["views"][0]
+    res, st, _ = render_gpu(ctx, cfg["scene"], [v], cfg["opts"], keep=True)
+    ref = _oracle(cfg["scene"], v, cfg["opts"])
+    _compare(res[0], ref)
+    _lists_equal(ctx, st, cfg["scene"], v)
+
+
 @pytest.mark.parametrize("eps", [0.0, 1e-4])
 def test_chunked_tiles_parity(ctx, eps):
     # every tile's list (2.7k-4.2k entries) is split into chunks whose
