@@ -1,4 +1,5 @@
-// Stable LSD radix sort of (key, value) pairs, 8-bit digits.
+// Stable LSD radix sort of (key, value) pairs, 8- or 9-bit digits (the
+// width that needs fewer passes over the key bits; 8 on a tie).
 //
 // Each pass: per-block digit histograms (LDS atomics), a device scan of the
 // digit-major count matrix, and a stable scatter.  In the scatter every
@@ -14,38 +15,43 @@ namespace dv {
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = TPB * RS_ITEMS;     // 4096 keys per block
 constexpr int RS_WAVE_SPAN = 64 * RS_ITEMS;  // 1024 keys per wave
-constexpr int RS_BINS = 256;
 
-template <class K>
+template <class K, int DB>
 __global__ void __launch_bounds__(TPB)
 k_rs_hist(const K* __restrict__ keys, int64_t n, int sh,
           uint32_t* __restrict__ counts, int64_t nb) {
-  __shared__ uint32_t hist[RS_BINS];
-  hist[threadIdx.x] = 0;
+  constexpr int BINS = 1 << DB;
+  constexpr uint32_t MASK = BINS - 1;
+  __shared__ uint32_t hist[BINS];
+  for (int d = threadIdx.x; d < BINS; d += TPB) hist[d] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * RS_TILE;
 #pragma unroll
   for (int i = 0; i < RS_ITEMS; ++i) {
     int64_t idx = base + (int64_t)i * TPB + threadIdx.x;
     if (idx < n) {
-      uint32_t d = (uint32_t)(keys[idx] >> sh) & 0xFF;
+      uint32_t d = (uint32_t)(keys[idx] >> sh) & MASK;
       atomicAdd(&hist[d], 1u);
     }
   }
   __syncthreads();
-  counts[(int64_t)threadIdx.x * nb + blockIdx.x] = hist[threadIdx.x];
+  for (int d = threadIdx.x; d < BINS; d += TPB)
+    counts[(int64_t)d * nb + blockIdx.x] = hist[d];
 }
 
-template <class K>
+template <class K, int DB>
 __global__ void __launch_bounds__(TPB)
 k_rs_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
              K* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n,
              int sh, const uint32_t* __restrict__ offs, int64_t nb) {
-  __shared__ uint32_t wcnt[TPB / 64][RS_BINS];
-  __shared__ uint32_t wbase[TPB / 64][RS_BINS];
+  constexpr int BINS = 1 << DB;
+  constexpr uint32_t MASK = BINS - 1;
+  __shared__ uint32_t wcnt[TPB / 64][BINS];
+  __shared__ uint32_t wbase[TPB / 64][BINS];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = threadIdx.x; d < BINS; d += TPB)
 #pragma unroll
-  for (int i = 0; i < TPB / 64; ++i) wcnt[i][threadIdx.x] = 0;
+    for (int i = 0; i < TPB / 64; ++i) wcnt[i][d] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * RS_WAVE_SPAN;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -57,10 +63,10 @@ k_rs_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
     const bool valid = idx < n;
     K k = valid ? kin[idx] : (K)0;
     uint32_t v = valid ? vin[idx] : 0u;
-    uint32_t d = (uint32_t)(k >> sh) & 0xFF;
+    uint32_t d = (uint32_t)(k >> sh) & MASK;
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < DB; ++b) {
       const bool bit = (d >> b) & 1;
       uint64_t bb = __ballot(bit);
       peers &= bit ? bb : ~bb;
@@ -76,8 +82,7 @@ k_rs_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
     pos[j] = c0 + r;
   }
   __syncthreads();
-  {
-    const int d = threadIdx.x;
+  for (int d = threadIdx.x; d < BINS; d += TPB) {
     uint32_t off = offs[(int64_t)d * nb + blockIdx.x];
 #pragma unroll
     for (int i = 0; i < TPB / 64; ++i) {
@@ -108,20 +113,26 @@ static dv_status radix_sort(dv_ctx* ctx, K* keys, uint32_t* vals, K* kalt,
     return DV_ERR_LIMIT;
   }
   const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+  // 9-bit digits where they save a pass (18 bits: 2 passes, not 3)
+  const bool wide = (bits + 8) / 9 < (bits + 7) / 8;
+  const int db = wide ? 9 : 8;
+  const int64_t bins = (int64_t)1 << db;
   DBuf cnt, off;
-  DV_TRY(alloc_n<uint32_t>(ctx, cnt, nb * RS_BINS, s));
-  DV_TRY(alloc_n<uint32_t>(ctx, off, nb * RS_BINS, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, cnt, nb * bins, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, off, nb * bins, s));
   K* ka = keys;
   uint32_t* va = vals;
   K* kb = kalt;
   uint32_t* vb = valt;
-  for (int sh = 0; sh < bits; sh += 8) {
-    hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nb), dim3(TPB), 0, s, ka,
-                       n, sh, cnt.as<uint32_t>(), nb);
+  auto hist = wide ? k_rs_hist<K, 9> : k_rs_hist<K, 8>;
+  auto scatter = wide ? k_rs_scatter<K, 9> : k_rs_scatter<K, 8>;
+  for (int sh = 0; sh < bits; sh += db) {
+    hipLaunchKernelGGL(hist, dim3((unsigned)nb), dim3(TPB), 0, s, ka, n, sh,
+                       cnt.as<uint32_t>(), nb);
     DV_TRY(exclusive_scan_u32(ctx, cnt.as<uint32_t>(), off.as<uint32_t>(),
-                              nullptr, nb * RS_BINS, s));
-    hipLaunchKernelGGL(k_rs_scatter<K>, dim3((unsigned)nb), dim3(TPB), 0, s,
-                       ka, va, kb, vb, n, sh, off.as<uint32_t>(), nb);
+                              nullptr, nb * bins, s));
+    hipLaunchKernelGGL(scatter, dim3((unsigned)nb), dim3(TPB), 0, s, ka, va, kb,
+                       vb, n, sh, off.as<uint32_t>(), nb);
     DV_TRY_HIP(hipGetLastError());
     std::swap(ka, kb);
     std::swap(va, vb);
