@@ -1685,7 +1685,7 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   ca.atps = atps.as<float2>();
   // the same work items as the forward, ordered by the work each took there
   DV_TRY(alloc_n<uint32_t>(ctx, st->order_bwd, st->max_items, s));
-  DV_TRY(launch_order_by_weight(st->max_items, nullptr, st->item_work.as<uint32_t>(),
+  DV_TRY(launch_order_by_weight(ctx, st->max_items, nullptr, st->item_work.as<uint32_t>(),
                                 st->order_bwd.as<uint32_t>(), s));
   ca.order = st->order_bwd.as<uint32_t>();
   ca.act_tile = st->act_tile.as<uint32_t>();

@@ -256,16 +256,16 @@ __device__ inline float explin_grad(float x, float c, float inv_c) {
 // the split (the tail) beside the totals, and the backward restarts P at 0
 // against the tail total there, so deep pieces see an error ~2^-24 T_REBASE
 // |L| instead.  Asset segments do the same on their own transmittance.
-// Heaviest-first launch order (render.hip) of n items of weight
-// w[i] - (w0 ? w0[i] : 0).
 // Pinned staging for small per-call host tables (one buffer per host
 // thread): acquire waits for the previous upload from it, release records
 // an event after the upload just enqueued on s.
 uint8_t* stage_acquire(size_t bytes);
 dv_status stage_release(hipStream_t s);
 
-dv_status launch_order_by_weight(int64_t n, const uint32_t* w0, const uint32_t* w,
-                                 uint32_t* order, hipStream_t s);
+// Heaviest-first launch order (render.hip) of n items of weight
+// w[i] - (w0 ? w0[i] : 0).
+dv_status launch_order_by_weight(dv_ctx* ctx, int64_t n, const uint32_t* w0,
+                                 const uint32_t* w, uint32_t* order, hipStream_t s);
 
 
 // Background entries per chunk: a tile whose list is longer than 1.5

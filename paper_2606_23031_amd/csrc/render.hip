@@ -484,8 +484,12 @@ __global__ void k_actor_ranges(int64_t n, const uint32_t* act_tile,
 
 // Launch orders: heaviest work first, so long items start early and short
 // ones fill the tail of the grid.  Items are bucketed by weight on a log
-// scale with 8 steps per octave; the order inside a bucket is whatever the
-// LDS atomics give, which changes no result (items are independent).
+// scale with 8 steps per octave; the order inside a bucket (what the LDS
+// atomics of the plan give, ascending ids in launch_order_by_weight)
+// changes no result (items are independent).
+// Up to this many lists (items) one block plans (orders) them: fewer
+// launches; above it the device-wide scans and sort are faster.
+constexpr int64_t PLAN_ONE_BLOCK = 32768;
 __device__ inline uint32_t weight_bucket(uint32_t w) {
   if (w == 0) return 0;
   const uint32_t lz = __builtin_clz(w);
@@ -538,11 +542,38 @@ __global__ void __launch_bounds__(1024) k_order_by_weight(int64_t n, const uint3
     order[atomicAdd(&off[255 - weight_bucket(w[i] - (w0 ? w0[i] : 0u))], 1u)] = (uint32_t)i;
 }
 
-dv_status launch_order_by_weight(int64_t n, const uint32_t* w0, const uint32_t* w,
-                                 uint32_t* order, hipStream_t s) {
+// Sort key of item i: heavier first (255 - weight bucket), value i.
+__global__ void __launch_bounds__(TPB) k_weight_keys(int64_t n, const uint32_t* w0,
+                                                     const uint32_t* w,
+                                                     uint32_t* keys, uint32_t* vals) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = 255u - weight_bucket(w[i] - (w0 ? w0[i] : 0u));
+  vals[i] = (uint32_t)i;
+}
+
+// One stable 8-bit radix pass over the bucket keys (equal buckets keep
+// ascending item order).
+dv_status launch_order_by_weight(dv_ctx* ctx, int64_t n, const uint32_t* w0,
+                                 const uint32_t* w, uint32_t* order, hipStream_t s) {
   if (n <= 0) return DV_OK;
-  hipLaunchKernelGGL(k_order_by_weight, dim3(1), dim3(1024), 0, s, n, w0, w, order);
+  if (n <= PLAN_ONE_BLOCK) {
+    hipLaunchKernelGGL(k_order_by_weight, dim3(1), dim3(1024), 0, s, n, w0, w, order);
+    DV_TRY_HIP(hipGetLastError());
+    return DV_OK;
+  }
+  DBuf keys, vals, kalt;
+  DV_TRY(alloc_n<uint32_t>(ctx, keys, n, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, vals, n, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, kalt, n, s));
+  // (a single item is its own order: written straight into order)
+  hipLaunchKernelGGL(k_weight_keys, dim3(grid_for(n, TPB)), dim3(TPB), 0, s, n, w0,
+                     w, keys.as<uint32_t>(), n == 1 ? order : vals.as<uint32_t>());
   DV_TRY_HIP(hipGetLastError());
+  if (n == 1) return DV_OK;
+  bool alt = false;
+  DV_TRY(radix_sort_u32(ctx, keys.as<uint32_t>(), vals.as<uint32_t>(),
+                        kalt.as<uint32_t>(), order, n, 8, s, &alt));
   return DV_OK;
 }
 
@@ -552,8 +583,9 @@ dv_status launch_order_by_weight(int64_t n, const uint32_t* w0, const uint32_t* 
 // item; split tiles keep their partial states in those slots.  The launch
 // order puts the longest chunks first.  counts[0] = items, counts[1] =
 // slots reserved.  The same for the (tile, actor) lists when range is given
-// (range[e] = [first, end) entries).  One block of 1024 threads, walking the
-// lists in rounds of 1024 consecutive ones (coalesced) with running totals.
+// (range[e] = [first, end) entries).  Device-wide: the slots each list
+// wants and the items it is granted are two exclusive scans over the lists,
+// and the order one stable radix pass over the items' weight buckets.
 struct PlanArgs {
   int64_t n_tiles;
   const uint32_t* start;
@@ -568,10 +600,66 @@ struct PlanArgs {
   uint32_t* order;
   uint32_t* counts;
   uint32_t* slot_tile;         // chunk slot -> its list (or null)
+  int64_t max_items;           // length of order (ids past the items unused)
 };
 
-// Block b plans list set b (the background lists and the (tile, actor)
-// lists run side by side).
+__device__ inline uint32_t plan_len(const PlanArgs& P, int64_t t) {
+  return P.range ? P.range[t].y - P.range[t].x : P.bgend[t] - P.start[t];
+}
+
+// Slots wanted by list t (its chunks when it splits, else none).
+__global__ void __launch_bounds__(TPB) k_plan_want(PlanArgs P, uint32_t* want) {
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= P.n_tiles) return;
+  const uint32_t kw = chunks_of(plan_len(P, t), P.chunk_len);
+  want[t] = kw > 1 ? kw : 0u;
+}
+
+// Chunks granted: all of them when the list's slots (from the scan of the
+// wanted slots) end within max_slots, else the list stays one item.
+__global__ void __launch_bounds__(TPB) k_plan_grant(PlanArgs P) {
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= P.n_tiles) return;
+  const uint32_t kw = chunks_of(plan_len(P, t), P.chunk_len);
+  const uint32_t pb = P.tile_pbase[t];
+  P.tile_nck[t] = (kw > 1 && pb + kw <= P.max_slots) ? kw : 1u;
+}
+
+// Every id starts as unused (lightest key, so it sorts last).
+__global__ void __launch_bounds__(TPB) k_plan_keys(int64_t n, uint32_t* keys,
+                                                   uint32_t* vals) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = 255u;
+  vals[i] = (uint32_t)i;
+}
+
+// The items of list t (ids from the scan of the granted counts), their
+// slots, and their order keys: heavier first.
+__global__ void __launch_bounds__(TPB) k_plan_emit(PlanArgs P, uint32_t* keys) {
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= P.n_tiles) return;
+  const uint32_t len = plan_len(P, t);
+  const uint32_t k = P.tile_nck[t], ib = P.tile_ibase[t], pb = P.tile_pbase[t];
+  if (P.slot_tile && k > 1)
+    for (uint32_t c = 0; c < k; ++c) P.slot_tile[pb + c] = (uint32_t)t;
+  for (uint32_t c = 0; c < k; ++c) {
+    uint32_t cb, ce;
+    chunk_range(0, len, k, c, cb, ce);
+    P.item_tile[ib + c] = (uint32_t)t;
+    P.item_chunk[ib + c] = c;
+    keys[ib + c] = 255u - weight_bucket(ce - cb);
+  }
+}
+
+__global__ void k_plan_counts(PlanArgs P, const uint64_t* tot) {
+  P.counts[0] = (uint32_t)tot[1];
+  P.counts[1] = (uint32_t)min(tot[0], (uint64_t)P.max_slots);
+}
+
+// Small list sets: one block of 1024 threads per set (block b plans set
+// b), walking the lists in rounds of 1024 consecutive ones (coalesced)
+// with running totals; the order by LDS-atomic bucket offsets.
 __global__ void __launch_bounds__(1024) k_plan_items(PlanArgs p0, PlanArgs p1) {
   const PlanArgs& P = blockIdx.x == 0 ? p0 : p1;
   const int64_t n_tiles = P.n_tiles;
@@ -643,6 +731,36 @@ __global__ void __launch_bounds__(1024) k_plan_items(PlanArgs p0, PlanArgs p1) {
       order[atomicAdd(&off[255 - weight_bucket(ce - cb)], 1u)] = ib + c;
     }
   }
+}
+
+static dv_status plan_items(dv_ctx* ctx, const PlanArgs& P, hipStream_t s) {
+  const int64_t n = P.n_tiles, m = P.max_items;
+  const dim3 gl(grid_for(n, TPB)), gi(grid_for(m, TPB));
+  DBuf want, tot, keys, vals, kalt;
+  DV_TRY(alloc_n<uint32_t>(ctx, want, n, s));
+  DV_TRY(alloc_n<uint64_t>(ctx, tot, 2, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, keys, m, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, vals, m, s));
+  DV_TRY(alloc_n<uint32_t>(ctx, kalt, m, s));
+  hipLaunchKernelGGL(k_plan_want, gl, dim3(TPB), 0, s, P, want.as<uint32_t>());
+  DV_TRY(exclusive_scan_u32(ctx, want.as<uint32_t>(), P.tile_pbase,
+                            tot.as<uint64_t>(), n, s));
+  hipLaunchKernelGGL(k_plan_grant, gl, dim3(TPB), 0, s, P);
+  DV_TRY(exclusive_scan_u32(ctx, P.tile_nck, P.tile_ibase, tot.as<uint64_t>() + 1,
+                            n, s));
+  // (a single id is its own order: written straight into order)
+  hipLaunchKernelGGL(k_plan_keys, gi, dim3(TPB), 0, s, m, keys.as<uint32_t>(),
+                     m == 1 ? P.order : vals.as<uint32_t>());
+  hipLaunchKernelGGL(k_plan_emit, gl, dim3(TPB), 0, s, P, keys.as<uint32_t>());
+  hipLaunchKernelGGL(k_plan_counts, dim3(1), dim3(1), 0, s, P,
+                     (const uint64_t*)tot.as<uint64_t>());
+  DV_TRY_HIP(hipGetLastError());
+  if (m > 1) {
+    bool alt = false;
+    DV_TRY(radix_sort_u32(ctx, keys.as<uint32_t>(), vals.as<uint32_t>(),
+                          kalt.as<uint32_t>(), P.order, m, 8, s, &alt));
+  }
+  return DV_OK;
 }
 
 // ------------------------------------------------------------------ composite
@@ -2218,7 +2336,8 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
                                 st->aitem_pair.as<uint32_t>(),
                                 st->aitem_chunk.as<uint32_t>(),
                                 st->aorder.as<uint32_t>(),
-                                st->aplan_counts.as<uint32_t>(), nullptr};
+                                st->aplan_counts.as<uint32_t>(), nullptr,
+                                st->max_aitems};
   }
   if (nt > 0)
     plans[n_plans++] = PlanArgs{nt, st->tile_start.as<uint32_t>(),
@@ -2230,11 +2349,20 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
                                 st->item_chunk.as<uint32_t>(),
                                 st->order_fwd.as<uint32_t>(),
                                 st->plan_counts.as<uint32_t>(),
-                                st->slot_tile.as<uint32_t>()};
-  if (n_plans > 0) {
-    hipLaunchKernelGGL(k_plan_items, dim3(n_plans), dim3(1024), 0, s, plans[0],
-                       plans[n_plans - 1]);
-    DV_TRY_HIP(hipGetLastError());
+                                st->slot_tile.as<uint32_t>(), st->max_items};
+  {
+    // small sets in one launch (a block each), large ones device-wide
+    PlanArgs small[2];
+    int n_small = 0;
+    for (int i = 0; i < n_plans; ++i) {
+      if (plans[i].n_tiles <= PLAN_ONE_BLOCK) small[n_small++] = plans[i];
+      else DV_TRY(plan_items(ctx, plans[i], s));
+    }
+    if (n_small > 0) {
+      hipLaunchKernelGGL(k_plan_items, dim3(n_small), dim3(1024), 0, s, small[0],
+                         small[n_small - 1]);
+      DV_TRY_HIP(hipGetLastError());
+    }
   }
   tm_dir.stop();
   // per-pixel scratch
