@@ -1233,6 +1233,39 @@ struct ShArgs {
   bool normals;
 };
 
+// Visibility ballots of views [v0, v0 + LB_VB) for the wave of leaves
+// x0.. of octree k (0 where the leaf set is not binned in a view), and for
+// each visible view the record slot of the wave's first visible lane.  The
+// loads of the LB_VB views are independent, so they are in flight together
+// rather than one dependent chain per view.
+constexpr int LB_VB = 8;
+__device__ inline void leaf_view_slots(const ShArgs& p, int k, int64_t x0, int v0,
+                                       uint64_t m[LB_VB], uint32_t base[LB_VB]) {
+  int64_t item0[LB_VB];
+  bool ok[LB_VB];
+#pragma unroll
+  for (int j = 0; j < LB_VB; ++j) {
+    const int v = v0 + j;
+    const int sg = min(v, p.n_views - 1) * p.n_oct + k;
+    ok[j] = v < p.n_views && p.seg_len[sg] != 0;
+    item0[j] = p.pstart[sg] + x0;
+  }
+#pragma unroll
+  for (int j = 0; j < LB_VB; ++j) m[j] = ok[j] ? p.wmask[item0[j] >> 6] : 0ull;
+#pragma unroll
+  for (int j = 0; j < LB_VB; ++j) {
+    base[j] = 0;
+    if (m[j] != 0) {
+      const int64_t blk = item0[j] / TPB;
+      const int wib = (int)((item0[j] >> 6) % (TPB / 64));
+      uint32_t b = p.boff[blk];
+      for (int i = 0; i < wib; ++i)
+        b += (uint32_t)__popcll(p.wmask[blk * (TPB / 64) + i]);
+      base[j] = b;
+    }
+  }
+}
+
 template <int S>
 __device__ inline void sh_leaf(const ShArgs& p, int k, int64_t x0, int lane,
                                int N, int deg, float* gsh, float* gcor,
@@ -1247,19 +1280,17 @@ __device__ inline void sh_leaf(const ShArgs& p, int k, int64_t x0, int lane,
     for (int q = 0; q < S; ++q) acc[ch][q] = 0.0f;
   float dgs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   bool any = false, anyc = false;
-  for (int v = 0; v < p.n_views; ++v) {
-    const int sg = v * p.n_oct + k;
-    if (p.seg_len[sg] == 0) continue;
-    const int64_t item0 = p.pstart[sg] + x0;   // the wave's first item
-    const uint64_t m = p.wmask[item0 >> 6];
+  for (int v0 = 0; v0 < p.n_views; v0 += LB_VB) {
+  uint64_t mv[LB_VB];
+  uint32_t bv[LB_VB];
+  leaf_view_slots(p, k, x0, v0, mv, bv);
+#pragma unroll
+  for (int j = 0; j < LB_VB; ++j) {
+    const uint64_t m = mv[j];
     if (m == 0) continue;
-    const int64_t blk = item0 / TPB;
-    const int wib = (int)((item0 >> 6) % (TPB / 64));
-    uint32_t base = p.boff[blk];
-    for (int i = 0; i < wib; ++i)
-      base += (uint32_t)__popcll(p.wmask[blk * (TPB / 64) + i]);
+    const int sg = (v0 + j) * p.n_oct + k;
     if (!in || !((m >> lane) & 1ull)) continue;
-    const uint32_t slot = base + (uint32_t)__popcll(m & lt);
+    const uint32_t slot = bv[j] + (uint32_t)__popcll(m & lt);
     if (gcor) {
       const float4 a8 = p.gg8a[slot], b8 = p.gg8b[slot];
       float dg[8] = {a8.x, a8.y, a8.z, a8.w, b8.x, b8.y, b8.z, b8.w};
@@ -1290,6 +1321,7 @@ __device__ inline void sh_leaf(const ShArgs& p, int k, int64_t x0, int lane,
 #pragma unroll
       for (int q = 0; q < S; ++q) acc[ch][q] = fmaf(Y[q], mc[ch], acc[ch][q]);
     any = true;
+  }
   }
   if (anyc) {
     int32_t ci[8];
@@ -1322,19 +1354,17 @@ __device__ inline void feat_leaf(const ShArgs& p, int k, int64_t x0, int lane,
   float acc[3] = {0.0f, 0.0f, 0.0f};
   float dgs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   bool any = false, anyc = false;
-  for (int v = 0; v < p.n_views; ++v) {
-    const int sg = v * p.n_oct + k;
-    if (p.seg_len[sg] == 0) continue;
-    const int64_t item0 = p.pstart[sg] + x0;
-    const uint64_t m = p.wmask[item0 >> 6];
+  for (int v0 = 0; v0 < p.n_views; v0 += LB_VB) {
+  uint64_t mv[LB_VB];
+  uint32_t bv[LB_VB];
+  leaf_view_slots(p, k, x0, v0, mv, bv);
+#pragma unroll
+  for (int j = 0; j < LB_VB; ++j) {
+    const uint64_t m = mv[j];
     if (m == 0) continue;
-    const int64_t blk = item0 / TPB;
-    const int wib = (int)((item0 >> 6) % (TPB / 64));
-    uint32_t base = p.boff[blk];
-    for (int i = 0; i < wib; ++i)
-      base += (uint32_t)__popcll(p.wmask[blk * (TPB / 64) + i]);
+    const int sg = (v0 + j) * p.n_oct + k;
     if (!in || !((m >> lane) & 1ull)) continue;
-    const uint32_t slot = base + (uint32_t)__popcll(m & lt);
+    const uint32_t slot = bv[j] + (uint32_t)__popcll(m & lt);
     if (gcor) {
       const float4 a8 = p.gg8a[slot], b8 = p.gg8b[slot];
       float dg[8] = {a8.x, a8.y, a8.z, a8.w, b8.x, b8.y, b8.z, b8.w};
@@ -1354,6 +1384,7 @@ __device__ inline void feat_leaf(const ShArgs& p, int k, int64_t x0, int lane,
     acc[1] += dc.y;
     acc[2] += dc.z;
     any = any || dc.x != 0.0f || dc.y != 0.0f || dc.z != 0.0f;
+  }
   }
   if (anyc) {
     int32_t ci[8];
