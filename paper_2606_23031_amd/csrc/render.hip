@@ -891,10 +891,13 @@ __device__ inline int build_segments(const CompArgs& a, uint32_t sbase,
 }
 
 // The same sweep with the box intervals in registers, for tiles of at most
-// BS_REG actor boxes: no box slot is written and read back, and the open
+// NR actor boxes: no box slot is written and read back, and the open
 // segment is stored once it is complete.  Same comparisons in the same
-// order, so the segments are those of build_segments.
+// order, so the segments are those of build_segments.  Two instances:
+// BS_REG boxes (nearly every tile) and BS_REG_BIG (a separate launch, so
+// the common case keeps few registers).
 constexpr int BS_REG = 8;
+constexpr int BS_REG_BIG = 40;
 __device__ inline void store_segment(const CompArgs& a, uint32_t q, int tid,
                                      float s, float e, uint32_t meta) {
   const size_t qi = seg_index(q, tid);
@@ -905,13 +908,14 @@ __device__ inline void store_segment(const CompArgs& a, uint32_t q, int tid,
   a.seg_t0[qi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   a.seg_t1[qi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
+template <int NR>
 __device__ inline int build_segments_reg(const CompArgs& a, uint32_t seg0,
                                          int n_at, uint32_t a_beg, int v,
                                          float3 d, int tid) {
-  float bs[BS_REG], be[BS_REG];
-  uint32_t bm[BS_REG];
+  float bs[NR], be[NR];
+  uint32_t bm[NR];
 #pragma unroll
-  for (int j = 0; j < BS_REG; ++j) {
+  for (int j = 0; j < NR; ++j) {
     bs[j] = F_INF;
     be[j] = F_INF;
     bm[j] = 0u;  // no box: never a breakpoint, never an owner
@@ -940,7 +944,7 @@ __device__ inline int build_segments_reg(const CompArgs& a, uint32_t seg0,
     float nb = F_INF;
     uint32_t nb_src = SRC_NONE;
 #pragma unroll
-    for (int j = 0; j < BS_REG; ++j) {
+    for (int j = 0; j < NR; ++j) {
       if (!(bm[j] & (1u << 20))) continue;
       if (bs[j] > cur && bs[j] < nb) { nb = bs[j]; nb_src = bm[j] & 0x3FF; }
       if (be[j] > cur && be[j] < nb) { nb = be[j]; nb_src = (bm[j] >> 10) & 0x3FF; }
@@ -950,7 +954,7 @@ __device__ inline int build_segments_reg(const CompArgs& a, uint32_t seg0,
     if (cur > -F_INF) {
       // the lowest index containing cur
 #pragma unroll
-      for (int j = BS_REG - 1; j >= 0; --j)
+      for (int j = NR - 1; j >= 0; --j)
         if ((bm[j] & (1u << 20)) && bs[j] <= cur && cur < be[j]) owner = j;
     }
     if (owner >= 0) {
@@ -1006,20 +1010,44 @@ __device__ inline void write_outputs(const A& a, const ViewConst& V, int v,
 // segments of the actor boxes its ray meets.
 // One block per (tile, actor) pair; the block of the tile's first pair
 // builds the tile's segments, the others exit (no block is spent on tiles
-// without actor boxes).
-__global__ void __launch_bounds__(TPB) k_build_segments(CompArgs a) {
+// without actor boxes).  A tile of more than BS_REG boxes (about one in a
+// hundred) is queued in big = {count, tiles...} for k_build_segments_big.
+__global__ void __launch_bounds__(TPB) k_build_segments(CompArgs a, uint32_t* big) {
   const uint32_t gt = a.act_tile[blockIdx.x];
   const uint32_t a_beg = a.act_beg[gt];
   if (blockIdx.x != a_beg) return;
   const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
   const int tid = threadIdx.x;
+  if (n_at > BS_REG) {
+    if (tid == 0) big[1 + atomicAdd(big, 1u)] = gt;
+    return;
+  }
   const PixSetup P = pixel_setup(a, gt, tid);
   int nseg = 0;
   if (P.valid)
-    nseg = n_at <= BS_REG
-               ? build_segments_reg(a, 3 * a_beg + n_at, n_at, a_beg, P.v, P.d, tid)
-               : build_segments(a, 3 * a_beg, n_at, a_beg, P.v, P.d, tid);
+    nseg = build_segments_reg<BS_REG>(a, 3 * a_beg + n_at, n_at, a_beg, P.v, P.d, tid);
   a.pix_nseg[P.pix] = (uint32_t)nseg;
+}
+
+// The queued tiles (grid-stride over the queue): at most BS_REG_BIG boxes
+// in registers, more through the box slots in memory.
+__global__ void __launch_bounds__(TPB) k_build_segments_big(CompArgs a,
+                                                            const uint32_t* big) {
+  const uint32_t cnt = big[0];
+  const int tid = threadIdx.x;
+  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const uint32_t gt = big[1 + i];
+    const uint32_t a_beg = a.act_beg[gt];
+    const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
+    const PixSetup P = pixel_setup(a, gt, tid);
+    int nseg = 0;
+    if (P.valid)
+      nseg = n_at <= BS_REG_BIG
+                 ? build_segments_reg<BS_REG_BIG>(a, 3 * a_beg + n_at, n_at, a_beg,
+                                                  P.v, P.d, tid)
+                 : build_segments(a, 3 * a_beg, n_at, a_beg, P.v, P.d, tid);
+    a.pix_nseg[P.pix] = (uint32_t)nseg;
+  }
 }
 
 // Segments of actor j on the ray of this lane: count, first and last.
@@ -2446,8 +2474,14 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
     const bool k1 = op.K == 1;
     if (st->n_apairs > 0) {
       StageTimer tm_act(ctx, ST_ACTOR_FWD, s);
-      hipLaunchKernelGGL(k_build_segments, dim3((unsigned)st->n_apairs), dim3(TPB), 0, s,
-                         ca);
+      DBuf big;
+      DV_TRY(alloc_n<uint32_t>(ctx, big, st->n_apairs + 1, s));
+      DV_TRY(fill_u32(big.as<uint32_t>(), 0u, 1, s));
+      hipLaunchKernelGGL(k_build_segments, dim3((unsigned)st->n_apairs), dim3(TPB), 0,
+                         s, ca, big.as<uint32_t>());
+      hipLaunchKernelGGL(k_build_segments_big,
+                         dim3((unsigned)std::min<int64_t>(st->n_apairs, 256)), dim3(TPB),
+                         0, s, ca, (const uint32_t*)big.as<uint32_t>());
       auto ka = nrm ? (k1 ? k_actor_fwd<true, 1> : k_actor_fwd<true, 0>)
                     : (k1 ? k_actor_fwd<false, 1> : k_actor_fwd<false, 0>);
       hipLaunchKernelGGL(ka, dim3((unsigned)st->max_aitems), dim3(TPB), 0, s, ca);

@@ -131,3 +131,28 @@ def dense_scene(seed=0, n_actors=2, level=5, deg=1, actor_level=None,
                 explin_c=1.1)
     return dict(scene=dict(octrees=octs, tracks=tracks), views=[view],
                 opts=opts)
+
+
+def crowd_scene(seed=0, n_actors=12, deg=1, W=32, H=32):
+    """Many small actor boxes stacked along the view direction (spaced
+    closer than their depth, so neighbours overlap): the central tiles hold
+    every box, for the segment builders' many-box paths."""
+    rng = np.random.default_rng(seed)
+    bg = random_octree(rng, (-2.0, -2.0, -2.0), 4.0, 2, 10, 4, deg,
+                       g_mean=-1.5, g_std=1.0)
+    octs = [bg]
+    tracks = [None]
+    eye = np.array([3.0, 1.5, 1.2])
+    fwd = -eye / np.linalg.norm(eye)
+    for i in range(n_actors):
+        a = random_octree(rng, (-0.15, -0.15, -0.15), 0.3, 1, 4, 3, deg,
+                          g_mean=1.0, g_std=1.0,
+                          box=((-0.13, -0.12, -0.1), (0.13, 0.12, 0.1)))
+        octs.append(a)
+        c = 0.5 * fwd + (i * 0.6 / max(n_actors, 1)) * fwd + rng.normal(0, 0.03, 3)
+        tracks.append(static_track(0.4 * i, c))
+    view = make_view(W, H, 12.0, look_at_c2w(eye, (0.0, 0.0, 0.0)), t=1.0)
+    opts = dict(K=1, eps_stop=0.0, tau_near=0.0, bg=(0.1, 0.2, 0.3),
+                explin_c=1.1)
+    return dict(scene=dict(octrees=octs, tracks=tracks), views=[view],
+                opts=opts)

@@ -122,6 +122,32 @@ def test_backward_actor_close_up(ctx, fov):
         _close(f"dp[{i}]", p[i, 9:], ref["dp"][i + 1])
 
 
+@pytest.mark.parametrize("n_actors", [12, 44])
+def test_backward_crowded_tiles(ctx, n_actors):
+    """Tiles holding 12 or 44 overlapping actor boxes (the segment
+    builder's wide register sweep, and the sweep through memory).  Deep in
+    the stack an actor owns a thin slice of each ray behind up to 2 n - 1
+    segments: its gradients are small, while their absolute FP32 error is
+    that of the whole ray's sums (background included).  So besides the
+    summand-magnitude term, the floor of every array is taken from the
+    largest gradient of the scene (1e-5 of it), not of that octree."""
+    from scenes import crowd_scene
+    cfg = crowd_scene(seed=4, n_actors=n_actors)
+    acc, pg, ref, _ = _run(ctx, cfg, mask_normals=True, seed=4)
+    top_c = max(float(np.abs(r).max()) for r in ref["corner"])
+    top_s = max(float(np.abs(r).max()) for r in ref["sh"])
+    for k in range(len(acc)):
+        _close(f"corner[{k}]", acc[k]["corner"].cpu().numpy(), ref["corner"][k],
+               summed=ref["corner_abs"][k], extra=1e-5 * top_c)
+        _close(f"sh[{k}]", acc[k]["sh"].cpu().numpy(), ref["sh"][k],
+               summed=ref["sh_abs"][k], extra=1e-5 * top_s)
+    p = pg.cpu().numpy()[0]
+    for i in range(len(acc) - 1):
+        _close(f"dR[{i}]", p[i, :9].reshape(3, 3), ref["dR"][i + 1],
+               summed=ref["dR_abs"][i + 1])
+        _close(f"dp[{i}]", p[i, 9:], ref["dp"][i + 1], summed=ref["dp_abs"][i + 1])
+
+
 def test_backward_normals_rendered_without_normal_gradient(ctx):
     """Normals are rendered but no view passes a normal gradient: the
     backward runs without normal terms (they are exactly zero), and the

@@ -109,6 +109,21 @@ def test_actor_close_up_parity(ctx, fov):
     _lists_equal(ctx, st, cfg["scene"], v)
 
 
+@pytest.mark.parametrize("n_actors", [12, 44])
+def test_crowded_tiles_parity(ctx, n_actors):
+    # every tile holds all n_actors boxes, stacked and overlapping along the
+    # rays: 12 takes the segment builder's wide register sweep, 44 (more
+    # than it holds) the sweep through memory
+    from gpu_helpers import render_gpu
+    from scenes import crowd_scene
+    cfg = crowd_scene(seed=3, n_actors=n_actors)
+    v = cfg["views"][0]
+    res, st, _ = render_gpu(ctx, cfg["scene"], [v], cfg["opts"], keep=True)
+    ref = _oracle(cfg["scene"], v, cfg["opts"])
+    _compare(res[0], ref)
+    _lists_equal(ctx, st, cfg["scene"], v)
+
+
 @pytest.mark.parametrize("eps", [0.0, 1e-4])
 def test_chunked_tiles_parity(ctx, eps):
     # every tile's list (2.7k-4.2k entries) is split into chunks whose
