@@ -441,19 +441,27 @@ def alu_roofline(stage, ms, calls, launches_per_step, counters):
                                 frac=fine / per / 1e12 / PEAK_FP32_TFLOPS))
 
 
+def radix_passes(bits):
+    """Passes of the library's radix sort over `bits` key bits: 9-bit digits
+    where they need fewer passes than 8-bit ones."""
+    p8, p9 = (bits + 7) // 8, (bits + 8) // 9
+    return p9 if p9 < p8 else p8
+
+
 def hbm_stages(stages, info, scene_stats):
     """Algorithmic HBM bytes of the streaming stages per step (the method's
     own reads and writes: preprocess V 8 + V_vis (12 S + 64) + V_vis 48,
-    sorts V_vis 16 p_v + P 24 p_p with p the radix passes, SH / record
-    backward V_vis (12 + 24 S)) over the stage's device time per step."""
+    sorts V_vis 24 p_v (8-byte key + 4-byte value, read and written) + P 16
+    p_p (4 + 4) with p the radix passes, SH / record backward
+    V_vis (12 + 24 S)) over the stage's device time per step."""
     nv, npairs = info["n_visible"], info["n_pairs"]
     S, V = scene_stats["S"], scene_stats["items"]
-    p_v = (info["key_bits"] + 7) // 8
-    p_p = (info["tile_bits"] + 7) // 8
+    p_v = radix_passes(info["key_bits"])
+    p_p = radix_passes(info["tile_bits"])
     algo = {
         "preprocess": V * 8 + nv * (12 * S + 64) + nv * 48,
-        "sort_records": nv * 16 * p_v,
-        "sort_pairs": npairs * 24 * p_p,
+        "sort_records": nv * 24 * p_v,
+        "sort_pairs": npairs * 16 * p_p,
         "record_bwd": nv * (12 + 24 * S),
     }
     out = {}
