@@ -536,8 +536,9 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
   const float3 inv = safe_inv(d);
   uint32_t beg, bgend;
   chunk_range(a.tile_start[gt], a.tile_bgend[gt], nck, chunk, beg, bgend);
-  float Bc, Bn;
-  chunk_bounds(a, gt, nck, chunk, tid, Bc, Bn);
+  // chunk boundaries: only to place a lane's segments between chunks
+  float Bc = -F_INF, Bn = F_INF;
+  if (nseg > 0) chunk_bounds(a, gt, nck, chunk, tid, Bc, Bn);
   auto suffix = [&]() { return T < T_REBASE ? ST : S; };
   // composite one piece of entry r and add its colour/normal/corner
   // gradients; returns dL/dtau, the piece's weight w (in the chunk) in wg

@@ -582,7 +582,8 @@ __device__ inline PixSetup pixel_setup(const A& a, uint32_t gt, int tid) {
 // segments starting before B'_c belong to earlier chunks (spliced by the
 // chunk before, at its end), the others to chunk c or later.  Chords along
 // one ray are disjoint and in depth order, so this splits the sequential
-// walk exactly.
+// walk exactly.  Only a pixel with segments uses them (and only its
+// B_c are searched).
 // B_c is searched by CB_SPLIT blocks over consecutive parts of the chunk;
 // the first part (in list order) with a chord gives it.
 constexpr int CB_SPLIT = 4;

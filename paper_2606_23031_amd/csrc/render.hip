@@ -1293,11 +1293,13 @@ __global__ void __launch_bounds__(TPB) k_actor_merge(CompArgs a) {
   a.seg_t1[qi] = make_float4(0, 0, 0, 0);
 }
 
-// Forward, part 2 (chunked tiles, chunks c > 0): B_c of every pixel, the
-// entry depth of its first non-empty chord among the chunk's entries.  The
-// grid walks the chunk slots (slot -> list from the plan; each chunk in
-// CB_SPLIT parts, one per block), so no block is spent on unchunked tiles;
-// every block leaves once the slots run out.
+// Forward, part 2 (chunked tiles, chunks c > 0): B_c of every pixel with
+// ownership segments, the entry depth of its first non-empty chord among
+// the chunk's entries (B_c only places segments between chunks, so tiles
+// without actor boxes and pixels without segments skip the search and
+// never read it).  The grid walks the chunk slots (slot -> list from the
+// plan; each chunk in CB_SPLIT parts, one per block), so no block is spent
+// on unchunked tiles; every block leaves once the slots run out.
 __global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a,
                                                       const uint32_t* slot_tile) {
   __shared__ Batch B;
@@ -1310,6 +1312,7 @@ __global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a,
     if (gt == 0xFFFFFFFFu) continue;           // slot of no granted list
     const uint32_t c = sl - a.tile_pbase[gt];
     if (c == 0) continue;                      // chunk 0 starts at the camera
+    if (a.act_beg[gt + 1] == a.act_beg[gt]) continue;   // no segments here
     const uint32_t nck = a.tile_nck[gt];
     const PixSetup P = pixel_setup(a, gt, tid);
     const float3 inv = safe_inv(P.d);
@@ -1323,8 +1326,9 @@ __global__ void __launch_bounds__(TPB) k_chunk_bounds(CompArgs a,
       cb = pb;
     }
     float Bc = F_INF;
-    bool found = !P.valid;
-    for (uint32_t base = cb; base < ce; base += TPB) {
+    bool found = !P.valid || a.pix_nseg[P.pix] == 0;
+    const bool all_found = __syncthreads_and(found);
+    for (uint32_t base = cb; base < ce && !all_found; base += TPB) {
       const uint32_t nb = min((uint32_t)TPB, ce - base);
       load_batch_geo(B, a, base, nb);
       __syncthreads();
@@ -1430,8 +1434,9 @@ __device__ __forceinline__ void composite_item(const A& a, uint32_t idx,
   };
   uint32_t beg, bgend;
   chunk_range(a.tile_start[gt], a.tile_bgend[gt], nck, chunk, beg, bgend);
-  float Bc, Bn;
-  chunk_bounds(a, gt, nck, chunk, tid, Bc, Bn);
+  // chunk boundaries: only to place a lane's segments between chunks
+  float Bc = -F_INF, Bn = F_INF;
+  if (nseg > 0) chunk_bounds(a, gt, nck, chunk, tid, Bc, Bn);
   // An entry takes the straight-line iteration (one piece per chord) when no
   // lane's chord meets a segment, which always holds for lanes without
   // segments (excl = -inf, ns = +inf); only the other entries splice.
