@@ -730,16 +730,38 @@ __global__ void __launch_bounds__(TPB, 4) k_composite_bwd(CompArgs a) {
   count_waves(a.counters, 10, w_iter, w_hit);
 }
 
-// Segments of actor j on the ray of this lane: count, first and last.
+// Segments of actor j on the ray of this lane, in one pass over the
+// lane's segments with the loads of 8 segments in flight together: their
+// count and first, and the first and last of those spliced by the
+// background walk (seg_bw.x >= 0; nseg and -1 when none).
 __device__ inline int segs_of_actor_b(const CompArgs& a, uint32_t seg0, int nseg,
-                                      int j, int tid, int& qfirst) {
+                                      int j, int tid, int& qfirst, int& sfirst,
+                                      int& slast) {
   int nj = 0;
   qfirst = nseg;
-  for (int i = 0; i < nseg; ++i)
-    if ((int)(a.seg_meta[seg_index(seg0 + i, tid)] & 0xFF) == j) {
-      if (nj == 0) qfirst = i;
+  sfirst = nseg;
+  slast = -1;
+  for (int i0 = 0; i0 < nseg; i0 += 8) {
+    bool own[8];
+    float bwx[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      own[k] = i0 + k < nseg &&
+               (int)(a.seg_meta[seg_index(seg0 + i0 + k, tid)] & 0xFF) == j;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      bwx[k] = own[k] ? a.seg_bw[seg_index(seg0 + i0 + k, tid)].x : -1.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (!own[k]) continue;
+      if (nj == 0) qfirst = i0 + k;
       ++nj;
+      if (bwx[k] >= 0.0f) {
+        if (sfirst == nseg) sfirst = i0 + k;
+        slast = i0 + k;
+      }
     }
+  }
   return nj;
 }
 
@@ -760,8 +782,9 @@ __global__ void __launch_bounds__(TPB) k_actor_prep(CompArgs a) {
   if (!P.valid) return;
   const uint32_t seg0 = 3 * a_beg + n_at;
   const int nseg = (int)a.pix_nseg[P.pix];
-  int qfirst;
-  if (segs_of_actor_b(a, seg0, nseg, (int)(e - a_beg), tid, qfirst) != 1) return;
+  int qfirst, sfirst, slast;
+  if (segs_of_actor_b(a, seg0, nseg, (int)(e - a_beg), tid, qfirst, sfirst, slast) != 1)
+    return;
   const PixGrad g = pixel_grads<NORMALS>(a, P);
   const size_t s0 = (size_t)a.pair_pbase[e] * TPB + tid;
   const float4* part = a.apart + s0 * 4;
@@ -814,15 +837,11 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
 
   // ---------------------------------------------------- B2: actor jsel
   for (int j = jsel; j == jsel; ++j) {
-    int qf;
-    const int nj = segs_of_actor_b(a, seg0, nseg, j, tid, qf);
+    // first and last spliced segment of slot j (once the last is done the
+    // lane has nothing left in this list)
+    int qf, q, qlast;
+    const int nj = segs_of_actor_b(a, seg0, nseg, j, tid, qf, q, qlast);
     const bool simple = nck > 1 && nj == 1;
-    // first spliced segment of slot j
-    int q = nseg;
-    for (int i = 0; i < nseg; ++i) {
-      const size_t qi = seg_index(seg0 + i, tid);
-      if ((int)(a.seg_meta[qi] & 0xFF) == j && a.seg_bw[qi].x >= 0.0f) { q = i; break; }
-    }
     bool has = q < nseg && (nck == 1 || simple || chunk == 0);
     if (!__syncthreads_or(has)) continue;
     const bool any_full = __syncthreads_or(has && nck > 1 && !simple);
@@ -863,13 +882,6 @@ __global__ void __launch_bounds__(TPB, 4) k_actor_bwd(CompArgs a) {
       return nseg;
     };
     if (has) load_q(q);
-    // last spliced segment of actor j on this ray: once it is done the lane
-    // has nothing left in this list
-    int qlast = -1;
-    for (int i = nseg - 1; i >= 0 && qlast < 0; --i) {
-      const size_t qi = seg_index(seg0 + i, tid);
-      if ((int)(a.seg_meta[qi] & 0xFF) == j && a.seg_bw[qi].x >= 0.0f) qlast = i;
-    }
     // a lane whose chord reached past its single segment is finished (fast
     // path below)
     bool fin = false;

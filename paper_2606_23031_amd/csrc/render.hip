@@ -1051,17 +1051,25 @@ __global__ void __launch_bounds__(TPB) k_build_segments_big(CompArgs a,
 }
 
 // Segments of actor j on the ray of this lane: count, first and last.
+// (the loads of 8 segments in flight together)
 __device__ inline int segs_of_actor(const CompArgs& a, uint32_t seg0, int nseg,
                                     int j, int tid, int& qfirst, int& qlast) {
   int nj = 0;
   qfirst = nseg;
   qlast = -1;
-  for (int i = 0; i < nseg; ++i)
-    if ((int)(a.seg_meta[seg_index(seg0 + i, tid)] & 0xFF) == j) {
-      if (nj == 0) qfirst = i;
-      qlast = i;
-      ++nj;
-    }
+  for (int i0 = 0; i0 < nseg; i0 += 8) {
+    uint32_t m[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      m[k] = i0 + k < nseg ? a.seg_meta[seg_index(seg0 + i0 + k, tid)] : 0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (i0 + k < nseg && (int)(m[k] & 0xFF) == j) {
+        if (nj == 0) qfirst = i0 + k;
+        qlast = i0 + k;
+        ++nj;
+      }
+  }
   return nj;
 }
 
