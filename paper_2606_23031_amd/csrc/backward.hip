@@ -300,10 +300,11 @@ __device__ inline float gdot(const PixGrad& g, float4 c, float4 n) {
 // boxes: (-1: not spliced yet, 0, 0, 0).  Only the pixel's own segments
 // are ever read.
 __global__ void __launch_bounds__(TPB) k_seg_bw_init(CompArgs a) {
-  const uint32_t gt = blockIdx.x;
+  // one block per (tile, actor) pair; the tile's first pair does the tile
+  const uint32_t gt = a.act_tile[blockIdx.x];
   const uint32_t a_beg = a.act_beg[gt];
+  if (blockIdx.x != a_beg) return;
   const int n_at = (int)(a.act_beg[gt + 1] - a_beg);
-  if (n_at == 0) return;
   const int tid = threadIdx.x;
   const uint32_t seg0 = 3 * a_beg + n_at;
   const int nseg = (int)a.pix_nseg[(size_t)gt * TPB + tid];
@@ -316,10 +317,8 @@ __global__ void __launch_bounds__(TPB) k_seg_bw_init(CompArgs a) {
 // S_after_c = sum_{c' > c} T_<c' V_c' + T (C_bg.G_C + G_T), summed from the
 // back so that no difference of large sums is formed.
 template <bool NORMALS>
-__global__ void __launch_bounds__(TPB) k_chunk_prep(CompArgs a) {
-  const uint32_t gt = blockIdx.x;
+__device__ inline void chunk_prep_tile(const CompArgs& a, uint32_t gt) {
   const uint32_t nck = a.tile_nck[gt];
-  if (nck <= 1) return;
   const int tid = threadIdx.x;
   const PixSetup P = pixel_setup(a, gt, tid);
   if (!P.valid) return;
@@ -339,6 +338,15 @@ __global__ void __launch_bounds__(TPB) k_chunk_prep(CompArgs a) {
     a.chunk_tps[s0 + q] = make_float2(Tp, S);
     const float Vc = gdot(g, part[q * 4], part[q * 4 + 1]);
     S = fmaf(Tp, Vc, S);
+  }
+}
+template <bool NORMALS>
+__global__ void __launch_bounds__(TPB) k_chunk_prep(CompArgs a,
+                                                    const uint32_t* slot_tile) {
+  const uint32_t n_slots = a.plan_counts[1];
+  for (uint32_t sl = blockIdx.x; sl < n_slots; sl += gridDim.x) {
+    const uint32_t gt = chunked_tile_at(a, slot_tile, sl);
+    if (gt != 0xFFFFFFFFu) chunk_prep_tile<NORMALS>(a, gt);
   }
 }
 
@@ -1743,9 +1751,12 @@ extern "C" dv_status dv_render_backward(dv_ctx* ctx, const dv_scene* scene,
   if (nt > 0) {
     const bool k1 = op.K == 1;
     if (st->n_apairs > 0)
-      hipLaunchKernelGGL(k_seg_bw_init, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
+      hipLaunchKernelGGL(k_seg_bw_init, dim3((unsigned)st->n_apairs), dim3(TPB), 0, s,
+                         ca);
     auto kp = normals ? k_chunk_prep<true> : k_chunk_prep<false>;
-    hipLaunchKernelGGL(kp, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
+    hipLaunchKernelGGL(kp, dim3((unsigned)std::min<int64_t>(st->max_slots, 16384)),
+                       dim3(TPB), 0, s, ca,
+                       (const uint32_t*)st->slot_tile.as<uint32_t>());
     tm_clear.stop();
     {
       StageTimer tm_comp(ctx, ST_COMPOSITE_BWD, s);

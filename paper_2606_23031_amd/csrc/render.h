@@ -587,6 +587,15 @@ __device__ inline PixSetup pixel_setup(const A& a, uint32_t gt, int tid) {
 // B_c is searched by CB_SPLIT blocks over consecutive parts of the chunk;
 // the first part (in list order) with a chord gives it.
 constexpr int CB_SPLIT = 4;
+// The chunked tile whose first chunk slot is sl (from the slot table of
+// the plan), else 0xFFFFFFFF: kernels over chunked tiles walk the slots
+// instead of launching a block per tile.
+template <class A>
+__device__ inline uint32_t chunked_tile_at(const A& a, const uint32_t* slot_tile,
+                                           uint32_t sl) {
+  const uint32_t gt = slot_tile[sl];
+  return (gt != 0xFFFFFFFFu && a.tile_pbase[gt] == sl) ? gt : 0xFFFFFFFFu;
+}
 template <class A>
 __device__ inline float chunk_first(const A& a, size_t slot, int tid) {
   const float* p = a.chunk_b + slot * CB_SPLIT * TPB + tid;

@@ -1595,8 +1595,14 @@ __device__ __forceinline__ void chunk_merge_tile(const A& a, uint32_t gt) {
   write_outputs(a, V, P.v, P.px, P.py, C3, D, N3, T, P.d);
 }
 
-__global__ void __launch_bounds__(TPB) k_chunk_merge(CompArgs a) {
-  chunk_merge_tile(a, blockIdx.x);
+// One chunked tile per slot-table hit, the grid walking the slots.
+__global__ void __launch_bounds__(TPB) k_chunk_merge(CompArgs a,
+                                                     const uint32_t* slot_tile) {
+  const uint32_t n_slots = a.plan_counts[1];
+  for (uint32_t sl = blockIdx.x; sl < n_slots; sl += gridDim.x) {
+    const uint32_t gt = chunked_tile_at(a, slot_tile, sl);
+    if (gt != 0xFFFFFFFFu) chunk_merge_tile(a, gt);
+  }
 }
 
 // ------------------------------------------------------------------ serving
@@ -2520,7 +2526,10 @@ dv_status run_forward(dv_ctx* ctx, const dv_scene* sc, dv_fwd_state* st,
       hipLaunchKernelGGL(kern, dim3(ni), dim3(TPB), 0, s, ca);
     }
     StageTimer tm_m(ctx, ST_OTHER, s);
-    hipLaunchKernelGGL(k_chunk_merge, dim3((unsigned)nt), dim3(TPB), 0, s, ca);
+    hipLaunchKernelGGL(k_chunk_merge,
+                       dim3((unsigned)std::min<int64_t>(st->max_slots, 16384)),
+                       dim3(TPB), 0, s, ca,
+                       (const uint32_t*)st->slot_tile.as<uint32_t>());
   }
   DV_TRY_HIP(hipGetLastError());
   return DV_OK;
