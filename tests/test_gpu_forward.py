@@ -124,6 +124,27 @@ def test_crowded_tiles_parity(ctx, n_actors):
     _lists_equal(ctx, st, cfg["scene"], v)
 
 
+def test_wide_digit_pair_sort_lists_exact(ctx):
+    # nine 1920x1080 views in one launch: 73 440 tiles, so the (leaf, tile)
+    # pairs carry 17-bit tile keys, which the pair sort takes in two passes
+    # of 9-bit digits; the per-tile lists must equal the oracle's binning
+    # and depth order exactly
+    from gpu_helpers import render_gpu
+    from paper_2606_23031_amd import dv
+    cfg = actor_scene(seed=21, n_actors=2, deg=1)
+    views = []
+    for i in range(9):
+        a = 2.0 * np.pi * i / 9
+        eye = np.array([3.2 * np.cos(a), 3.2 * np.sin(a), 1.0 + 0.1 * i])
+        views.append(make_view(1920, 1080, 60.0, look_at_c2w(eye, (0.0, 0.0, 0.0)),
+                               t=2.5))
+    res, st, _ = render_gpu(ctx, cfg["scene"], views, cfg["opts"], keep=True)
+    assert dv.dv_fwd_state_info(st)["tile_bits"] == 17
+    for vi in (0, 4, 8):
+        _lists_equal(ctx, st, cfg["scene"], views[vi], view_idx=vi)
+    dv.dv_fwd_state_release(st)
+
+
 @pytest.mark.parametrize("eps", [0.0, 1e-4])
 def test_chunked_tiles_parity(ctx, eps):
     # every tile's list (2.7k-4.2k entries) is split into chunks whose
