@@ -1559,8 +1559,11 @@ __device__ __forceinline__ void composite_item(const A& a, uint32_t idx,
   write_outputs(a, V, v, px, py, C3, D, N3, T, d);
 }
 
+// Seven blocks per CU (the LDS of seven batches fits the CU's 160 KB):
+// the walk gains more from the waves than it loses to the spills that the
+// 72-register limit causes (six and four blocks per CU measured slower).
 template <bool NORMALS, int KC>
-__global__ void __launch_bounds__(TPB, NORMALS ? 5 : 6) k_composite_fwd(CompArgs a) {
+__global__ void __launch_bounds__(TPB, 7) k_composite_fwd(CompArgs a) {
   __shared__ Batch B;
   __shared__ uint32_t blk_work;
   if (blockIdx.x >= a.plan_counts[0]) return;
